@@ -1,0 +1,43 @@
+"""FP64 CPU oracle for polynomial-filtered subspace extraction.
+
+TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, deliberately
+unoptimised reference of what one extraction computes (Li, Liu, Wen, Yuan,
+"Polynomial-filtered methods for matrix optimization", arXiv 1904.10585):
+
+  * the Chebyshev filter rho(A) U evaluated by its three-term recurrence
+    (section 2.1, eq. cheb, eq. cheb-linear-map, eq. subspace-update),
+  * orthonormalisation of the filtered block by one QR (section 2.1),
+  * the Rayleigh-Ritz step H = Q^T X Q, H = Z Theta Z^T, V = Q Z
+    (section 2.2, eq. RR), with the low-rank projection P_V(X) and the PSD
+    projection P_+(P_V(X)) used by PFPG/PFAM (section 2.2-2.3),
+  * the SVD route through A^T A (section 5.2.1),
+  * the BF16 / FP8-E4M3 quantisers that define the low-precision copies
+    of X the GPU filter reads.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import it.  It shares no code with the HIP path (no common
+kernels, headers, helpers or constants) and never imports it; the product
+path fails loudly when its HIP library is missing instead of falling back
+here.
+
+Parity status of each function is stated in its docstring; every function
+here is pinned by ``tests/test_oracle_*.py`` against closed forms,
+invariants, brute force or an independent algorithm.
+"""
+
+from .chebyshev import cheb_T, interval_map, rho, chebyshev_filter
+from .extract import (orthonormalize, rayleigh_ritz, extract, extract_gram,
+                      psd_projection, lowrank_projection, ritz_residuals)
+from .metrics import sin_theta, projector_distance, ritz_rel_err, orth_error
+from .jacobi import jacobi_eigh
+from .quantize import (bf16_round, fp8_e4m3_round, fp8_tile_quantize,
+                       fp8_tile_dequantize)
+
+__all__ = [
+    "cheb_T", "interval_map", "rho", "chebyshev_filter",
+    "orthonormalize", "rayleigh_ritz", "extract", "extract_gram",
+    "psd_projection", "lowrank_projection", "ritz_residuals",
+    "sin_theta", "projector_distance", "ritz_rel_err", "orth_error",
+    "jacobi_eigh",
+    "bf16_round", "fp8_e4m3_round", "fp8_tile_quantize", "fp8_tile_dequantize",
+]
