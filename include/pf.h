@@ -1,0 +1,220 @@
+/*
+ * pf.h -- polynomial-filtered subspace extraction on one MI355X (gfx950).
+ *
+ * One *extraction* is the step PFPG and PFAM call each iteration in place of
+ * a full eigendecomposition (Li, Liu, Wen, Yuan, arXiv 1904.10585):
+ *
+ *   1. Chebyshev filter  Y = rho(A)^q U,  rho(t) = T_d((t - c)/e),
+ *      c = (a+b)/2, e = (b-a)/2 (section 2.1, eq. cheb, eq. cheb-linear-map),
+ *      evaluated by the three-term recurrence
+ *          Y_1 = (A Y_0 - c Y_0)/e,  Y_{k+1} = 2 (A Y_k - c Y_k)/e - Y_{k-1}
+ *      (section 4, eq. cheby-recursion-map, read with the t-coefficient
+ *      2/(b-a));
+ *   2. orthonormalisation of Y (section 2.1, eq. subspace-update: U+ =
+ *      orth(rho(A) U)), done on the device by CholeskyQR2;
+ *   3. Rayleigh-Ritz (section 2.2, eq. RR): H = Q^T X Q, H = Z Theta Z^T,
+ *      Ritz vectors V = Q Z, which give the low-rank projection
+ *      P_V(X) = V Theta V^T and the PSD projection P_+(P_V(X)) of
+ *      eq. PFAM1 (keep theta_i > 0).
+ *
+ * A is either a dense symmetric X (PF_OP_SYM) or A = M^T M for a
+ * rectangular M (PF_OP_GRAM, the SVD route of section 5.2.1; the Ritz
+ * values are then sigma^2 and Rayleigh-Ritz runs on B = M Q).
+ *
+ * Conventions
+ *  - Every matrix is column-major with a leading dimension (BLAS style).
+ *  - Every data pointer passed to the library is DEVICE memory on the
+ *    current HIP device unless the argument says "host".
+ *  - Calls are stream-ordered on the given hipStream_t (passed as void*;
+ *    NULL = the default stream).  They return as soon as the work is
+ *    enqueued; argument errors are detected synchronously before any work
+ *    is enqueued and leave every output untouched.
+ *  - Numerical outcomes (Cholesky breakdown, Jacobi non-convergence,
+ *    non-finite data) are written by the device into a pf_info record
+ *    once the stream reaches the end of the extraction.
+ *  - No C++ exception crosses this boundary.  pf_last_error() returns a
+ *    thread-local message for the last non-PF_OK status of this thread.
+ *  - The library is not re-entrant per session; distinct sessions and
+ *    distinct pf_extract calls on distinct streams may run concurrently.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PF_ABI_VERSION 1
+
+typedef enum pf_status {
+  PF_OK = 0,
+  PF_ERR_ARG = 1,         /* invalid argument (see pf_last_error) */
+  PF_ERR_NOMEM = 2,       /* device or host allocation failed */
+  PF_ERR_DEVICE = 3,      /* a HIP runtime call failed */
+  PF_ERR_BREAKDOWN = 4,   /* Cholesky of the Gram matrix broke down */
+  PF_ERR_NOCONV = 5,      /* Jacobi eigensolver hit its sweep limit */
+  PF_ERR_NONFINITE = 6,   /* Inf/NaN met in the filtered block */
+  PF_ERR_BUSY = 7,        /* session has work in flight */
+  PF_ERR_UNSUPPORTED = 8  /* valid request this build does not implement */
+} pf_status;
+
+typedef enum pf_dtype {
+  PF_F64 = 0,
+  PF_F32 = 1,
+  PF_BF16 = 2,
+  PF_F8E4M3 = 3  /* OCP E4M3FN, with one FP32 scale per tile x tile block */
+} pf_dtype;
+
+typedef enum pf_op {
+  PF_OP_SYM = 0,  /* A = X, X n-by-n symmetric */
+  PF_OP_GRAM = 1  /* A = M^T M, M m-by-n */
+} pf_op;
+
+/* Flags of pf_desc.flags. */
+#define PF_FLAG_NO_PREROTATE 0x1u /* skip the Ritz rotation of U by X U before
+                                     the recurrence (on by default: it keeps
+                                     every column of the recurrence dominated
+                                     by one eigen-direction, which the FP32
+                                     forms need; the span is unchanged) */
+#define PF_FLAG_SCALED 0x2u       /* divide step k of the recurrence by
+                                     T_k(s_ref), s_ref = mapped spec_ub: the
+                                     same span, no overflow for large |A| */
+#define PF_FLAG_COLD 0x4u         /* the start block is not a warm start:
+                                     every second step the pair (Y_k, Y_{k-1})
+                                     is multiplied by the same R^{-1} from a
+                                     CholeskyQR2 of Y_k, which keeps the block
+                                     well conditioned and (the recurrence
+                                     acting column by column) leaves the span
+                                     of the result unchanged.  Sessions set it
+                                     on their first step. */
+
+/* A matrix operand.  data: device pointer; rows/cols implied by the call;
+ * ld: leading dimension in elements (>= rows; a multiple of 16 bytes /
+ * element size).  For PF_F8E4M3, tile_scale points to ceil(rows/tile) x
+ * ceil(cols/tile) FP32 scales, column-major with leading dimension
+ * ceil(rows/tile); element value = code * scale of its tile. */
+typedef struct pf_mat {
+  const void* data;
+  pf_dtype dtype;
+  int64_t ld;
+  const float* tile_scale;
+  int32_t tile;
+} pf_mat;
+
+/* Problem description.  struct_size must be sizeof(pf_desc) (versioning). */
+typedef struct pf_desc {
+  uint32_t struct_size;
+  pf_op op;
+  int64_t n;        /* order of A (columns of M for PF_OP_GRAM) */
+  int64_t m;        /* rows of M (PF_OP_GRAM only) */
+  int32_t p;        /* block size, 1 <= p <= min(n, 128) */
+  int32_t degree;   /* Chebyshev degree d >= 1 */
+  int32_t q;        /* filter power q >= 1 (eq. pfpg2) */
+  double a, b;      /* damping interval, a < b: eigenvalues in [a, b] are
+                       damped, those above b amplified (section 4.1) */
+  double spec_ub;   /* PF_FLAG_SCALED: an upper bound of the spectrum of A
+                       (> b); ignored otherwise */
+  pf_dtype work;    /* PF_F64 or PF_F32: storage of U, Y, Q, V */
+  uint32_t flags;
+  int32_t max_sweeps; /* Jacobi sweep limit (0 = default 30) */
+} pf_desc;
+
+/* Written by the device at the end of an extraction (device memory). */
+typedef struct pf_info {
+  int32_t status;       /* pf_status of the numerical phase */
+  int32_t n_pos;        /* #{theta_i > 0} */
+  int32_t sweeps_rr;    /* Jacobi sweeps of the Rayleigh-Ritz eigensolve */
+  int32_t sweeps_pre;   /* Jacobi sweeps of the pre-rotation */
+  int32_t deficient;    /* columns replaced because the block lost rank */
+  int32_t reserved[3];
+} pf_info;
+
+/* One extraction (section 2.1 then eq. RR).
+ *  X_filter: the operator the filter applies (X n-by-n, or M m-by-n for
+ *            PF_OP_GRAM); F64 (work F64), F32/BF16/F8E4M3 (work F32).
+ *  X_rr:     the operator Rayleigh-Ritz projects; same shape; F64 or F32
+ *            (may equal X_filter).  BF16/FP8 filters need an F32 X_rr.
+ *  U_inout:  n-by-p block in the work dtype, leading dimension ldu >= n.
+ *            In: start block (any full-rank block; Ritz vectors of the
+ *            previous call for a warm start).  Out: the Ritz vectors V,
+ *            ordered by descending theta.  Left untouched if the device
+ *            reports a numerical error.
+ *  theta_out: p doubles (device), Ritz values in descending order
+ *            (sigma^2 for PF_OP_GRAM).
+ *  info_out: device pf_info, may be NULL.
+ *  stream:   hipStream_t or NULL.
+ * Returns PF_OK once enqueued (PF_ERR_ARG / PF_ERR_NOMEM / PF_ERR_DEVICE
+ * synchronously).  Workspace is allocated on first use for a shape and
+ * reused; the call is stream-ordered with respect to it. */
+pf_status pf_extract(const pf_desc* desc, const pf_mat* X_filter, const pf_mat* X_rr,
+                     void* U_inout, int64_t ldu, double* theta_out, pf_info* info_out,
+                     void* stream);
+
+/* Sessions: a warm-started chain of extractions (eq. pfpg2 / eq. PFAM2:
+ * U^{k+1} = orth(rho(X^{k+1}) U^k)), whose subspace stays on the device.
+ *  U0: device n-by-p block in the work dtype (ld ldu0), or NULL for an
+ *      N(0,1) start drawn on the device from seed. */
+typedef struct pf_session pf_session;
+
+typedef struct pf_result {
+  int32_t status;          /* host copy of pf_info.status (after wait) */
+  int32_t n_pos;           /* host copy of pf_info.n_pos (after wait) */
+  const double* theta;     /* device, p values, valid until next step/close */
+  const void* V;           /* device n-by-p Ritz vectors (work dtype) */
+  int64_t ldv;
+  const pf_info* info;     /* device */
+} pf_result;
+
+pf_status pf_session_open(const pf_desc* desc, const void* U0, int64_t ldu0, uint64_t seed,
+                          pf_session** out);
+/* Enqueue one step on X (and X_rr) on the stream; out (host) receives
+ * device pointers immediately and host status fields after pf_session_wait. */
+pf_status pf_session_step(pf_session* s, const pf_mat* X_filter, const pf_mat* X_rr,
+                          pf_result* out, void* stream);
+/* Block until the session's last step is done; fills out->status/n_pos. */
+pf_status pf_session_wait(pf_session* s, pf_result* out);
+/* Free the session.  PF_ERR_BUSY if a step is still in flight. */
+pf_status pf_session_close(pf_session* s);
+
+/* Quantise an FP32 matrix (rows x cols, ld) into BF16 (dst ld = ld_dst) or
+ * FP8-E4M3 codes with FP32 per-tile scales amax/448 (tile x tile,
+ * column-major scale grid).  Round to nearest even; FP8 saturates at 448. */
+pf_status pf_quantize(void* dst, int64_t ld_dst, float* tile_scale, int32_t tile,
+                      pf_dtype dtype, const float* src, int64_t rows, int64_t cols,
+                      int64_t ld_src, void* stream);
+
+/* Dense PSD projection P_+ = V_+ diag(theta_+) V_+^T (eq. PFAM1) from the
+ * Ritz pairs of an extraction: out n-by-n (work dtype), ld_out >= n. */
+pf_status pf_psd_dense(const void* V, int64_t ldv, const double* theta, int64_t n, int32_t p,
+                       pf_dtype work, void* out, int64_t ld_out, void* stream);
+
+/* Kernel timing hooks (diagnostics).  While enabled, the library records a
+ * HIP event pair on the launch stream around every kernel launch of the
+ * given class; pf_profile_read synchronises on the recorded events and
+ * returns the number of launches and their summed duration in ms.
+ * Classes: PF_PROF_FILTER (the filter product kernel of the Chebyshev
+ * recurrence, without its split-K sum), PF_PROF_FILTER_REDUCE (that sum),
+ * PF_PROF_RR (the Rayleigh-Ritz product X Q), PF_PROF_EXTRACT (one whole
+ * extraction, first to last launch).  pf_profile_set(1) clears the counts. */
+#define PF_PROF_FILTER 0
+#define PF_PROF_FILTER_REDUCE 1
+#define PF_PROF_RR 2
+#define PF_PROF_EXTRACT 3
+pf_status pf_profile_set(int enable);
+pf_status pf_profile_read(int which, int64_t* launches, double* total_ms);
+
+/* Device workspace bytes pf_extract uses for desc (allocated on first use). */
+pf_status pf_workspace_size(const pf_desc* desc, size_t* bytes);
+
+const char* pf_status_string(pf_status s);
+const char* pf_last_error(void);
+int pf_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PF_H */

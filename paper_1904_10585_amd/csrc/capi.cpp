@@ -1,0 +1,323 @@
+// The C ABI of include/pf.h: argument validation, error reporting, the
+// per-stream workspace cache of pf_extract, and sessions.
+#include "pf_internal.h"
+
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <utility>
+#include <vector>
+
+namespace pfx {
+
+[[noreturn]] void fail(pf_status s, const std::string& msg) { throw Error{s, msg}; }
+
+void check_hip(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) fail(PF_ERR_NOMEM, std::string(what) + ": out of memory");
+    fail(PF_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+pf_status guarded(F&& f) {
+  try {
+    f();
+    return PF_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return PF_ERR_NOMEM;
+  } catch (...) {
+    g_last_error = "unexpected internal error";
+    return PF_ERR_DEVICE;
+  }
+}
+
+// pf_extract workspaces: one per (device, stream, shape); calls on one
+// stream are ordered, so a workspace is never used by two extractions at once.
+using PlanKey = std::tuple<int, uintptr_t, int64_t, int, int, int, int, int>;
+std::mutex g_plans_mu;
+std::map<PlanKey, Plan*> g_plans;
+
+Plan* cached_plan(const pf_desc& d, hipStream_t st) {
+  int dev = 0;
+  PFX_HIP(hipGetDevice(&dev));
+  PlanKey key{dev, (uintptr_t)st, d.n, d.p, (int)d.work, (int)d.op, d.degree, d.q};
+  std::lock_guard<std::mutex> lk(g_plans_mu);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    // the plan keeps the descriptor it was built for; refresh the fields
+    // that do not change its layout
+    return it->second;
+  }
+  Plan* P = plan_create(d);
+  g_plans[key] = P;
+  return P;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Kernel timing hooks.  Event pairs are pooled per class and reused after
+// pf_profile_set(1); recording is stream-ordered and adds no synchronisation.
+namespace {
+struct ProfClass {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  size_t used = 0;
+  bool open = false;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+ProfClass g_prof[kProfClasses];
+}  // namespace
+
+bool prof_enabled() { return g_prof_on; }
+
+void prof_begin(int cls, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  ProfClass& c = g_prof[cls];
+  if (c.used == c.pool.size()) {
+    hipEvent_t a, b;
+    PFX_HIP(hipEventCreate(&a));
+    PFX_HIP(hipEventCreate(&b));
+    c.pool.emplace_back(a, b);
+  }
+  PFX_HIP(hipEventRecord(c.pool[c.used].first, st));
+  c.open = true;
+}
+
+void prof_end(int cls, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  ProfClass& c = g_prof[cls];
+  if (!c.open) return;
+  PFX_HIP(hipEventRecord(c.pool[c.used].second, st));
+  c.used++;
+  c.open = false;
+}
+
+}  // namespace pfx
+
+struct pf_session {
+  pfx::Plan* plan = nullptr;
+  pf_desc desc;
+  void* U = nullptr;        // n_pad x p_pad, work dtype
+  int64_t ldu = 0;
+  double* theta = nullptr;
+  pf_info* info = nullptr;
+  hipEvent_t done = nullptr;
+  bool stepped = false;
+  int64_t steps = 0;
+  int device = 0;
+};
+
+using namespace pfx;
+
+extern "C" {
+
+const char* pf_status_string(pf_status s) {
+  switch (s) {
+    case PF_OK: return "PF_OK";
+    case PF_ERR_ARG: return "PF_ERR_ARG: invalid argument";
+    case PF_ERR_NOMEM: return "PF_ERR_NOMEM: allocation failed";
+    case PF_ERR_DEVICE: return "PF_ERR_DEVICE: HIP runtime error";
+    case PF_ERR_BREAKDOWN: return "PF_ERR_BREAKDOWN: Cholesky of the Gram matrix broke down";
+    case PF_ERR_NOCONV: return "PF_ERR_NOCONV: Jacobi did not converge";
+    case PF_ERR_NONFINITE: return "PF_ERR_NONFINITE: non-finite values in the filtered block";
+    case PF_ERR_BUSY: return "PF_ERR_BUSY: work in flight";
+    case PF_ERR_UNSUPPORTED: return "PF_ERR_UNSUPPORTED: not implemented in this build";
+  }
+  return "unknown pf_status";
+}
+
+const char* pf_last_error(void) { return g_last_error.c_str(); }
+
+int pf_abi_version(void) { return PF_ABI_VERSION; }
+
+pf_status pf_profile_set(int enable) {
+  return guarded([&] {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = enable != 0;
+    for (auto& c : g_prof) { c.used = 0; c.open = false; }
+  });
+}
+
+pf_status pf_profile_read(int which, int64_t* launches, double* total_ms) {
+  return guarded([&] {
+    if (which < 0 || which >= kProfClasses) fail(PF_ERR_ARG, "unknown profiling class");
+    if (!launches || !total_ms) fail(PF_ERR_ARG, "NULL output");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    ProfClass& c = g_prof[which];
+    double tot = 0.0;
+    for (size_t i = 0; i < c.used; ++i) {
+      PFX_HIP(hipEventSynchronize(c.pool[i].second));
+      float ms = 0.f;
+      PFX_HIP(hipEventElapsedTime(&ms, c.pool[i].first, c.pool[i].second));
+      tot += ms;
+    }
+    *launches = (int64_t)c.used;
+    *total_ms = tot;
+  });
+}
+
+pf_status pf_workspace_size(const pf_desc* desc, size_t* bytes) {
+  return guarded([&] {
+    if (!desc || !bytes) fail(PF_ERR_ARG, "NULL argument");
+    plan_validate(*desc, nullptr, nullptr);
+    *bytes = plan_bytes(*desc);
+  });
+}
+
+pf_status pf_extract(const pf_desc* desc, const pf_mat* X_filter, const pf_mat* X_rr, void* U_inout, int64_t ldu,
+                     double* theta_out, pf_info* info_out, void* stream) {
+  return guarded([&] {
+    if (!desc) fail(PF_ERR_ARG, "desc is NULL");
+    plan_validate(*desc, X_filter, X_rr);
+    if (!U_inout) fail(PF_ERR_ARG, "U_inout is NULL");
+    if (ldu < desc->n) fail(PF_ERR_ARG, "ldu is smaller than n");
+    if (!theta_out) fail(PF_ERR_ARG, "theta_out is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Plan* P = cached_plan(*desc, st);
+    plan_set_desc(P, *desc);
+    enqueue_extraction(P, *X_filter, *X_rr, U_inout, ldu, U_inout, ldu, theta_out, info_out, st);
+  });
+}
+
+pf_status pf_session_open(const pf_desc* desc, const void* U0, int64_t ldu0, uint64_t seed, pf_session** out) {
+  return guarded([&] {
+    if (!desc || !out) fail(PF_ERR_ARG, "NULL argument");
+    plan_validate(*desc, nullptr, nullptr);
+    if (U0 && ldu0 < desc->n) fail(PF_ERR_ARG, "ldu0 is smaller than n");
+    pf_session* s = new pf_session();
+    try {
+      PFX_HIP(hipGetDevice(&s->device));
+      s->desc = *desc;
+      s->plan = plan_create(*desc);
+      const Elem W = desc->work == PF_F64 ? Elem::F64 : Elem::F32;
+      const size_t esz = W == Elem::F64 ? 8 : 4;
+      s->ldu = round_up(desc->n, 64);
+      const size_t ubytes = (size_t)s->ldu * desc->p * esz;
+      PFX_HIP(hipMalloc(&s->U, ubytes));
+      PFX_HIP(hipMalloc(&s->theta, sizeof(double) * desc->p));
+      PFX_HIP(hipMalloc(&s->info, sizeof(pf_info)));
+      PFX_HIP(hipMemset(s->U, 0, ubytes));
+      PFX_HIP(hipMemset(s->theta, 0, sizeof(double) * desc->p));
+      PFX_HIP(hipMemset(s->info, 0, sizeof(pf_info)));
+      PFX_HIP(hipEventCreateWithFlags(&s->done, hipEventDisableTiming));
+      if (U0) launch_copy_block(U0, ldu0, W, s->U, s->ldu, W, desc->n, desc->p, desc->n, desc->p, nullptr);
+      else launch_normal_block(s->U, s->ldu, W, desc->n, desc->p, seed, nullptr);
+      PFX_HIP(hipDeviceSynchronize());
+    } catch (...) {
+      if (s->U) (void)hipFree(s->U);
+      if (s->theta) (void)hipFree(s->theta);
+      if (s->info) (void)hipFree(s->info);
+      if (s->done) (void)hipEventDestroy(s->done);
+      plan_destroy(s->plan);
+      delete s;
+      throw;
+    }
+    *out = s;
+  });
+}
+
+pf_status pf_session_step(pf_session* s, const pf_mat* X_filter, const pf_mat* X_rr, pf_result* out,
+                          void* stream) {
+  return guarded([&] {
+    if (!s) fail(PF_ERR_ARG, "session is NULL");
+    plan_validate(s->desc, X_filter, X_rr);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    pf_desc d = s->desc;
+    if (s->steps == 0) d.flags |= PF_FLAG_COLD;        // first step starts from U0
+    plan_set_desc(s->plan, d);
+    enqueue_extraction(s->plan, *X_filter, *X_rr, s->U, s->ldu, s->U, s->ldu, s->theta, s->info, st);
+    PFX_HIP(hipEventRecord(s->done, st));
+    s->stepped = true;
+    s->steps++;
+    if (out) {
+      out->status = 0;
+      out->n_pos = 0;
+      out->theta = s->theta;
+      out->V = s->U;
+      out->ldv = s->ldu;
+      out->info = s->info;
+    }
+  });
+}
+
+pf_status pf_session_wait(pf_session* s, pf_result* out) {
+  pf_info host{};
+  pf_status st = guarded([&] {
+    if (!s) fail(PF_ERR_ARG, "session is NULL");
+    if (s->stepped) PFX_HIP(hipEventSynchronize(s->done));
+    PFX_HIP(hipMemcpy(&host, s->info, sizeof(pf_info), hipMemcpyDeviceToHost));
+    if (out) {
+      out->status = host.status;
+      out->n_pos = host.n_pos;
+      out->theta = s->theta;
+      out->V = s->U;
+      out->ldv = s->ldu;
+      out->info = s->info;
+    }
+  });
+  if (st != PF_OK) return st;
+  if (host.status != 0) {
+    g_last_error = pf_status_string((pf_status)host.status);
+    return (pf_status)host.status;
+  }
+  return PF_OK;
+}
+
+pf_status pf_session_close(pf_session* s) {
+  return guarded([&] {
+    if (!s) fail(PF_ERR_ARG, "session is NULL");
+    if (s->stepped) {
+      hipError_t q = hipEventQuery(s->done);
+      if (q == hipErrorNotReady) fail(PF_ERR_BUSY, "session has a step in flight");
+    }
+    (void)hipFree(s->U);
+    (void)hipFree(s->theta);
+    (void)hipFree(s->info);
+    (void)hipEventDestroy(s->done);
+    plan_destroy(s->plan);
+    delete s;
+  });
+}
+
+pf_status pf_quantize(void* dst, int64_t ld_dst, float* tile_scale, int32_t tile, pf_dtype dtype, const float* src,
+                      int64_t rows, int64_t cols, int64_t ld_src, void* stream) {
+  return guarded([&] {
+    if (!dst || !src) fail(PF_ERR_ARG, "NULL matrix pointer");
+    if (rows < 1 || cols < 1) fail(PF_ERR_ARG, "empty matrix");
+    if (ld_src < rows || ld_dst < rows) fail(PF_ERR_ARG, "leading dimension smaller than rows");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (dtype == PF_BF16) {
+      launch_quantize_bf16(src, rows, cols, ld_src, static_cast<uint16_t*>(dst), ld_dst, st);
+    } else if (dtype == PF_F8E4M3) {
+      if (!tile_scale) fail(PF_ERR_ARG, "FP8 needs tile_scale");
+      if (tile < 1) fail(PF_ERR_ARG, "tile must be >= 1");
+      launch_quantize_fp8(src, rows, cols, ld_src, static_cast<uint8_t*>(dst), ld_dst, tile_scale, tile, st);
+    } else {
+      fail(PF_ERR_ARG, "pf_quantize: dtype must be PF_BF16 or PF_F8E4M3");
+    }
+  });
+}
+
+pf_status pf_psd_dense(const void* V, int64_t ldv, const double* theta, int64_t n, int32_t p, pf_dtype work,
+                       void* out, int64_t ld_out, void* stream) {
+  return guarded([&] {
+    if (!V || !theta || !out) fail(PF_ERR_ARG, "NULL argument");
+    if (n < 1 || p < 1 || p > n) fail(PF_ERR_ARG, "bad n / p");
+    if (ldv < n || ld_out < n) fail(PF_ERR_ARG, "leading dimension smaller than n");
+    if (work != PF_F32 && work != PF_F64) fail(PF_ERR_ARG, "work must be F32 or F64");
+    launch_psd_dense(V, ldv, work == PF_F64 ? Elem::F64 : Elem::F32, theta, n, p, out, ld_out,
+                     static_cast<hipStream_t>(stream));
+  });
+}
+
+}  // extern "C"

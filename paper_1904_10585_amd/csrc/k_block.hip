@@ -1,0 +1,319 @@
+// Tall-skinny block operations of an extraction and the quantisers.
+//
+//  * apply: C1 = A1 S and C2 = alpha (A2 S) + beta C1 for an n x p block
+//    times a p x p FP64 matrix S held in LDS.  Used for the pre-rotation
+//    (U W0, X U W0, and the first recurrence step in the same pass), for
+//    Q = Y R^{-1} of CholeskyQR (section 2.1), and for the Ritz vectors
+//    V = Q Z of eq. RR.  Products and sums in FP64.
+//  * quantisers for the low-precision copies of X: BF16 (round to nearest
+//    even) and OCP FP8-E4M3FN with one FP32 scale amax/448 per tile,
+//    saturating at 448.
+//  * psd_dense: P_+ = V_+ diag(theta_+) V_+^T (eq. PFAM1) as a dense matrix.
+#include "pf_internal.h"
+
+#include <cmath>
+
+namespace pfx {
+namespace {
+
+__device__ inline uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// uniform in (0, 1) from 53 random bits
+__device__ inline double u01(uint64_t h) { return ((double)(h >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+
+template <typename T, int NJ>
+__global__ __launch_bounds__(256) void apply_kernel(int64_t n, int p, const T* __restrict__ A1, int64_t lda1,
+                                                    const T* __restrict__ A2, int64_t lda2,
+                                                    const double* __restrict__ S, int lds_, T* C1, int64_t ldc1,
+                                                    T* C2, int64_t ldc2, double alpha, double beta,
+                                                    const int* __restrict__ deficient,
+                                                    const pf_info* gate) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Sl = reinterpret_cast<double*>(smem_raw);    // Sl[k * p + j] = S[k][j]
+  if (gate && gate->status != 0) return;
+  for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
+    const int k = idx / p, j = idx % p;
+    Sl[idx] = S[k + (int64_t)j * lds_];
+  }
+  __syncthreads();
+  const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
+  const int64_t row = (int64_t)blockIdx.x * 64 + r;
+  if (row >= n) return;
+  double acc1[NJ], acc2[NJ];
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) { acc1[u] = 0.0; acc2[u] = 0.0; }
+  for (int k = 0; k < p; ++k) {
+    const double a1 = (double)A1[row + k * lda1];
+    const double a2 = A2 ? (double)A2[row + k * lda2] : 0.0;
+    const double* sk = Sl + k * p;
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const int j = cg + 4 * u;
+      if (j < p) {
+        const double sv = sk[j];
+        acc1[u] += a1 * sv;
+        acc2[u] += a2 * sv;
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int j = cg + 4 * u;
+    if (j >= p) continue;
+    double v1 = acc1[u];
+    if (deficient && deficient[j]) {
+      // rank-deficient column: a fixed pseudo-random direction, which the
+      // next CholeskyQR pass orthogonalises against the others
+      v1 = (2.0 * u01(mix64(((uint64_t)row << 8) ^ (uint64_t)j ^ 0x5DEECE66Dull)) - 1.0) /
+           sqrt((double)n);
+    }
+    C1[row + j * ldc1] = (T)v1;
+    if (C2) C2[row + j * ldc2] = (T)(alpha * acc2[u] + beta * (double)(T)v1);
+  }
+}
+
+template <typename T>
+__global__ void copy_block_kernel(const T* __restrict__ src, int64_t lds_, T* __restrict__ dst, int64_t ldd,
+                                  int64_t n, int p, int64_t n_pad, int p_pad) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n_pad || j >= p_pad) return;
+  dst[i + j * ldd] = (i < n && j < p) ? src[i + j * lds_] : T(0);
+}
+
+template <typename T>
+__global__ void axpby_kernel(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ dst, int64_t ld,
+                             int64_t n, int p, double alpha, double beta) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n || j >= p) return;
+  dst[i + j * ld] = (T)(alpha * (double)A[i + j * ld] + beta * (double)B[i + j * ld]);
+}
+
+__global__ void info_init_kernel(pf_info* info) {
+  if (threadIdx.x == 0) {
+    info->status = 0; info->n_pos = 0; info->sweeps_rr = 0; info->sweeps_pre = 0;
+    info->deficient = 0; info->reserved[0] = info->reserved[1] = info->reserved[2] = 0;
+  }
+}
+
+__global__ void info_copy_kernel(const pf_info* src, pf_info* dst, const double* th, double* thd, int p) {
+  const int t = threadIdx.x;
+  if (dst && t == 0) *dst = *src;
+  if (thd && src->status == 0)
+    for (int i = t; i < p; i += blockDim.x) thd[i] = th[i];
+}
+
+template <typename T>
+__global__ void normal_block_kernel(T* dst, int64_t ld, int64_t n, int p, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n) return;
+  const uint64_t h1 = mix64(seed ^ mix64(((uint64_t)j << 40) ^ (uint64_t)i));
+  const uint64_t h2 = mix64(h1);
+  const double r = sqrt(-2.0 * log(u01(h1)));
+  dst[i + j * ld] = (T)(r * cos(6.283185307179586 * u01(h2)));   // Box-Muller
+}
+
+__device__ inline uint16_t f32_to_bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40);   // quiet NaN
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__global__ void quantize_bf16_kernel(const float* __restrict__ src, int64_t rows, int64_t cols, int64_t lds_,
+                                     uint16_t* __restrict__ dst, int64_t ldd) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i >= rows || j >= cols) return;
+  dst[i + j * ldd] = f32_to_bf16_rne(src[i + j * lds_]);
+}
+
+// E4M3FN code of v (round to nearest even, saturating at 448).
+__device__ inline uint8_t f32_to_e4m3(float v) {
+  const uint8_t sign = (__float_as_uint(v) >> 31) ? 0x80 : 0x00;
+  const float a = fabsf(v);
+  uint32_t code;
+  if (!(a < 448.0f)) {
+    code = 0x7E;                                  // +-448 (NaN inputs saturate too)
+  } else if (a < 0.015625f) {                     // below 2^-6: multiples of 2^-9
+    code = (uint32_t)rintf(a * 512.0f);           // 8 here is the smallest normal
+  } else {
+    int e;
+    const float m = frexpf(a, &e);                // a = m 2^e, m in [0.5, 1)
+    float q = rintf(m * 16.0f);                   // 4 significant bits
+    if (q == 16.0f) { q = 8.0f; e += 1; }
+    code = (uint32_t)((e + 6) << 3) | (uint32_t)(q - 8.0f);
+    if (code > 0x7E) code = 0x7E;
+  }
+  return (uint8_t)(sign | code);
+}
+
+// One workgroup per tile: amax, scale = fp32(amax / 448), codes.
+__global__ __launch_bounds__(256) void quantize_fp8_kernel(const float* __restrict__ src, int64_t rows,
+                                                           int64_t cols, int64_t lds_, uint8_t* __restrict__ dst,
+                                                           int64_t ldd, float* __restrict__ scales, int tile) {
+  __shared__ float red[256];
+  const int64_t I = blockIdx.x, J = blockIdx.y;
+  const int64_t r0 = I * tile, c0 = J * tile;
+  const int64_t rn = min((int64_t)tile, rows - r0), cn = min((int64_t)tile, cols - c0);
+  float amax = 0.0f;
+  for (int64_t e = threadIdx.x; e < rn * cn; e += 256) {
+    const int64_t i = r0 + e % rn, j = c0 + e / rn;
+    amax = fmaxf(amax, fabsf(src[i + j * lds_]));
+  }
+  red[threadIdx.x] = amax;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  amax = red[0];
+  const float scale = amax > 0.0f ? amax / 448.0f : 1.0f;
+  if (threadIdx.x == 0) scales[I + J * gridDim.x] = scale;
+  for (int64_t e = threadIdx.x; e < rn * cn; e += 256) {
+    const int64_t i = r0 + e % rn, j = c0 + e / rn;
+    dst[i + j * ldd] = f32_to_e4m3(src[i + j * lds_] / scale);
+  }
+}
+
+// out = V_+ diag(theta_+) V_+^T, 64 x 64 output tile per workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void psd_dense_kernel(const T* __restrict__ V, int64_t ldv,
+                                                        const double* __restrict__ theta, int64_t n, int p,
+                                                        T* __restrict__ out, int64_t ldo) {
+  __shared__ double Vi[64][33], Vj[64][33];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < p; k0 += 32) {
+    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+      const int rr = e % 64, kk = e / 64;
+      const int k = k0 + kk;
+      const double th = (k < p) ? fmax(theta[k], 0.0) : 0.0;
+      Vi[rr][kk] = (k < p && i0 + rr < n) ? (double)V[i0 + rr + k * ldv] * th : 0.0;
+      Vj[rr][kk] = (k < p && j0 + rr < n) ? (double)V[j0 + rr + k * ldv] : 0.0;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < 32; ++kk)
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) acc[a][b] += Vi[tx + 16 * a][kk] * Vj[ty + 16 * b][kk];
+    __syncthreads();
+  }
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      const int64_t i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
+      if (i < n && j < n) out[i + j * ldo] = (T)acc[a][b];
+    }
+}
+
+template <typename T>
+void apply_t(const ApplyArgs& a, hipStream_t st) {
+  const int nj = (a.p + 3) / 4;
+  const dim3 grid((unsigned)((a.n + 63) / 64));
+  const size_t lds = (size_t)a.p * a.p * 8;
+  const T* A1 = static_cast<const T*>(a.A1);
+  const T* A2 = static_cast<const T*>(a.A2);
+  T* C1 = static_cast<T*>(a.C1);
+  T* C2 = static_cast<T*>(a.C2);
+#define PFX_APPLY(NJ)                                                                               \
+  do {                                                                                              \
+    static size_t cur = 0;                                                                          \
+    ensure_lds((const void*)apply_kernel<T, NJ>, lds, cur);                                         \
+    apply_kernel<T, NJ><<<grid, 256, lds, st>>>(a.n, a.p, A1, a.lda1, A2, a.lda2, a.S, a.lds_, C1,  \
+                                                a.ldc1, C2, a.ldc2, a.alpha, a.beta, a.deficient,   \
+                                                a.gate);                                            \
+  } while (0)
+  if (nj <= 4) PFX_APPLY(4);
+  else if (nj <= 8) PFX_APPLY(8);
+  else if (nj <= 16) PFX_APPLY(16);
+  else PFX_APPLY(32);
+#undef PFX_APPLY
+  PFX_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void launch_apply(const ApplyArgs& a, hipStream_t st) {
+  if (a.p <= 0 || a.p > 128) fail(PF_ERR_ARG, "apply: p out of range");
+  if (a.ta1 != a.tc1 || (a.A2 && (a.ta2 != a.ta1 || a.tc2 != a.tc1)))
+    fail(PF_ERR_UNSUPPORTED, "apply: mixed element types");
+  if (a.ta1 == Elem::F64) apply_t<double>(a, st);
+  else apply_t<float>(a, st);
+}
+
+void launch_copy_block(const void* src, int64_t lds_, Elem ts, void* dst, int64_t ldd, Elem td, int64_t n,
+                       int p, int64_t n_pad, int p_pad, hipStream_t st) {
+  if (ts != td) fail(PF_ERR_UNSUPPORTED, "copy_block: element types differ");
+  dim3 grid((unsigned)((n_pad + 255) / 256), (unsigned)p_pad);
+  if (ts == Elem::F64)
+    copy_block_kernel<double><<<grid, 256, 0, st>>>(static_cast<const double*>(src), lds_,
+                                                    static_cast<double*>(dst), ldd, n, p, n_pad, p_pad);
+  else
+    copy_block_kernel<float><<<grid, 256, 0, st>>>(static_cast<const float*>(src), lds_,
+                                                   static_cast<float*>(dst), ldd, n, p, n_pad, p_pad);
+  PFX_HIP(hipGetLastError());
+}
+
+void launch_axpby(const void* A, const void* B, void* dst, int64_t ld, Elem t, int64_t n, int p, double alpha,
+                  double beta, hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)p);
+  if (t == Elem::F64)
+    axpby_kernel<double><<<grid, 256, 0, st>>>(static_cast<const double*>(A), static_cast<const double*>(B),
+                                               static_cast<double*>(dst), ld, n, p, alpha, beta);
+  else
+    axpby_kernel<float><<<grid, 256, 0, st>>>(static_cast<const float*>(A), static_cast<const float*>(B),
+                                              static_cast<float*>(dst), ld, n, p, alpha, beta);
+  PFX_HIP(hipGetLastError());
+}
+
+void launch_info_init(pf_info* info, hipStream_t st) {
+  info_init_kernel<<<1, 64, 0, st>>>(info);
+  PFX_HIP(hipGetLastError());
+}
+
+void launch_info_copy(const pf_info* src, pf_info* dst, const double* th, double* thd, int p, hipStream_t st) {
+  info_copy_kernel<<<1, 128, 0, st>>>(src, dst, th, thd, p);
+  PFX_HIP(hipGetLastError());
+}
+
+void launch_normal_block(void* dst, int64_t ld, Elem t, int64_t n, int p, uint64_t seed, hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)p);
+  if (t == Elem::F64) normal_block_kernel<double><<<grid, 256, 0, st>>>(static_cast<double*>(dst), ld, n, p, seed);
+  else normal_block_kernel<float><<<grid, 256, 0, st>>>(static_cast<float*>(dst), ld, n, p, seed);
+  PFX_HIP(hipGetLastError());
+}
+
+void launch_quantize_bf16(const float* src, int64_t rows, int64_t cols, int64_t lds_, uint16_t* dst,
+                          int64_t ldd, hipStream_t st) {
+  dim3 grid((unsigned)((rows + 255) / 256), (unsigned)cols);
+  quantize_bf16_kernel<<<grid, 256, 0, st>>>(src, rows, cols, lds_, dst, ldd);
+  PFX_HIP(hipGetLastError());
+}
+
+void launch_quantize_fp8(const float* src, int64_t rows, int64_t cols, int64_t lds_, uint8_t* dst,
+                         int64_t ldd, float* scales, int tile, hipStream_t st) {
+  dim3 grid((unsigned)((rows + tile - 1) / tile), (unsigned)((cols + tile - 1) / tile));
+  quantize_fp8_kernel<<<grid, 256, 0, st>>>(src, rows, cols, lds_, dst, ldd, scales, tile);
+  PFX_HIP(hipGetLastError());
+}
+
+void launch_psd_dense(const void* V, int64_t ldv, Elem t, const double* theta, int64_t n, int p, void* out,
+                      int64_t ldo, hipStream_t st) {
+  dim3 grid((unsigned)((n + 63) / 64), (unsigned)((n + 63) / 64));
+  if (t == Elem::F64)
+    psd_dense_kernel<double><<<grid, 256, 0, st>>>(static_cast<const double*>(V), ldv, theta, n, p,
+                                                   static_cast<double*>(out), ldo);
+  else
+    psd_dense_kernel<float><<<grid, 256, 0, st>>>(static_cast<const float*>(V), ldv, theta, n, p,
+                                                  static_cast<float*>(out), ldo);
+  PFX_HIP(hipGetLastError());
+}
+
+}  // namespace pfx

@@ -1,0 +1,136 @@
+// Internal declarations of the pfx library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+#include <string>
+
+#include "../../include/pf.h"
+
+namespace pfx {
+
+// ---------------------------------------------------------------------------
+// Errors.  Host code throws pfx::Error; the C-ABI layer converts it to a
+// pf_status and a thread-local message.  Kernels never throw.
+struct Error {
+  pf_status status;
+  std::string msg;
+};
+[[noreturn]] void fail(pf_status s, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+#define PFX_HIP(call) ::pfx::check_hip((call), #call)
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Raise a kernel's dynamic-LDS limit to `bytes` when it needs more than the
+// 64 KiB default (tracked per kernel in `cur`; the kernel's static LDS plus
+// `bytes` must stay within the 160 KiB of a CU).
+inline void ensure_lds(const void* kernel, size_t bytes, size_t& cur) {
+  if (bytes > 65536 && bytes > cur) {
+    PFX_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    cur = bytes;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Contractions C = A^T B over the long dimension K (the hot kernels).
+//
+// A is K x M and B is K x N, both column-major, so both operands are read
+// along K, the contiguous direction: for the symmetric filter product
+// X Y = X^T Y the A operand is X itself (section 2.1), for Gram matrices
+// Y^T Y and Rayleigh-Ritz H = Q^T W it is the tall block.
+enum class Elem : int { F32 = 0, F64 = 1 };
+
+struct ContractArgs {
+  const void* A; int64_t lda; Elem ta;
+  const void* B; int64_t ldb; Elem tb;
+  int64_t K, M, N;          // N is a multiple of 16 (padded block width)
+  // epilogue: out = alpha * (A^T B) + beta * D1 + gamma * D2  (D1/D2 optional)
+  void* out; int64_t ldo; Elem to;
+  const void* D1; int64_t ld1;   // same type as out
+  const void* D2; int64_t ld2;
+  double alpha, beta, gamma;
+  // split-K workspace (S slabs of round_up(M,64) x N in the MFMA type)
+  void* part; size_t part_bytes;
+  int splitk;               // 0 = choose automatically
+  bool f64_mfma;            // contract in FP64 (products and sums) even for F32 operands
+  int prof_main = -1;       // profiling class of the product kernel (-1: none)
+  int prof_reduce = -1;     // profiling class of the split-K sum
+};
+// Enqueue; returns the split-K factor used.
+int contract(const ContractArgs& a, hipStream_t st);
+// Partial-workspace bytes contract() needs for these shapes and types.
+size_t contract_part_bytes(int64_t K, int64_t M, int64_t N, Elem ta, Elem tb, bool f64_mfma, int splitk);
+
+// ---------------------------------------------------------------------------
+// Small dense kernels on p x p matrices (one workgroup each).
+void launch_chol_rinv(const double* G, int ldg, int p, double* Rinv, int ldr,
+                      int* deficient, pf_info* info, int pass, hipStream_t st);
+void launch_jacobi(const double* H, int ldh, int p, double* theta, double* Z, int ldz,
+                   double* Zwork, pf_info* info, int which, int max_sweeps, hipStream_t st);
+size_t jacobi_lds_bytes(int p);
+
+// ---------------------------------------------------------------------------
+// Tall-skinny block operations (n x p blocks, p <= 128).
+// C1 = A1 * S;  if A2: C2 = alpha * (A2 * S) + beta * C1.
+// S is p x p FP64 column-major (ld lds_).  Elem of A1/A2/C1/C2 given.
+struct ApplyArgs {
+  int64_t n; int p;
+  const void* A1; int64_t lda1; Elem ta1;
+  const void* A2; int64_t lda2; Elem ta2;
+  const double* S; int lds_;
+  void* C1; int64_t ldc1; Elem tc1;
+  void* C2; int64_t ldc2; Elem tc2;
+  double alpha, beta;
+  const int* deficient;      // replace flagged columns of C1 (CholQR)
+  const pf_info* gate;       // if non-null: skip writes unless gate->status == 0
+};
+void launch_apply(const ApplyArgs& a, hipStream_t st);
+
+// Copy an n x p block (column-major, ld) into a padded buffer (ld_dst,
+// p_pad columns, zero fill of padding columns and rows up to n_pad).
+void launch_copy_block(const void* src, int64_t lds, Elem ts, void* dst, int64_t ldd, Elem td,
+                       int64_t n, int p, int64_t n_pad, int p_pad, hipStream_t st);
+// dst = alpha * A + beta * B (n x p blocks, same element type)
+void launch_axpby(const void* A, const void* B, void* dst, int64_t ld, Elem t, int64_t n, int p,
+                  double alpha, double beta, hipStream_t st);
+void launch_info_init(pf_info* info, hipStream_t st);
+void launch_info_copy(const pf_info* src, pf_info* dst, const double* theta_src, double* theta_dst,
+                      int p, hipStream_t st);
+void launch_normal_block(void* dst, int64_t ld, Elem t, int64_t n, int p, uint64_t seed,
+                         hipStream_t st);
+
+// quantisers
+void launch_quantize_bf16(const float* src, int64_t rows, int64_t cols, int64_t lds,
+                          uint16_t* dst, int64_t ldd, hipStream_t st);
+void launch_quantize_fp8(const float* src, int64_t rows, int64_t cols, int64_t lds,
+                         uint8_t* dst, int64_t ldd, float* scales, int tile, hipStream_t st);
+void launch_psd_dense(const void* V, int64_t ldv, Elem t, const double* theta, int64_t n, int p,
+                      void* out, int64_t ldo, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Kernel timing hooks (pf_profile_*): event pairs around launches of a class.
+constexpr int kProfClasses = 4;
+bool prof_enabled();
+void prof_begin(int cls, hipStream_t st);
+void prof_end(int cls, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// The extraction pipeline.
+struct Plan;
+Plan* plan_create(const pf_desc& d);
+void plan_destroy(Plan* p);
+size_t plan_bytes(const pf_desc& d);
+void plan_validate(const pf_desc& d, const pf_mat* Xf, const pf_mat* Xr);
+// Enqueue one extraction.  U_in (ld ldu_in) may alias U_out.
+void enqueue_extraction(Plan* plan, const pf_mat& Xf, const pf_mat& Xr, const void* U_in,
+                        int64_t ldu_in, void* U_out, int64_t ldu_out, double* theta_out,
+                        pf_info* info_out, hipStream_t st);
+// refresh the numeric fields (interval, flags, sweeps) of a cached plan
+void plan_set_desc(Plan* P, const pf_desc& d);
+// plan-owned buffers (for sessions)
+double* plan_theta(Plan* p);
+pf_info* plan_info(Plan* p);
+
+}  // namespace pfx

@@ -1,0 +1,345 @@
+// The extraction pipeline: workspace plan and the launch sequence of one
+// polynomial-filtered subspace extraction (section 2.1 then eq. RR).
+//
+//   Z = A U                                   first filter product
+//   pre-rotation: H0 = U^T Z, H0 = W0 L0 W0^T, Y_0 = U W0,
+//                 Y_1 = (Z W0 - c Y_0) / (e tau_1)
+//   Y_{k+1} = (tau_k / tau_{k+1}) ((2/e) A Y_k - (2c/e) Y_k)
+//             - (tau_{k-1} / tau_{k+1}) Y_{k-1}          k = 1 .. d-1
+//   CholeskyQR2: G = Y^T Y, R = chol(G), Q = Y R^{-1}, twice
+//   Rayleigh-Ritz: W = X_rr Q (FP64), H = Q^T W, H = Z Theta Z^T, V = Q Z
+//
+// tau_k = T_k(s_ref) rescales the recurrence (PF_FLAG_SCALED); with tau = 1
+// it is the plain three-term recurrence of eq. cheby-recursion-map.  The
+// pre-rotation replaces U by its Ritz basis for the current matrix, which
+// leaves span(rho(A) U) unchanged because the recurrence acts column by
+// column (section 2.1: rho(A) (U W) = (rho(A) U) W).
+#include "pf_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace pfx {
+
+struct Plan {
+  pf_desc d;
+  Elem work;
+  int64_t n, n_pad;
+  int p, p_pad;
+  size_t esz;
+  void* mem = nullptr;
+  size_t bytes = 0;
+  void* U;
+  void* Z;
+  void* Yb[3];
+  void* Q1;
+  void* Q;
+  double* W;
+  double* G;
+  double* Rinv;
+  double* Zeig;
+  double* Zwork;
+  double* theta;
+  double* theta_pre;
+  int* deficient;
+  pf_info* info;
+  void* part;
+  size_t part_bytes;
+};
+
+namespace {
+
+struct Layout {
+  size_t off_U, off_Z, off_Y[3], off_Q1, off_Q, off_W, off_G, off_Rinv, off_Zeig, off_Zwork, off_theta,
+      off_theta_pre, off_def, off_info, off_part, total, part_bytes;
+};
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+Layout layout_for(const pf_desc& d) {
+  Layout L;
+  const Elem work = d.work == PF_F64 ? Elem::F64 : Elem::F32;
+  const size_t esz = work == Elem::F64 ? 8 : 4;
+  const int64_t n_pad = round_up(d.n, 64);
+  const int p_pad = (int)round_up(d.p, 16);
+  const size_t blk = align256((size_t)n_pad * p_pad * esz);
+  const size_t blk64 = align256((size_t)n_pad * p_pad * 8);
+  const size_t sq = align256((size_t)p_pad * p_pad * 8);
+  size_t o = 0;
+  L.off_U = o; o += blk;
+  L.off_Z = o; o += blk;
+  for (int i = 0; i < 3; ++i) { L.off_Y[i] = o; o += blk; }
+  L.off_Q1 = o; o += blk;
+  L.off_Q = o; o += blk;
+  L.off_W = o; o += blk64;
+  L.off_G = o; o += sq;
+  L.off_Rinv = o; o += sq;
+  L.off_Zeig = o; o += sq;
+  L.off_Zwork = o; o += sq;
+  L.off_theta = o; o += align256((size_t)p_pad * 8);
+  L.off_theta_pre = o; o += align256((size_t)p_pad * 8);
+  L.off_def = o; o += align256((size_t)p_pad * 4);
+  L.off_info = o; o += align256(sizeof(pf_info));
+  // split-K slabs: the largest any contraction of the sequence asks for
+  const Elem xf = work;   // filter operand type (same as work in these forms)
+  size_t part = 0;
+  part = std::max(part, contract_part_bytes(d.n, d.n, p_pad, xf, work, work == Elem::F64, 0));
+  part = std::max(part, contract_part_bytes(d.n, d.n, p_pad, Elem::F32, work, true, 0));
+  part = std::max(part, contract_part_bytes(d.n, d.n, p_pad, Elem::F64, Elem::F64, true, 0));
+  part = std::max(part, contract_part_bytes(d.n, p_pad, p_pad, work, work, true, 0));
+  part = std::max(part, contract_part_bytes(d.n, p_pad, p_pad, work, Elem::F64, true, 0));
+  L.part_bytes = align256(part);
+  L.off_part = o; o += L.part_bytes;
+  L.total = o;
+  return L;
+}
+
+bool elem_ok_for_filter(const pf_desc& d, pf_dtype t) {
+  if (d.work == PF_F64) return t == PF_F64;
+  return t == PF_F32;
+}
+
+void check_mat(const pf_mat* M, const char* name, int64_t rows) {
+  if (!M) fail(PF_ERR_ARG, std::string(name) + " is NULL");
+  if (!M->data) fail(PF_ERR_ARG, std::string(name) + ".data is NULL");
+  if (M->ld < rows) fail(PF_ERR_ARG, std::string(name) + ".ld is smaller than the row count");
+  size_t esz = M->dtype == PF_F64 ? 8 : M->dtype == PF_F32 ? 4 : M->dtype == PF_BF16 ? 2 : 1;
+  if (((uintptr_t)M->data) % 16 != 0) fail(PF_ERR_ARG, std::string(name) + ".data must be 16-byte aligned");
+  if (((size_t)M->ld * esz) % 16 != 0)
+    fail(PF_ERR_ARG, std::string(name) + ".ld * element size must be a multiple of 16 bytes");
+}
+
+void host_coefficients(const pf_desc& d, std::vector<double>& tau) {
+  const double c = 0.5 * (d.a + d.b), e = 0.5 * (d.b - d.a);
+  tau.assign(d.degree + 2, 1.0);
+  if (d.flags & PF_FLAG_SCALED) {
+    const double s = (d.spec_ub - c) / e;
+    if (s > 1.0) {
+      tau[0] = 1.0;
+      tau[1] = s;
+      for (int k = 1; k <= d.degree; ++k) tau[k + 1] = 2.0 * s * tau[k] - tau[k - 1];
+    }
+  }
+}
+
+}  // namespace
+
+void plan_validate(const pf_desc& d, const pf_mat* Xf, const pf_mat* Xr) {
+  if (d.struct_size != sizeof(pf_desc)) fail(PF_ERR_ARG, "pf_desc.struct_size does not match this library");
+  if (d.op != PF_OP_SYM && d.op != PF_OP_GRAM) fail(PF_ERR_ARG, "pf_desc.op is not a pf_op value");
+  if (d.op == PF_OP_GRAM) fail(PF_ERR_UNSUPPORTED, "PF_OP_GRAM is not implemented in this build");
+  if (d.n < 1) fail(PF_ERR_ARG, "pf_desc.n must be >= 1");
+  if (d.p < 1 || d.p > 128 || d.p > d.n) fail(PF_ERR_ARG, "pf_desc.p must satisfy 1 <= p <= min(n, 128)");
+  if (d.degree < 1) fail(PF_ERR_ARG, "pf_desc.degree must be >= 1");
+  if (d.q < 1) fail(PF_ERR_ARG, "pf_desc.q must be >= 1");
+  if (!std::isfinite(d.a) || !std::isfinite(d.b) || !(d.a < d.b))
+    fail(PF_ERR_ARG, "damping interval must be finite with a < b");
+  if (d.work != PF_F32 && d.work != PF_F64) fail(PF_ERR_ARG, "pf_desc.work must be PF_F32 or PF_F64");
+  if ((d.flags & PF_FLAG_SCALED) && !(std::isfinite(d.spec_ub) && d.spec_ub > d.b))
+    fail(PF_ERR_ARG, "PF_FLAG_SCALED needs a finite spec_ub > b");
+  if (d.flags & ~(PF_FLAG_NO_PREROTATE | PF_FLAG_SCALED | PF_FLAG_COLD))
+    fail(PF_ERR_ARG, "unknown bits in pf_desc.flags");
+  if (d.max_sweeps < 0) fail(PF_ERR_ARG, "pf_desc.max_sweeps must be >= 0");
+  if (Xf || Xr) {
+    check_mat(Xf, "X_filter", d.n);
+    check_mat(Xr, "X_rr", d.n);
+    if (Xf->dtype == PF_BF16 || Xf->dtype == PF_F8E4M3)
+      fail(PF_ERR_UNSUPPORTED, "BF16 / FP8 filter operands are not implemented in this build");
+    if (!elem_ok_for_filter(d, Xf->dtype)) fail(PF_ERR_ARG, "X_filter dtype does not match pf_desc.work");
+    if (d.work == PF_F64 && Xr->dtype != PF_F64) fail(PF_ERR_ARG, "work F64 needs an F64 X_rr");
+    if (d.work == PF_F32 && Xr->dtype != PF_F32) fail(PF_ERR_ARG, "work F32 needs an F32 X_rr");
+  }
+}
+
+size_t plan_bytes(const pf_desc& d) { return layout_for(d).total; }
+
+Plan* plan_create(const pf_desc& d) {
+  plan_validate(d, nullptr, nullptr);
+  Layout L = layout_for(d);
+  Plan* P = new Plan();
+  P->d = d;
+  P->work = d.work == PF_F64 ? Elem::F64 : Elem::F32;
+  P->esz = P->work == Elem::F64 ? 8 : 4;
+  P->n = d.n;
+  P->n_pad = round_up(d.n, 64);
+  P->p = d.p;
+  P->p_pad = (int)round_up(d.p, 16);
+  P->bytes = L.total;
+  hipError_t e = hipMalloc(&P->mem, L.total);
+  if (e != hipSuccess) {
+    delete P;
+    (void)hipGetLastError();
+    fail(PF_ERR_NOMEM, "hipMalloc of the extraction workspace failed");
+  }
+  // zero once: padding rows/columns of every block stay zero forever
+  e = hipMemset(P->mem, 0, L.total);
+  if (e != hipSuccess) {
+    (void)hipFree(P->mem);
+    delete P;
+    fail(PF_ERR_DEVICE, "hipMemset of the workspace failed");
+  }
+  char* b = static_cast<char*>(P->mem);
+  P->U = b + L.off_U;
+  P->Z = b + L.off_Z;
+  for (int i = 0; i < 3; ++i) P->Yb[i] = b + L.off_Y[i];
+  P->Q1 = b + L.off_Q1;
+  P->Q = b + L.off_Q;
+  P->W = reinterpret_cast<double*>(b + L.off_W);
+  P->G = reinterpret_cast<double*>(b + L.off_G);
+  P->Rinv = reinterpret_cast<double*>(b + L.off_Rinv);
+  P->Zeig = reinterpret_cast<double*>(b + L.off_Zeig);
+  P->Zwork = reinterpret_cast<double*>(b + L.off_Zwork);
+  P->theta = reinterpret_cast<double*>(b + L.off_theta);
+  P->theta_pre = reinterpret_cast<double*>(b + L.off_theta_pre);
+  P->deficient = reinterpret_cast<int*>(b + L.off_def);
+  P->info = reinterpret_cast<pf_info*>(b + L.off_info);
+  P->part = b + L.off_part;
+  P->part_bytes = L.part_bytes;
+  return P;
+}
+
+void plan_destroy(Plan* P) {
+  if (!P) return;
+  if (P->mem) (void)hipFree(P->mem);
+  delete P;
+}
+
+void plan_set_desc(Plan* P, const pf_desc& d) { P->d = d; }
+
+double* plan_theta(Plan* p) { return p->theta; }
+pf_info* plan_info(Plan* p) { return p->info; }
+
+namespace {
+
+Elem elem_of(pf_dtype t) { return t == PF_F64 ? Elem::F64 : Elem::F32; }
+
+void contract_into(Plan* P, const void* A, int64_t lda, Elem ta, const void* B, int64_t ldb, Elem tb,
+                   int64_t K, int64_t M, void* out, int64_t ldo, Elem to, const void* D1,
+                   const void* D2, int64_t ldd, double alpha, double beta, double gamma, bool f64,
+                   hipStream_t st, int prof_main = -1, int prof_reduce = -1) {
+  ContractArgs c;
+  c.A = A; c.lda = lda; c.ta = ta;
+  c.B = B; c.ldb = ldb; c.tb = tb;
+  c.K = K; c.M = M; c.N = P->p_pad;
+  c.out = out; c.ldo = ldo; c.to = to;
+  c.D1 = D1; c.ld1 = ldd; c.D2 = D2; c.ld2 = ldd;
+  c.alpha = alpha; c.beta = beta; c.gamma = gamma;
+  c.part = P->part; c.part_bytes = P->part_bytes;
+  c.splitk = 0;
+  c.f64_mfma = f64;
+  c.prof_main = prof_main;
+  c.prof_reduce = prof_reduce;
+  contract(c, st);
+}
+
+void gram(Plan* P, const void* A, Elem ta, const void* B, Elem tb, double* out, hipStream_t st) {
+  contract_into(P, A, P->n_pad, ta, B, P->n_pad, tb, P->n, P->p_pad, out, P->p_pad, Elem::F64, nullptr,
+                nullptr, 0, 1.0, 0.0, 0.0, true, st);
+}
+
+void apply(Plan* P, const void* A1, const void* A2, const double* S, void* C1, int64_t ldc1, void* C2,
+           double alpha, double beta, const int* deficient, const pf_info* gate, hipStream_t st) {
+  ApplyArgs a;
+  a.n = P->n; a.p = P->p;
+  a.A1 = A1; a.lda1 = P->n_pad; a.ta1 = P->work;
+  a.A2 = A2; a.lda2 = P->n_pad; a.ta2 = P->work;
+  a.S = S; a.lds_ = P->p_pad;
+  a.C1 = C1; a.ldc1 = ldc1; a.tc1 = P->work;
+  a.C2 = C2; a.ldc2 = P->n_pad; a.tc2 = P->work;
+  a.alpha = alpha; a.beta = beta;
+  a.deficient = deficient;
+  a.gate = gate;
+  launch_apply(a, st);
+}
+
+}  // namespace
+
+void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void* U_in, int64_t ldu_in,
+                        void* U_out, int64_t ldu_out, double* theta_out, pf_info* info_out, hipStream_t st) {
+  const pf_desc& d = P->d;
+  const double c = 0.5 * (d.a + d.b), e = 0.5 * (d.b - d.a);
+  std::vector<double> tau;
+  host_coefficients(d, tau);
+  const Elem W = P->work;
+  const Elem tf = elem_of(Xf.dtype), tr = elem_of(Xr.dtype);
+  const bool f64 = W == Elem::F64;
+  const int max_sweeps = d.max_sweeps > 0 ? d.max_sweeps : 30;
+  const int64_t ld = P->n_pad;
+
+  const bool prof = prof_enabled();
+  if (prof) prof_begin(PF_PROF_EXTRACT, st);
+  launch_info_init(P->info, st);
+  launch_copy_block(U_in, ldu_in, W, P->U, ld, W, P->n, P->p, P->n_pad, P->p_pad, st);
+
+  void* cur = P->U;
+  for (int pass = 0; pass < d.q; ++pass) {
+    // first product Z = A Y_0
+    contract_into(P, Xf.data, Xf.ld, tf, cur, ld, W, P->n, P->n, P->Z, ld, W, nullptr, nullptr, ld, 1.0, 0.0,
+                  0.0, f64, st, PF_PROF_FILTER, PF_PROF_FILTER_REDUCE);
+    const double a1 = 1.0 / (e * tau[1]), b1 = -c / (e * tau[1]);
+    void* y_prev;
+    void* y_cur;
+    if (pass == 0 && !(d.flags & PF_FLAG_NO_PREROTATE)) {
+      gram(P, cur, W, P->Z, W, P->G, st);
+      launch_jacobi(P->G, P->p_pad, P->p, P->theta_pre, P->Zeig, P->p_pad, P->Zwork, P->info, 0, 8, st);
+      apply(P, cur, P->Z, P->Zeig, P->Yb[0], ld, P->Yb[1], a1, b1, nullptr, nullptr, st);
+      y_prev = P->Yb[0];
+      y_cur = P->Yb[1];
+    } else {
+      void* dst = (cur == P->Yb[1]) ? P->Yb[2] : P->Yb[1];
+      launch_axpby(P->Z, cur, dst, ld, W, P->n, P->p_pad, a1, b1, st);
+      y_prev = cur;
+      y_cur = dst;
+    }
+    const bool cold = (d.flags & PF_FLAG_COLD) && pass == 0;
+    if (y_prev == P->U && cold) {
+      // keep U intact for re-orthonormalisation: move Y_0 into the ring
+      launch_axpby(y_prev, y_prev, P->Yb[0], ld, W, P->n, P->p_pad, 1.0, 0.0, st);
+      y_prev = P->Yb[0];
+    }
+    for (int k = 1; k < d.degree; ++k) {
+      void* y_next = nullptr;
+      for (int i = 0; i < 3; ++i)
+        if (P->Yb[i] != y_cur && P->Yb[i] != y_prev) { y_next = P->Yb[i]; break; }
+      const double r = tau[k] / tau[k + 1];
+      const double al = 2.0 * r / e, be = -2.0 * c * r / e, ga = -tau[k - 1] / tau[k + 1];
+      contract_into(P, Xf.data, Xf.ld, tf, y_cur, ld, W, P->n, P->n, y_next, ld, W, y_cur, y_prev, ld, al, be,
+                    ga, f64, st, PF_PROF_FILTER, PF_PROF_FILTER_REDUCE);
+      y_prev = y_cur;
+      y_cur = y_next;
+      if (cold && (k + 1) % 2 == 0 && k + 1 < d.degree) {
+        // (Y_{k+1}, Y_k) <- (Y_{k+1}, Y_k) R^{-1}, R from CholeskyQR2 of Y_{k+1}
+        for (int pass2 = 0; pass2 < 2; ++pass2) {
+          void* src_c = pass2 == 0 ? y_cur : P->Q1;
+          void* src_p = pass2 == 0 ? y_prev : P->Q;
+          void* dst_c = pass2 == 0 ? P->Q1 : y_cur;
+          void* dst_p = pass2 == 0 ? P->Q : y_prev;
+          gram(P, src_c, W, src_c, W, P->G, st);
+          launch_chol_rinv(P->G, P->p_pad, P->p, P->Rinv, P->p_pad, P->deficient, P->info, 0, st);
+          apply(P, src_c, src_p, P->Rinv, dst_c, ld, dst_p, 1.0, 0.0, P->deficient, nullptr, st);
+        }
+      }
+    }
+    cur = y_cur;
+  }
+
+  // CholeskyQR2 (section 2.1: orthonormalise the filtered block)
+  gram(P, cur, W, cur, W, P->G, st);
+  launch_chol_rinv(P->G, P->p_pad, P->p, P->Rinv, P->p_pad, P->deficient, P->info, 1, st);
+  apply(P, cur, nullptr, P->Rinv, P->Q1, ld, nullptr, 0.0, 0.0, P->deficient, nullptr, st);
+  gram(P, P->Q1, W, P->Q1, W, P->G, st);
+  launch_chol_rinv(P->G, P->p_pad, P->p, P->Rinv, P->p_pad, P->deficient, P->info, 2, st);
+  apply(P, P->Q1, nullptr, P->Rinv, P->Q, ld, nullptr, 0.0, 0.0, P->deficient, nullptr, st);
+
+  // Rayleigh-Ritz in FP64 (eq. RR)
+  contract_into(P, Xr.data, Xr.ld, tr, P->Q, ld, W, P->n, P->n, P->W, ld, Elem::F64, nullptr, nullptr, ld, 1.0,
+                0.0, 0.0, true, st, PF_PROF_RR, -1);
+  gram(P, P->Q, W, P->W, Elem::F64, P->G, st);
+  launch_jacobi(P->G, P->p_pad, P->p, P->theta, P->Zeig, P->p_pad, P->Zwork, P->info, 1, max_sweeps, st);
+  apply(P, P->Q, nullptr, P->Zeig, U_out, ldu_out, nullptr, 0.0, 0.0, nullptr, P->info, st);
+  if (info_out || theta_out) launch_info_copy(P->info, info_out, P->theta, theta_out, P->p, st);
+  if (prof) prof_end(PF_PROF_EXTRACT, st);
+}
+
+}  // namespace pfx

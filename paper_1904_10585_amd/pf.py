@@ -1,0 +1,245 @@
+"""ctypes binding of include/pf.h (argument marshalling only).
+
+Every function here forwards to the C ABI of ``libpfx.so``; every step of
+an extraction runs in the library's HIP kernels.  Tensors are torch device
+tensors used only as device memory; matrices are column-major, i.e. a
+tensor ``T`` of shape (rows, cols) with ``T.stride(0) == 1`` and leading
+dimension ``T.stride(1)`` (``torch.empty(cols, ld).t()[:rows]`` makes one).
+Importing this module raises if the library has not been built.
+"""
+import ctypes
+import os
+
+# torch first: its HIP runtime must be the one libpfx.so binds to.  Loading
+# the library before torch would bring in a second libamdhip64 (the ROCm
+# install's, found through the library's RUNPATH) next to torch's own.
+import torch  # noqa: F401
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpfx.so")
+
+PF_OK, PF_ERR_ARG, PF_ERR_NOMEM, PF_ERR_DEVICE, PF_ERR_BREAKDOWN, PF_ERR_NOCONV, PF_ERR_NONFINITE, \
+    PF_ERR_BUSY, PF_ERR_UNSUPPORTED = range(9)
+PF_F64, PF_F32, PF_BF16, PF_F8E4M3 = range(4)
+PF_OP_SYM, PF_OP_GRAM = range(2)
+PF_FLAG_NO_PREROTATE = 0x1
+PF_FLAG_SCALED = 0x2
+PF_FLAG_COLD = 0x4
+PF_PROF_FILTER, PF_PROF_FILTER_REDUCE, PF_PROF_RR, PF_PROF_EXTRACT = range(4)
+
+
+class PfMat(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int), ("ld", ctypes.c_int64),
+                ("tile_scale", ctypes.c_void_p), ("tile", ctypes.c_int32)]
+
+
+class PfDesc(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("op", ctypes.c_int), ("n", ctypes.c_int64),
+                ("m", ctypes.c_int64), ("p", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("q", ctypes.c_int32), ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("spec_ub", ctypes.c_double), ("work", ctypes.c_int), ("flags", ctypes.c_uint32),
+                ("max_sweeps", ctypes.c_int32)]
+
+
+class PfInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_pos", ctypes.c_int32), ("sweeps_rr", ctypes.c_int32),
+                ("sweeps_pre", ctypes.c_int32), ("deficient", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+class PfResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_pos", ctypes.c_int32), ("theta", ctypes.c_void_p),
+                ("V", ctypes.c_void_p), ("ldv", ctypes.c_int64), ("info", ctypes.c_void_p)]
+
+
+class PfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status_string(status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1904_10585_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    sig = {
+        "pf_extract": (i32, [P(PfDesc), P(PfMat), P(PfMat), vp, i64, vp, vp, vp]),
+        "pf_session_open": (i32, [P(PfDesc), vp, i64, ctypes.c_uint64, P(vp)]),
+        "pf_session_step": (i32, [vp, P(PfMat), P(PfMat), P(PfResult), vp]),
+        "pf_session_wait": (i32, [vp, P(PfResult)]),
+        "pf_session_close": (i32, [vp]),
+        "pf_quantize": (i32, [vp, i64, vp, i32, ctypes.c_int, vp, i64, i64, i64, vp]),
+        "pf_psd_dense": (i32, [vp, i64, vp, i64, i32, ctypes.c_int, vp, i64, vp]),
+        "pf_workspace_size": (i32, [P(PfDesc), P(ctypes.c_size_t)]),
+        "pf_profile_set": (i32, [ctypes.c_int]),
+        "pf_profile_read": (i32, [ctypes.c_int, P(i64), P(dbl)]),
+        "pf_status_string": (ctypes.c_char_p, [i32]),
+        "pf_last_error": (ctypes.c_char_p, []),
+        "pf_abi_version": (ctypes.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _ = dbl
+    return lib
+
+
+LIB = _load()
+
+
+def status_string(s):
+    return LIB.pf_status_string(int(s)).decode()
+
+
+def last_error():
+    return LIB.pf_last_error().decode()
+
+
+def _check(s):
+    if s != PF_OK:
+        raise PfError(s, last_error())
+
+
+def desc(n, p, degree, a, b, *, q=1, work=PF_F32, op=PF_OP_SYM, m=0, flags=0, spec_ub=0.0, max_sweeps=0):
+    d = PfDesc()
+    d.struct_size = ctypes.sizeof(PfDesc)
+    d.op, d.n, d.m, d.p, d.degree, d.q = op, n, m, p, degree, q
+    d.a, d.b, d.spec_ub = float(a), float(b), float(spec_ub)
+    d.work, d.flags, d.max_sweeps = work, flags, max_sweeps
+    return d
+
+
+_TORCH_DTYPE = {}
+
+
+def dtype_of(t):
+    import torch
+    if not _TORCH_DTYPE:
+        _TORCH_DTYPE.update({torch.float64: PF_F64, torch.float32: PF_F32, torch.bfloat16: PF_BF16,
+                             torch.uint16: PF_BF16, torch.float8_e4m3fn: PF_F8E4M3, torch.uint8: PF_F8E4M3})
+    return _TORCH_DTYPE[t.dtype]
+
+
+def ld_of(t):
+    """Leading dimension of a column-major 2-D tensor view."""
+    if t.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    if t.stride(0) != 1 and t.shape[1] > 1:
+        raise ValueError("expected a column-major view (stride(0) == 1)")
+    return max(t.stride(1), t.shape[0]) if t.shape[1] > 1 else t.shape[0]
+
+
+def mat(t, tile_scale=None, tile=128):
+    m = PfMat()
+    m.data = t.data_ptr()
+    m.dtype = dtype_of(t)
+    m.ld = ld_of(t)
+    m.tile_scale = tile_scale.data_ptr() if tile_scale is not None else None
+    m.tile = tile
+    return m
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def pf_extract(d, X_filter, X_rr, U, theta, info=None, stream=None):
+    """Enqueue one extraction; U (column-major n x p) is overwritten by the Ritz vectors."""
+    xf, xr = mat(X_filter), mat(X_rr)
+    _check(LIB.pf_extract(ctypes.byref(d), ctypes.byref(xf), ctypes.byref(xr), ctypes.c_void_p(U.data_ptr()),
+                          ld_of(U), ctypes.c_void_p(theta.data_ptr()),
+                          ctypes.c_void_p(info.data_ptr()) if info is not None else None, _stream(stream)))
+
+
+def pf_session_open(d, U0=None, seed=0):
+    h = ctypes.c_void_p()
+    _check(LIB.pf_session_open(ctypes.byref(d), ctypes.c_void_p(U0.data_ptr()) if U0 is not None else None,
+                               ld_of(U0) if U0 is not None else 0, seed, ctypes.byref(h)))
+    return h
+
+
+def pf_session_step(h, X_filter, X_rr, stream=None):
+    r = PfResult()
+    xf, xr = mat(X_filter), mat(X_rr)
+    _check(LIB.pf_session_step(h, ctypes.byref(xf), ctypes.byref(xr), ctypes.byref(r), _stream(stream)))
+    return r
+
+
+def pf_session_wait(h):
+    r = PfResult()
+    s = LIB.pf_session_wait(h, ctypes.byref(r))
+    return s, r
+
+
+def pf_session_close(h):
+    _check(LIB.pf_session_close(h))
+
+
+def pf_quantize(dst, tile_scale, tile, dtype, src, stream=None):
+    rows, cols = src.shape
+    _check(LIB.pf_quantize(ctypes.c_void_p(dst.data_ptr()), ld_of(dst),
+                           ctypes.c_void_p(tile_scale.data_ptr()) if tile_scale is not None else None, tile, dtype,
+                           ctypes.c_void_p(src.data_ptr()), rows, cols, ld_of(src), _stream(stream)))
+
+
+def pf_psd_dense(V, theta, n, p, work, out, stream=None):
+    _check(LIB.pf_psd_dense(ctypes.c_void_p(V.data_ptr()), ld_of(V), ctypes.c_void_p(theta.data_ptr()), n, p, work,
+                            ctypes.c_void_p(out.data_ptr()), ld_of(out), _stream(stream)))
+
+
+def pf_workspace_size(d):
+    n = ctypes.c_size_t()
+    _check(LIB.pf_workspace_size(ctypes.byref(d), ctypes.byref(n)))
+    return n.value
+
+
+def pf_profile_set(enable):
+    _check(LIB.pf_profile_set(1 if enable else 0))
+
+
+def pf_profile_read(which):
+    """(launches, total milliseconds) of a kernel class since pf_profile_set(1)."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(LIB.pf_profile_read(which, ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+_HIP = None
+
+
+def device_to_numpy(ptr, shape, dtype):
+    """Copy device memory at a raw pointer (e.g. a pf_result field) to a new
+    host array of the given shape (C order)."""
+    import numpy as np
+    global _HIP
+    if _HIP is None:
+        _HIP = ctypes.CDLL("libamdhip64.so")
+        _HIP.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _HIP.hipMemcpy.restype = ctypes.c_int
+    out = np.empty(shape, dtype=dtype)
+    rc = _HIP.hipMemcpy(out.ctypes.data, ptr, out.nbytes, 2)   # hipMemcpyDeviceToHost
+    if rc != 0:
+        raise PfError(PF_ERR_DEVICE, f"hipMemcpy failed ({rc})")
+    return out
+
+
+def colmajor(rows, cols, dtype, device, ld=None):
+    """A zeroed column-major rows x cols tensor view with leading dimension ld."""
+    import torch
+    ld = ld or rows
+    return torch.zeros((cols, ld), dtype=dtype, device=device).t()[:rows]
+
+
+def to_colmajor(a, dtype, device):
+    """Copy a (rows x cols) array-like into a fresh column-major device tensor."""
+    import torch
+    t = torch.as_tensor(a)
+    out = colmajor(t.shape[0], t.shape[1], dtype, device)
+    out.copy_(t.to(dtype))
+    return out

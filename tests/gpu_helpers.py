@@ -1,0 +1,50 @@
+"""Shared helpers of the GPU parity tests: run one extraction through the
+C ABI on seeded inputs and compare with the oracle."""
+import numpy as np
+import torch
+
+import oracle
+
+
+def pf_module():
+    from paper_1904_10585_amd import pf
+    return pf
+
+
+def device_matrix(A, dtype, ld=None):
+    pf = pf_module()
+    rows, cols = A.shape
+    ld = -(-(ld or rows) // 4) * 4            # 16-byte aligned columns
+    t = pf.colmajor(rows, cols, dtype, "cuda", ld=ld)
+    t.copy_(torch.from_numpy(np.ascontiguousarray(A)).to(dtype))
+    return t
+
+
+def run_extract(X, U, degree, a, b, work="f64", q=1, flags=0, Xrr=None, ld_pad=0, max_sweeps=0):
+    """One pf_extract on host arrays; returns (theta, V, info dict)."""
+    pf = pf_module()
+    n, p = U.shape
+    tdt = torch.float64 if work == "f64" else torch.float32
+    wk = pf.PF_F64 if work == "f64" else pf.PF_F32
+    ldx = n + ld_pad
+    Xd = device_matrix(X, tdt, ld=ldx)
+    Xr = Xd if Xrr is None else device_matrix(Xrr, tdt, ld=ldx)
+    Ud = device_matrix(U, tdt, ld=n + ld_pad)
+    theta = torch.zeros(p, dtype=torch.float64, device="cuda")
+    info = torch.zeros(8, dtype=torch.int32, device="cuda")
+    d = pf.desc(n, p, degree, a, b, q=q, work=wk, flags=flags, max_sweeps=max_sweeps)
+    pf.pf_extract(d, Xd, Xr, Ud, theta, info)
+    torch.cuda.synchronize()
+    inf = info.cpu().numpy()
+    return (theta.cpu().numpy(), Ud.cpu().double().numpy(),
+            {"status": int(inf[0]), "n_pos": int(inf[1]), "sweeps_rr": int(inf[2]),
+             "sweeps_pre": int(inf[3]), "deficient": int(inf[4])})
+
+
+def compare(theta_g, V_g, ref, r):
+    """(Ritz relative error, largest sin-angle) on the leading r Ritz pairs."""
+    rel = oracle.ritz_rel_err(theta_g, ref["theta"], r)
+    Vg = V_g[:, :r]
+    Qg, _ = np.linalg.qr(Vg)
+    sin = oracle.sin_theta(Qg, ref["V"][:, :r])
+    return rel, sin

@@ -1,0 +1,156 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/pf.h declares, and rejects invalid arguments before touching the
+device.  Every call below fails validation, so none reaches a kernel."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pf.h")
+
+pf = pytest.importorskip("paper_1904_10585_amd.pf")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pf_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert "pf_extract" in names and "pf_session_step" in names
+    lib = ctypes.CDLL(pf.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_abi_version_and_strings():
+    assert pf.LIB.pf_abi_version() == 1
+    for s in range(9):
+        assert pf.status_string(s).startswith("PF_")
+    assert pf.status_string(99) == "unknown pf_status"
+
+
+def test_struct_layout_matches_c_compiler(tmp_path):
+    """ctypes mirrors of the pf.h structs have the C compiler's sizes and offsets."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"pf_desc": pf.PfDesc, "pf_mat": pf.PfMat, "pf_info": pf.PfInfo, "pf_result": pf.PfResult}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pf.h"', "int main(void){"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(l.rsplit(" ", 1) for l in out if l.strip())
+    for cname, cls in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(cls, fname).offset, (cname, fname)
+
+
+def good_desc(**kw):
+    args = dict(n=256, p=16, degree=4, a=-1.0, b=0.5)
+    args.update(kw)
+    return pf.desc(**args)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n", 0), ("p", 0), ("p", 129), ("p", 300), ("degree", 0), ("q", 0),
+    ("a", 1.0), ("b", -2.0), ("work", 7), ("flags", 0x100), ("max_sweeps", -1), ("op", 5),
+])
+def test_workspace_size_rejects(field, value):
+    d = good_desc()
+    setattr(d, field, value)
+    with pytest.raises(pf.PfError) as e:
+        pf.pf_workspace_size(d)
+    assert e.value.status == pf.PF_ERR_ARG
+
+
+def test_struct_size_versioning():
+    d = good_desc()
+    d.struct_size = 12
+    with pytest.raises(pf.PfError) as e:
+        pf.pf_workspace_size(d)
+    assert e.value.status == pf.PF_ERR_ARG
+    assert "struct_size" in pf.last_error()
+
+
+def test_scaled_needs_upper_bound():
+    d = good_desc(flags=pf.PF_FLAG_SCALED, spec_ub=0.2)
+    with pytest.raises(pf.PfError) as e:
+        pf.pf_workspace_size(d)
+    assert e.value.status == pf.PF_ERR_ARG
+
+
+def test_workspace_size_valid():
+    assert pf.pf_workspace_size(good_desc()) > 256 * 16 * 4 * 6
+    assert pf.pf_workspace_size(good_desc(work=pf.PF_F64)) > pf.pf_workspace_size(good_desc())
+
+
+def _extract_raw(d, xf, xr, U, ldu, theta):
+    return pf.LIB.pf_extract(ctypes.byref(d), ctypes.byref(xf) if xf else None, ctypes.byref(xr) if xr else None,
+                             U, ldu, theta, None, None)
+
+
+def fake_mat(ptr=0x10000, dtype=pf.PF_F32, ld=256):
+    m = pf.PfMat()
+    m.data, m.dtype, m.ld, m.tile_scale, m.tile = ptr, dtype, ld, None, 128
+    return m
+
+
+@pytest.mark.parametrize("case", ["null_x", "null_rr", "short_ld", "misaligned", "bad_ld_bytes", "dtype",
+                                  "rr_dtype", "null_u", "short_ldu", "null_theta", "f64_rr", "bf16"])
+def test_extract_rejects_before_launch(case):
+    d = good_desc()
+    xf, xr = fake_mat(), fake_mat()
+    U, ldu, theta = 0x20000, 256, 0x30000
+    want = pf.PF_ERR_ARG
+    if case == "null_x":
+        xf = None
+    elif case == "null_rr":
+        xr = None
+    elif case == "short_ld":
+        xf.ld = 100
+    elif case == "misaligned":
+        xf.data = 0x10004
+    elif case == "bad_ld_bytes":
+        xf.ld = 257
+    elif case == "dtype":
+        xf.dtype = pf.PF_F64
+    elif case == "rr_dtype":
+        xr.dtype = 9
+    elif case == "null_u":
+        U = None
+    elif case == "short_ldu":
+        ldu = 10
+    elif case == "null_theta":
+        theta = None
+    elif case == "f64_rr":
+        xr.dtype = pf.PF_F64
+    elif case == "bf16":
+        xf.dtype = pf.PF_BF16
+        want = pf.PF_ERR_UNSUPPORTED
+    assert _extract_raw(d, xf, xr, U, ldu, theta) == want
+    assert pf.last_error()
+
+
+def test_session_and_helpers_reject_nulls():
+    assert pf.LIB.pf_session_close(None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_session_step(None, None, None, None, None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_quantize(None, 1, None, 128, pf.PF_BF16, None, 1, 1, 1, None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_psd_dense(None, 1, None, 1, 1, pf.PF_F32, None, 1, None) == pf.PF_ERR_ARG
+    d = good_desc()
+    h = ctypes.c_void_p()
+    assert pf.LIB.pf_session_open(ctypes.byref(d), ctypes.c_void_p(0x1000), 3, 0, ctypes.byref(h)) == pf.PF_ERR_ARG

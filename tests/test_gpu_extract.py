@@ -1,0 +1,221 @@
+"""Parity of pf_extract (HIP path, through the C ABI) with the FP64 oracle.
+
+Tolerances: FP64 work, Ritz relative error and largest sin-angle <= 1e-10
+on the planted target set from the first step; FP32 work <= 1e-5 and
+<= 1e-4 on warm steps (k >= 3), both against the oracle fed the same
+start block U_in and the same (rounded) matrix.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1904_10585_amd import workloads as wl
+from gpu_helpers import run_extract, compare, device_matrix, pf_module
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pf_module()
+
+
+def tiny_chain():
+    w = wl.WORKLOADS["tiny_fp64"]
+    X, _, _ = wl.workload_matrices(w)
+    U = wl.start_block(w.n, w.p, w.config)
+    for k in range(w.steps):
+        if k:
+            X = X + wl.perturbation(w.n, w.config, k)
+        yield k, X, U
+        U = oracle.extract(X, X, U, w.degree, w.a, w.b)["V"]
+
+
+def test_tiny_fp64_every_step():
+    w = wl.WORKLOADS["tiny_fp64"]
+    bad = []
+    for k, X, U in tiny_chain():
+        ref = oracle.extract(X, X, U, w.degree, w.a, w.b)
+        th, V, info = run_extract(X, U, w.degree, w.a, w.b, work="f64", flags=(4 if k == 0 else 0))
+        assert info["status"] == 0, info
+        rel, sin = compare(th, V, ref, w.n_top)
+        print(f"tiny fp64 step {k}: rel {rel:.2e} sin {sin:.2e} sweeps {info['sweeps_rr']}/{info['sweeps_pre']}"
+              f" deficient {info['deficient']}")
+        if not (rel <= 1e-10 and sin <= 1e-10):
+            bad.append((k, rel, sin))
+        assert info["n_pos"] == ref["n_pos"]
+    assert not bad, bad
+
+
+def test_tiny_fp32_warm_steps():
+    w = wl.WORKLOADS["tiny_fp64"]
+    for k, X, U in tiny_chain():
+        X32 = X.astype(np.float32).astype(np.float64)
+        U32 = U.astype(np.float32).astype(np.float64)
+        ref = oracle.extract(X32, X32, U32, w.degree, w.a, w.b)
+        th, V, info = run_extract(X32, U32, w.degree, w.a, w.b, work="f32")
+        assert info["status"] == 0, info
+        rel, sin = compare(th, V, ref, w.n_top)
+        print(f"tiny fp32 step {k}: rel {rel:.2e} sin {sin:.2e}")
+        if k >= 3:
+            assert rel <= 1e-5 and sin <= 1e-4, (k, rel, sin)
+
+
+@pytest.mark.parametrize("n,p,d", [(100, 1, 3), (100, 5, 1), (300, 16, 2), (300, 20, 3), (777, 33, 4),
+                                   (1000, 48, 3), (129, 64, 2), (1030, 96, 2), (2100, 128, 2)])
+@pytest.mark.parametrize("work", ["f64", "f32"])
+def test_ragged_shapes(n, p, d, work):
+    r = max(1, p // 2)
+    X, lam, Q = wl.planted(n, r, (4.0, 10.0), (-1.0, 0.5), config=90, index=n * 1000 + p)
+    U = wl.start_block(n, p, config=90, index=n + p)
+    a, b = -1.0, 0.5
+    for _ in range(3):                       # warm the start block on the oracle
+        U = oracle.extract(X, X, U, 6, a, b)["V"]
+    if work == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+        U = U.astype(np.float32).astype(np.float64)
+    ref = oracle.extract(X, X, U, d, a, b)
+    th, V, info = run_extract(X, U, d, a, b, work=work, ld_pad=(4 if work == "f32" else 2))
+    assert info["status"] == 0, info
+    rel, sin = compare(th, V, ref, r)
+    tol_rel, tol_sin = (1e-10, 1e-10) if work == "f64" else (1e-5, 1e-4)
+    print(f"ragged n={n} p={p} d={d} {work}: rel {rel:.2e} sin {sin:.2e}")
+    assert rel <= tol_rel and sin <= tol_sin
+    # orthonormal Ritz vectors
+    assert oracle.orth_error(V) < (1e-12 if work == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("q", [2, 3])
+def test_filter_power(q):
+    n, p, r = 400, 12, 6
+    X, _, _ = wl.planted(n, r, (2.0, 5.0), (-1.0, 0.5), config=91, index=q)
+    U = oracle.extract(X, X, wl.start_block(n, p, config=91, index=q), 4, -1.0, 0.5)["V"]
+    ref = oracle.extract(X, X, U, 3, -1.0, 0.5, q=q)
+    th, V, info = run_extract(X, U, 3, -1.0, 0.5, work="f64", q=q)
+    rel, sin = compare(th, V, ref, r)
+    assert info["status"] == 0 and rel <= 1e-10 and sin <= 1e-10, (rel, sin)
+
+
+def test_scaled_recurrence_same_span():
+    # dividing step k by T_k(s_ref) changes no span (the recurrence is linear)
+    n, p, r = 500, 10, 5
+    X, lam, _ = wl.planted(n, r, (50.0, 200.0), (-1.0, 0.5), config=92)
+    U = oracle.extract(X, X, wl.start_block(n, p, config=92), 6, -1.0, 0.5)["V"]
+    pf = pf_module()
+    ref = oracle.extract(X, X, U, 12, -1.0, 0.5)
+    th, V, info = run_extract(X, U, 12, -1.0, 0.5, work="f64", flags=0)
+    # scaled run
+    Xd = device_matrix(X, torch.float64)
+    Ud = device_matrix(U, torch.float64)
+    theta = torch.zeros(p, dtype=torch.float64, device="cuda")
+    d = pf.desc(n, p, 12, -1.0, 0.5, work=pf.PF_F64, flags=pf.PF_FLAG_SCALED, spec_ub=float(lam.max()) * 1.01)
+    pf.pf_extract(d, Xd, Xd, Ud, theta)
+    torch.cuda.synchronize()
+    rel_s, sin_s = compare(theta.cpu().numpy(), Ud.cpu().numpy(), ref, r)
+    rel, sin = compare(th, V, ref, r)
+    assert rel <= 1e-10 and sin <= 1e-10
+    assert rel_s <= 1e-10 and sin_s <= 1e-10
+
+
+def test_bitwise_repeatable():
+    n, p = 1000, 24
+    X, _, _ = wl.planted(n, 10, (2.0, 9.0), (-1.0, 0.5), config=93)
+    U = wl.start_block(n, p, config=93)
+    outs = [run_extract(X, U, 5, -1.0, 0.5, work=w) for w in ("f32", "f32", "f64", "f64")]
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[2][0], outs[3][0]) and np.array_equal(outs[2][1], outs[3][1])
+
+
+def test_nonfinite_input_reported_and_u_untouched():
+    n, p = 256, 8
+    X, _, _ = wl.planted(n, 4, (2.0, 9.0), (-1.0, 0.5), config=94)
+    U = wl.start_block(n, p, config=94)
+    U[5, 3] = np.nan
+    pf = pf_module()
+    Xd = device_matrix(X, torch.float64)
+    Ud = device_matrix(U, torch.float64)
+    before = Ud.clone()
+    theta = torch.zeros(p, dtype=torch.float64, device="cuda")
+    info = torch.zeros(8, dtype=torch.int32, device="cuda")
+    pf.pf_extract(pf.desc(n, p, 3, -1.0, 0.5, work=pf.PF_F64), Xd, Xd, Ud, theta, info)
+    torch.cuda.synchronize()
+    assert int(info[0]) == pf.PF_ERR_NONFINITE
+    assert torch.equal(torch.nan_to_num(Ud, nan=7.0), torch.nan_to_num(before, nan=7.0))
+
+
+def test_duplicate_columns_recovered():
+    n, p, r = 300, 10, 4
+    X, _, Q = wl.planted(n, r, (3.0, 9.0), (-1.0, 0.5), config=95)
+    U = wl.start_block(n, p, config=95)
+    U[:, 7] = U[:, 2]
+    U[:, 9] = U[:, 2]
+    th, V, info = run_extract(X, U, 6, -1.0, 0.5, work="f64")
+    assert info["status"] == 0, info
+    assert oracle.orth_error(V) < 1e-12
+    # the top of the spectrum is still found
+    for _ in range(4):
+        th, V, info = run_extract(X, V, 6, -1.0, 0.5, work="f64")
+    assert oracle.ritz_rel_err(th, np.sort(np.linalg.eigvalsh(X))[::-1], r) < 1e-10
+
+
+def test_session_chain_matches_oracle_chain():
+    pf = pf_module()
+    w = wl.WORKLOADS["tiny_fp64"]
+    X, _, _ = wl.workload_matrices(w)
+    U0 = wl.start_block(w.n, w.p, w.config)
+    d = pf.desc(w.n, w.p, w.degree, w.a, w.b, work=pf.PF_F64)
+    h = pf.pf_session_open(d, device_matrix(U0, torch.float64), seed=0)
+    U = U0
+    try:
+        for k in range(w.steps):
+            if k:
+                X = X + wl.perturbation(w.n, w.config, k)
+            Xd = device_matrix(X, torch.float64)
+            pf.pf_session_step(h, Xd, Xd)
+            s, res = pf.pf_session_wait(h)
+            assert s == pf.PF_OK and res.status == 0
+            ref = oracle.extract(X, X, U, w.degree, w.a, w.b)
+            U = ref["V"]
+            th = pf.device_to_numpy(res.theta, (w.p,), np.float64)
+            V = pf.device_to_numpy(res.V, (w.p, res.ldv), np.float64).T[:w.n]
+            rel, sin = compare(th, V, ref, w.n_top)
+            assert rel <= 1e-9 and sin <= 1e-9, (k, rel, sin)
+    finally:
+        pf.pf_session_close(h)
+
+
+@pytest.mark.parametrize("shape", [(256, 256), (300, 200), (1000, 700)])
+def test_quantize_matches_oracle(shape):
+    pf = pf_module()
+    g = np.random.default_rng(shape[0])
+    A = (g.standard_normal(shape) * np.exp(g.uniform(-3, 3, shape))).astype(np.float32)
+    src = device_matrix(A, torch.float32)
+    dst16 = pf.colmajor(shape[0], shape[1], torch.int16, "cuda")
+    pf.pf_quantize(dst16, None, 0, pf.PF_BF16, src)
+    dst8 = pf.colmajor(shape[0], shape[1], torch.uint8, "cuda")
+    tm, tn = -(-shape[0] // 128), -(-shape[1] // 128)
+    scales = torch.zeros((tn, tm), dtype=torch.float32, device="cuda").t()
+    pf.pf_quantize(dst8, scales, 128, pf.PF_F8E4M3, src)
+    torch.cuda.synchronize()
+    bf = dst16.contiguous().view(torch.bfloat16).double().cpu().numpy()
+    np.testing.assert_array_equal(bf, oracle.bf16_round(A.astype(np.float64)))
+    codes_ref, scales_ref = oracle.fp8_tile_quantize(A)
+    np.testing.assert_array_equal(scales.cpu().numpy(), scales_ref)
+    codes = dst8.contiguous().view(torch.float8_e4m3fn).double().cpu().numpy()
+    np.testing.assert_array_equal(codes, codes_ref)
+
+
+def test_psd_dense_matches_oracle():
+    pf = pf_module()
+    n, p = 200, 12
+    X, _, _ = wl.planted(n, 5, (2.0, 9.0), (-3.0, 0.5), config=96)
+    th, V, info = run_extract(X, wl.start_block(n, p, config=96), 6, -3.0, 0.5, work="f64")
+    Vd = device_matrix(V, torch.float64)
+    thd = torch.from_numpy(th).cuda()
+    out = pf.colmajor(n, n, torch.float64, "cuda")
+    pf.pf_psd_dense(Vd, thd, n, p, pf.PF_F64, out)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(out.cpu().numpy(), oracle.psd_projection(V, th), atol=1e-12)
