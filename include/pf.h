@@ -82,6 +82,10 @@ typedef enum pf_op {
 #define PF_FLAG_SCALED 0x2u       /* divide step k of the recurrence by
                                      T_k(s_ref), s_ref = mapped spec_ub: the
                                      same span, no overflow for large |A| */
+#define PF_FLAG_NATIVE_F32 0x8u   /* F32 filter products on the FP32 MFMA
+                                     pipe instead of the default exact
+                                     three-way BF16 split (six BF16 MFMA
+                                     cross terms, FP32 accumulation) */
 #define PF_FLAG_COLD 0x4u         /* the start block is not a warm start:
                                      every second step the pair (Y_k, Y_{k-1})
                                      is multiplied by the same R^{-1} from a

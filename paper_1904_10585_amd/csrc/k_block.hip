@@ -26,54 +26,62 @@ __device__ inline uint64_t mix64(uint64_t z) {
 // uniform in (0, 1) from 53 random bits
 __device__ inline double u01(uint64_t h) { return ((double)(h >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
 
-template <typename T, int NJ>
-__global__ __launch_bounds__(256) void apply_kernel(int64_t n, int p, const T* __restrict__ A1, int64_t lda1,
-                                                    const T* __restrict__ A2, int64_t lda2,
-                                                    const double* __restrict__ S, int lds_, T* C1, int64_t ldc1,
-                                                    T* C2, int64_t ldc2, double alpha, double beta,
-                                                    const int* __restrict__ deficient,
-                                                    const pf_info* gate) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* Sl = reinterpret_cast<double*>(smem_raw);    // Sl[k * p + j] = S[k][j]
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// One wave per 16 rows: C1[16 x p] = A1[16 x p] S with FP64 MFMA 16x16x4
+// (lane l holds A1[row0 + l%16][k + l/16] and S[k + l/16][16 nb + l%16];
+// the accumulator element r of lane l is row 4r + l/16, column l%16).
+template <typename T, int NB, bool TWO>
+__global__ __launch_bounds__(64) void apply_kernel(int64_t n, int p, const T* __restrict__ A1, int64_t lda1,
+                                                   const T* __restrict__ A2, int64_t lda2,
+                                                   const double* __restrict__ S, int lds_, T* C1, int64_t ldc1,
+                                                   T* C2, int64_t ldc2, double alpha, double beta,
+                                                   const int* __restrict__ deficient,
+                                                   const pf_info* gate) {
   if (gate && gate->status != 0) return;
-  for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
-    const int k = idx / p, j = idx % p;
-    Sl[idx] = S[k + (int64_t)j * lds_];
-  }
-  __syncthreads();
-  const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
-  const int64_t row = (int64_t)blockIdx.x * 64 + r;
-  if (row >= n) return;
-  double acc1[NJ], acc2[NJ];
+  const int l = threadIdx.x, c = l & 15, g = l >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * 16;
+  const int64_t arow = row0 + c;
+  const bool rok = arow < n;
+  d4v acc1[NB], acc2[NB];
 #pragma unroll
-  for (int u = 0; u < NJ; ++u) { acc1[u] = 0.0; acc2[u] = 0.0; }
-  for (int k = 0; k < p; ++k) {
-    const double a1 = (double)A1[row + k * lda1];
-    const double a2 = A2 ? (double)A2[row + k * lda2] : 0.0;
-    const double* sk = Sl + k * p;
+  for (int nb = 0; nb < NB; ++nb) { acc1[nb] = d4v{0, 0, 0, 0}; acc2[nb] = d4v{0, 0, 0, 0}; }
+  // compile-time trip count (4 NB steps of 4 cover the padded width 16 NB),
+  // fully unrolled up to 64 columns so all loads are in flight together
+  constexpr int UNROLL = NB <= 4 ? 16 : 8;
+#pragma unroll UNROLL
+  for (int ks = 0; ks < 4 * NB; ++ks) {
+    const int k = 4 * ks + g;
+    const bool kok = k < p;
+    const double a1 = (rok && kok) ? (double)A1[arow + k * lda1] : 0.0;
+    double a2 = 0.0;
+    if constexpr (TWO) a2 = (rok && kok) ? (double)A2[arow + k * lda2] : 0.0;
 #pragma unroll
-    for (int u = 0; u < NJ; ++u) {
-      const int j = cg + 4 * u;
-      if (j < p) {
-        const double sv = sk[j];
-        acc1[u] += a1 * sv;
-        acc2[u] += a2 * sv;
-      }
+    for (int nb = 0; nb < NB; ++nb) {
+      const double b = kok ? S[k + (int64_t)(16 * nb + c) * lds_] : 0.0;
+      acc1[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc1[nb], 0, 0, 0);
+      if constexpr (TWO) acc2[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b, acc2[nb], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int u = 0; u < NJ; ++u) {
-    const int j = cg + 4 * u;
+  for (int nb = 0; nb < NB; ++nb) {
+    const int j = 16 * nb + c;
     if (j >= p) continue;
-    double v1 = acc1[u];
-    if (deficient && deficient[j]) {
-      // rank-deficient column: a fixed pseudo-random direction, which the
-      // next CholeskyQR pass orthogonalises against the others
-      v1 = (2.0 * u01(mix64(((uint64_t)row << 8) ^ (uint64_t)j ^ 0x5DEECE66Dull)) - 1.0) /
-           sqrt((double)n);
+    const bool defj = deficient && deficient[j];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row0 + 4 * r + g;
+      if (row >= n) continue;
+      double v1 = acc1[nb][r];
+      if (defj) {
+        // rank-deficient column: a fixed pseudo-random direction, which the
+        // next CholeskyQR pass orthogonalises against the others
+        v1 = (2.0 * u01(mix64(((uint64_t)row << 8) ^ (uint64_t)j ^ 0x5DEECE66Dull)) - 1.0) /
+             sqrt((double)n);
+      }
+      C1[row + j * ldc1] = (T)v1;
+      if constexpr (TWO) C2[row + j * ldc2] = (T)(alpha * acc2[nb][r] + beta * (double)(T)v1);
     }
-    C1[row + j * ldc1] = (T)v1;
-    if (C2) C2[row + j * ldc2] = (T)(alpha * acc2[u] + beta * (double)(T)v1);
   }
 }
 
@@ -213,27 +221,27 @@ __global__ __launch_bounds__(256) void psd_dense_kernel(const T* __restrict__ V,
     }
 }
 
-template <typename T>
+template <typename T, bool TWO>
 void apply_t(const ApplyArgs& a, hipStream_t st) {
-  const int nj = (a.p + 3) / 4;
-  const dim3 grid((unsigned)((a.n + 63) / 64));
-  const size_t lds = (size_t)a.p * a.p * 8;
+  const int nb = (a.p + 15) / 16;
+  const dim3 grid((unsigned)((a.n + 15) / 16));
   const T* A1 = static_cast<const T*>(a.A1);
   const T* A2 = static_cast<const T*>(a.A2);
   T* C1 = static_cast<T*>(a.C1);
   T* C2 = static_cast<T*>(a.C2);
-#define PFX_APPLY(NJ)                                                                               \
-  do {                                                                                              \
-    static size_t cur = 0;                                                                          \
-    ensure_lds((const void*)apply_kernel<T, NJ>, lds, cur);                                         \
-    apply_kernel<T, NJ><<<grid, 256, lds, st>>>(a.n, a.p, A1, a.lda1, A2, a.lda2, a.S, a.lds_, C1,  \
-                                                a.ldc1, C2, a.ldc2, a.alpha, a.beta, a.deficient,   \
-                                                a.gate);                                            \
-  } while (0)
-  if (nj <= 4) PFX_APPLY(4);
-  else if (nj <= 8) PFX_APPLY(8);
-  else if (nj <= 16) PFX_APPLY(16);
-  else PFX_APPLY(32);
+#define PFX_APPLY(NB)                                                                                    \
+  apply_kernel<T, NB, TWO><<<grid, 64, 0, st>>>(a.n, a.p, A1, a.lda1, A2, a.lda2, a.S, a.lds_, C1, a.ldc1, \
+                                                C2, a.ldc2, a.alpha, a.beta, a.deficient, a.gate)
+  switch (nb) {
+    case 1: PFX_APPLY(1); break;
+    case 2: PFX_APPLY(2); break;
+    case 3: PFX_APPLY(3); break;
+    case 4: PFX_APPLY(4); break;
+    case 5: PFX_APPLY(5); break;
+    case 6: PFX_APPLY(6); break;
+    case 7: PFX_APPLY(7); break;
+    default: PFX_APPLY(8); break;
+  }
 #undef PFX_APPLY
   PFX_HIP(hipGetLastError());
 }
@@ -244,8 +252,9 @@ void launch_apply(const ApplyArgs& a, hipStream_t st) {
   if (a.p <= 0 || a.p > 128) fail(PF_ERR_ARG, "apply: p out of range");
   if (a.ta1 != a.tc1 || (a.A2 && (a.ta2 != a.ta1 || a.tc2 != a.tc1)))
     fail(PF_ERR_UNSUPPORTED, "apply: mixed element types");
-  if (a.ta1 == Elem::F64) apply_t<double>(a, st);
-  else apply_t<float>(a, st);
+  const bool two = a.A2 != nullptr;
+  if (a.ta1 == Elem::F64) { if (two) apply_t<double, true>(a, st); else apply_t<double, false>(a, st); }
+  else { if (two) apply_t<float, true>(a, st); else apply_t<float, false>(a, st); }
 }
 
 void launch_copy_block(const void* src, int64_t lds_, Elem ts, void* dst, int64_t ldd, Elem td, int64_t n,

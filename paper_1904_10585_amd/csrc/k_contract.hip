@@ -276,10 +276,19 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(DevArgs a) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t j = blockIdx.y;
   if (i >= a.M) return;
-  const TC* part = static_cast<const TC*>(a.part);
+  const TC* part = static_cast<const TC*>(a.part) + i + j * a.ldp;
   const int64_t slab = a.ldp * a.N;
-  TC sum = part[i + j * a.ldp];
-  for (int s = 1; s < a.splitk; ++s) sum += part[s * slab + i + j * a.ldp];
+  // loads of 8 slabs in flight at a time, summed in slab order
+  TC sum = TC(0);
+  int s = 0;
+  for (; s + 8 <= a.splitk; s += 8) {
+    TC v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(s + u) * slab];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sum = (s + u == 0) ? v[u] : sum + v[u];
+  }
+  for (; s < a.splitk; ++s) sum = (s == 0) ? part[0] : sum + part[(int64_t)s * slab];
   TC v = (TC)a.alpha * sum;
   if (a.D1) v += (TC)a.beta * (TC) static_cast<const TO*>(a.D1)[i + j * a.ld1];
   if (a.D2) v += (TC)a.gamma * (TC) static_cast<const TO*>(a.D2)[i + j * a.ld2];

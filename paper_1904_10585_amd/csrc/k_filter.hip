@@ -1,0 +1,462 @@
+// The FP32 filter product on BF16 matrix cores: Y_{k+1} = alpha X Y_k +
+// beta Y_k + gamma Y_{k-1} (the Chebyshev recurrence step of section 2.1,
+// eq. cheby-recursion-map) with products accurate to FP32.
+//
+// Every FP32 value splits exactly into three BF16 values by truncation:
+// x = x1 + x2 + x3 with x1 the top 8 significand bits, x2 the next 8 and
+// x3 the last 8.  X is streamed from HBM as FP32 and split in registers;
+// Y_k is read as three BF16 planes written by the previous step.  The
+// product keeps the six cross terms of order >= 2^-16,
+//   x1 y1 + x1 y2 + x2 y1 + x1 y3 + x2 y2 + x3 y1,
+// each exact in the FP32 accumulator of v_mfma_f32_16x16x32_bf16; the
+// dropped terms are below 2^-24 relative, the rounding level of FP32.
+// This moves the product from the FP32 MFMA rate (which bounds a native
+// FP32 product at p = 64 below the HBM roof) to the BF16 rate, so the
+// kernel is bound by the HBM stream of X.
+//
+// Layout: X is K x M column-major and used as X^T (X symmetric).  A
+// workgroup of four waves owns 4 * 16 * MB output rows (16 * MB per wave)
+// and all 16 * NB columns over a K range; grid.z splits K (summed in slab
+// order by a second kernel).  The three Y planes of each K step of 32 are
+// staged once per workgroup in double-buffered LDS and shared by the four
+// waves.  Lane l holds A[m = l%16][k = 8(l/16) .. +7] (eight consecutive K
+// values of one X column: 32 bytes, one cache line per column and step) and
+// B[k = 8(l/16) .. +7][n = l%16] (16 bytes of one Y plane column).
+#include "pf_internal.h"
+
+#include <algorithm>
+#include <type_traits>
+
+namespace pfx {
+namespace {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int KSTEP = 32;
+
+struct FArgs {
+  const float* X; int64_t ldx;
+  const uint16_t* Yp; int64_t ldy; int64_t yplane;   // 3 planes of K x N
+  int64_t K, M, N;
+  int64_t kchunk;
+  float* out; int64_t ldo;
+  const float* D1; const float* D2; int64_t ldd;
+  float alpha, beta, gamma;
+  uint16_t* outp; int64_t ldop; int64_t oplane;       // planes of out (may be null)
+  float* part; int64_t ldp;
+  int splitk;
+};
+
+__device__ inline bf8v as_bf8(u4v v) { return __builtin_bit_cast(bf8v, v); }
+
+// Exact three-way BF16 split of 8 FP32 values, packed two per dword.
+__device__ inline void split8(const float (&x)[8], u4v& p1, u4v& p2, u4v& p3) {
+  unsigned h[8], m[8], l[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const unsigned u = __float_as_uint(x[i]);
+    const unsigned uh = u & 0xFFFF0000u;
+    const float r = x[i] - __uint_as_float(uh);
+    const unsigned ur = __float_as_uint(r);
+    const unsigned um = ur & 0xFFFF0000u;
+    const float rl = r - __uint_as_float(um);
+    h[i] = uh;
+    m[i] = um;
+    l[i] = __float_as_uint(rl);
+  }
+  // v_perm_b32 with selector 0x07060302: low half = upper 16 bits of the
+  // first value, high half = upper 16 bits of the second
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    p1[i] = __builtin_amdgcn_perm(h[2 * i + 1], h[2 * i], 0x07060302u);
+    p2[i] = __builtin_amdgcn_perm(m[2 * i + 1], m[2 * i], 0x07060302u);
+    p3[i] = __builtin_amdgcn_perm(l[2 * i + 1], l[2 * i], 0x07060302u);
+  }
+}
+
+__device__ inline void split1(float x, uint16_t& a, uint16_t& b, uint16_t& c) {
+  const unsigned u = __float_as_uint(x);
+  const unsigned uh = u & 0xFFFF0000u;
+  const float r = x - __uint_as_float(uh);
+  const unsigned ur = __float_as_uint(r);
+  const unsigned um = ur & 0xFFFF0000u;
+  const float rl = r - __uint_as_float(um);
+  a = (uint16_t)(uh >> 16);
+  b = (uint16_t)(um >> 16);
+  c = (uint16_t)(__float_as_uint(rl) >> 16);
+}
+
+__device__ inline void store_out(const FArgs& a, int64_t row, int64_t col, float v) {
+  float r = a.alpha * v;
+  if (a.D1) r += a.beta * a.D1[row + col * a.ldd];
+  if (a.D2) r += a.gamma * a.D2[row + col * a.ldd];
+  a.out[row + col * a.ldo] = r;
+  if (a.outp) {
+    uint16_t p1, p2, p3;
+    split1(r, p1, p2, p3);
+    uint16_t* o = a.outp + row + col * a.ldop;
+    o[0] = p1;
+    o[a.oplane] = p2;
+    o[2 * a.oplane] = p3;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Main kernel: a four-stage LDS ring filled by direct global->LDS loads
+// (global_load_lds_dwordx4: no VGPRs held by loads in flight, so three
+// stages of X and Y stream while one is consumed).  One __shared__ array per
+// stage keeps the compiler's LDS-DMA dependency tracking exact.
+//
+// X stage: ROWS columns of X x 32 K values, 16-byte chunk (col, kc) at
+// position col * 8 + (kc ^ (col & 7)) (the swizzle spreads the 16 lanes of a
+// ds_read_b128 over all banks).  Y stage: 3 planes x N columns x 32 K values,
+// chunk (q, j, kc) at ((q * N + j) * 4) + (kc ^ ((j >> 1) & 3)).
+template <int MB, int NB>
+struct FCfg {
+  static constexpr int ROWS = kWaves * 16 * MB;   // output rows (X columns) per workgroup
+  static constexpr int N16 = 16 * NB;
+  static constexpr int XCH = ROWS * 8;            // 16-byte X chunks per stage
+  static constexpr int YCH = 3 * N16 * 4;         // 16-byte Y chunks per stage
+  static constexpr int XOPS = XCH / kThreads;     // X wave-loads per wave per stage
+  static constexpr int YINSTR = YCH / 64;         // Y wave-loads per workgroup per stage
+  static constexpr int YMAX = (YINSTR + kWaves - 1) / kWaves;
+  // every wave issues YMAX Y loads; those past YINSTR repeat a valid chunk
+  // into padding after the Y chunks, so the issue code has no branch
+  static constexpr int STAGE = XCH + kWaves * YMAX * 64;
+  static constexpr int OPS = XOPS + YMAX;         // loads each wave issues per stage
+};
+
+// The four stage buffers are file-scope LDS objects (sized for the largest
+// tile): the compiler gives each its own alias scope, so the LDS reads of one
+// stage wait only for the direct loads into that stage.
+constexpr int kStageChunks = 2048;                 // 32 KiB per stage
+__shared__ u4v g_st0[kStageChunks], g_st1[kStageChunks], g_st2[kStageChunks], g_st3[kStageChunks];
+
+// One 16-byte direct global->LDS load per lane (global_load_lds_dwordx4).
+// Kept out of the kernel templates: the builtin exists only for the device.
+__device__ inline void dma16(const void* src, u4v* lds) {
+  __builtin_amdgcn_global_load_lds(src, lds, 16, 0, 0);
+}
+
+// gfx9 s_waitcnt: vmcnt [3:0] + [15:14], expcnt [6:4] = 7 (no wait),
+// lgkmcnt [11:8] (15 = no wait)
+template <int N, int LGKM = 15>
+__device__ inline void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (LGKM << 8));
+}
+
+__device__ inline void wg_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <int MB, int NB>
+__global__ __launch_bounds__(kThreads, 1) void filter_bf16x6_kernel(FArgs a) {
+  using C = FCfg<MB, NB>;
+  static_assert(C::STAGE <= kStageChunks, "stage does not fit its LDS buffer");
+  u4v* const st0 = g_st0;
+  u4v* const st1 = g_st1;
+  u4v* const st2 = g_st2;
+  u4v* const st3 = g_st3;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  // XCD-aware tile order: workgroups are dispatched round-robin over the 8
+  // XCDs, so the K range (slab) is the fast index and each XCD works on few
+  // K ranges, keeping their Y rows in its L2.
+  const int64_t L = blockIdx.x;
+  const int zslab = (int)(L % a.splitk);
+  const int64_t mtile = L / a.splitk;
+  const int64_t mt0 = mtile * C::ROWS;
+  const int64_t kbeg = (int64_t)zslab * a.kchunk;
+  const int64_t kend = min(a.K, kbeg + a.kchunk);
+
+  // per-lane global bases of the stage loads (K offset added per stage)
+  const float* xsrc[C::XOPS];
+#pragma unroll
+  for (int u = 0; u < C::XOPS; ++u) {
+    const int pos = (wave * C::XOPS + u) * 64 + lane;
+    const int col = pos >> 3, kc = (pos & 7) ^ (col & 7);
+    const int64_t gcol = min(mt0 + col, a.M - 1);          // columns past M: any valid column
+    xsrc[u] = a.X + gcol * a.ldx + 4 * kc;
+  }
+  const uint16_t* ysrc[C::YMAX];
+#pragma unroll
+  for (int u = 0; u < C::YMAX; ++u) {
+    const int instr = wave + kWaves * u;
+    const int pos = (instr < C::YINSTR ? instr : 0) * 64 + lane;
+    const int qj = pos >> 2, q = qj / C::N16, j = qj % C::N16;
+    const int kc = (pos & 3) ^ ((j >> 1) & 3);
+    ysrc[u] = a.Yp + q * a.yplane + (int64_t)j * a.ldy + 8 * kc;
+  }
+  auto issue = [&](u4v* xs, int64_t k0) {
+    u4v* ys = xs + C::XCH;
+#pragma unroll
+    for (int u = 0; u < C::XOPS; ++u)
+      dma16(xsrc[u] + k0, xs + (wave * C::XOPS + u) * 64);
+#pragma unroll
+    for (int u = 0; u < C::YMAX; ++u)
+      dma16(ysrc[u] + k0, ys + (wave + kWaves * u) * 64);
+  };
+
+  f4v acc[MB][NB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4v{0, 0, 0, 0};
+
+  auto compute = [&](const u4v* xs, const u4v* ys) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int col = wave * (16 * MB) + 16 * mb + c;
+      const u4v lo = xs[col * 8 + ((2 * g) ^ (col & 7))];
+      const u4v hi = xs[col * 8 + ((2 * g + 1) ^ (col & 7))];
+      float xv[8];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) { xv[i] = __uint_as_float(lo[i]); xv[4 + i] = __uint_as_float(hi[i]); }
+      u4v x1, x2, x3;
+      split8(xv, x1, x2, x3);
+      const bf8v a1 = as_bf8(x1), a2 = as_bf8(x2), a3 = as_bf8(x3);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int j = 16 * nb + c;
+        const int sw = g ^ ((j >> 1) & 3);
+        const bf8v b1 = as_bf8(ys[(0 * C::N16 + j) * 4 + sw]);
+        const bf8v b2 = as_bf8(ys[(1 * C::N16 + j) * 4 + sw]);
+        const bf8v b3 = as_bf8(ys[(2 * C::N16 + j) * 4 + sw]);
+        f4v cc = acc[mb][nb];
+        cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, b1, cc, 0, 0, 0);   // smallest terms first
+        cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b2, cc, 0, 0, 0);
+        cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b3, cc, 0, 0, 0);
+        cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b1, cc, 0, 0, 0);
+        cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b2, cc, 0, 0, 0);
+        cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, cc, 0, 0, 0);
+        acc[mb][nb] = cc;
+      }
+    }
+  };
+
+  u4v* const slot[4] = {st0, st1, st2, st3};
+  const int64_t nfull = (kend - kbeg) / KSTEP;
+  // Every stage issues the loads of the stage three ahead; past the last
+  // full stage they repeat the last one (an L2 hit, never consumed), so the
+  // issue code and the wait counts are the same on every stage.
+  const int64_t klast = kbeg + (nfull - 1) * KSTEP;
+  // sl is a literal at every call, so each stage's LDS object is known
+  auto body = [&](int sl, int64_t st) {
+    // this wave's loads of stage st are done once only the loads of the two
+    // stages issued after it are outstanding, and its LDS reads of stage
+    // st - 1 once lgkmcnt is 0; the barrier then makes every wave's loads
+    // of stage st visible and frees the slot of stage st - 1
+    wait_vmcnt<2 * C::OPS, 0>();
+    wg_barrier();
+    issue(slot[(sl + 3) & 3], min(kbeg + (st + 3) * KSTEP, klast));
+    compute(slot[sl], slot[sl] + C::XCH);
+  };
+  if (nfull > 0) {
+    issue(st0, kbeg);
+    issue(st1, min(kbeg + KSTEP, klast));
+    issue(st2, min(kbeg + 2 * KSTEP, klast));
+    int64_t st = 0;
+    for (; st + 4 <= nfull; st += 4) {
+      body(0, st);
+      body(1, st + 1);
+      body(2, st + 2);
+      body(3, st + 3);
+    }
+    if (st < nfull) body(0, st);
+    if (st + 1 < nfull) body(1, st + 1);
+    if (st + 2 < nfull) body(2, st + 2);
+    wait_vmcnt<0>();                       // the repeated loads land before LDS is reused
+  }
+  const int64_t ktail = kbeg + nfull * KSTEP;
+  if (ktail < kend) {
+    // ragged last step: masked register loads into stage 0
+    wait_vmcnt<0>();
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < C::XOPS; ++u) {
+      const int pos = (wave * C::XOPS + u) * 64 + lane;
+      const int col = pos >> 3, kc = (pos & 7) ^ (col & 7);
+      unsigned w[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = ktail + 4 * kc + i;
+        w[i] = r < kend ? __float_as_uint(xsrc[u][ktail + i]) : 0u;
+      }
+      st0[pos] = u4v{w[0], w[1], w[2], w[3]};
+    }
+#pragma unroll
+    for (int u = 0; u < C::YMAX; ++u) {
+      const int instr = wave + kWaves * u;
+      if (instr >= C::YINSTR) continue;
+      const int pos = instr * 64 + lane;
+      const int j = (pos >> 2) % C::N16;
+      const int kc = (pos & 3) ^ ((j >> 1) & 3);
+      unsigned w[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = ktail + 8 * kc + 2 * i;
+        const unsigned lo = r < kend ? ysrc[u][ktail + 2 * i] : 0u;
+        const unsigned hi = r + 1 < kend ? ysrc[u][ktail + 2 * i + 1] : 0u;
+        w[i] = lo | (hi << 16);
+      }
+      st0[C::XCH + pos] = u4v{w[0], w[1], w[2], w[3]};
+    }
+    __syncthreads();
+    compute(st0, st0 + C::XCH);
+  }
+  const int64_t m0 = mt0 + (int64_t)wave * (16 * MB);
+
+  // accumulator element r of lane (c, g): row 4g + r, column c of its block
+  if (a.splitk == 1) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = m0 + 16 * mb + 4 * g + r;
+          if (row < a.M) store_out(a, row, 16 * nb + c, acc[mb][nb][r]);
+        }
+  } else {
+    float* part = a.part + (int64_t)zslab * a.ldp * a.N;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int64_t row = m0 + 16 * mb + 4 * g;
+        *reinterpret_cast<f4v*>(part + row + (16 * nb + c) * a.ldp) = acc[mb][nb];
+      }
+  }
+}
+
+// Sum of the split-K slabs in slab order, then the epilogue.
+__global__ __launch_bounds__(256) void filter_reduce_kernel(FArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i >= a.M) return;
+  const float* part = a.part + i + j * a.ldp;
+  const int64_t slab = a.ldp * a.N;
+  float sum = 0.0f;
+  int s = 0;
+  for (; s + 8 <= a.splitk; s += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(s + u) * slab];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sum = (s + u == 0) ? v[u] : sum + v[u];
+  }
+  for (; s < a.splitk; ++s) sum = (s == 0) ? part[0] : sum + part[(int64_t)s * slab];
+  store_out(a, i, j, sum);
+}
+
+// Three BF16 planes of an n x p FP32 block (rows up to n_pad, columns up to
+// p_pad; padding is zero).
+__global__ void split_planes_kernel(const float* __restrict__ src, int64_t lds_, int64_t n, int p,
+                                    uint16_t* __restrict__ dst, int64_t ldd, int64_t plane, int64_t n_pad) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n_pad) return;
+  const float v = (i < n && j < p) ? src[i + j * lds_] : 0.0f;
+  uint16_t p1, p2, p3;
+  split1(v, p1, p2, p3);
+  uint16_t* o = dst + i + j * ldd;
+  o[0] = p1;
+  o[plane] = p2;
+  o[2 * plane] = p3;
+}
+
+struct FSplit {
+  int S;
+  int64_t kchunk, ldp, mtiles;
+};
+
+// Split-K so that the grid is about one resident workgroup per CU (the
+// kernel's LDS ring fills most of a CU's LDS), each with a long K range.
+FSplit fplan(int MB, int64_t K, int64_t M, int requested) {
+  FSplit sp;
+  const int64_t rows = (int64_t)kWaves * 16 * MB;
+  sp.mtiles = (M + rows - 1) / rows;
+  const int64_t unit = KSTEP;
+  const int64_t min_chunk = unit * 8;
+  int64_t S = requested > 0 ? requested : std::max<int64_t>(1, 256 / std::max<int64_t>(1, sp.mtiles));
+  S = std::min<int64_t>(S, std::max<int64_t>(1, (K + min_chunk - 1) / min_chunk));
+  S = std::max<int64_t>(1, std::min<int64_t>(S, 64));
+  if (requested <= 0 && S >= 8) S = S / 8 * 8;        // a multiple of the XCD count
+  (void)min_chunk;
+  int64_t kchunk = round_up((K + S - 1) / S, unit);
+  S = std::max<int64_t>(1, (K + kchunk - 1) / kchunk);
+  sp.S = (int)S;
+  sp.kchunk = kchunk;
+  sp.ldp = sp.mtiles * rows;
+  return sp;
+}
+
+template <int MB, int NB>
+void launch_f(FArgs& a, const FSplit& sp, int pm, int pr, hipStream_t st) {
+  dim3 grid((unsigned)(sp.mtiles * sp.S), 1, 1);
+  const bool prof = prof_enabled();
+  if (prof && pm >= 0) prof_begin(pm, st);
+  filter_bf16x6_kernel<MB, NB><<<grid, kThreads, 0, st>>>(a);
+  PFX_HIP(hipGetLastError());
+  if (prof && pm >= 0) prof_end(pm, st);
+  if (sp.S > 1) {
+    dim3 g2((unsigned)((a.M + 255) / 256), (unsigned)a.N);
+    if (prof && pr >= 0) prof_begin(pr, st);
+    filter_reduce_kernel<<<g2, 256, 0, st>>>(a);
+    PFX_HIP(hipGetLastError());
+    if (prof && pr >= 0) prof_end(pr, st);
+  }
+}
+
+int mb_for(int NB) { return NB <= 4 ? 2 : 1; }
+
+}  // namespace
+
+size_t filter_bf16x6_part_bytes(int64_t K, int64_t M, int64_t N) {
+  const int NB = (int)(N / 16);
+  const FSplit sp = fplan(mb_for(NB), K, M, 0);
+  return sp.S > 1 ? (size_t)sp.S * sp.ldp * N * sizeof(float) : 0;
+}
+
+void filter_bf16x6(const FilterArgs& x, hipStream_t st) {
+  if (x.N % 16 != 0 || x.N <= 0 || x.N > 128) fail(PF_ERR_ARG, "filter: N must be 16..128, multiple of 16");
+  const int NB = (int)(x.N / 16);
+  const int MB = mb_for(NB);
+  FSplit sp = fplan(MB, x.K, x.M, x.splitk);
+  while (sp.S > 1 && (size_t)sp.S * sp.ldp * x.N * sizeof(float) > x.part_bytes) sp = fplan(MB, x.K, x.M, sp.S - 1);
+  FArgs a;
+  a.X = x.X; a.ldx = x.ldx;
+  a.Yp = x.Yp; a.ldy = x.ldy; a.yplane = x.yplane;
+  a.K = x.K; a.M = x.M; a.N = x.N; a.kchunk = sp.kchunk;
+  a.out = x.out; a.ldo = x.ldo; a.D1 = x.D1; a.D2 = x.D2; a.ldd = x.ldd;
+  a.alpha = (float)x.alpha; a.beta = (float)x.beta; a.gamma = (float)x.gamma;
+  a.outp = x.outp; a.ldop = x.ldop; a.oplane = x.oplane;
+  a.part = static_cast<float*>(x.part); a.ldp = sp.ldp; a.splitk = sp.S;
+  switch (NB) {
+    case 1: launch_f<2, 1>(a, sp, x.prof_main, x.prof_reduce, st); break;
+    case 2: launch_f<2, 2>(a, sp, x.prof_main, x.prof_reduce, st); break;
+    case 3: launch_f<2, 3>(a, sp, x.prof_main, x.prof_reduce, st); break;
+    case 4: launch_f<2, 4>(a, sp, x.prof_main, x.prof_reduce, st); break;
+    case 5: launch_f<1, 5>(a, sp, x.prof_main, x.prof_reduce, st); break;
+    case 6: launch_f<1, 6>(a, sp, x.prof_main, x.prof_reduce, st); break;
+    case 7: launch_f<1, 7>(a, sp, x.prof_main, x.prof_reduce, st); break;
+    default: launch_f<1, 8>(a, sp, x.prof_main, x.prof_reduce, st); break;
+  }
+}
+
+void launch_split_planes(const float* src, int64_t lds, int64_t n, int p, uint16_t* dst, int64_t ldd,
+                         int64_t plane, int64_t n_pad, int p_pad, hipStream_t st) {
+  dim3 grid((unsigned)((n_pad + 255) / 256), (unsigned)p_pad);
+  split_planes_kernel<<<grid, 256, 0, st>>>(src, lds, n, p, dst, ldd, plane, n_pad);
+  PFX_HIP(hipGetLastError());
+}
+
+}  // namespace pfx

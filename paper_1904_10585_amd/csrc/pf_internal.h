@@ -64,6 +64,27 @@ int contract(const ContractArgs& a, hipStream_t st);
 size_t contract_part_bytes(int64_t K, int64_t M, int64_t N, Elem ta, Elem tb, bool f64_mfma, int splitk);
 
 // ---------------------------------------------------------------------------
+// FP32 filter product on BF16 matrix cores (exact three-way split of X in
+// registers, Y as three BF16 planes, six cross terms):
+// out = alpha X^T Y + beta D1 + gamma D2, optionally also the planes of out.
+struct FilterArgs {
+  const float* X; int64_t ldx;
+  const uint16_t* Yp; int64_t ldy; int64_t yplane;
+  int64_t K, M, N;
+  float* out; int64_t ldo;
+  const float* D1; const float* D2; int64_t ldd;
+  double alpha, beta, gamma;
+  uint16_t* outp; int64_t ldop; int64_t oplane;
+  void* part; size_t part_bytes;
+  int splitk = 0;
+  int prof_main = -1, prof_reduce = -1;
+};
+void filter_bf16x6(const FilterArgs& a, hipStream_t st);
+size_t filter_bf16x6_part_bytes(int64_t K, int64_t M, int64_t N);
+void launch_split_planes(const float* src, int64_t lds, int64_t n, int p, uint16_t* dst, int64_t ldd,
+                         int64_t plane, int64_t n_pad, int p_pad, hipStream_t st);
+
+// ---------------------------------------------------------------------------
 // Small dense kernels on p x p matrices (one workgroup each).
 void launch_chol_rinv(const double* G, int ldg, int p, double* Rinv, int ldr,
                       int* deficient, pf_info* info, int pass, hipStream_t st);

@@ -33,6 +33,9 @@ struct Plan {
   void* U;
   void* Z;
   void* Yb[3];
+  uint16_t* Up;       // BF16 planes of U (split-BF16 filter)
+  uint16_t* Ypl[3];   // BF16 planes of the recurrence ring
+  int64_t plane;      // elements per plane
   void* Q1;
   void* Q;
   double* W;
@@ -51,6 +54,7 @@ struct Plan {
 namespace {
 
 struct Layout {
+  size_t off_Up, off_Ypl[3];
   size_t off_U, off_Z, off_Y[3], off_Q1, off_Q, off_W, off_G, off_Rinv, off_Zeig, off_Zwork, off_theta,
       off_theta_pre, off_def, off_info, off_part, total, part_bytes;
 };
@@ -81,6 +85,9 @@ Layout layout_for(const pf_desc& d) {
   L.off_theta_pre = o; o += align256((size_t)p_pad * 8);
   L.off_def = o; o += align256((size_t)p_pad * 4);
   L.off_info = o; o += align256(sizeof(pf_info));
+  const size_t planes = align256((size_t)3 * n_pad * p_pad * 2);
+  L.off_Up = o; o += (work == Elem::F32) ? planes : 0;
+  for (int i = 0; i < 3; ++i) { L.off_Ypl[i] = o; o += (work == Elem::F32) ? planes : 0; }
   // split-K slabs: the largest any contraction of the sequence asks for
   const Elem xf = work;   // filter operand type (same as work in these forms)
   size_t part = 0;
@@ -89,6 +96,7 @@ Layout layout_for(const pf_desc& d) {
   part = std::max(part, contract_part_bytes(d.n, d.n, p_pad, Elem::F64, Elem::F64, true, 0));
   part = std::max(part, contract_part_bytes(d.n, p_pad, p_pad, work, work, true, 0));
   part = std::max(part, contract_part_bytes(d.n, p_pad, p_pad, work, Elem::F64, true, 0));
+  if (work == Elem::F32) part = std::max(part, filter_bf16x6_part_bytes(d.n, d.n, p_pad));
   L.part_bytes = align256(part);
   L.off_part = o; o += L.part_bytes;
   L.total = o;
@@ -138,7 +146,7 @@ void plan_validate(const pf_desc& d, const pf_mat* Xf, const pf_mat* Xr) {
   if (d.work != PF_F32 && d.work != PF_F64) fail(PF_ERR_ARG, "pf_desc.work must be PF_F32 or PF_F64");
   if ((d.flags & PF_FLAG_SCALED) && !(std::isfinite(d.spec_ub) && d.spec_ub > d.b))
     fail(PF_ERR_ARG, "PF_FLAG_SCALED needs a finite spec_ub > b");
-  if (d.flags & ~(PF_FLAG_NO_PREROTATE | PF_FLAG_SCALED | PF_FLAG_COLD))
+  if (d.flags & ~(PF_FLAG_NO_PREROTATE | PF_FLAG_SCALED | PF_FLAG_COLD | PF_FLAG_NATIVE_F32))
     fail(PF_ERR_ARG, "unknown bits in pf_desc.flags");
   if (d.max_sweeps < 0) fail(PF_ERR_ARG, "pf_desc.max_sweeps must be >= 0");
   if (Xf || Xr) {
@@ -195,6 +203,10 @@ Plan* plan_create(const pf_desc& d) {
   P->deficient = reinterpret_cast<int*>(b + L.off_def);
   P->info = reinterpret_cast<pf_info*>(b + L.off_info);
   P->part = b + L.off_part;
+  P->plane = P->n_pad * P->p_pad;
+  P->Up = P->work == Elem::F32 ? reinterpret_cast<uint16_t*>(b + L.off_Up) : nullptr;
+  for (int i = 0; i < 3; ++i)
+    P->Ypl[i] = P->work == Elem::F32 ? reinterpret_cast<uint16_t*>(b + L.off_Ypl[i]) : nullptr;
   P->part_bytes = L.part_bytes;
   return P;
 }
@@ -213,11 +225,15 @@ pf_info* plan_info(Plan* p) { return p->info; }
 namespace {
 
 Elem elem_of(pf_dtype t) { return t == PF_F64 ? Elem::F64 : Elem::F32; }
+void contract_into(Plan* P, const void* A, int64_t lda, Elem ta, const void* B, int64_t ldb, Elem tb,
+                   int64_t K, int64_t M, void* out, int64_t ldo, Elem to, const void* D1,
+                   const void* D2, int64_t ldd, double alpha, double beta, double gamma, bool f64,
+                   hipStream_t st, int prof_main, int prof_reduce);
 
 void contract_into(Plan* P, const void* A, int64_t lda, Elem ta, const void* B, int64_t ldb, Elem tb,
                    int64_t K, int64_t M, void* out, int64_t ldo, Elem to, const void* D1,
                    const void* D2, int64_t ldd, double alpha, double beta, double gamma, bool f64,
-                   hipStream_t st, int prof_main = -1, int prof_reduce = -1) {
+                   hipStream_t st, int prof_main, int prof_reduce) {
   ContractArgs c;
   c.A = A; c.lda = lda; c.ta = ta;
   c.B = B; c.ldb = ldb; c.tb = tb;
@@ -233,9 +249,46 @@ void contract_into(Plan* P, const void* A, int64_t lda, Elem ta, const void* B, 
   contract(c, st);
 }
 
+uint16_t* planes_of(Plan* P, const void* y) {
+  if (y == P->U) return P->Up;
+  for (int i = 0; i < 3; ++i)
+    if (y == P->Yb[i]) return P->Ypl[i];
+  fail(PF_ERR_DEVICE, "internal: block without BF16 planes");
+}
+
+void refresh_planes(Plan* P, const void* y, hipStream_t st) {
+  launch_split_planes(static_cast<const float*>(y), P->n_pad, P->n, P->p_pad, planes_of(P, y), P->n_pad, P->plane,
+                      P->n_pad, P->p_pad, st);
+}
+
+// One filter product out = alpha X Y + beta D1 + gamma D2 on the split-BF16
+// path (FP32 work) or on the native MFMA path (FP32 with PF_FLAG_NATIVE_F32,
+// or FP64).  want_planes: also write the planes of out for the next product.
+void filter_product(Plan* P, const pf_mat& Xf, const void* y, void* out, const void* D1, const void* D2,
+                    double alpha, double beta, double gamma, bool want_planes, hipStream_t st) {
+  const bool split = P->work == Elem::F32 && !(P->d.flags & PF_FLAG_NATIVE_F32);
+  const int64_t ld = P->n_pad;
+  if (split) {
+    FilterArgs f;
+    f.X = static_cast<const float*>(Xf.data); f.ldx = Xf.ld;
+    f.Yp = planes_of(P, y); f.ldy = ld; f.yplane = P->plane;
+    f.K = P->n; f.M = P->n; f.N = P->p_pad;
+    f.out = static_cast<float*>(out); f.ldo = ld;
+    f.D1 = static_cast<const float*>(D1); f.D2 = static_cast<const float*>(D2); f.ldd = ld;
+    f.alpha = alpha; f.beta = beta; f.gamma = gamma;
+    f.outp = want_planes ? planes_of(P, out) : nullptr; f.ldop = ld; f.oplane = P->plane;
+    f.part = P->part; f.part_bytes = P->part_bytes;
+    f.prof_main = PF_PROF_FILTER; f.prof_reduce = PF_PROF_FILTER_REDUCE;
+    filter_bf16x6(f, st);
+  } else {
+    contract_into(P, Xf.data, Xf.ld, elem_of(Xf.dtype), y, ld, P->work, P->n, P->n, out, ld, P->work, D1, D2, ld,
+                  alpha, beta, gamma, P->work == Elem::F64, st, PF_PROF_FILTER, PF_PROF_FILTER_REDUCE);
+  }
+}
+
 void gram(Plan* P, const void* A, Elem ta, const void* B, Elem tb, double* out, hipStream_t st) {
   contract_into(P, A, P->n_pad, ta, B, P->n_pad, tb, P->n, P->p_pad, out, P->p_pad, Elem::F64, nullptr,
-                nullptr, 0, 1.0, 0.0, 0.0, true, st);
+                nullptr, 0, 1.0, 0.0, 0.0, true, st, -1, -1);
 }
 
 void apply(Plan* P, const void* A1, const void* A2, const double* S, void* C1, int64_t ldc1, void* C2,
@@ -262,8 +315,7 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
   std::vector<double> tau;
   host_coefficients(d, tau);
   const Elem W = P->work;
-  const Elem tf = elem_of(Xf.dtype), tr = elem_of(Xr.dtype);
-  const bool f64 = W == Elem::F64;
+  const Elem tr = elem_of(Xr.dtype);
   const int max_sweeps = d.max_sweeps > 0 ? d.max_sweeps : 30;
   const int64_t ld = P->n_pad;
 
@@ -272,17 +324,21 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
   launch_info_init(P->info, st);
   launch_copy_block(U_in, ldu_in, W, P->U, ld, W, P->n, P->p, P->n_pad, P->p_pad, st);
 
+  const bool split = W == Elem::F32 && !(d.flags & PF_FLAG_NATIVE_F32);
   void* cur = P->U;
   for (int pass = 0; pass < d.q; ++pass) {
+    if (split) {
+      if (pass == 0) refresh_planes(P, cur, st);
+      // later passes start from Y_d, whose planes the last step wrote
+    }
     // first product Z = A Y_0
-    contract_into(P, Xf.data, Xf.ld, tf, cur, ld, W, P->n, P->n, P->Z, ld, W, nullptr, nullptr, ld, 1.0, 0.0,
-                  0.0, f64, st, PF_PROF_FILTER, PF_PROF_FILTER_REDUCE);
+    filter_product(P, Xf, cur, P->Z, nullptr, nullptr, 1.0, 0.0, 0.0, false, st);
     const double a1 = 1.0 / (e * tau[1]), b1 = -c / (e * tau[1]);
     void* y_prev;
     void* y_cur;
     if (pass == 0 && !(d.flags & PF_FLAG_NO_PREROTATE)) {
       gram(P, cur, W, P->Z, W, P->G, st);
-      launch_jacobi(P->G, P->p_pad, P->p, P->theta_pre, P->Zeig, P->p_pad, P->Zwork, P->info, 0, 8, st);
+      launch_jacobi(P->G, P->p_pad, P->p, P->theta_pre, P->Zeig, P->p_pad, P->Zwork, P->info, 0, 3, st);
       apply(P, cur, P->Z, P->Zeig, P->Yb[0], ld, P->Yb[1], a1, b1, nullptr, nullptr, st);
       y_prev = P->Yb[0];
       y_cur = P->Yb[1];
@@ -292,6 +348,7 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
       y_prev = cur;
       y_cur = dst;
     }
+    if (split && (d.degree > 1 || pass + 1 < d.q)) refresh_planes(P, y_cur, st);
     const bool cold = (d.flags & PF_FLAG_COLD) && pass == 0;
     if (y_prev == P->U && cold) {
       // keep U intact for re-orthonormalisation: move Y_0 into the ring
@@ -304,11 +361,13 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
         if (P->Yb[i] != y_cur && P->Yb[i] != y_prev) { y_next = P->Yb[i]; break; }
       const double r = tau[k] / tau[k + 1];
       const double al = 2.0 * r / e, be = -2.0 * c * r / e, ga = -tau[k - 1] / tau[k + 1];
-      contract_into(P, Xf.data, Xf.ld, tf, y_cur, ld, W, P->n, P->n, y_next, ld, W, y_cur, y_prev, ld, al, be,
-                    ga, f64, st, PF_PROF_FILTER, PF_PROF_FILTER_REDUCE);
+      const bool reorth = cold && (k + 1) % 2 == 0 && k + 1 < d.degree;
+      // planes of Y_{k+1} feed the next product (or the next pass)
+      const bool want = split && ((k + 1 < d.degree && !reorth) || (k + 1 == d.degree && pass + 1 < d.q));
+      filter_product(P, Xf, y_cur, y_next, y_cur, y_prev, al, be, ga, want, st);
       y_prev = y_cur;
       y_cur = y_next;
-      if (cold && (k + 1) % 2 == 0 && k + 1 < d.degree) {
+      if (reorth) {
         // (Y_{k+1}, Y_k) <- (Y_{k+1}, Y_k) R^{-1}, R from CholeskyQR2 of Y_{k+1}
         for (int pass2 = 0; pass2 < 2; ++pass2) {
           void* src_c = pass2 == 0 ? y_cur : P->Q1;
@@ -319,6 +378,7 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
           launch_chol_rinv(P->G, P->p_pad, P->p, P->Rinv, P->p_pad, P->deficient, P->info, 0, st);
           apply(P, src_c, src_p, P->Rinv, dst_c, ld, dst_p, 1.0, 0.0, P->deficient, nullptr, st);
         }
+        if (split) refresh_planes(P, y_cur, st);
       }
     }
     cur = y_cur;

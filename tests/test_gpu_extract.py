@@ -88,15 +88,41 @@ def test_ragged_shapes(n, p, d, work):
     assert oracle.orth_error(V) < (1e-12 if work == "f64" else 1e-5)
 
 
+@pytest.mark.parametrize("n,p,d", [(300, 20, 3), (1000, 48, 3), (2100, 128, 2), (4096, 64, 10)])
+def test_native_f32_filter_path(n, p, d):
+    """The FP32 filter on the native FP32 MFMA pipe (PF_FLAG_NATIVE_F32)
+    matches the oracle like the default split-BF16 path."""
+    r = max(1, p // 2)
+    X, lam, Q = wl.planted(n, r, (4.0, 10.0), (-1.0, 0.5), config=89, index=n + p)
+    U = wl.start_block(n, p, config=89, index=n)
+    for _ in range(3):
+        U = oracle.extract(X, X, U, 6, -1.0, 0.5)["V"]
+    X = X.astype(np.float32).astype(np.float64)
+    U = U.astype(np.float32).astype(np.float64)
+    ref = oracle.extract(X, X, U, d, -1.0, 0.5)
+    out = {}
+    for name, flags in (("split", 0), ("native", 8)):
+        th, V, info = run_extract(X, U, d, -1.0, 0.5, work="f32", flags=flags)
+        assert info["status"] == 0, info
+        out[name] = compare(th, V, ref, r)
+        print(f"n={n} p={p} d={d} {name}: rel {out[name][0]:.2e} sin {out[name][1]:.2e}")
+        assert out[name][0] <= 1e-5 and out[name][1] <= 1e-4
+
+
 @pytest.mark.parametrize("q", [2, 3])
-def test_filter_power(q):
+@pytest.mark.parametrize("work,d", [("f64", 3), ("f32", 3), ("f32", 1)])
+def test_filter_power(q, work, d):
     n, p, r = 400, 12, 6
     X, _, _ = wl.planted(n, r, (2.0, 5.0), (-1.0, 0.5), config=91, index=q)
     U = oracle.extract(X, X, wl.start_block(n, p, config=91, index=q), 4, -1.0, 0.5)["V"]
-    ref = oracle.extract(X, X, U, 3, -1.0, 0.5, q=q)
-    th, V, info = run_extract(X, U, 3, -1.0, 0.5, work="f64", q=q)
+    if work == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+        U = U.astype(np.float32).astype(np.float64)
+    ref = oracle.extract(X, X, U, d, -1.0, 0.5, q=q)
+    th, V, info = run_extract(X, U, d, -1.0, 0.5, work=work, q=q)
     rel, sin = compare(th, V, ref, r)
-    assert info["status"] == 0 and rel <= 1e-10 and sin <= 1e-10, (rel, sin)
+    tol = (1e-10, 1e-10) if work == "f64" else (1e-5, 1e-4)
+    assert info["status"] == 0 and rel <= tol[0] and sin <= tol[1], (rel, sin)
 
 
 def test_scaled_recurrence_same_span():
