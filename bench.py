@@ -131,6 +131,7 @@ def main():
     s, res = pf.pf_session_wait(sess)
     if s != pf.PF_OK:
         raise SystemExit(f"timed step failed: {pf.status_string(s)}")
+    info = pf.device_to_numpy(res.info, (8,), np.int32)
     step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(K)])
     total_ms = ev[0].elapsed_time(ev[K])
     prof = {}
@@ -163,6 +164,8 @@ def main():
                    "steps_chain": "X_k = X_{k-1} + 1e-3 sym(N(0,1))/sqrt(n)"},
         "hbm_GBps_algorithmic": round(bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
         "bytes_per_step_algorithmic": bytes_step,
+        "last_step_info": {"n_pos": int(info[1]), "sweeps_rr": int(info[2]), "sweeps_pre": int(info[3]),
+                           "deficient": int(info[4])},
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
                        "p99": round(float(np.percentile(step_ms, 99)), 4),
                        "max": round(float(step_ms.max()), 4)},

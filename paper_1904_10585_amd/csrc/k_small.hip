@@ -22,132 +22,146 @@ __device__ inline void set_status(pf_info* info, int code) {
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky + triangular inverse.  LDS: A (p*p doubles, row-major): lower
-// triangle holds the elimination, strict upper triangle later holds the
-// strictly lower part of L^{-1} transposed; plus D, pivots, L^{-1} diagonal.
+// Cholesky + triangular inverse, register resident.  Thread (bi, bj) of a
+// (PMAX/4)^2 grid holds the 4x4 blocks (bi, bj) of the equilibrated Gram
+// matrix G and of W, which starts as I.  Step k of the right-looking
+// elimination in L D L^T form broadcasts column k of G and row k of W
+// through LDS (double-buffered: one barrier per step) and applies
+//     G[i][j] -= G[i][k] G[k][j] / d_k   (i, j > k)
+//     W[i][:] -= G[i][k] / d_k * W[k][:] (i > k),
+// the same row operations on W as on G, so that at the end
+// G = L_1 D L_1^T with L_1 unit lower triangular and W = L_1^{-1}.  Then
+// R = D^{1/2} L_1^T (of the equilibrated matrix) and
+//     R^{-1}[i][j] = s_i W[j][i] / sqrt(d_j),   i <= j,
+// with s = diag(G)^{-1/2} the equilibration.
 template <int PMAX>
-__global__ __launch_bounds__(256) void chol_rinv_kernel(const double* __restrict__ G, int ldg, int p,
-                                                        double* __restrict__ Rinv, int ldr,
-                                                        int* __restrict__ deficient,
-                                                        pf_info* info, int pass, double tol) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int lda = p + 1;                        // odd stride: rows spread over banks
-  double* A = reinterpret_cast<double*>(smem_raw);
-  double* D = A + p * lda;
-  double* piv = D + p;
-  double* xd = piv + p;
-  int* def = reinterpret_cast<int*>(xd + p);
-  __shared__ int bad_nonfinite;
-  const int t = threadIdx.x, nt = blockDim.x;
-  if (t == 0) bad_nonfinite = 0;
+__global__ __launch_bounds__((PMAX / 4) * (PMAX / 4)) void chol_rinv_kernel(
+    const double* __restrict__ G, int ldg, int p, double* __restrict__ Rinv, int ldr,
+    int* __restrict__ deficient, pf_info* info, int pass, double tol) {
+  constexpr int NBK = PMAX / 4;
+  constexpr int NT = NBK * NBK;
+  __shared__ __align__(16) double s_eq[PMAX], s_piv[PMAX], s_col[2][PMAX], s_row[2][PMAX];
+  __shared__ int s_def[PMAX];
+  __shared__ int s_bad;
+  const int t = threadIdx.x;
+  const int bi = t / NBK, bj = t % NBK;
+  const int i0 = 4 * bi, j0 = 4 * bj;
+  if (t == 0) s_bad = 0;
   __syncthreads();
 
-  for (int i = t; i < p; i += nt) {
-    const double gii = G[i + (int64_t)i * ldg];
-    if (!isfinite(gii)) bad_nonfinite = 1;
-    D[i] = gii > 0.0 ? 1.0 / sqrt(gii) : 0.0;
-    def[i] = 0;
+  double g[4][4], w[4][4];
+  bool bad = false;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = i0 + r, j = j0 + c;
+      double v = i == j ? 1.0 : 0.0;                 // identity padding past p
+      if (i < p && j < p) {
+        v = G[i + (int64_t)j * ldg];
+        bad |= !isfinite(v);
+      }
+      g[r][c] = v;
+      w[r][c] = i == j ? 1.0 : 0.0;
+    }
+  if (bad) s_bad = 1;
+  if (bi == bj) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s_eq[i0 + r] = g[r][r] > 0.0 ? 1.0 / sqrt(g[r][r]) : 0.0;
   }
   __syncthreads();
-  for (int idx = t; idx < p * p; idx += nt) {
-    const int j = idx / p, i = idx - j * p;            // coalesced over i
-    const double gij = G[i + (int64_t)j * ldg];
-    if (!isfinite(gij)) bad_nonfinite = 1;
-    A[i * lda + j] = (i >= j) ? gij * D[i] * D[j] : 0.0;
-  }
-  __syncthreads();
-  if (bad_nonfinite) {
+  if (s_bad) {
     if (t == 0) set_status(info, PF_ERR_NONFINITE);
-    for (int idx = t; idx < ldr * ldr; idx += nt) Rinv[idx] = 0.0;
+    for (int idx = t; idx < ldr * ldr; idx += NT) Rinv[idx] = 0.0;
     return;
   }
+  double si[4], sj[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) { si[u] = s_eq[i0 + u]; sj[u] = s_eq[j0 + u]; }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (i0 + r < p && j0 + c < p) g[r][c] *= si[r] * sj[c];
 
-  // Right-looking elimination in the L D L^T form: column k stays
-  // unscaled, so each step needs one barrier; scaling happens at the end.
-  // Thread t updates rows k+1 + (t>>2) + 64m, columns k+1 + (t&3) + 4u.
-  const int tr = t >> 2, tc = t & 3;
   for (int k = 0; k < p; ++k) {
-    const double pk = A[k * lda + k];
-    const bool ok = pk > tol && D[k] > 0.0;
-    if (t == 0) { piv[k] = ok ? pk : 1.0; def[k] = ok ? 0 : 1; }
-    if (ok) {
-      const double inv = 1.0 / pk;
-      for (int i = k + 1 + tr; i < p; i += 64) {
-        const double lik = A[i * lda + k] * inv;
-        // all loads of the row segment first, then the stores (one LDS
-        // round trip instead of one per element)
-        // loads are unconditional (indices clamped into the matrix) so that
-        // they issue back to back; only the stores are predicated
-        double cj[PMAX / 4], aj[PMAX / 4];
-#pragma unroll
-        for (int u = 0; u < PMAX / 4; ++u) {
-          const int j = min(k + 1 + tc + 4 * u, i);
-          cj[u] = A[j * lda + k];
-          aj[u] = A[i * lda + j];
-        }
-#pragma unroll
-        for (int u = 0; u < PMAX / 4; ++u) {
-          const int j = k + 1 + tc + 4 * u;
-          if (j <= i) A[i * lda + j] = aj[u] - lik * cj[u];
-        }
+    const int buf = k & 1, kb = k >> 2, kr = k & 3;
+    // owners publish column k of G and row k of W (kr is uniform: a scalar
+    // branch picks the registers)
+    if (bj == kb) {
+      switch (kr) {
+        case 0: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][0]; break;
+        case 1: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][1]; break;
+        case 2: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][2]; break;
+        default: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][3]; break;
+      }
+    }
+    if (bi == kb) {
+      switch (kr) {
+        case 0: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[0][c]; break;
+        case 1: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[1][c]; break;
+        case 2: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[2][c]; break;
+        default: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[3][c]; break;
       }
     }
     __syncthreads();
-  }
-  // L[i][k] = A[i][k] / sqrt(piv_k); deficient columns become e_k.
-  for (int i = tr; i < p; i += 64) {
-    for (int k = tc; k <= i; k += 4) {
-      const int idx = i * lda + k;
-      if (def[k]) A[idx] = (i == k) ? 1.0 : 0.0;
-      else A[idx] = (i == k) ? sqrt(piv[k]) : A[idx] / sqrt(piv[k]);
+    const double pk = s_col[buf][k];
+    double ci[4], cj[4], wk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ci[u] = s_col[buf][i0 + u];
+      cj[u] = s_col[buf][j0 + u];
+      wk[u] = s_row[buf][j0 + u];
     }
-    for (int j = i + 1 + tc; j < p; j += 4) A[i * lda + j] = 0.0;   // upper part: L^{-1} storage
+    // a dependent column (equilibrated pivot <= tol; a zero column has pivot
+    // 0) is left out of the elimination
+    const bool ok = pk > tol;
+    if (t == 0) { s_piv[k] = ok ? pk : 1.0; s_def[k] = ok ? 0 : 1; }
+    const double inv = ok ? 1.0 / pk : 0.0;
+    double li[4], gj[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      li[u] = (i0 + u > k) ? ci[u] * inv : 0.0;
+      gj[u] = (j0 + u > k) ? cj[u] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        g[r][c] -= li[r] * gj[c];
+        w[r][c] -= li[r] * wk[c];
+      }
   }
-  for (int i = t; i < p; i += nt) xd[i] = 1.0;
   __syncthreads();
 
-  // X = L^{-1} by right-looking substitution on L X = I, rows left unscaled
-  // (Xu) until the end: X[i][j] -= L[i][k] * Xu[k][j] / L[k][k].
-  // Strictly lower X[i][j] (i > j) lives at A[j*p + i].
-  for (int k = 0; k < p - 1; ++k) {
-    const double invk = 1.0 / A[k * lda + k];
-    for (int i = k + 1 + tr; i < p; i += 64) {
-      const double lik = A[i * lda + k] * invk;
-      if (lik == 0.0) continue;
-      double xk[PMAX / 4], xi[PMAX / 4];
+  // R^{-1}[i][j] = s_i W[j][i] / sqrt(d_j) for i <= j: this thread's W block
+  // (rows i0.., columns j0..) lands transposed at rows j0.., columns i0..
 #pragma unroll
-      for (int u = 0; u < PMAX / 4; ++u) {
-        const int j = min(tc + 4 * u, k);
-        xk[u] = A[j * lda + k];                 // position (k, k) is L[k][k]: replaced below
-        xi[u] = A[j * lda + i];
-        if (tc + 4 * u == k) xk[u] = xd[k];
-      }
+  for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int u = 0; u < PMAX / 4; ++u) {
-        const int j = tc + 4 * u;
-        if (j <= k) A[j * lda + i] = xi[u] - lik * xk[u];
+    for (int c = 0; c < 4; ++c) {
+      const int wr = i0 + r, wc = j0 + c;          // W[wr][wc] -> Rinv[wc][wr]
+      if (wr < p && wc < p && wc < ldr && wr < ldr) {
+        double v = 0.0;
+        if (wc <= wr) {
+          const double s = s_def[wc] ? 1.0 : s_eq[wc];
+          v = s * w[r][c] / sqrt(s_piv[wr]);
+        }
+        Rinv[wc + (int64_t)wr * ldr] = v;
       }
     }
-    __syncthreads();
+  for (int idx = t; idx < ldr * ldr; idx += NT) {
+    const int i = idx % ldr, j = idx / ldr;
+    if (i >= p || j >= p) Rinv[idx] = 0.0;
   }
-  // Rinv = D L^{-T}: Rinv[i][j] = D_i X[j][i] (j >= i), X[j][i] = Xu[j][i] / L[j][j]
-  for (int idx = t; idx < ldr * ldr; idx += nt) {
-    const int i = idx % ldr, j = idx / ldr;   // column-major output
-    double v = 0.0;
-    if (i < p && j < p && j >= i) {
-      const double ljj = A[j * lda + j];
-      const double xji = (i == j) ? xd[j] : A[i * lda + j];
-      const double di = def[i] ? 1.0 : D[i];
-      v = di * xji / ljj;
+  for (int i = t; i < ldr; i += NT) deficient[i] = (i < p) ? s_def[i] : 0;
+  if (t == 0) {
+    int ndef = 0;
+    for (int i = 0; i < p; ++i) ndef += s_def[i];
+    if (info) {
+      info->deficient += ndef;
+      if (pass >= 2 && ndef > 0) set_status(info, PF_ERR_BREAKDOWN);
     }
-    Rinv[idx] = v;
-  }
-  int ndef = 0;
-  for (int i = 0; i < p; ++i) ndef += def[i];
-  for (int i = t; i < ldr; i += nt) deficient[i] = (i < p) ? def[i] : 0;
-  if (t == 0 && info) {
-    info->deficient += ndef;
-    if (pass >= 2 && ndef > 0) set_status(info, PF_ERR_BREAKDOWN);
   }
 }
 
@@ -168,29 +182,48 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-template <int PMAX>
+// Pair k of round r of the round-robin order over pe (even) indices: index
+// pe-1 stays, the others rotate; every pair meets once in pe-1 rounds.
+__device__ inline void rr_pair(int r, int k, int pe, int& i, int& j) {
+  if (k == 0) {
+    i = r;
+    j = pe - 1;
+  } else {
+    i = r + k;
+    if (i >= pe - 1) i -= pe - 1;
+    j = r - k;
+    if (j < 0) j += pe - 1;
+  }
+  if (i > j) { const int x = i; i = j; j = x; }
+}
+
+// VLDS: V^T lives in LDS (p <= 98); otherwise in the global work buffer.
+// Separate instantiations keep every LDS access a ds_* instruction (a
+// pointer that may be either would make them all flat accesses).
+template <int PMAX, bool VLDS>
 __global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ H, int ldh, int p,
                                                      double* __restrict__ theta, double* __restrict__ Z,
                                                      int ldz, double* __restrict__ Vglob, pf_info* info,
                                                      int which, int max_sweeps, double tol_rel,
-                                                     int v_in_lds, int first_order) {
+                                                     int first_order) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int pe = (p + 1) & ~1;
   const int half = pe / 2;
   const int nblk = half * (half + 1) / 2;
   const int lda = pe + 1;
-  const int ldv = v_in_lds ? pe + 2 : pe;
+  const int ldv = VLDS ? pe + 2 : pe;
   double* A = reinterpret_cast<double*>(smem_raw);
   double* rc = A + pe * lda;
   double* rs = rc + half;
   double* rt = rs + half;
-  double* dg = rt + half;                        // pe values: first-order eigenvalues
-  int* ri = reinterpret_cast<int*>(dg + pe);
-  int* rj = ri + half;
-  unsigned* blk = reinterpret_cast<unsigned*>(rj + half);
-  double* VT = v_in_lds ? reinterpret_cast<double*>(blk + ((nblk + 1) & ~1)) : Vglob;
+  double* dg = rt + half;                        // pe values
+  int* perm = reinterpret_cast<int*>(dg + pe);   // pe values
+  unsigned* blk = reinterpret_cast<unsigned*>(perm + pe);
+  double* VT;
+  if constexpr (VLDS) VT = reinterpret_cast<double*>(blk + ((nblk + 1) & ~1));
+  else VT = Vglob;
   __shared__ double wsum[4];
-  __shared__ int sweeps_done, not_diag;
+  __shared__ int not_diag;
   const int t = threadIdx.x, nt = blockDim.x;
 
   double local = 0.0;
@@ -213,6 +246,17 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ 
   const double fro = sqrt(wsum[0] + wsum[1] + wsum[2] + wsum[3]);   // fixed order
   // below this an off-diagonal entry is rounding noise of the rotations
   const double tol_abs = 2.220446049250313e-16 * fro;
+
+  // the 2x2 blocks (P, Q), P <= Q, of pair space this thread updates
+  constexpr int BMAX = ((PMAX / 2) * (PMAX / 2 + 1) / 2 + 255) / 256;
+  int bP[BMAX], bQ[BMAX];
+#pragma unroll
+  for (int u = 0; u < BMAX; ++u) {
+    const int b = t + u * nt;
+    const unsigned pq = blk[min(b, nblk - 1)];
+    bP[u] = b < nblk ? (int)(pq >> 16) : -1;
+    bQ[u] = (int)(pq & 0xFFFF);
+  }
 
   bool converged = false;
   int sweep = 0;
@@ -246,48 +290,54 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ 
     }
   }
 
-  for (; !converged && sweep < max_sweeps; ++sweep) {
-    int any_in_sweep = 0;
+  while (!converged) {
+    // a sweep runs only while some off-diagonal entry is above its threshold
+    int above = 0;
+    for (int idx = t; idx < p * p; idx += nt) {
+      const int i = idx / p, j = idx - i * p;
+      if (i < j) {
+        const double thr = fmax(tol_rel * sqrt(fabs(A[i * lda + i]) * fabs(A[j * lda + j])), tol_abs);
+        above |= fabs(A[i * lda + j]) > thr;
+      }
+    }
+    above = __syncthreads_or(above);
+    if (!above) { converged = true; break; }
+    if (sweep >= max_sweeps) break;
+    ++sweep;
     for (int r = 0; r < pe - 1; ++r) {
-      int act = 0;
+      // rotation of each pair (one lane per pair, first wave only)
       if (t < half) {
         int i, j;
-        if (t == 0) { i = r; j = pe - 1; }
-        else { i = r + t; if (i >= pe - 1) i -= pe - 1; j = r - t; if (j < 0) j += pe - 1; }
-        if (i > j) { const int tmp = i; i = j; j = tmp; }
+        rr_pair(r, t, pe, i, j);
         const double aii = A[i * lda + i], ajj = A[j * lda + j], aij = A[i * lda + j];
         const double thr = fmax(tol_rel * sqrt(fabs(aii) * fabs(ajj)), tol_abs);
-        double c = 1.0, s = 0.0, tt = 0.0;
+        double c = 1.0, sn = 0.0, tt = 0.0;
         if (fabs(aij) > thr) {
-          const double tau = (ajj - aii) / (2.0 * aij);
-          tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          // tan of the rotation angle, smaller root: t = sign(d) x / (|d| + hypot(d, x))
+          const double d = ajj - aii, x = 2.0 * aij;
+          const double tq = x / (fabs(d) + sqrt(d * d + x * x));
+          tt = d >= 0.0 ? tq : -tq;
           c = 1.0 / sqrt(1.0 + tt * tt);
-          s = tt * c;
-          act = 1;
+          sn = tt * c;
         }
-        rc[t] = c; rs[t] = s; rt[t] = act ? tt : 0.0; ri[t] = i; rj[t] = j;
+        rc[t] = c; rs[t] = sn; rt[t] = tt;
       }
-      act = __syncthreads_or(act);
-      if (!act) continue;
-      any_in_sweep = 1;
-      // A <- J^T A J on 2x2 blocks of pairs, upper blocks mirrored.  A thread
-      // owns up to BMAX blocks: all loads, then all stores.
+      __syncthreads();
+      // A <- J^T A J on the 2x2 blocks of pairs (upper blocks mirrored): all
+      // loads of this thread's blocks, then the stores
       {
-        // blocks per thread: ceil((PMAX/2)(PMAX/2 + 1)/2 / 256)
-        constexpr int BMAX = ((PMAX / 2) * (PMAX / 2 + 1) / 2 + 255) / 256;
         double a11[BMAX], a12[BMAX], a21[BMAX], a22[BMAX];
-        int bi1[BMAX], bj1[BMAX], bi2[BMAX], bj2[BMAX], kind[BMAX];
+        int i1[BMAX], j1[BMAX], i2[BMAX], j2[BMAX], kind[BMAX];
 #pragma unroll
         for (int u = 0; u < BMAX; ++u) {
-          const int b = min(t + u * nt, nblk - 1);   // clamped: loads stay unconditional
-          const unsigned pq = blk[b];
-          const int P = pq >> 16, Q = pq & 0xFFFF;
-          bi1[u] = ri[P]; bj1[u] = rj[P]; bi2[u] = ri[Q]; bj2[u] = rj[Q];
+          const int P = max(bP[u], 0), Q = bQ[u];
+          rr_pair(r, P, pe, i1[u], j1[u]);
+          rr_pair(r, Q, pe, i2[u], j2[u]);
           const double tP = rt[P], tQ = rt[Q];
-          kind[u] = (t + u * nt >= nblk || (tP == 0.0 && tQ == 0.0)) ? 0 : (P == Q ? 1 : 2);
-          a11[u] = A[bi1[u] * lda + bi2[u]]; a12[u] = A[bi1[u] * lda + bj2[u]];
-          a21[u] = A[bj1[u] * lda + bi2[u]]; a22[u] = A[bj1[u] * lda + bj2[u]];
           const double c1 = rc[P], s1 = rs[P], c2 = rc[Q], s2 = rs[Q];
+          a11[u] = A[i1[u] * lda + i2[u]]; a12[u] = A[i1[u] * lda + j2[u]];
+          a21[u] = A[j1[u] * lda + i2[u]]; a22[u] = A[j1[u] * lda + j2[u]];
+          kind[u] = (bP[u] < 0 || (tP == 0.0 && tQ == 0.0)) ? 0 : (P == Q ? 1 : 2);
           if (kind[u] == 1) {
             a21[u] = tP;                                 // keep t of the pair
           } else {
@@ -300,64 +350,70 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ 
 #pragma unroll
         for (int u = 0; u < BMAX; ++u) {
           if (kind[u] == 0) continue;
-          const int i1 = bi1[u], j1 = bj1[u], i2 = bi2[u], j2 = bj2[u];
+          const int x1 = i1[u], y1 = j1[u], x2 = i2[u], y2 = j2[u];
           if (kind[u] == 1) {
-            // diagonal block of pair (i1, j1): a11, a22 the diagonal entries,
-            // a12 = a_{i1 j1}, a21 = t; the rotation zeroes a_{i1 j1}
-            A[i1 * lda + i1] = a11[u] - a21[u] * a12[u];
-            A[j1 * lda + j1] = a22[u] + a21[u] * a12[u];
-            A[i1 * lda + j1] = 0.0;
-            A[j1 * lda + i1] = 0.0;
+            // diagonal block of the pair: the rotation zeroes a_{x1 y1}
+            A[x1 * lda + x1] = a11[u] - a21[u] * a12[u];
+            A[y1 * lda + y1] = a22[u] + a21[u] * a12[u];
+            A[x1 * lda + y1] = 0.0;
+            A[y1 * lda + x1] = 0.0;
           } else {
-            A[i1 * lda + i2] = a11[u]; A[i1 * lda + j2] = a12[u];
-            A[j1 * lda + i2] = a21[u]; A[j1 * lda + j2] = a22[u];
-            A[i2 * lda + i1] = a11[u]; A[j2 * lda + i1] = a12[u];
-            A[i2 * lda + j1] = a21[u]; A[j2 * lda + j1] = a22[u];
+            A[x1 * lda + x2] = a11[u]; A[x1 * lda + y2] = a12[u];
+            A[y1 * lda + x2] = a21[u]; A[y1 * lda + y2] = a22[u];
+            A[x2 * lda + x1] = a11[u]; A[y2 * lda + x1] = a12[u];
+            A[x2 * lda + y1] = a21[u]; A[y2 * lda + y1] = a22[u];
           }
         }
       }
-      // V <- V J: thread (k = t/8, part t%8) rotates a contiguous run of
-      // rows i_k, j_k of V^T; all loads issue before the stores.
+      // V <- V J: eight threads per pair rotate a run of the two rows of V^T
       {
+        constexpr int CH = PMAX / 8;                 // entries per thread and row
         const int part = t & 7;
-        const int chunk = (pe + 7) >> 3;
-        const int x0 = part * chunk;
-        const int xe = min(pe, x0 + chunk);
+        const int x0 = part * CH;
         for (int k = t >> 3; k < half; k += nt >> 3) {
           if (rt[k] == 0.0) continue;
-          const double c = rc[k], s = rs[k];
-          double* __restrict__ vi = VT + ri[k] * ldv;
-          double* __restrict__ vj = VT + rj[k] * ldv;
-          double va[16], vb[16];
+          int i, j;
+          rr_pair(r, k, pe, i, j);
+          const double c = rc[k], sn = rs[k];
+          double* __restrict__ vi = VT + i * ldv;
+          double* __restrict__ vj = VT + j * ldv;
+          double va[CH], vb[CH];
 #pragma unroll
-          for (int u = 0; u < 16; ++u)
-            if (x0 + u < xe) { va[u] = vi[x0 + u]; vb[u] = vj[x0 + u]; }
+          for (int u = 0; u < CH; ++u) {            // clamped loads, predicated stores
+            const int x = min(x0 + u, pe - 1);
+            va[u] = vi[x];
+            vb[u] = vj[x];
+          }
 #pragma unroll
-          for (int u = 0; u < 16; ++u)
-            if (x0 + u < xe) { vi[x0 + u] = c * va[u] - s * vb[u]; vj[x0 + u] = s * va[u] + c * vb[u]; }
+          for (int u = 0; u < CH; ++u)
+            if (x0 + u < pe) { vi[x0 + u] = c * va[u] - sn * vb[u]; vj[x0 + u] = sn * va[u] + c * vb[u]; }
         }
       }
       __syncthreads();
     }
-    if (!any_in_sweep) { converged = true; break; }
   }
-  if (t == 0) sweeps_done = first_order && !not_diag ? 0 : sweep;
-  __syncthreads();
+  const int sweeps_done = first_order && !not_diag ? 0 : sweep;
 
-  // Sort by descending theta (ties by index) and write out.
+  // Sort by descending theta, ties by index.  The key orders NaN below every
+  // number, so (key, index) is a strict total order even for non-finite
+  // input and the ranks are a permutation of 0..p-1.
   for (int i = t; i < p; i += nt) {
     const double ti = A[i * lda + i];
+    const double ki = isnan(ti) ? -INFINITY : ti;
     int rank = 0;
     for (int j = 0; j < p; ++j) {
       const double tj = A[j * lda + j];
-      rank += (tj > ti) || (tj == ti && j < i);
+      const double kj = isnan(tj) ? -INFINITY : tj;
+      rank += (kj > ki) || (kj == ki && j < i);
     }
     theta[rank] = ti;
-    for (int row = 0; row < p; ++row) Z[row + (int64_t)rank * ldz] = VT[i * ldv + row];
+    perm[rank] = i;
   }
+  __syncthreads();
   for (int idx = t; idx < ldz * ldz; idx += nt) {
     const int row = idx % ldz, col = idx / ldz;
-    if (row >= p || col >= p) Z[idx] = (row == col) ? 1.0 : 0.0;
+    const int src = min(max(col < p ? perm[col] : 0, 0), p - 1);
+    Z[idx] = (row < p && col < p) ? VT[src * ldv + row] : (row == col ? 1.0 : 0.0);
   }
   if (t == 0 && info) {
     if (which == 1) {
@@ -376,20 +432,17 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ 
 
 void launch_chol_rinv(const double* G, int ldg, int p, double* Rinv, int ldr, int* deficient,
                       pf_info* info, int pass, hipStream_t st) {
-  const size_t lds = (size_t)p * (p + 1) * 8 + 3 * (size_t)p * 8 + (size_t)p * 4 + 16;
   // Pivots of the equilibrated Gram are squared sines of the angle between a
   // column and the span of the previous ones.  Below 1e-10 (angle < 1e-5)
   // the column is treated as dependent: CholeskyQR2 reaches working
   // orthogonality only while cond(Y) stays well below 1/sqrt(eps).
   const double tol = 1e-10;
   if (p <= 32) {
-    chol_rinv_kernel<32><<<1, 256, lds, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol);
+    chol_rinv_kernel<32><<<1, 64, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol);
   } else if (p <= 64) {
-    chol_rinv_kernel<64><<<1, 256, lds, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol);
+    chol_rinv_kernel<64><<<1, 256, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol);
   } else {
-    static size_t cur = 0;
-    ensure_lds((const void*)chol_rinv_kernel<128>, lds, cur);
-    chol_rinv_kernel<128><<<1, 256, lds, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol);
+    chol_rinv_kernel<128><<<1, 1024, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol);
   }
   PFX_HIP(hipGetLastError());
 }
@@ -398,7 +451,7 @@ static size_t jacobi_base_bytes(int p) {
   const int pe = (p + 1) & ~1;
   const int half = pe / 2;
   const int nblk = half * (half + 1) / 2;
-  return (size_t)pe * (pe + 1) * 8 + (size_t)half * (3 * 8 + 2 * 4) + (size_t)pe * 8 +
+  return (size_t)pe * (pe + 1) * 8 + (size_t)half * 3 * 8 + (size_t)pe * (8 + 4) +
          (size_t)((nblk + 1) & ~1) * 4;
 }
 
@@ -413,24 +466,28 @@ void launch_jacobi(const double* H, int ldh, int p, double* theta, double* Z, in
                    double* Zwork, pf_info* info, int which, int max_sweeps, hipStream_t st) {
   const size_t base = jacobi_base_bytes(p);
   const size_t lds = jacobi_lds_bytes(p);
-  const int v_in_lds = lds > base;
-  static size_t cur32 = 0, cur64 = 0, cur128 = 0;
+  const bool v_in_lds = lds > base;
+  static size_t cur32 = 0, cur64 = 0, cur128 = 0, cur128g = 0;
   // Rayleigh-Ritz: converge to FP64 resolution; pre-rotation: a rotation
   // accurate to 1e-10 keeps every FP32 recurrence column on its direction.
   const double tol_rel = which == 1 ? 1e-15 : 1e-10;
   const int fo = which == 0 ? 1 : 0;
   if (p <= 32) {
-    ensure_lds((const void*)jacobi_kernel<32>, lds, cur32);
-    jacobi_kernel<32><<<1, 256, lds, st>>>(H, ldh, p, theta, Z, ldz, Zwork, info, which, max_sweeps, tol_rel,
-                                           v_in_lds, fo);
+    ensure_lds((const void*)jacobi_kernel<32, true>, lds, cur32);
+    jacobi_kernel<32, true><<<1, 256, lds, st>>>(H, ldh, p, theta, Z, ldz, Zwork, info, which, max_sweeps,
+                                                 tol_rel, fo);
   } else if (p <= 64) {
-    ensure_lds((const void*)jacobi_kernel<64>, lds, cur64);
-    jacobi_kernel<64><<<1, 256, lds, st>>>(H, ldh, p, theta, Z, ldz, Zwork, info, which, max_sweeps, tol_rel,
-                                           v_in_lds, fo);
+    ensure_lds((const void*)jacobi_kernel<64, true>, lds, cur64);
+    jacobi_kernel<64, true><<<1, 256, lds, st>>>(H, ldh, p, theta, Z, ldz, Zwork, info, which, max_sweeps,
+                                                 tol_rel, fo);
+  } else if (v_in_lds) {
+    ensure_lds((const void*)jacobi_kernel<128, true>, lds, cur128);
+    jacobi_kernel<128, true><<<1, 256, lds, st>>>(H, ldh, p, theta, Z, ldz, Zwork, info, which, max_sweeps,
+                                                  tol_rel, fo);
   } else {
-    ensure_lds((const void*)jacobi_kernel<128>, lds, cur128);
-    jacobi_kernel<128><<<1, 256, lds, st>>>(H, ldh, p, theta, Z, ldz, Zwork, info, which, max_sweeps, tol_rel,
-                                            v_in_lds, fo);
+    ensure_lds((const void*)jacobi_kernel<128, false>, lds, cur128g);
+    jacobi_kernel<128, false><<<1, 256, lds, st>>>(H, ldh, p, theta, Z, ldz, Zwork, info, which, max_sweeps,
+                                                   tol_rel, fo);
   }
   PFX_HIP(hipGetLastError());
 }
