@@ -33,13 +33,16 @@ namespace {
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+typedef unsigned int uint2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int KSTEP = 32;
 
 struct FArgs {
-  const float* X; int64_t ldx;
+  const void* X; int64_t ldx;                          // K x M column-major, element type of XK
+  const float* xscale; int64_t ldsc; int tile;         // FP8: one scale per tile x tile block
   const uint16_t* Yp; int64_t ldy; int64_t yplane;   // 3 planes of K x N
   int64_t K, M, N;
   int64_t kchunk;
@@ -111,23 +114,37 @@ __device__ inline void store_out(const FArgs& a, int64_t row, int64_t col, float
 // stages of X and Y stream while one is consumed).  One __shared__ array per
 // stage keeps the compiler's LDS-DMA dependency tracking exact.
 //
-// X stage: ROWS columns of X x 32 K values, 16-byte chunk (col, kc) at
-// position col * 8 + (kc ^ (col & 7)) (the swizzle spreads the 16 lanes of a
-// ds_read_b128 over all banks).  Y stage: 3 planes x N columns x 32 K values,
-// chunk (q, j, kc) at ((q * N + j) * 4) + (kc ^ ((j >> 1) & 3)).
-template <int MB, int NB>
+// X element kinds.  F32: split exactly into three BF16 pieces in registers
+// (six MFMA cross terms).  BF16: used as stored (three MFMAs, one per Y
+// plane).  FP8 (OCP E4M3FN): decoded exactly to BF16 in registers, three
+// MFMAs per tile, then scaled by the FP32 scale of its tile x tile block.
+constexpr int XK_F32 = 0, XK_BF16 = 1, XK_FP8 = 2;
+
+// X stage: ROWS columns of X x 32 K values in 16-byte chunks, XCPC chunks
+// per column; chunk (col, kc) at col * XCPC + (kc ^ swizzle(col)), the
+// swizzle spreading the lanes of one LDS read over the banks.  Y stage:
+// 3 planes x N columns x 32 K values, chunk (q, j, kc) at
+// ((q * N + j) * 4) + (kc ^ ((j >> 1) & 3)).
+template <int XK, int MB, int NB>
 struct FCfg {
+  static constexpr int ES = XK == XK_F32 ? 4 : XK == XK_BF16 ? 2 : 1;   // bytes per X element
+  static constexpr int XCPC = KSTEP * ES / 16;    // X chunks per column and stage
+  static constexpr int EPC = 16 / ES;             // X elements per chunk
   static constexpr int ROWS = kWaves * 16 * MB;   // output rows (X columns) per workgroup
   static constexpr int N16 = 16 * NB;
-  static constexpr int XCH = ROWS * 8;            // 16-byte X chunks per stage
+  static constexpr int XCH = ROWS * XCPC;         // 16-byte X chunks per stage
   static constexpr int YCH = 3 * N16 * 4;         // 16-byte Y chunks per stage
   static constexpr int XOPS = XCH / kThreads;     // X wave-loads per wave per stage
+  static_assert(XOPS * kThreads == XCH, "X stage must be a whole number of wave-loads");
   static constexpr int YINSTR = YCH / 64;         // Y wave-loads per workgroup per stage
   static constexpr int YMAX = (YINSTR + kWaves - 1) / kWaves;
   // every wave issues YMAX Y loads; those past YINSTR repeat a valid chunk
   // into padding after the Y chunks, so the issue code has no branch
   static constexpr int STAGE = XCH + kWaves * YMAX * 64;
   static constexpr int OPS = XOPS + YMAX;         // loads each wave issues per stage
+  __device__ static int xswz(int col) {
+    return XK == XK_F32 ? (col & 7) : XK == XK_BF16 ? ((col >> 1) & 3) : ((col >> 2) & 1);
+  }
 };
 
 // The four stage buffers are file-scope LDS objects (sized for the largest
@@ -156,9 +173,9 @@ __device__ inline void wg_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-template <int MB, int NB>
+template <int XK, int MB, int NB>
 __global__ __launch_bounds__(kThreads, 1) void filter_bf16x6_kernel(FArgs a) {
-  using C = FCfg<MB, NB>;
+  using C = FCfg<XK, MB, NB>;
   static_assert(C::STAGE <= kStageChunks, "stage does not fit its LDS buffer");
   u4v* const st0 = g_st0;
   u4v* const st1 = g_st1;
@@ -178,13 +195,14 @@ __global__ __launch_bounds__(kThreads, 1) void filter_bf16x6_kernel(FArgs a) {
   const int64_t kend = min(a.K, kbeg + a.kchunk);
 
   // per-lane global bases of the stage loads (K offset added per stage)
-  const float* xsrc[C::XOPS];
+  // (byte pointers; stage k0 adds k0 * ES)
+  const unsigned char* xsrc[C::XOPS];
 #pragma unroll
   for (int u = 0; u < C::XOPS; ++u) {
     const int pos = (wave * C::XOPS + u) * 64 + lane;
-    const int col = pos >> 3, kc = (pos & 7) ^ (col & 7);
+    const int col = pos / C::XCPC, kc = (pos % C::XCPC) ^ C::xswz(col);
     const int64_t gcol = min(mt0 + col, a.M - 1);          // columns past M: any valid column
-    xsrc[u] = a.X + gcol * a.ldx + 4 * kc;
+    xsrc[u] = static_cast<const unsigned char*>(a.X) + (gcol * a.ldx + (int64_t)kc * C::EPC) * C::ES;
   }
   const uint16_t* ysrc[C::YMAX];
 #pragma unroll
@@ -199,7 +217,7 @@ __global__ __launch_bounds__(kThreads, 1) void filter_bf16x6_kernel(FArgs a) {
     u4v* ys = xs + C::XCH;
 #pragma unroll
     for (int u = 0; u < C::XOPS; ++u)
-      dma16(xsrc[u] + k0, xs + (wave * C::XOPS + u) * 64);
+      dma16(xsrc[u] + k0 * C::ES, xs + (wave * C::XOPS + u) * 64);
 #pragma unroll
     for (int u = 0; u < C::YMAX; ++u)
       dma16(ysrc[u] + k0, ys + (wave + kWaves * u) * 64);
@@ -211,33 +229,82 @@ __global__ __launch_bounds__(kThreads, 1) void filter_bf16x6_kernel(FArgs a) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4v{0, 0, 0, 0};
 
-  auto compute = [&](const u4v* xs, const u4v* ys) {
+  // per-stage scale of an FP8 tile: the workgroup's rows lie in one tile
+  // column (tile is a multiple of ROWS) and a stage in one tile row
+  auto xscale = [&](int64_t k0) -> float {
+    if constexpr (XK == XK_FP8) return a.xscale[k0 / a.tile + (mt0 / a.tile) * a.ldsc];
+    else return 1.0f;
+  };
+  auto compute = [&](const u4v* xs, const u4v* ys, float sc) {
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
       const int col = wave * (16 * MB) + 16 * mb + c;
-      const u4v lo = xs[col * 8 + ((2 * g) ^ (col & 7))];
-      const u4v hi = xs[col * 8 + ((2 * g + 1) ^ (col & 7))];
-      float xv[8];
+      if constexpr (XK == XK_F32) {
+        const u4v lo = xs[col * 8 + ((2 * g) ^ C::xswz(col))];
+        const u4v hi = xs[col * 8 + ((2 * g + 1) ^ C::xswz(col))];
+        float xv[8];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) { xv[i] = __uint_as_float(lo[i]); xv[4 + i] = __uint_as_float(hi[i]); }
-      u4v x1, x2, x3;
-      split8(xv, x1, x2, x3);
-      const bf8v a1 = as_bf8(x1), a2 = as_bf8(x2), a3 = as_bf8(x3);
+        for (int i = 0; i < 4; ++i) { xv[i] = __uint_as_float(lo[i]); xv[4 + i] = __uint_as_float(hi[i]); }
+        u4v x1, x2, x3;
+        split8(xv, x1, x2, x3);
+        const bf8v a1 = as_bf8(x1), a2 = as_bf8(x2), a3 = as_bf8(x3);
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int j = 16 * nb + c;
-        const int sw = g ^ ((j >> 1) & 3);
-        const bf8v b1 = as_bf8(ys[(0 * C::N16 + j) * 4 + sw]);
-        const bf8v b2 = as_bf8(ys[(1 * C::N16 + j) * 4 + sw]);
-        const bf8v b3 = as_bf8(ys[(2 * C::N16 + j) * 4 + sw]);
-        f4v cc = acc[mb][nb];
-        cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, b1, cc, 0, 0, 0);   // smallest terms first
-        cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b2, cc, 0, 0, 0);
-        cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b3, cc, 0, 0, 0);
-        cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b1, cc, 0, 0, 0);
-        cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b2, cc, 0, 0, 0);
-        cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, cc, 0, 0, 0);
-        acc[mb][nb] = cc;
+        for (int nb = 0; nb < NB; ++nb) {
+          const int j = 16 * nb + c;
+          const int sw = g ^ ((j >> 1) & 3);
+          const bf8v b1 = as_bf8(ys[(0 * C::N16 + j) * 4 + sw]);
+          const bf8v b2 = as_bf8(ys[(1 * C::N16 + j) * 4 + sw]);
+          const bf8v b3 = as_bf8(ys[(2 * C::N16 + j) * 4 + sw]);
+          f4v cc = acc[mb][nb];
+          cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, b1, cc, 0, 0, 0);   // smallest terms first
+          cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b2, cc, 0, 0, 0);
+          cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b3, cc, 0, 0, 0);
+          cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b1, cc, 0, 0, 0);
+          cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b2, cc, 0, 0, 0);
+          cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, cc, 0, 0, 0);
+          acc[mb][nb] = cc;
+        }
+      } else {
+        bf8v ax;
+        if constexpr (XK == XK_BF16) {
+          ax = as_bf8(xs[col * 4 + (g ^ C::xswz(col))]);
+        } else {
+          // eight E4M3 codes (half a chunk) -> exact BF16 via FP32
+          const uint2v* xh = reinterpret_cast<const uint2v*>(xs);
+          const uint2v q = xh[(col * 2 + ((g >> 1) ^ C::xswz(col))) * 2 + (g & 1)];
+          const f2v f0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)q[0], false);
+          const f2v f1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)q[0], true);
+          const f2v f2 = __builtin_amdgcn_cvt_pk_f32_fp8((int)q[1], false);
+          const f2v f3 = __builtin_amdgcn_cvt_pk_f32_fp8((int)q[1], true);
+          u4v w;
+          w[0] = __builtin_amdgcn_perm(__float_as_uint(f0[1]), __float_as_uint(f0[0]), 0x07060302u);
+          w[1] = __builtin_amdgcn_perm(__float_as_uint(f1[1]), __float_as_uint(f1[0]), 0x07060302u);
+          w[2] = __builtin_amdgcn_perm(__float_as_uint(f2[1]), __float_as_uint(f2[0]), 0x07060302u);
+          w[3] = __builtin_amdgcn_perm(__float_as_uint(f3[1]), __float_as_uint(f3[0]), 0x07060302u);
+          ax = as_bf8(w);
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int j = 16 * nb + c;
+          const int sw = g ^ ((j >> 1) & 3);
+          const bf8v b1 = as_bf8(ys[(0 * C::N16 + j) * 4 + sw]);
+          const bf8v b2 = as_bf8(ys[(1 * C::N16 + j) * 4 + sw]);
+          const bf8v b3 = as_bf8(ys[(2 * C::N16 + j) * 4 + sw]);
+          if constexpr (XK == XK_BF16) {
+            f4v cc = acc[mb][nb];
+            cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, b3, cc, 0, 0, 0);
+            cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, b2, cc, 0, 0, 0);
+            cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, b1, cc, 0, 0, 0);
+            acc[mb][nb] = cc;
+          } else {
+            f4v cc = f4v{0, 0, 0, 0};
+            cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, b3, cc, 0, 0, 0);
+            cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, b2, cc, 0, 0, 0);
+            cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, b1, cc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[mb][nb][r] = fmaf(sc, cc[r], acc[mb][nb][r]);
+          }
+        }
       }
     }
   };
@@ -256,8 +323,9 @@ __global__ __launch_bounds__(kThreads, 1) void filter_bf16x6_kernel(FArgs a) {
     // of stage st visible and frees the slot of stage st - 1
     wait_vmcnt<2 * C::OPS, 0>();
     wg_barrier();
+    const float sc = xscale(kbeg + st * KSTEP);
     issue(slot[(sl + 3) & 3], min(kbeg + (st + 3) * KSTEP, klast));
-    compute(slot[sl], slot[sl] + C::XCH);
+    compute(slot[sl], slot[sl] + C::XCH, sc);
   };
   if (nfull > 0) {
     issue(st0, kbeg);
@@ -283,14 +351,21 @@ __global__ __launch_bounds__(kThreads, 1) void filter_bf16x6_kernel(FArgs a) {
 #pragma unroll
     for (int u = 0; u < C::XOPS; ++u) {
       const int pos = (wave * C::XOPS + u) * 64 + lane;
-      const int col = pos >> 3, kc = (pos & 7) ^ (col & 7);
-      unsigned w[4];
+      const int col = pos / C::XCPC, kc = (pos % C::XCPC) ^ C::xswz(col);
+      unsigned char bytes[16];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t r = ktail + 4 * kc + i;
-        w[i] = r < kend ? __float_as_uint(xsrc[u][ktail + i]) : 0u;
+      for (int e = 0; e < C::EPC; ++e) {
+        const int64_t r = ktail + (int64_t)kc * C::EPC + e;   // K index of element e
+#pragma unroll
+        for (int bb = 0; bb < C::ES; ++bb)
+          bytes[e * C::ES + bb] = r < kend ? xsrc[u][(ktail + e) * C::ES + bb] : 0;
       }
-      st0[pos] = u4v{w[0], w[1], w[2], w[3]};
+      u4v w;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        w[i] = (unsigned)bytes[4 * i] | ((unsigned)bytes[4 * i + 1] << 8) | ((unsigned)bytes[4 * i + 2] << 16) |
+               ((unsigned)bytes[4 * i + 3] << 24);
+      st0[pos] = w;
     }
 #pragma unroll
     for (int u = 0; u < C::YMAX; ++u) {
@@ -310,7 +385,7 @@ __global__ __launch_bounds__(kThreads, 1) void filter_bf16x6_kernel(FArgs a) {
       st0[C::XCH + pos] = u4v{w[0], w[1], w[2], w[3]};
     }
     __syncthreads();
-    compute(st0, st0 + C::XCH);
+    compute(st0, st0 + C::XCH, xscale(ktail));
   }
   const int64_t m0 = mt0 + (int64_t)wave * (16 * MB);
 
@@ -399,12 +474,12 @@ FSplit fplan(int MB, int64_t K, int64_t M, int requested) {
   return sp;
 }
 
-template <int MB, int NB>
+template <int XK, int MB, int NB>
 void launch_f(FArgs& a, const FSplit& sp, int pm, int pr, hipStream_t st) {
   dim3 grid((unsigned)(sp.mtiles * sp.S), 1, 1);
   const bool prof = prof_enabled();
   if (prof && pm >= 0) prof_begin(pm, st);
-  filter_bf16x6_kernel<MB, NB><<<grid, kThreads, 0, st>>>(a);
+  filter_bf16x6_kernel<XK, MB, NB><<<grid, kThreads, 0, st>>>(a);
   PFX_HIP(hipGetLastError());
   if (prof && pm >= 0) prof_end(pm, st);
   if (sp.S > 1) {
@@ -416,39 +491,77 @@ void launch_f(FArgs& a, const FSplit& sp, int pm, int pr, hipStream_t st) {
   }
 }
 
-int mb_for(int NB) { return NB <= 4 ? 2 : 1; }
+// Rows per workgroup: two 16-row blocks per wave where the stage fits the
+// 32 KiB LDS slot (an FP32 X stage is twice a BF16 one).
+int mb_for(int xk, int NB) { return xk == XK_F32 && NB > 4 ? 1 : 2; }
+
+int xk_of(pf_dtype t) {
+  switch (t) {
+    case PF_F32: return XK_F32;
+    case PF_BF16: return XK_BF16;
+    case PF_F8E4M3: return XK_FP8;
+    default: fail(PF_ERR_UNSUPPORTED, "filter: X must be FP32, BF16 or FP8-E4M3 for FP32 work");
+  }
+  return XK_F32;
+}
+
+template <int XK>
+void launch_xk(FArgs& a, const FSplit& sp, int NB, int pm, int pr, hipStream_t st) {
+  if constexpr (XK == XK_F32) {
+    switch (NB) {
+      case 1: launch_f<XK, 2, 1>(a, sp, pm, pr, st); break;
+      case 2: launch_f<XK, 2, 2>(a, sp, pm, pr, st); break;
+      case 3: launch_f<XK, 2, 3>(a, sp, pm, pr, st); break;
+      case 4: launch_f<XK, 2, 4>(a, sp, pm, pr, st); break;
+      case 5: launch_f<XK, 1, 5>(a, sp, pm, pr, st); break;
+      case 6: launch_f<XK, 1, 6>(a, sp, pm, pr, st); break;
+      case 7: launch_f<XK, 1, 7>(a, sp, pm, pr, st); break;
+      default: launch_f<XK, 1, 8>(a, sp, pm, pr, st); break;
+    }
+  } else {
+    switch (NB) {
+      case 1: launch_f<XK, 2, 1>(a, sp, pm, pr, st); break;
+      case 2: launch_f<XK, 2, 2>(a, sp, pm, pr, st); break;
+      case 3: launch_f<XK, 2, 3>(a, sp, pm, pr, st); break;
+      case 4: launch_f<XK, 2, 4>(a, sp, pm, pr, st); break;
+      case 5: launch_f<XK, 2, 5>(a, sp, pm, pr, st); break;
+      case 6: launch_f<XK, 2, 6>(a, sp, pm, pr, st); break;
+      case 7: launch_f<XK, 2, 7>(a, sp, pm, pr, st); break;
+      default: launch_f<XK, 2, 8>(a, sp, pm, pr, st); break;
+    }
+  }
+}
 
 }  // namespace
 
-size_t filter_bf16x6_part_bytes(int64_t K, int64_t M, int64_t N) {
+size_t filter_bf16x6_part_bytes(pf_dtype xdt, int64_t K, int64_t M, int64_t N) {
   const int NB = (int)(N / 16);
-  const FSplit sp = fplan(mb_for(NB), K, M, 0);
+  const FSplit sp = fplan(mb_for(xk_of(xdt), NB), K, M, 0);
   return sp.S > 1 ? (size_t)sp.S * sp.ldp * N * sizeof(float) : 0;
 }
 
 void filter_bf16x6(const FilterArgs& x, hipStream_t st) {
   if (x.N % 16 != 0 || x.N <= 0 || x.N > 128) fail(PF_ERR_ARG, "filter: N must be 16..128, multiple of 16");
+  const int xk = xk_of(x.xdtype);
+  if (xk == XK_FP8 && (x.xscale == nullptr || x.tile <= 0 || x.tile % 128 != 0))
+    fail(PF_ERR_ARG, "filter: FP8 X needs tile scales with a tile that is a multiple of 128");
   const int NB = (int)(x.N / 16);
-  const int MB = mb_for(NB);
+  const int MB = mb_for(xk, NB);
   FSplit sp = fplan(MB, x.K, x.M, x.splitk);
   while (sp.S > 1 && (size_t)sp.S * sp.ldp * x.N * sizeof(float) > x.part_bytes) sp = fplan(MB, x.K, x.M, sp.S - 1);
   FArgs a;
   a.X = x.X; a.ldx = x.ldx;
+  a.xscale = x.xscale; a.ldsc = x.ldsc; a.tile = x.tile;
   a.Yp = x.Yp; a.ldy = x.ldy; a.yplane = x.yplane;
   a.K = x.K; a.M = x.M; a.N = x.N; a.kchunk = sp.kchunk;
   a.out = x.out; a.ldo = x.ldo; a.D1 = x.D1; a.D2 = x.D2; a.ldd = x.ldd;
   a.alpha = (float)x.alpha; a.beta = (float)x.beta; a.gamma = (float)x.gamma;
   a.outp = x.outp; a.ldop = x.ldop; a.oplane = x.oplane;
   a.part = static_cast<float*>(x.part); a.ldp = sp.ldp; a.splitk = sp.S;
-  switch (NB) {
-    case 1: launch_f<2, 1>(a, sp, x.prof_main, x.prof_reduce, st); break;
-    case 2: launch_f<2, 2>(a, sp, x.prof_main, x.prof_reduce, st); break;
-    case 3: launch_f<2, 3>(a, sp, x.prof_main, x.prof_reduce, st); break;
-    case 4: launch_f<2, 4>(a, sp, x.prof_main, x.prof_reduce, st); break;
-    case 5: launch_f<1, 5>(a, sp, x.prof_main, x.prof_reduce, st); break;
-    case 6: launch_f<1, 6>(a, sp, x.prof_main, x.prof_reduce, st); break;
-    case 7: launch_f<1, 7>(a, sp, x.prof_main, x.prof_reduce, st); break;
-    default: launch_f<1, 8>(a, sp, x.prof_main, x.prof_reduce, st); break;
+  switch (xk) {
+    case XK_F32: launch_xk<XK_F32>(a, sp, NB, x.prof_main, x.prof_reduce, st); break;
+    case XK_BF16: launch_xk<XK_BF16>(a, sp, NB, x.prof_main, x.prof_reduce, st); break;
+    default: launch_xk<XK_FP8>(a, sp, NB, x.prof_main, x.prof_reduce, st); break;
   }
 }
 

@@ -68,7 +68,8 @@ size_t contract_part_bytes(int64_t K, int64_t M, int64_t N, Elem ta, Elem tb, bo
 // registers, Y as three BF16 planes, six cross terms):
 // out = alpha X^T Y + beta D1 + gamma D2, optionally also the planes of out.
 struct FilterArgs {
-  const float* X; int64_t ldx;
+  const void* X; int64_t ldx; pf_dtype xdtype = PF_F32;   // F32, BF16 or F8E4M3 (K x M column-major)
+  const float* xscale = nullptr; int64_t ldsc = 0; int tile = 0;   // FP8 tile scales
   const uint16_t* Yp; int64_t ldy; int64_t yplane;
   int64_t K, M, N;
   float* out; int64_t ldo;
@@ -80,7 +81,7 @@ struct FilterArgs {
   int prof_main = -1, prof_reduce = -1;
 };
 void filter_bf16x6(const FilterArgs& a, hipStream_t st);
-size_t filter_bf16x6_part_bytes(int64_t K, int64_t M, int64_t N);
+size_t filter_bf16x6_part_bytes(pf_dtype xdt, int64_t K, int64_t M, int64_t N);
 void launch_split_planes(const float* src, int64_t lds, int64_t n, int p, uint16_t* dst, int64_t ldd,
                          int64_t plane, int64_t n_pad, int p_pad, hipStream_t st);
 

@@ -96,7 +96,8 @@ Layout layout_for(const pf_desc& d) {
   part = std::max(part, contract_part_bytes(d.n, d.n, p_pad, Elem::F64, Elem::F64, true, 0));
   part = std::max(part, contract_part_bytes(d.n, p_pad, p_pad, work, work, true, 0));
   part = std::max(part, contract_part_bytes(d.n, p_pad, p_pad, work, Elem::F64, true, 0));
-  if (work == Elem::F32) part = std::max(part, filter_bf16x6_part_bytes(d.n, d.n, p_pad));
+  if (work == Elem::F32)
+    for (pf_dtype xt : {PF_F32, PF_BF16, PF_F8E4M3}) part = std::max(part, filter_bf16x6_part_bytes(xt, d.n, d.n, p_pad));
   L.part_bytes = align256(part);
   L.off_part = o; o += L.part_bytes;
   L.total = o;
@@ -105,7 +106,7 @@ Layout layout_for(const pf_desc& d) {
 
 bool elem_ok_for_filter(const pf_desc& d, pf_dtype t) {
   if (d.work == PF_F64) return t == PF_F64;
-  return t == PF_F32;
+  return t == PF_F32 || t == PF_BF16 || t == PF_F8E4M3;
 }
 
 void check_mat(const pf_mat* M, const char* name, int64_t rows) {
@@ -152,9 +153,13 @@ void plan_validate(const pf_desc& d, const pf_mat* Xf, const pf_mat* Xr) {
   if (Xf || Xr) {
     check_mat(Xf, "X_filter", d.n);
     check_mat(Xr, "X_rr", d.n);
-    if (Xf->dtype == PF_BF16 || Xf->dtype == PF_F8E4M3)
-      fail(PF_ERR_UNSUPPORTED, "BF16 / FP8 filter operands are not implemented in this build");
     if (!elem_ok_for_filter(d, Xf->dtype)) fail(PF_ERR_ARG, "X_filter dtype does not match pf_desc.work");
+    if ((Xf->dtype == PF_BF16 || Xf->dtype == PF_F8E4M3) && (d.flags & PF_FLAG_NATIVE_F32))
+      fail(PF_ERR_ARG, "PF_FLAG_NATIVE_F32 needs an FP32 X_filter");
+    if (Xf->dtype == PF_F8E4M3 && (!Xf->tile_scale || Xf->tile <= 0 || Xf->tile % 128 != 0))
+      fail(PF_ERR_ARG, "an FP8 X_filter needs tile_scale with a tile that is a positive multiple of 128");
+    if (Xr->dtype == PF_BF16 || Xr->dtype == PF_F8E4M3)
+      fail(PF_ERR_ARG, "X_rr must be F32 or F64 (Rayleigh-Ritz runs on the unquantised matrix)");
     if (d.work == PF_F64 && Xr->dtype != PF_F64) fail(PF_ERR_ARG, "work F64 needs an F64 X_rr");
     if (d.work == PF_F32 && Xr->dtype != PF_F32) fail(PF_ERR_ARG, "work F32 needs an F32 X_rr");
   }
@@ -270,7 +275,10 @@ void filter_product(Plan* P, const pf_mat& Xf, const void* y, void* out, const v
   const int64_t ld = P->n_pad;
   if (split) {
     FilterArgs f;
-    f.X = static_cast<const float*>(Xf.data); f.ldx = Xf.ld;
+    f.X = Xf.data; f.ldx = Xf.ld; f.xdtype = Xf.dtype;
+    if (Xf.dtype == PF_F8E4M3) {
+      f.xscale = Xf.tile_scale; f.tile = Xf.tile; f.ldsc = (P->n + Xf.tile - 1) / Xf.tile;
+    }
     f.Yp = planes_of(P, y); f.ldy = ld; f.yplane = P->plane;
     f.K = P->n; f.M = P->n; f.N = P->p_pad;
     f.out = static_cast<float*>(out); f.ldo = ld;

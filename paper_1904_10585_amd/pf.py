@@ -134,6 +134,12 @@ def ld_of(t):
 
 
 def mat(t, tile_scale=None, tile=128):
+    """pf_mat of a column-major device tensor.  A (tensor, tile_scale, tile)
+    tuple or an existing PfMat is accepted too (FP8 operands)."""
+    if isinstance(t, PfMat):
+        return t
+    if isinstance(t, tuple):
+        return mat(*t)
     m = PfMat()
     m.data = t.data_ptr()
     m.dtype = dtype_of(t)

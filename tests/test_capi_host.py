@@ -111,7 +111,8 @@ def fake_mat(ptr=0x10000, dtype=pf.PF_F32, ld=256):
 
 
 @pytest.mark.parametrize("case", ["null_x", "null_rr", "short_ld", "misaligned", "bad_ld_bytes", "dtype",
-                                  "rr_dtype", "null_u", "short_ldu", "null_theta", "f64_rr", "bf16"])
+                                  "rr_dtype", "null_u", "short_ldu", "null_theta", "f64_rr", "fp8_noscale",
+                                  "fp8_tile", "rr_bf16", "native_bf16"])
 def test_extract_rejects_before_launch(case):
     d = good_desc()
     xf, xr = fake_mat(), fake_mat()
@@ -139,9 +140,15 @@ def test_extract_rejects_before_launch(case):
         theta = None
     elif case == "f64_rr":
         xr.dtype = pf.PF_F64
-    elif case == "bf16":
+    elif case == "fp8_noscale":
+        xf.dtype = pf.PF_F8E4M3
+    elif case == "fp8_tile":
+        xf.dtype, xf.tile_scale, xf.tile = pf.PF_F8E4M3, 0x40000, 64
+    elif case == "rr_bf16":
+        xr.dtype = pf.PF_BF16
+    elif case == "native_bf16":
         xf.dtype = pf.PF_BF16
-        want = pf.PF_ERR_UNSUPPORTED
+        d.flags = pf.PF_FLAG_NATIVE_F32
     assert _extract_raw(d, xf, xr, U, ldu, theta) == want
     assert pf.last_error()
 

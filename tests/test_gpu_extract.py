@@ -245,3 +245,80 @@ def test_psd_dense_matches_oracle():
     pf.pf_psd_dense(Vd, thd, n, p, pf.PF_F64, out)
     torch.cuda.synchronize()
     np.testing.assert_allclose(out.cpu().numpy(), oracle.psd_projection(V, th), atol=1e-12)
+
+
+def quantized_operand(X32, kind, tile=128):
+    """Device copy of an FP32 matrix quantised by pf_quantize (the library's
+    own a0 step), its pf_mat argument, and the dequantised matrix in FP64
+    from the oracle's quantiser."""
+    pf = pf_module()
+    n = X32.shape[0]
+    src = device_matrix(X32, torch.float32)
+    ldq = -(-n // 16) * 16                        # 16-byte columns for every dtype
+    if kind == "bf16":
+        dst = pf.colmajor(n, n, torch.bfloat16, "cuda", ld=ldq)
+        pf.pf_quantize(dst, None, 0, pf.PF_BF16, src)
+        m = pf.mat(dst)
+        deq = oracle.bf16_round(X32.astype(np.float64))
+        keep = (dst, src)
+    else:
+        dst = pf.colmajor(n, n, torch.uint8, "cuda", ld=ldq)
+        tm = -(-n // tile)
+        scales = torch.zeros((tm, tm), dtype=torch.float32, device="cuda").t()
+        pf.pf_quantize(dst, scales, tile, pf.PF_F8E4M3, src)
+        m = pf.mat(dst, scales, tile)
+        codes, sc = oracle.fp8_tile_quantize(X32, tile)
+        deq = oracle.fp8_tile_dequantize(codes, sc, tile)
+        keep = (dst, src, scales)
+    torch.cuda.synchronize()
+    return m, deq, keep
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+@pytest.mark.parametrize("n,p,d", [(1000, 48, 4), (777, 16, 3), (2100, 128, 2), (1030, 96, 5)])
+def test_quantized_filter_same_math(kind, n, p, d):
+    """Filter on the BF16 / FP8 copy of X, Rayleigh-Ritz on the FP32 X:
+    parity with the oracle fed the dequantised copy for the filter and the
+    FP32 X for Rayleigh-Ritz, at the FP32 tolerances; the error against the
+    oracle on the unquantised X (the quantisation floor) is printed."""
+    pf = pf_module()
+    r = max(1, p // 2)
+    X, lam, Q = wl.planted(n, r, (4.0, 10.0), (-1.0, 0.5), config=97, index=n * 1000 + p)
+    U = wl.start_block(n, p, config=97, index=n + p)
+    a, b = -1.0, 0.5
+    for _ in range(3):
+        U = oracle.extract(X, X, U, 6, a, b)["V"]
+    X32 = X.astype(np.float32).astype(np.float64)
+    U32 = U.astype(np.float32).astype(np.float64)
+    Xf, deq, keep = quantized_operand(X32.astype(np.float32), kind)
+    ref = oracle.extract(deq, X32, U32, d, a, b)
+    floor_ref = oracle.extract(X32, X32, U32, d, a, b)
+    Xr = device_matrix(X32, torch.float32)
+    Ud = device_matrix(U32, torch.float32)
+    theta = torch.zeros(p, dtype=torch.float64, device="cuda")
+    info = torch.zeros(8, dtype=torch.int32, device="cuda")
+    pf.pf_extract(pf.desc(n, p, d, a, b, work=pf.PF_F32), Xf, Xr, Ud, theta, info)
+    torch.cuda.synchronize()
+    assert int(info[0]) == 0, int(info[0])
+    th, V = theta.cpu().numpy(), Ud.cpu().double().numpy()
+    rel, sin = compare(th, V, ref, r)
+    frel, fsin = compare(th, V, floor_ref, r)
+    print(f"{kind} n={n} p={p} d={d}: same-math rel {rel:.2e} sin {sin:.2e}; "
+          f"vs unquantised rel {frel:.2e} sin {fsin:.2e}")
+    assert rel <= 1e-5 and sin <= 1e-4, (rel, sin)
+
+
+def test_fp8_operand_checks():
+    """An FP8 filter operand without scales, or with a tile that is not a
+    multiple of 128, is an argument error raised before any work."""
+    pf = pf_module()
+    n, p = 256, 16
+    X = np.eye(n, dtype=np.float32)
+    Xr = device_matrix(X, torch.float32)
+    Ud = device_matrix(np.ones((n, p), np.float32), torch.float32)
+    codes = pf.colmajor(n, n, torch.uint8, "cuda")
+    theta = torch.zeros(p, dtype=torch.float64, device="cuda")
+    for m in (pf.mat(codes), pf.mat(codes, torch.ones((2, 2), device="cuda"), 64)):
+        with pytest.raises(pf.PfError) as e:
+            pf.pf_extract(pf.desc(n, p, 3, -1.0, 0.5, work=pf.PF_F32), m, Xr, Ud, theta)
+        assert e.value.status == pf.PF_ERR_ARG
