@@ -86,6 +86,13 @@ typedef enum pf_op {
                                      pipe instead of the default exact
                                      three-way BF16 split (six BF16 MFMA
                                      cross terms, FP32 accumulation) */
+#define PF_FLAG_OPERATOR_UNCHANGED 0x10u /* PF_OP_GRAM: X_filter / X_rr hold the
+                                     same values as in the previous call on
+                                     this stream (or session) with the same
+                                     buffers, so the library may reuse its
+                                     transposed copies of M instead of
+                                     rebuilding them (a fixed M over a chain
+                                     of extractions) */
 #define PF_FLAG_COLD 0x4u         /* the start block is not a warm start:
                                      every second step the pair (Y_k, Y_{k-1})
                                      is multiplied by the same R^{-1} from a
@@ -94,6 +101,16 @@ typedef enum pf_op {
                                      acting column by column) leaves the span
                                      of the result unchanged.  Sessions set it
                                      on their first step. */
+
+/* PF_OP_GRAM (section 5.2.1): X_filter and X_rr are M, m-by-n column-major.
+ * Every filter product A Y is T = M Y followed by M^T T (the Chebyshev
+ * epilogue fused into the second); the products over the n columns of M read
+ * a transposed copy of M that the library builds in device memory it owns
+ * (n x m in the dtype of the operand, allocated on first use, rebuilt on each
+ * call unless PF_FLAG_OPERATOR_UNCHANGED).  Rayleigh-Ritz forms B = M Q and
+ * H = B^T B in FP64: theta_i = sigma_i^2, V the right Ritz vectors.  With a
+ * large spectrum (sigma^2 up to 1e8 at the 12000 x 6000 workload) the
+ * recurrence needs PF_FLAG_SCALED with spec_ub >= sigma_max^2. */
 
 /* A matrix operand.  data: device pointer; rows/cols implied by the call;
  * ld: leading dimension in elements (>= rows; a multiple of 16 bytes /

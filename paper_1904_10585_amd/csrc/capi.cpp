@@ -42,14 +42,14 @@ pf_status guarded(F&& f) {
 
 // pf_extract workspaces: one per (device, stream, shape); calls on one
 // stream are ordered, so a workspace is never used by two extractions at once.
-using PlanKey = std::tuple<int, uintptr_t, int64_t, int, int, int, int, int>;
+using PlanKey = std::tuple<int, uintptr_t, int64_t, int64_t, int, int, int, int, int>;
 std::mutex g_plans_mu;
 std::map<PlanKey, Plan*> g_plans;
 
 Plan* cached_plan(const pf_desc& d, hipStream_t st) {
   int dev = 0;
   PFX_HIP(hipGetDevice(&dev));
-  PlanKey key{dev, (uintptr_t)st, d.n, d.p, (int)d.work, (int)d.op, d.degree, d.q};
+  PlanKey key{dev, (uintptr_t)st, d.n, d.op == PF_OP_GRAM ? d.m : 0, d.p, (int)d.work, (int)d.op, d.degree, d.q};
   std::lock_guard<std::mutex> lk(g_plans_mu);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) {

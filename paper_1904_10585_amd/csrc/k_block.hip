@@ -246,6 +246,27 @@ void apply_t(const ApplyArgs& a, hipStream_t st) {
   PFX_HIP(hipGetLastError());
 }
 
+// dst = src^T for a rows x cols column-major matrix (element type T), in
+// 64 x 64 tiles through LDS: reads and writes both run along columns.
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ src, int64_t lds_, int64_t rows,
+                                                        int64_t cols, T* __restrict__ dst, int64_t ldd) {
+  __shared__ T tile[64][65];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t i = i0 + tx, j = j0 + ty + 4 * r;
+    if (i < rows && j < cols) tile[ty + 4 * r][tx] = src[i + j * lds_];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t j = j0 + tx, i = i0 + ty + 4 * r;      // dst row j, column i
+    if (i < rows && j < cols) dst[j + i * ldd] = tile[tx][ty + 4 * r];
+  }
+}
+
 }  // namespace
 
 void launch_apply(const ApplyArgs& a, hipStream_t st) {
@@ -322,6 +343,31 @@ void launch_psd_dense(const void* V, int64_t ldv, Elem t, const double* theta, i
   else
     psd_dense_kernel<float><<<grid, 256, 0, st>>>(static_cast<const float*>(V), ldv, theta, n, p,
                                                   static_cast<float*>(out), ldo);
+  PFX_HIP(hipGetLastError());
+}
+
+void launch_transpose(const void* src, int64_t lds_, int64_t rows, int64_t cols, int esize, void* dst,
+                      int64_t ldd, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return;
+  dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((cols + 63) / 64));
+  switch (esize) {
+    case 8:
+      transpose_kernel<double><<<grid, 256, 0, st>>>(static_cast<const double*>(src), lds_, rows, cols,
+                                                     static_cast<double*>(dst), ldd);
+      break;
+    case 4:
+      transpose_kernel<float><<<grid, 256, 0, st>>>(static_cast<const float*>(src), lds_, rows, cols,
+                                                    static_cast<float*>(dst), ldd);
+      break;
+    case 2:
+      transpose_kernel<uint16_t><<<grid, 256, 0, st>>>(static_cast<const uint16_t*>(src), lds_, rows, cols,
+                                                       static_cast<uint16_t*>(dst), ldd);
+      break;
+    default:
+      transpose_kernel<uint8_t><<<grid, 256, 0, st>>>(static_cast<const uint8_t*>(src), lds_, rows, cols,
+                                                      static_cast<uint8_t*>(dst), ldd);
+      break;
+  }
   PFX_HIP(hipGetLastError());
 }
 

@@ -128,6 +128,9 @@ void launch_quantize_bf16(const float* src, int64_t rows, int64_t cols, int64_t 
                           uint16_t* dst, int64_t ldd, hipStream_t st);
 void launch_quantize_fp8(const float* src, int64_t rows, int64_t cols, int64_t lds,
                          uint8_t* dst, int64_t ldd, float* scales, int tile, hipStream_t st);
+// dst (cols x rows, ld ldd) = src^T (src rows x cols, ld lds), esize 1/2/4/8.
+void launch_transpose(const void* src, int64_t lds, int64_t rows, int64_t cols, int esize, void* dst,
+                      int64_t ldd, hipStream_t st);
 void launch_psd_dense(const void* V, int64_t ldv, Elem t, const double* theta, int64_t n, int p,
                       void* out, int64_t ldo, hipStream_t st);
 

@@ -9,6 +9,11 @@
 //   CholeskyQR2: G = Y^T Y, R = chol(G), Q = Y R^{-1}, twice
 //   Rayleigh-Ritz: W = X_rr Q (FP64), H = Q^T W, H = Z Theta Z^T, V = Q Z
 //
+// For A = M^T M (PF_OP_GRAM, the SVD route of section 5.2.1) every product
+// A Y is T = M Y followed by M^T T, and Rayleigh-Ritz runs on B = M Q:
+// H = B^T B = Q^T A Q, theta = sigma^2.  The products contracting over the
+// columns of M read a transposed copy of M (K contiguous for the MFMA).
+//
 // tau_k = T_k(s_ref) rescales the recurrence (PF_FLAG_SCALED); with tau = 1
 // it is the plain three-term recurrence of eq. cheby-recursion-map.  The
 // pre-rotation replaces U by its Ritz basis for the current matrix, which
@@ -49,12 +54,25 @@ struct Plan {
   pf_info* info;
   void* part;
   size_t part_bytes;
+  // PF_OP_GRAM: M is m x n
+  int64_t m = 0, m_pad = 0;
+  void* T = nullptr;            // M Y (m x p, work dtype)
+  uint16_t* Tpl = nullptr;      // its BF16 planes (split path)
+  int64_t tplane = 0;
+  double* B = nullptr;          // M Q (m x p, FP64) for Rayleigh-Ritz
+  // transposed copies of the operators (n x m), allocated on first use
+  struct Copy {
+    void* data = nullptr; size_t bytes = 0; int64_t ld = 0;
+    float* scale = nullptr; size_t scale_bytes = 0;
+    const void* src = nullptr; pf_dtype dt = PF_F32; int64_t src_ld = 0; const float* src_scale = nullptr;
+    int tile = 0;
+  } mft, mrt;
 };
 
 namespace {
 
 struct Layout {
-  size_t off_Up, off_Ypl[3];
+  size_t off_Up, off_Ypl[3], off_T = 0, off_Tpl = 0, off_B = 0;
   size_t off_U, off_Z, off_Y[3], off_Q1, off_Q, off_W, off_G, off_Rinv, off_Zeig, off_Zwork, off_theta,
       off_theta_pre, off_def, off_info, off_part, total, part_bytes;
 };
@@ -88,9 +106,30 @@ Layout layout_for(const pf_desc& d) {
   const size_t planes = align256((size_t)3 * n_pad * p_pad * 2);
   L.off_Up = o; o += (work == Elem::F32) ? planes : 0;
   for (int i = 0; i < 3; ++i) { L.off_Ypl[i] = o; o += (work == Elem::F32) ? planes : 0; }
+  const bool gram = d.op == PF_OP_GRAM;
+  const int64_t m_pad = gram ? round_up(d.m, 64) : 0;
+  if (gram) {
+    L.off_T = o; o += align256((size_t)m_pad * p_pad * esz);
+    L.off_Tpl = o; o += (work == Elem::F32) ? align256((size_t)3 * m_pad * p_pad * 2) : 0;
+    L.off_B = o; o += align256((size_t)m_pad * p_pad * 8);
+  }
   // split-K slabs: the largest any contraction of the sequence asks for
   const Elem xf = work;   // filter operand type (same as work in these forms)
   size_t part = 0;
+  if (gram) {
+    for (Elem ta : {work, Elem::F32, Elem::F64}) {
+      part = std::max(part, contract_part_bytes(d.n, d.m, p_pad, ta, work, true, 0));
+      part = std::max(part, contract_part_bytes(d.m, d.n, p_pad, ta, work, true, 0));
+      part = std::max(part, contract_part_bytes(d.n, d.m, p_pad, ta, work, false, 0));
+      part = std::max(part, contract_part_bytes(d.m, d.n, p_pad, ta, work, false, 0));
+    }
+    part = std::max(part, contract_part_bytes(d.m, p_pad, p_pad, Elem::F64, Elem::F64, true, 0));
+    if (work == Elem::F32)
+      for (pf_dtype xt : {PF_F32, PF_BF16, PF_F8E4M3}) {
+        part = std::max(part, filter_bf16x6_part_bytes(xt, d.n, d.m, p_pad));
+        part = std::max(part, filter_bf16x6_part_bytes(xt, d.m, d.n, p_pad));
+      }
+  }
   part = std::max(part, contract_part_bytes(d.n, d.n, p_pad, xf, work, work == Elem::F64, 0));
   part = std::max(part, contract_part_bytes(d.n, d.n, p_pad, Elem::F32, work, true, 0));
   part = std::max(part, contract_part_bytes(d.n, d.n, p_pad, Elem::F64, Elem::F64, true, 0));
@@ -137,8 +176,8 @@ void host_coefficients(const pf_desc& d, std::vector<double>& tau) {
 void plan_validate(const pf_desc& d, const pf_mat* Xf, const pf_mat* Xr) {
   if (d.struct_size != sizeof(pf_desc)) fail(PF_ERR_ARG, "pf_desc.struct_size does not match this library");
   if (d.op != PF_OP_SYM && d.op != PF_OP_GRAM) fail(PF_ERR_ARG, "pf_desc.op is not a pf_op value");
-  if (d.op == PF_OP_GRAM) fail(PF_ERR_UNSUPPORTED, "PF_OP_GRAM is not implemented in this build");
   if (d.n < 1) fail(PF_ERR_ARG, "pf_desc.n must be >= 1");
+  if (d.op == PF_OP_GRAM && d.m < 1) fail(PF_ERR_ARG, "pf_desc.m must be >= 1 for PF_OP_GRAM");
   if (d.p < 1 || d.p > 128 || d.p > d.n) fail(PF_ERR_ARG, "pf_desc.p must satisfy 1 <= p <= min(n, 128)");
   if (d.degree < 1) fail(PF_ERR_ARG, "pf_desc.degree must be >= 1");
   if (d.q < 1) fail(PF_ERR_ARG, "pf_desc.q must be >= 1");
@@ -147,12 +186,14 @@ void plan_validate(const pf_desc& d, const pf_mat* Xf, const pf_mat* Xr) {
   if (d.work != PF_F32 && d.work != PF_F64) fail(PF_ERR_ARG, "pf_desc.work must be PF_F32 or PF_F64");
   if ((d.flags & PF_FLAG_SCALED) && !(std::isfinite(d.spec_ub) && d.spec_ub > d.b))
     fail(PF_ERR_ARG, "PF_FLAG_SCALED needs a finite spec_ub > b");
-  if (d.flags & ~(PF_FLAG_NO_PREROTATE | PF_FLAG_SCALED | PF_FLAG_COLD | PF_FLAG_NATIVE_F32))
+  if (d.flags & ~(PF_FLAG_NO_PREROTATE | PF_FLAG_SCALED | PF_FLAG_COLD | PF_FLAG_NATIVE_F32 |
+                  PF_FLAG_OPERATOR_UNCHANGED))
     fail(PF_ERR_ARG, "unknown bits in pf_desc.flags");
   if (d.max_sweeps < 0) fail(PF_ERR_ARG, "pf_desc.max_sweeps must be >= 0");
   if (Xf || Xr) {
-    check_mat(Xf, "X_filter", d.n);
-    check_mat(Xr, "X_rr", d.n);
+    const int64_t rows = d.op == PF_OP_GRAM ? d.m : d.n;
+    check_mat(Xf, "X_filter", rows);
+    check_mat(Xr, "X_rr", rows);
     if (!elem_ok_for_filter(d, Xf->dtype)) fail(PF_ERR_ARG, "X_filter dtype does not match pf_desc.work");
     if ((Xf->dtype == PF_BF16 || Xf->dtype == PF_F8E4M3) && (d.flags & PF_FLAG_NATIVE_F32))
       fail(PF_ERR_ARG, "PF_FLAG_NATIVE_F32 needs an FP32 X_filter");
@@ -213,12 +254,24 @@ Plan* plan_create(const pf_desc& d) {
   for (int i = 0; i < 3; ++i)
     P->Ypl[i] = P->work == Elem::F32 ? reinterpret_cast<uint16_t*>(b + L.off_Ypl[i]) : nullptr;
   P->part_bytes = L.part_bytes;
+  if (d.op == PF_OP_GRAM) {
+    P->m = d.m;
+    P->m_pad = round_up(d.m, 64);
+    P->T = b + L.off_T;
+    P->Tpl = P->work == Elem::F32 ? reinterpret_cast<uint16_t*>(b + L.off_Tpl) : nullptr;
+    P->tplane = P->m_pad * P->p_pad;
+    P->B = reinterpret_cast<double*>(b + L.off_B);
+  }
   return P;
 }
 
 void plan_destroy(Plan* P) {
   if (!P) return;
   if (P->mem) (void)hipFree(P->mem);
+  for (Plan::Copy* c : {&P->mft, &P->mrt}) {
+    if (c->data) (void)hipFree(c->data);
+    if (c->scale) (void)hipFree(c->scale);
+  }
   delete P;
 }
 
@@ -266,6 +319,70 @@ void refresh_planes(Plan* P, const void* y, hipStream_t st) {
                       P->n_pad, P->p_pad, st);
 }
 
+size_t esize_of(pf_dtype t) { return t == PF_F64 ? 8 : t == PF_F32 ? 4 : t == PF_BF16 ? 2 : 1; }
+
+// Transposed copy (n x m, ld = n rounded up to 64 elements) of an m x n operand,
+// with the transposed tile-scale grid for FP8.  Rebuilt on every call unless
+// PF_FLAG_OPERATOR_UNCHANGED is set and the same buffer was copied last time.
+void ensure_copy(Plan* P, Plan::Copy& c, const pf_mat& M, hipStream_t st) {
+  const bool same = c.data && c.src == M.data && c.dt == M.dtype && c.src_ld == M.ld &&
+                    c.src_scale == M.tile_scale && c.tile == (M.dtype == PF_F8E4M3 ? M.tile : 0);
+  if (same && (P->d.flags & PF_FLAG_OPERATOR_UNCHANGED)) return;
+  const size_t es = esize_of(M.dtype);
+  const int64_t ld = round_up(P->n, 64);          // the copy is n x m: n rows
+  const size_t bytes = (size_t)ld * P->m * es;
+  if (c.bytes < bytes) {
+    if (c.data) (void)hipFree(c.data);
+    c.data = nullptr;
+    c.bytes = 0;
+    if (hipMalloc(&c.data, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(PF_ERR_NOMEM, "hipMalloc of the transposed operator copy failed");
+    }
+    c.bytes = bytes;
+  }
+  c.ld = ld;
+  launch_transpose(M.data, M.ld, P->m, P->n, (int)es, c.data, ld, st);
+  c.tile = 0;
+  if (M.dtype == PF_F8E4M3) {
+    const int64_t gm = (P->m + M.tile - 1) / M.tile, gn = (P->n + M.tile - 1) / M.tile;
+    const size_t sb = (size_t)gm * gn * sizeof(float);
+    if (c.scale_bytes < sb) {
+      if (c.scale) (void)hipFree(c.scale);
+      c.scale = nullptr;
+      c.scale_bytes = 0;
+      if (hipMalloc(&c.scale, sb) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(PF_ERR_NOMEM, "hipMalloc of the transposed scale grid failed");
+      }
+      c.scale_bytes = sb;
+    }
+    launch_transpose(M.tile_scale, gm, gm, gn, 4, c.scale, gn, st);
+    c.tile = M.tile;
+  }
+  c.src = M.data; c.dt = M.dtype; c.src_ld = M.ld; c.src_scale = M.tile_scale;
+}
+
+// One split-BF16 product out = alpha A^T Y + beta D1 + gamma D2 with A K x M
+// (column-major, any filter dtype) and Y given by its planes.
+void split_product(Plan* P, const void* A, int64_t lda, pf_dtype adt, const float* ascale, int tile, int64_t K,
+                   int64_t M, const uint16_t* Yp, int64_t ldy, int64_t yplane, void* out, int64_t ldo,
+                   const void* D1, const void* D2, double alpha, double beta, double gamma, uint16_t* outp,
+                   int64_t oplane, hipStream_t st) {
+  FilterArgs f;
+  f.X = A; f.ldx = lda; f.xdtype = adt;
+  if (adt == PF_F8E4M3) { f.xscale = ascale; f.tile = tile; f.ldsc = (K + tile - 1) / tile; }
+  f.Yp = Yp; f.ldy = ldy; f.yplane = yplane;
+  f.K = K; f.M = M; f.N = P->p_pad;
+  f.out = static_cast<float*>(out); f.ldo = ldo;
+  f.D1 = static_cast<const float*>(D1); f.D2 = static_cast<const float*>(D2); f.ldd = ldo;
+  f.alpha = alpha; f.beta = beta; f.gamma = gamma;
+  f.outp = outp; f.ldop = ldo; f.oplane = oplane;
+  f.part = P->part; f.part_bytes = P->part_bytes;
+  f.prof_main = PF_PROF_FILTER; f.prof_reduce = PF_PROF_FILTER_REDUCE;
+  filter_bf16x6(f, st);
+}
+
 // One filter product out = alpha X Y + beta D1 + gamma D2 on the split-BF16
 // path (FP32 work) or on the native MFMA path (FP32 with PF_FLAG_NATIVE_F32,
 // or FP64).  want_planes: also write the planes of out for the next product.
@@ -273,6 +390,25 @@ void filter_product(Plan* P, const pf_mat& Xf, const void* y, void* out, const v
                     double alpha, double beta, double gamma, bool want_planes, hipStream_t st) {
   const bool split = P->work == Elem::F32 && !(P->d.flags & PF_FLAG_NATIVE_F32);
   const int64_t ld = P->n_pad;
+  if (P->d.op == PF_OP_GRAM) {
+    // T = M Y (contraction over the n columns of M: the transposed copy),
+    // then out = alpha M^T T + beta D1 + gamma D2 (contraction over m)
+    const Plan::Copy& c = P->mft;
+    if (split) {
+      split_product(P, c.data, c.ld, Xf.dtype, c.scale, c.tile, P->n, P->m, planes_of(P, y), ld, P->plane, P->T,
+                    P->m_pad, nullptr, nullptr, 1.0, 0.0, 0.0, P->Tpl, P->tplane, st);
+      split_product(P, Xf.data, Xf.ld, Xf.dtype, Xf.tile_scale, Xf.tile, P->m, P->n, P->Tpl, P->m_pad, P->tplane,
+                    out, ld, D1, D2, alpha, beta, gamma, want_planes ? planes_of(P, out) : nullptr, P->plane, st);
+    } else {
+      contract_into(P, c.data, c.ld, elem_of(Xf.dtype), y, ld, P->work, P->n, P->m, P->T, P->m_pad, P->work,
+                    nullptr, nullptr, P->m_pad, 1.0, 0.0, 0.0, P->work == Elem::F64, st, PF_PROF_FILTER,
+                    PF_PROF_FILTER_REDUCE);
+      contract_into(P, Xf.data, Xf.ld, elem_of(Xf.dtype), P->T, P->m_pad, P->work, P->m, P->n, out, ld, P->work,
+                    D1, D2, ld, alpha, beta, gamma, P->work == Elem::F64, st, PF_PROF_FILTER,
+                    PF_PROF_FILTER_REDUCE);
+    }
+    return;
+  }
   if (split) {
     FilterArgs f;
     f.X = Xf.data; f.ldx = Xf.ld; f.xdtype = Xf.dtype;
@@ -331,6 +467,16 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
   if (prof) prof_begin(PF_PROF_EXTRACT, st);
   launch_info_init(P->info, st);
   launch_copy_block(U_in, ldu_in, W, P->U, ld, W, P->n, P->p, P->n_pad, P->p_pad, st);
+  const Plan::Copy* rr_copy = nullptr;
+  if (d.op == PF_OP_GRAM) {
+    ensure_copy(P, P->mft, Xf, st);
+    if (Xr.data == Xf.data && Xr.dtype == Xf.dtype && Xr.ld == Xf.ld) {
+      rr_copy = &P->mft;                      // one operator for both: one copy
+    } else {
+      ensure_copy(P, P->mrt, Xr, st);
+      rr_copy = &P->mrt;
+    }
+  }
 
   const bool split = W == Elem::F32 && !(d.flags & PF_FLAG_NATIVE_F32);
   void* cur = P->U;
@@ -401,9 +547,17 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
   apply(P, P->Q1, nullptr, P->Rinv, P->Q, ld, nullptr, 0.0, 0.0, P->deficient, nullptr, st);
 
   // Rayleigh-Ritz in FP64 (eq. RR)
-  contract_into(P, Xr.data, Xr.ld, tr, P->Q, ld, W, P->n, P->n, P->W, ld, Elem::F64, nullptr, nullptr, ld, 1.0,
-                0.0, 0.0, true, st, PF_PROF_RR, -1);
-  gram(P, P->Q, W, P->W, Elem::F64, P->G, st);
+  if (d.op == PF_OP_GRAM) {
+    // B = M Q (FP64), H = B^T B = Q^T (M^T M) Q: theta = sigma^2
+    contract_into(P, rr_copy->data, rr_copy->ld, tr, P->Q, ld, W, P->n, P->m, P->B, P->m_pad, Elem::F64, nullptr,
+                  nullptr, P->m_pad, 1.0, 0.0, 0.0, true, st, PF_PROF_RR, -1);
+    contract_into(P, P->B, P->m_pad, Elem::F64, P->B, P->m_pad, Elem::F64, P->m, P->p_pad, P->G, P->p_pad,
+                  Elem::F64, nullptr, nullptr, 0, 1.0, 0.0, 0.0, true, st, -1, -1);
+  } else {
+    contract_into(P, Xr.data, Xr.ld, tr, P->Q, ld, W, P->n, P->n, P->W, ld, Elem::F64, nullptr, nullptr, ld, 1.0,
+                  0.0, 0.0, true, st, PF_PROF_RR, -1);
+    gram(P, P->Q, W, P->W, Elem::F64, P->G, st);
+  }
   launch_jacobi(P->G, P->p_pad, P->p, P->theta, P->Zeig, P->p_pad, P->Zwork, P->info, 1, max_sweeps, st);
   apply(P, P->Q, nullptr, P->Zeig, U_out, ldu_out, nullptr, 0.0, 0.0, nullptr, P->info, st);
   if (info_out || theta_out) launch_info_copy(P->info, info_out, P->theta, theta_out, P->p, st);

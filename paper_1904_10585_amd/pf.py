@@ -26,6 +26,7 @@ PF_FLAG_NO_PREROTATE = 0x1
 PF_FLAG_SCALED = 0x2
 PF_FLAG_COLD = 0x4
 PF_FLAG_NATIVE_F32 = 0x8
+PF_FLAG_OPERATOR_UNCHANGED = 0x10
 PF_PROF_FILTER, PF_PROF_FILTER_REDUCE, PF_PROF_RR, PF_PROF_EXTRACT = range(4)
 
 

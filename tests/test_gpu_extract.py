@@ -322,3 +322,119 @@ def test_fp8_operand_checks():
         with pytest.raises(pf.PfError) as e:
             pf.pf_extract(pf.desc(n, p, 3, -1.0, 0.5, work=pf.PF_F32), m, Xr, Ud, theta)
         assert e.value.status == pf.PF_ERR_ARG
+
+
+def run_gram(Mf, Mr, U, d, a, b, work, flags=0, spec_ub=0.0, keep_plan=None):
+    """One PF_OP_GRAM extraction; Mf is a device tensor, a (codes, scales,
+    tile) tuple or a PfMat; Mr a device tensor."""
+    pf = pf_module()
+    n, p = U.shape
+    m = Mr.shape[0]
+    tdt = torch.float64 if work == "f64" else torch.float32
+    Ud = device_matrix(U, tdt)
+    theta = torch.zeros(p, dtype=torch.float64, device="cuda")
+    info = torch.zeros(8, dtype=torch.int32, device="cuda")
+    dsc = pf.desc(n, p, d, a, b, work=pf.PF_F64 if work == "f64" else pf.PF_F32, op=pf.PF_OP_GRAM, m=m,
+                  flags=flags, spec_ub=spec_ub)
+    pf.pf_extract(dsc, Mf, Mr, Ud, theta, info)
+    torch.cuda.synchronize()
+    return theta.cpu().numpy(), Ud.cpu().double().numpy(), info.cpu().numpy()
+
+
+def gram_case(m, n, r, p, config):
+    M = wl.lowrank_plus_noise(m, n, r, 0.01, config=config)
+    U = wl.start_block(n, p, config=config)
+    b = 4.0 * 0.01 ** 2 * m                   # above the noise: sigma_noise^2 <~ 0.01^2 (sqrt m + sqrt n)^2
+    for _ in range(3):
+        U = oracle.extract_gram(M, M, U, 4, 0.0, b)["V"]
+    return M, U, b
+
+
+@pytest.mark.parametrize("m,n,r,p,d", [(300, 120, 6, 10, 4), (777, 333, 12, 20, 3), (1030, 513, 20, 48, 5)])
+@pytest.mark.parametrize("work", ["f64", "f32"])
+def test_gram_operator(m, n, r, p, d, work):
+    M, U, b = gram_case(m, n, r, p, config=98)
+    if work == "f32":
+        M = M.astype(np.float32).astype(np.float64)
+        U = U.astype(np.float32).astype(np.float64)
+    ref = oracle.extract_gram(M, M, U, d, 0.0, b)
+    tdt = torch.float64 if work == "f64" else torch.float32
+    Md = device_matrix(M, tdt)
+    th, V, info = run_gram(Md, Md, U, d, 0.0, b, work)
+    assert info[0] == 0, info
+    rel, sin = compare(th, V, ref, r)
+    print(f"gram {work} m={m} n={n} p={p}: rel {rel:.2e} sin {sin:.2e}")
+    tol = (1e-10, 1e-10) if work == "f64" else (1e-5, 1e-4)
+    assert rel <= tol[0] and sin <= tol[1], (rel, sin)
+
+
+@pytest.mark.parametrize("kind,p", [("f32", 16), ("fp8", 10), ("fp8", 16)])
+def test_gram_scaled_large_spectrum(kind, p):
+    """sigma^2 ~ 1e5: T_8 of it overflows FP32 unless the recurrence is
+    scaled (PF_FLAG_SCALED, spec_ub >= sigma_max^2); the FP8 form filters
+    on per-tile E4M3 codes of M and projects with the FP32 M.
+
+    With guard columns (p > r) the filter amplifies the signal by ~1e59 over
+    the noise, so the guard columns of the filtered block are numerically
+    dependent and replaced by arbitrary directions (pseudo-random on the
+    GPU, Householder's choice in the oracle).  Where the filter matrix is
+    the FP32 M, its top singular subspace lies in span(Q) whatever the
+    guards are, and the Ritz vectors are unique; with the FP8 copy the
+    subspace is that of the quantised M, M's own singular vectors lie
+    ~1e-3 outside it, and which guard directions Rayleigh-Ritz may mix in
+    decides the Ritz vectors at that level.  There only the Ritz values are
+    unique; the vectors are compared for p = r."""
+    pf = pf_module()
+    m, n, r, d = 700, 300, 10, 8
+    M = wl.lowrank_plus_noise(m, n, r, 0.01, config=99).astype(np.float32).astype(np.float64)
+    U = wl.start_block(n, p, config=99)
+    a, b = 0.0, 4.0 * 0.01 ** 2 * m
+    for _ in range(2):
+        U = oracle.extract_gram(M, M, U, d, a, b)["V"]
+    U = U.astype(np.float32).astype(np.float64)
+    smax2 = np.linalg.svd(M, compute_uv=False)[0] ** 2
+    Mr = device_matrix(M, torch.float32)
+    if kind == "fp8":
+        src = Mr
+        ldq = -(-m // 16) * 16
+        codes_d = pf.colmajor(m, n, torch.uint8, "cuda", ld=ldq)
+        tm, tn = -(-m // 128), -(-n // 128)
+        scales = torch.zeros((tn, tm), dtype=torch.float32, device="cuda").t()
+        pf.pf_quantize(codes_d, scales, 128, pf.PF_F8E4M3, src)
+        codes, sc = oracle.fp8_tile_quantize(M.astype(np.float32), 128)
+        Mf_host = oracle.fp8_tile_dequantize(codes, sc, 128)
+        Mf = (codes_d, scales, 128)
+    else:
+        Mf_host, Mf = M, Mr
+    ref = oracle.extract_gram(Mf_host, M, U, d, a, b)
+    flags = pf.PF_FLAG_SCALED
+    th, V, info = run_gram(Mf, Mr, U, d, a, b, "f32", flags=flags, spec_ub=1.01 * smax2)
+    assert info[0] == 0, info
+    rel, sin = compare(th, V, ref, r)
+    srel = np.max(np.abs(np.sqrt(th[:r]) - ref["sigma"][:r]) / ref["sigma"][:r])
+    print(f"gram scaled {kind} p={p}: rel {rel:.2e} sin {sin:.2e} sigma rel {srel:.2e}")
+    assert rel <= 1e-5, rel
+    if kind == "f32" or p == r:
+        assert sin <= 1e-4, sin
+    else:
+        assert np.abs(V.T @ V - np.eye(p)).max() < 1e-5
+    # without scaling the FP32 recurrence overflows and is reported
+    th2, V2, info2 = run_gram(Mf, Mr, U, d, a, b, "f32")
+    assert info2[0] in (pf.PF_ERR_NONFINITE, pf.PF_ERR_BREAKDOWN), info2
+
+
+def test_gram_operator_unchanged_reuses_copy():
+    """PF_FLAG_OPERATOR_UNCHANGED on a second call with the same M gives the
+    same result as rebuilding the transposed copy."""
+    pf = pf_module()
+    M, U, b = gram_case(400, 200, 8, 16, config=100)
+    M32 = M.astype(np.float32).astype(np.float64)
+    Md = device_matrix(M32, torch.float32)
+    U32 = U.astype(np.float32).astype(np.float64)
+    th1, V1, i1 = run_gram(Md, Md, U32, 4, 0.0, b, "f32")
+    th2, V2, i2 = run_gram(Md, Md, U32, 4, 0.0, b, "f32", flags=pf.PF_FLAG_OPERATOR_UNCHANGED)
+    th3, V3, i3 = run_gram(Md, Md, U32, 4, 0.0, b, "f32", flags=pf.PF_FLAG_OPERATOR_UNCHANGED)
+    assert i1[0] == i2[0] == i3[0] == 0
+    np.testing.assert_array_equal(th1, th2)
+    np.testing.assert_array_equal(th1, th3)
+    np.testing.assert_array_equal(V1, V3)
