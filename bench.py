@@ -39,6 +39,10 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle extractions in the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event hooks")
+    ap.add_argument("--sessions", type=int, default=2000, help="serving: sessions in the Poisson stream")
+    ap.add_argument("--session-steps", type=int, default=30, help="serving: steps per session")
+    ap.add_argument("--load", type=float, default=0.7, help="serving: arrival rate / saturated session rate")
+    ap.add_argument("--hbm-budget-gb", type=float, default=160.0, help="serving: HBM budget of the server")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (the byte-counter calibration of a profiler run)")
     return ap.parse_args()
@@ -91,8 +95,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the extraction runs on one MI355X; see DESIGN.md for how it would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the extraction runs on a single MI355X and has no "
+              "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -102,6 +106,8 @@ def main():
     from paper_1904_10585_amd import pf
     from paper_1904_10585_amd import workloads as wl
 
+    if args.workload == "serving":
+        return serve_main(args)
     w = wl.WORKLOADS[args.workload]
     n, p, d = w.n, w.p, w.degree
     dev = "cuda"
@@ -274,6 +280,165 @@ def main():
                          "target": "planted top-64, warm steps, vs FP64 oracle fed the same U_in and X_k",
                          "tolerance": {"ritz_rel": 1e-5, "sin": 1e-4}}
     pf.pf_session_close(sess)
+    print(json.dumps(out), flush=True)
+
+
+def serve_main(args):
+    """Serving form: a Poisson stream of warm-started extraction sessions of
+    mixed n, p and degree through the library's server (admission by HBM
+    footprint, concurrent sessions over HIP streams, graph replay of warm
+    steps).  Each session is a chain of steps on its own device copy of a
+    planted matrix, perturbed in place between steps (the client's work,
+    outside the step latency).  Two runs: a saturated one (every session
+    queued at t=0) gives the session rate the hardware sustains; the Poisson
+    run offers --load times that rate.  Reported: steps/s, p50/p99 of
+    submit-to-done step latency, aggregate algorithmic GB/s."""
+    import torch
+    from paper_1904_10585_amd import pf
+    from paper_1904_10585_amd import workloads as wl
+    torch.cuda.set_device(0)
+    dev = "cuda"
+    S = wl.SERVING
+    g = wl.rng(4, wl.S_SESSION)
+    nS, steps = args.sessions, args.session_steps
+    ns = g.choice(S["n_choices"], nS)
+    ps = g.choice(S["p_choices"], nS)
+    ds = g.choice(S["degree_choices"], nS)
+    # base matrices: for every n two seeded Haar factors Q, and for every
+    # (n, factor, p) the planted X = Q diag(lambda) Q^T with p/2 eigenvalues
+    # on top (FP32, built on the device); a session copies its base X into
+    # a buffer of its own.  E_n = sym(G)/sqrt(n): the perturbation direction.
+    t0 = time.time()
+    base, E = {}, {}
+    gen = torch.Generator(device=dev)
+    for n in S["n_choices"]:
+        n = int(n)
+        for k in range(2):
+            gen.manual_seed(wl.SEED_ROOT * 100 + n + k)
+            G = torch.randn((n, n), generator=gen, device=dev, dtype=torch.float32)
+            Q, R = torch.linalg.qr(G)
+            Q = Q * torch.sign(torch.diagonal(R))
+            del G, R
+            lam_top = torch.rand(n, generator=gen, device=dev) * (S["top"][1] - S["top"][0]) + S["top"][0]
+            lam_rest = torch.rand(n, generator=gen, device=dev) * (S["rest"][1] - S["rest"][0]) + S["rest"][0]
+            for p in S["p_choices"]:
+                lam = lam_rest.clone()
+                lam[: int(p) // 2] = lam_top[: int(p) // 2]
+                X = (Q * lam) @ Q.t()
+                base[(n, k, int(p))] = (0.5 * (X + X.t())).contiguous()
+                del X
+            del Q
+        gen.manual_seed(wl.SEED_ROOT * 100 + n + 7)
+        G = torch.randn((n, n), generator=gen, device=dev, dtype=torch.float32)
+        E[n] = ((G + G.t()) * (0.5 / math.sqrt(n))).contiguous()
+        del G
+    torch.cuda.synchronize()
+    log(f"serving: {len(base)} base matrices built on the device in {time.time() - t0:.1f}s")
+    zs = wl.rng(4, wl.S_PERTURB).standard_normal((nS, steps))
+
+    def session_x(i):
+        return base[(int(ns[i]), i % 2, int(ps[i]))].clone().t()   # column-major view of symmetric X
+
+    def perturb(X, i, k):
+        X.add_(E[X.shape[0]], alpha=1e-3 * float(zs[i, k]))     # E symmetric: X stays symmetric
+
+    def run(arrivals, label):
+        srv = pf.pf_server_create(int(args.hbm_budget_gb * (1 << 30)), max_active=256, streams=8)
+        Xs, ids, left, lat, step_bytes = {}, {}, {}, [], 0.0
+        pending = sorted(range(nS), key=lambda i: arrivals[i])
+        t_start = time.perf_counter()
+        nxt = 0
+        done_steps = 0
+        first_submit, last_done = None, None
+        while done_steps < nS * steps:
+            now = time.perf_counter() - t_start
+            # arrivals due: open and queue the first step (held back while
+            # the server already has sessions waiting for memory, so that
+            # operator copies exist only for sessions about to run)
+            opened = []
+            st = pf.pf_server_stats(srv)
+            room = max(0, 4 - st.waiting)
+            while nxt < nS and arrivals[pending[nxt]] <= now and len(opened) < room:
+                i = pending[nxt]
+                nxt += 1
+                n, p, d = int(ns[i]), int(ps[i]), int(ds[i])
+                a, b = wl.serving_interval(d)
+                Xs[i] = session_x(i)
+                dsc = pf.desc(n, p, d, a, b, work=pf.PF_F32)
+                ids[i] = pf.pf_server_open(srv, dsc, seed=i, operator_bytes=n * n * 4)
+                left[i] = steps
+                opened.append(i)
+            if opened:
+                torch.cuda.synchronize()
+                for i in opened:
+                    pf.pf_server_submit(srv, ids[i], Xs[i], Xs[i], tag=i)
+                if first_submit is None:
+                    first_submit = time.perf_counter()
+            wait = 0.002
+            if nxt < nS and not opened:
+                wait = max(0.0, min(wait, arrivals[pending[nxt]] - (time.perf_counter() - t_start)))
+            evs = pf.pf_server_poll(srv, max_events=512, timeout_s=wait)
+            resubmit = []
+            by_id = {v: k for k, v in ids.items()} if evs else {}
+            for ev in evs:
+                if ev.status != pf.PF_OK:
+                    raise SystemExit(f"serving step failed: {pf.status_string(ev.status)}")
+                i = by_id[ev.session]
+                lat.append((ev.done_ns - ev.submit_ns) * 1e-6)
+                n, d = int(ns[i]), int(ds[i])
+                step_bytes += (d + 1) * 4.0 * n * n
+                done_steps += 1
+                last_done = time.perf_counter()
+                left[i] -= 1
+                if left[i] > 0:
+                    perturb(Xs[i], i, steps - left[i])
+                    resubmit.append(i)
+                else:
+                    pf.pf_server_close(srv, ids[i])
+                    del Xs[i], ids[i]
+            if resubmit:
+                torch.cuda.synchronize()
+                for i in resubmit:
+                    pf.pf_server_submit(srv, ids[i], Xs[i], Xs[i], tag=i)
+            if done_steps and done_steps % 5000 < len(evs):
+                log(f"serving {label}: {done_steps} steps done")
+        st = pf.pf_server_stats(srv)
+        pf.pf_server_destroy(srv)
+        wall = last_done - first_submit
+        lat = np.array(lat)
+        log(f"serving {label}: {done_steps} steps in {wall:.2f}s, p50 {np.percentile(lat, 50):.3f} ms, "
+            f"p99 {np.percentile(lat, 99):.3f} ms, graphs {st.graph_launches}/{st.launched}")
+        return dict(steps_per_s=done_steps / wall, sessions_per_s=nS / wall, wall_s=wall,
+                    p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                    gbps=step_bytes / wall / 1e9, graph_launches=int(st.graph_launches),
+                    launched=int(st.launched), captures=int(st.captures))
+
+    sat = run(np.zeros(nS), "saturated")
+    rate = args.load * sat["sessions_per_s"]
+    arr = np.cumsum(wl.rng(4, wl.S_ARRIVAL).exponential(1.0 / rate, nS))
+    pois = run(arr, f"poisson load {args.load}")
+    out = {
+        "metric": "serving steps/s with p50/p99 step latency (mixed n, p, degree sessions)",
+        "value": round(pois["steps_per_s"], 2),
+        "unit": "extraction steps/s",
+        "n_gpus": 1,
+        "steps": int(nS * steps),
+        "warmup": 0,
+        "ms_per_step": round(1000.0 / pois["steps_per_s"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic planted-spectrum sessions (seeded), device-resident",
+        "config": {"workload": "serving", "sessions": nS, "steps_per_session": steps,
+                   "n_choices": list(S["n_choices"]), "p_choices": list(S["p_choices"]),
+                   "degree_choices": list(S["degree_choices"]), "arrivals": f"Poisson at {args.load} x saturated",
+                   "hbm_budget_gb": args.hbm_budget_gb},
+        "latency_ms": {"p50": round(pois["p50_ms"], 3), "p99": round(pois["p99_ms"], 3)},
+        "hbm_GBps_algorithmic": round(pois["gbps"], 1),
+        "saturated": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sat.items()},
+        "poisson": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in pois.items()},
+    }
     print(json.dumps(out), flush=True)
 
 

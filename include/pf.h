@@ -200,6 +200,79 @@ pf_status pf_session_wait(pf_session* s, pf_result* out);
 /* Free the session.  PF_ERR_BUSY if a step is still in flight. */
 pf_status pf_session_close(pf_session* s);
 
+/* ------------------------------------------------------------------------
+ * Serving loop: many warm-started sessions of different n, p, degree and
+ * operator, driven by a stream of step requests (the per-iteration calls of
+ * many PFPG/PFAM solvers sharing one GPU).
+ *
+ *  - Admission by HBM footprint: a session is resident (workspace, V, theta)
+ *    only while its footprint fits the budget; sessions opened while the
+ *    budget is full wait in FIFO order and are admitted as closed sessions
+ *    free memory.  footprint = the session's device bytes + operator_bytes
+ *    (what the caller declares for its X, so that the budget covers it).
+ *  - Continuous batching: a worker thread launches every resident session's
+ *    next requested step as soon as its previous step is done; the steps of
+ *    different sessions run concurrently on a pool of HIP streams.
+ *  - HIP graphs: a session's first step runs eagerly (cold start); its warm
+ *    step is captured once as a graph and replayed for later steps whose
+ *    operator buffers are the ones captured (re-captured when they change).
+ *  - Every finished step produces a pf_server_event with host timestamps
+ *    (steady clock, ns) of submission, launch and observed completion.
+ *  - Results of a session are bitwise the same whether it runs alone or in
+ *    a mix (its kernels are deterministic and touch only its own buffers).
+ * All pf_server_* calls are thread-safe.  Operator buffers passed to
+ * pf_server_submit must stay valid and unmodified until that step's event. */
+typedef struct pf_server pf_server;
+
+#define PF_SERVER_NO_GRAPHS 0x1u  /* launch warm steps eagerly, no capture */
+
+typedef struct pf_server_config {
+  uint32_t struct_size;   /* sizeof(pf_server_config) */
+  uint32_t flags;
+  size_t hbm_budget;      /* bytes sessions may hold together (> 0) */
+  int32_t max_active;     /* resident sessions at most (0 = 64) */
+  int32_t streams;        /* HIP streams of the worker (0 = 8, at most 64) */
+} pf_server_config;
+
+typedef struct pf_server_event {
+  int32_t session;
+  int32_t status;         /* pf_status of the step (numerical or PF_ERR_DEVICE) */
+  int32_t n_pos;
+  int32_t graph;          /* 1 if the step ran as a graph replay */
+  int64_t step;           /* 0-based index of the step within its session */
+  uint64_t tag;           /* the caller's tag from pf_server_submit */
+  int64_t submit_ns, launch_ns, done_ns;
+} pf_server_event;
+
+typedef struct pf_server_stats {
+  int32_t active, waiting;
+  size_t used_bytes;
+  int64_t launched, completed, graph_launches, captures;
+} pf_server_stats;
+
+pf_status pf_server_create(const pf_server_config* cfg, pf_server** out);
+/* Open a session (waits for admission inside the server; returns at once).
+ * U0: device n x p block in the work dtype that stays valid until the
+ * session's first step has completed, or NULL for an N(0,1) start from seed.
+ * PF_ERR_NOMEM if its footprint alone exceeds the budget. */
+pf_status pf_server_open(pf_server* s, const pf_desc* desc, const void* U0, int64_t ldu0, uint64_t seed,
+                         size_t operator_bytes, int32_t* session);
+/* Queue one step of a session on (X_filter, X_rr); steps of one session run
+ * in submission order. */
+pf_status pf_server_submit(pf_server* s, int32_t session, const pf_mat* X_filter, const pf_mat* X_rr,
+                           uint64_t tag);
+/* Up to max finished-step events; waits up to timeout_ns for the first. */
+pf_status pf_server_poll(pf_server* s, pf_server_event* events, int32_t max, int32_t* count, int64_t timeout_ns);
+/* Device pointers of a resident session's theta / V (valid until its next
+ * step is launched or it is closed). PF_ERR_BUSY while a step is queued or
+ * running, PF_ERR_ARG if the session is not resident. */
+pf_status pf_server_result(pf_server* s, int32_t session, pf_result* out);
+/* Close a session once its queued steps are done; frees its memory. */
+pf_status pf_server_close(pf_server* s, int32_t session);
+pf_status pf_server_stats_get(pf_server* s, pf_server_stats* out);
+/* Finish every queued step, free every session, stop the worker. */
+pf_status pf_server_destroy(pf_server* s);
+
 /* Quantise an FP32 matrix (rows x cols, ld) into BF16 (dst ld = ld_dst) or
  * FP8-E4M3 codes with FP32 per-tile scales amax/448 (tile x tile,
  * column-major scale grid).  Round to nearest even; FP8 saturates at 448. */

@@ -2,6 +2,7 @@
 // per-stream workspace cache of pf_extract, and sessions.
 #include "pf_internal.h"
 
+#include <functional>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -17,6 +18,55 @@ void check_hip(hipError_t e, const char* what) {
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) fail(PF_ERR_NOMEM, std::string(what) + ": out of memory");
     fail(PF_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
   }
+}
+
+size_t session_bytes(const pf_desc& d) {
+  const size_t esz = d.work == PF_F64 ? 8 : 4;
+  return plan_bytes(d) + (size_t)round_up(d.n, 64) * d.p * esz + sizeof(double) * d.p + sizeof(pf_info) + 3 * 256;
+}
+
+SessionCore* session_create(const pf_desc& d, const void* U0, int64_t ldu0, uint64_t seed, hipStream_t st,
+                            bool sync) {
+  SessionCore* s = new SessionCore();
+  try {
+    PFX_HIP(hipGetDevice(&s->device));
+    s->desc = d;
+    s->plan = plan_create(d, st, !sync);
+    const Elem W = d.work == PF_F64 ? Elem::F64 : Elem::F32;
+    const size_t esz = W == Elem::F64 ? 8 : 4;
+    s->ldu = round_up(d.n, 64);
+    const size_t ubytes = (size_t)s->ldu * d.p * esz;
+    PFX_HIP(hipMalloc(&s->U, ubytes));
+    PFX_HIP(hipMalloc(&s->theta, sizeof(double) * d.p));
+    PFX_HIP(hipMalloc(&s->info, sizeof(pf_info)));
+    PFX_HIP(hipMemsetAsync(s->U, 0, ubytes, st));
+    PFX_HIP(hipMemsetAsync(s->theta, 0, sizeof(double) * d.p, st));
+    PFX_HIP(hipMemsetAsync(s->info, 0, sizeof(pf_info), st));
+    if (U0) launch_copy_block(U0, ldu0, W, s->U, s->ldu, W, d.n, d.p, d.n, d.p, st);
+    else launch_normal_block(s->U, s->ldu, W, d.n, d.p, seed, st);
+    if (sync) PFX_HIP(hipStreamSynchronize(st));
+  } catch (...) {
+    session_destroy(s);
+    throw;
+  }
+  return s;
+}
+
+void session_destroy(SessionCore* s) {
+  if (!s) return;
+  if (s->U) (void)hipFree(s->U);
+  if (s->theta) (void)hipFree(s->theta);
+  if (s->info) (void)hipFree(s->info);
+  plan_destroy(s->plan);
+  delete s;
+}
+
+void session_enqueue_step(SessionCore* s, const pf_mat& Xf, const pf_mat& Xr, hipStream_t st) {
+  pf_desc d = s->desc;
+  if (s->steps == 0) d.flags |= PF_FLAG_COLD;        // first step starts from U0
+  plan_set_desc(s->plan, d);
+  enqueue_extraction(s->plan, Xf, Xr, s->U, s->ldu, s->U, s->ldu, s->theta, s->info, st);
+  s->steps++;
 }
 
 namespace {
@@ -39,6 +89,12 @@ pf_status guarded(F&& f) {
     return PF_ERR_DEVICE;
   }
 }
+
+}  // namespace
+
+pf_status run_guarded(const std::function<void()>& f) { return guarded(f); }
+
+namespace {
 
 // pf_extract workspaces: one per (device, stream, shape); calls on one
 // stream are ordered, so a workspace is never used by two extractions at once.
@@ -105,18 +161,10 @@ void prof_end(int cls, hipStream_t st) {
 }  // namespace pfx
 
 struct pf_session {
-  pfx::Plan* plan = nullptr;
-  pf_desc desc;
-  void* U = nullptr;        // n_pad x p_pad, work dtype
-  int64_t ldu = 0;
-  double* theta = nullptr;
-  pf_info* info = nullptr;
+  pfx::SessionCore* core = nullptr;
   hipEvent_t done = nullptr;
   bool stepped = false;
-  int64_t steps = 0;
-  int device = 0;
 };
-
 using namespace pfx;
 
 extern "C" {
@@ -196,29 +244,10 @@ pf_status pf_session_open(const pf_desc* desc, const void* U0, int64_t ldu0, uin
     if (U0 && ldu0 < desc->n) fail(PF_ERR_ARG, "ldu0 is smaller than n");
     pf_session* s = new pf_session();
     try {
-      PFX_HIP(hipGetDevice(&s->device));
-      s->desc = *desc;
-      s->plan = plan_create(*desc);
-      const Elem W = desc->work == PF_F64 ? Elem::F64 : Elem::F32;
-      const size_t esz = W == Elem::F64 ? 8 : 4;
-      s->ldu = round_up(desc->n, 64);
-      const size_t ubytes = (size_t)s->ldu * desc->p * esz;
-      PFX_HIP(hipMalloc(&s->U, ubytes));
-      PFX_HIP(hipMalloc(&s->theta, sizeof(double) * desc->p));
-      PFX_HIP(hipMalloc(&s->info, sizeof(pf_info)));
-      PFX_HIP(hipMemset(s->U, 0, ubytes));
-      PFX_HIP(hipMemset(s->theta, 0, sizeof(double) * desc->p));
-      PFX_HIP(hipMemset(s->info, 0, sizeof(pf_info)));
+      s->core = session_create(*desc, U0, ldu0, seed, nullptr, true);
       PFX_HIP(hipEventCreateWithFlags(&s->done, hipEventDisableTiming));
-      if (U0) launch_copy_block(U0, ldu0, W, s->U, s->ldu, W, desc->n, desc->p, desc->n, desc->p, nullptr);
-      else launch_normal_block(s->U, s->ldu, W, desc->n, desc->p, seed, nullptr);
-      PFX_HIP(hipDeviceSynchronize());
     } catch (...) {
-      if (s->U) (void)hipFree(s->U);
-      if (s->theta) (void)hipFree(s->theta);
-      if (s->info) (void)hipFree(s->info);
-      if (s->done) (void)hipEventDestroy(s->done);
-      plan_destroy(s->plan);
+      session_destroy(s->core);
       delete s;
       throw;
     }
@@ -230,22 +259,18 @@ pf_status pf_session_step(pf_session* s, const pf_mat* X_filter, const pf_mat* X
                           void* stream) {
   return guarded([&] {
     if (!s) fail(PF_ERR_ARG, "session is NULL");
-    plan_validate(s->desc, X_filter, X_rr);
+    plan_validate(s->core->desc, X_filter, X_rr);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    pf_desc d = s->desc;
-    if (s->steps == 0) d.flags |= PF_FLAG_COLD;        // first step starts from U0
-    plan_set_desc(s->plan, d);
-    enqueue_extraction(s->plan, *X_filter, *X_rr, s->U, s->ldu, s->U, s->ldu, s->theta, s->info, st);
+    session_enqueue_step(s->core, *X_filter, *X_rr, st);
     PFX_HIP(hipEventRecord(s->done, st));
     s->stepped = true;
-    s->steps++;
     if (out) {
       out->status = 0;
       out->n_pos = 0;
-      out->theta = s->theta;
-      out->V = s->U;
-      out->ldv = s->ldu;
-      out->info = s->info;
+      out->theta = s->core->theta;
+      out->V = s->core->U;
+      out->ldv = s->core->ldu;
+      out->info = s->core->info;
     }
   });
 }
@@ -255,14 +280,14 @@ pf_status pf_session_wait(pf_session* s, pf_result* out) {
   pf_status st = guarded([&] {
     if (!s) fail(PF_ERR_ARG, "session is NULL");
     if (s->stepped) PFX_HIP(hipEventSynchronize(s->done));
-    PFX_HIP(hipMemcpy(&host, s->info, sizeof(pf_info), hipMemcpyDeviceToHost));
+    PFX_HIP(hipMemcpy(&host, s->core->info, sizeof(pf_info), hipMemcpyDeviceToHost));
     if (out) {
       out->status = host.status;
       out->n_pos = host.n_pos;
-      out->theta = s->theta;
-      out->V = s->U;
-      out->ldv = s->ldu;
-      out->info = s->info;
+      out->theta = s->core->theta;
+      out->V = s->core->U;
+      out->ldv = s->core->ldu;
+      out->info = s->core->info;
     }
   });
   if (st != PF_OK) return st;
@@ -280,11 +305,8 @@ pf_status pf_session_close(pf_session* s) {
       hipError_t q = hipEventQuery(s->done);
       if (q == hipErrorNotReady) fail(PF_ERR_BUSY, "session has a step in flight");
     }
-    (void)hipFree(s->U);
-    (void)hipFree(s->theta);
-    (void)hipFree(s->info);
+    session_destroy(s->core);
     (void)hipEventDestroy(s->done);
-    plan_destroy(s->plan);
     delete s;
   });
 }

@@ -313,6 +313,11 @@ void launch_info_copy(const pf_info* src, pf_info* dst, const double* th, double
   PFX_HIP(hipGetLastError());
 }
 
+void launch_info_to_host(const pf_info* src, pf_info* host_mapped, hipStream_t st) {
+  info_copy_kernel<<<1, 64, 0, st>>>(src, host_mapped, nullptr, nullptr, 0);
+  PFX_HIP(hipGetLastError());
+}
+
 void launch_normal_block(void* dst, int64_t ld, Elem t, int64_t n, int p, uint64_t seed, hipStream_t st) {
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)p);
   if (t == Elem::F64) normal_block_kernel<double><<<grid, 256, 0, st>>>(static_cast<double*>(dst), ld, n, p, seed);

@@ -144,7 +144,9 @@ void prof_end(int cls, hipStream_t st);
 // ---------------------------------------------------------------------------
 // The extraction pipeline.
 struct Plan;
-Plan* plan_create(const pf_desc& d);
+// zero_stream: clear the workspace with hipMemsetAsync on that stream (the
+// stream the plan is first used on) instead of a synchronous hipMemset.
+Plan* plan_create(const pf_desc& d, hipStream_t zero_stream = nullptr, bool async_zero = false);
 void plan_destroy(Plan* p);
 size_t plan_bytes(const pf_desc& d);
 void plan_validate(const pf_desc& d, const pf_mat* Xf, const pf_mat* Xr);
@@ -157,5 +159,32 @@ void plan_set_desc(Plan* P, const pf_desc& d);
 // plan-owned buffers (for sessions)
 double* plan_theta(Plan* p);
 pf_info* plan_info(Plan* p);
+
+// ---------------------------------------------------------------------------
+// Session state shared by pf_session_* and the server: the warm-start block
+// V (updated in place by every step), theta, the device info record, and
+// the workspace plan.
+struct SessionCore {
+  Plan* plan = nullptr;
+  pf_desc desc{};
+  void* U = nullptr;        // n_pad x p, work dtype
+  int64_t ldu = 0;
+  double* theta = nullptr;
+  pf_info* info = nullptr;
+  int64_t steps = 0;
+  int device = 0;
+};
+// Device bytes a session holds (workspace, block, theta, info).
+size_t session_bytes(const pf_desc& d);
+// Allocate and initialise (U0 copied, or N(0,1) from seed when U0 is NULL),
+// stream-ordered on st; sync: wait for the initialisation on the host.
+SessionCore* session_create(const pf_desc& d, const void* U0, int64_t ldu0, uint64_t seed, hipStream_t st,
+                            bool sync);
+void session_destroy(SessionCore* s);
+// Enqueue one step on st (the first step of a session runs as a cold start).
+void session_enqueue_step(SessionCore* s, const pf_mat& Xf, const pf_mat& Xr, hipStream_t st);
+// Copy the info record of the last step to host-visible memory (a mapped
+// pinned buffer), stream-ordered: the host reads it once the step is done.
+void launch_info_to_host(const pf_info* src, pf_info* host_mapped, hipStream_t st);
 
 }  // namespace pfx

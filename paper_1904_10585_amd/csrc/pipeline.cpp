@@ -208,7 +208,7 @@ void plan_validate(const pf_desc& d, const pf_mat* Xf, const pf_mat* Xr) {
 
 size_t plan_bytes(const pf_desc& d) { return layout_for(d).total; }
 
-Plan* plan_create(const pf_desc& d) {
+Plan* plan_create(const pf_desc& d, hipStream_t zero_stream, bool async_zero) {
   plan_validate(d, nullptr, nullptr);
   Layout L = layout_for(d);
   Plan* P = new Plan();
@@ -227,7 +227,7 @@ Plan* plan_create(const pf_desc& d) {
     fail(PF_ERR_NOMEM, "hipMalloc of the extraction workspace failed");
   }
   // zero once: padding rows/columns of every block stay zero forever
-  e = hipMemset(P->mem, 0, L.total);
+  e = async_zero ? hipMemsetAsync(P->mem, 0, L.total, zero_stream) : hipMemset(P->mem, 0, L.total);
   if (e != hipSuccess) {
     (void)hipFree(P->mem);
     delete P;

@@ -1,0 +1,427 @@
+// The serving loop of include/pf.h: admission by HBM footprint, continuous
+// launching of many sessions' steps over a pool of HIP streams, and HIP
+// graph replay of warm steps.
+//
+// One worker thread owns every HIP call on session state.  Caller threads
+// only queue work (open / submit / close) under the server mutex and read
+// finished-step events.  Per session at most one step is in flight: a step
+// starts from the V its predecessor wrote, so the next one is launched when
+// the previous one's event has completed; other sessions fill the GPU
+// meanwhile.  A finished step's status reaches the host through a mapped
+// pinned pf_info written by the last kernel of the step.
+#include "pf_internal.h"
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+namespace pfx {
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+bool same_mat(const pf_mat& a, const pf_mat& b) {
+  return a.data == b.data && a.dtype == b.dtype && a.ld == b.ld && a.tile_scale == b.tile_scale && a.tile == b.tile;
+}
+
+struct Request {
+  pf_mat xf, xr;
+  uint64_t tag;
+  int64_t submit_ns;
+};
+
+struct InFlight {
+  Request req;
+  int64_t step;
+  int64_t launch_ns;
+  bool graph;
+};
+
+struct SrvSession {
+  int32_t id = 0;
+  pf_desc desc{};
+  size_t footprint = 0;
+  bool resident = false;
+  bool closing = false;
+  const void* U0 = nullptr;
+  int64_t ldu0 = 0;
+  uint64_t seed = 0;
+  SessionCore* core = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  pf_info* host_info = nullptr;     // mapped pinned: host address
+  pf_info* host_info_dev = nullptr; // the same memory as the device sees it
+  std::deque<Request> pending;
+  bool busy = false;
+  InFlight cur{};
+  hipGraphExec_t exec = nullptr;
+  pf_mat g_xf{}, g_xr{};
+};
+
+}  // namespace
+}  // namespace pfx
+
+using namespace pfx;
+
+struct pf_server {
+  pf_server_config cfg{};
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv;       // work for the worker
+  std::condition_variable done_cv;  // events for pollers
+  std::map<int32_t, SrvSession*> sessions;
+  std::deque<int32_t> waitq;
+  std::deque<pf_server_event> events;
+  size_t used = 0;
+  int active = 0;
+  int32_t next_id = 1;
+  std::vector<hipStream_t> streams;
+  int next_stream = 0;
+  bool stop = false;
+  pf_server_stats stats{};
+  std::thread worker;
+};
+
+namespace {
+
+void free_session(pf_server* S, SrvSession* s) {
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->done) (void)hipEventDestroy(s->done);
+  if (s->host_info) (void)hipHostFree(s->host_info);
+  session_destroy(s->core);
+  if (s->resident) {
+    S->used -= s->footprint;
+    S->active--;
+  }
+  delete s;
+}
+
+// Admit s: allocate and initialise it on its stream (no device-wide sync).
+void admit(pf_server* S, SrvSession* s) {
+  s->stream = S->streams[S->next_stream];
+  S->next_stream = (S->next_stream + 1) % (int)S->streams.size();
+  PFX_HIP(hipEventCreateWithFlags(&s->done, hipEventDisableTiming));
+  PFX_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->host_info), sizeof(pf_info), hipHostMallocMapped));
+  PFX_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&s->host_info_dev), s->host_info, 0));
+  s->core = session_create(s->desc, s->U0, s->ldu0, s->seed, s->stream, false);
+  s->resident = true;
+  S->used += s->footprint;
+  S->active++;
+}
+
+void finish(pf_server* S, SrvSession* s, int32_t status, int32_t n_pos);
+void launch_step(pf_server* S, SrvSession* s, const Request& r, int64_t step);
+
+// Launch the next queued step of s (caller holds the mutex).  A failure to
+// enqueue finishes the step at once with its status.
+void launch(pf_server* S, SrvSession* s) {
+  Request r = s->pending.front();
+  s->pending.pop_front();
+  const int64_t step = s->core->steps;
+  try {
+    launch_step(S, s, r, step);
+  } catch (const Error& e) {
+    s->cur = InFlight{r, step, now_ns(), false};
+    finish(S, s, e.status, 0);
+  }
+}
+
+void launch_step(pf_server* S, SrvSession* s, const Request& r, int64_t step) {
+  const bool warm = step > 0;
+  bool graph = warm && !(S->cfg.flags & PF_SERVER_NO_GRAPHS) && !prof_enabled();
+  if (graph && !(s->exec && same_mat(s->g_xf, r.xf) && same_mat(s->g_xr, r.xr))) {
+    // capture the warm step on these operator buffers
+    if (s->exec) {
+      (void)hipGraphExecDestroy(s->exec);
+      s->exec = nullptr;
+    }
+    PFX_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    hipGraph_t g = nullptr;
+    try {
+      pf_desc d = s->desc;                          // warm: no cold-start flag
+      plan_set_desc(s->core->plan, d);
+      enqueue_extraction(s->core->plan, r.xf, r.xr, s->core->U, s->core->ldu, s->core->U, s->core->ldu,
+                         s->core->theta, s->core->info, s->stream);
+      launch_info_to_host(s->core->info, s->host_info_dev, s->stream);
+    } catch (...) {
+      (void)hipStreamEndCapture(s->stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    PFX_HIP(hipStreamEndCapture(s->stream, &g));
+    hipError_t e = hipGraphInstantiate(&s->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    PFX_HIP(e);
+    s->g_xf = r.xf;
+    s->g_xr = r.xr;
+    S->stats.captures++;
+  }
+  if (graph) {
+    PFX_HIP(hipGraphLaunch(s->exec, s->stream));
+    s->core->steps++;
+    S->stats.graph_launches++;
+  } else {
+    session_enqueue_step(s->core, r.xf, r.xr, s->stream);
+    launch_info_to_host(s->core->info, s->host_info_dev, s->stream);
+  }
+  PFX_HIP(hipEventRecord(s->done, s->stream));
+  s->busy = true;
+  s->cur = InFlight{r, step, now_ns(), graph};
+  S->stats.launched++;
+}
+
+void finish(pf_server* S, SrvSession* s, int32_t status, int32_t n_pos) {
+  pf_server_event ev{};
+  ev.session = s->id;
+  ev.status = status;
+  ev.n_pos = n_pos;
+  ev.graph = s->cur.graph ? 1 : 0;
+  ev.step = s->cur.step;
+  ev.tag = s->cur.req.tag;
+  ev.submit_ns = s->cur.req.submit_ns;
+  ev.launch_ns = s->cur.launch_ns;
+  ev.done_ns = now_ns();
+  S->events.push_back(ev);
+  S->stats.completed++;
+  s->busy = false;
+}
+
+void fail_request(pf_server* S, SrvSession* s, const Request& r, int32_t status) {
+  s->cur = InFlight{r, s->core ? s->core->steps : 0, now_ns(), false};
+  finish(S, s, status, 0);
+}
+
+void worker_loop(pf_server* S) {
+  (void)hipSetDevice(S->device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    bool progress = false;
+    // completions
+    for (auto& kv : S->sessions) {
+      SrvSession* s = kv.second;
+      if (!s->busy) continue;
+      const hipError_t q = hipEventQuery(s->done);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) {
+        finish(S, s, PF_ERR_DEVICE, 0);
+      } else {
+        const volatile pf_info* hi = s->host_info;
+        finish(S, s, hi->status, hi->n_pos);
+      }
+      progress = true;
+    }
+    // closes of drained sessions
+    for (auto it = S->sessions.begin(); it != S->sessions.end();) {
+      SrvSession* s = it->second;
+      if (s->closing && !s->busy && s->pending.empty()) {
+        if (!s->resident) {
+          for (auto w = S->waitq.begin(); w != S->waitq.end(); ++w)
+            if (*w == s->id) { S->waitq.erase(w); break; }
+        }
+        free_session(S, s);
+        it = S->sessions.erase(it);
+        progress = true;
+      } else {
+        ++it;
+      }
+    }
+    // admission in FIFO order
+    while (!S->waitq.empty()) {
+      SrvSession* s = S->sessions[S->waitq.front()];
+      if (S->used + s->footprint > S->cfg.hbm_budget || S->active >= S->cfg.max_active) break;
+      S->waitq.pop_front();
+      try {
+        admit(S, s);
+      } catch (const Error&) {
+        // could not allocate: fail its queued steps; it stays closed-out
+        while (!s->pending.empty()) {
+          fail_request(S, s, s->pending.front(), PF_ERR_NOMEM);
+          s->pending.pop_front();
+        }
+        s->closing = true;
+      }
+      progress = true;
+    }
+    // launches
+    for (auto& kv : S->sessions) {
+      SrvSession* s = kv.second;
+      if (!s->resident || s->busy || s->pending.empty()) continue;
+      launch(S, s);
+      progress = true;
+    }
+    if (!S->events.empty()) S->done_cv.notify_all();
+    if (S->stop) {
+      bool idle = S->waitq.empty();
+      for (auto& kv : S->sessions) idle = idle && !kv.second->busy && kv.second->pending.empty();
+      if (idle) break;
+    }
+    if (!progress) {
+      bool any_busy = false;
+      for (auto& kv : S->sessions) any_busy = any_busy || kv.second->busy;
+      // poll quickly while steps run; otherwise sleep until work arrives
+      if (any_busy) S->cv.wait_for(lk, std::chrono::microseconds(20));
+      else S->cv.wait_for(lk, std::chrono::milliseconds(5));
+    }
+  }
+  for (auto& kv : S->sessions) free_session(S, kv.second);
+  S->sessions.clear();
+  S->waitq.clear();
+  S->done_cv.notify_all();
+}
+
+}  // namespace
+
+// guarded() of capi.cpp is file-local; the server reports errors the same way.
+namespace pfx {
+pf_status run_guarded(const std::function<void()>& f);
+}
+
+extern "C" {
+
+pf_status pf_server_create(const pf_server_config* cfg, pf_server** out) {
+  return run_guarded([&] {
+    if (!cfg || !out) fail(PF_ERR_ARG, "NULL argument");
+    if (cfg->struct_size != sizeof(pf_server_config)) fail(PF_ERR_ARG, "pf_server_config.struct_size mismatch");
+    if (cfg->hbm_budget == 0) fail(PF_ERR_ARG, "pf_server_config.hbm_budget must be > 0");
+    if (cfg->max_active < 0 || cfg->streams < 0 || cfg->streams > 64) fail(PF_ERR_ARG, "bad server limits");
+    if (cfg->flags & ~PF_SERVER_NO_GRAPHS) fail(PF_ERR_ARG, "unknown bits in pf_server_config.flags");
+    pf_server* S = new pf_server();
+    S->cfg = *cfg;
+    if (S->cfg.max_active == 0) S->cfg.max_active = 64;
+    if (S->cfg.streams == 0) S->cfg.streams = 8;
+    try {
+      PFX_HIP(hipGetDevice(&S->device));
+      for (int i = 0; i < S->cfg.streams; ++i) {
+        hipStream_t st;
+        PFX_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));   // default priority
+        S->streams.push_back(st);
+      }
+      S->worker = std::thread(worker_loop, S);
+    } catch (...) {
+      for (hipStream_t st : S->streams) (void)hipStreamDestroy(st);
+      delete S;
+      throw;
+    }
+    *out = S;
+  });
+}
+
+pf_status pf_server_open(pf_server* S, const pf_desc* desc, const void* U0, int64_t ldu0, uint64_t seed,
+                         size_t operator_bytes, int32_t* session) {
+  return run_guarded([&] {
+    if (!S || !desc || !session) fail(PF_ERR_ARG, "NULL argument");
+    plan_validate(*desc, nullptr, nullptr);
+    if (U0 && ldu0 < desc->n) fail(PF_ERR_ARG, "ldu0 is smaller than n");
+    const size_t fp = session_bytes(*desc) + operator_bytes;
+    if (fp > S->cfg.hbm_budget) fail(PF_ERR_NOMEM, "session footprint exceeds the server's HBM budget");
+    SrvSession* s = new SrvSession();
+    s->desc = *desc;
+    s->footprint = fp;
+    s->U0 = U0;
+    s->ldu0 = ldu0;
+    s->seed = seed;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) {
+      delete s;
+      fail(PF_ERR_ARG, "server is shutting down");
+    }
+    s->id = S->next_id++;
+    S->sessions[s->id] = s;
+    S->waitq.push_back(s->id);
+    *session = s->id;
+    S->cv.notify_one();
+  });
+}
+
+pf_status pf_server_submit(pf_server* S, int32_t session, const pf_mat* X_filter, const pf_mat* X_rr,
+                           uint64_t tag) {
+  return run_guarded([&] {
+    if (!S) fail(PF_ERR_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->sessions.find(session);
+    if (it == S->sessions.end() || it->second->closing) fail(PF_ERR_ARG, "unknown or closing session");
+    plan_validate(it->second->desc, X_filter, X_rr);
+    it->second->pending.push_back(Request{*X_filter, *X_rr, tag, now_ns()});
+    S->cv.notify_one();
+  });
+}
+
+pf_status pf_server_poll(pf_server* S, pf_server_event* events, int32_t max, int32_t* count, int64_t timeout_ns) {
+  return run_guarded([&] {
+    if (!S || !count || (max > 0 && !events)) fail(PF_ERR_ARG, "NULL argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (S->events.empty() && timeout_ns > 0)
+      S->done_cv.wait_for(lk, std::chrono::nanoseconds(timeout_ns), [&] { return !S->events.empty(); });
+    int32_t n = 0;
+    while (n < max && !S->events.empty()) {
+      events[n++] = S->events.front();
+      S->events.pop_front();
+    }
+    *count = n;
+  });
+}
+
+pf_status pf_server_result(pf_server* S, int32_t session, pf_result* out) {
+  return run_guarded([&] {
+    if (!S || !out) fail(PF_ERR_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->sessions.find(session);
+    if (it == S->sessions.end() || !it->second->resident) fail(PF_ERR_ARG, "session is not resident");
+    SrvSession* s = it->second;
+    if (s->busy || !s->pending.empty()) fail(PF_ERR_BUSY, "session has steps queued or running");
+    out->status = s->host_info->status;
+    out->n_pos = s->host_info->n_pos;
+    out->theta = s->core->theta;
+    out->V = s->core->U;
+    out->ldv = s->core->ldu;
+    out->info = s->core->info;
+  });
+}
+
+pf_status pf_server_close(pf_server* S, int32_t session) {
+  return run_guarded([&] {
+    if (!S) fail(PF_ERR_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->sessions.find(session);
+    if (it == S->sessions.end() || it->second->closing) fail(PF_ERR_ARG, "unknown or closing session");
+    it->second->closing = true;
+    S->cv.notify_one();
+  });
+}
+
+pf_status pf_server_stats_get(pf_server* S, pf_server_stats* out) {
+  return run_guarded([&] {
+    if (!S || !out) fail(PF_ERR_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out = S->stats;
+    out->active = S->active;
+    out->waiting = (int32_t)S->waitq.size();
+    out->used_bytes = S->used;
+  });
+}
+
+pf_status pf_server_destroy(pf_server* S) {
+  return run_guarded([&] {
+    if (!S) fail(PF_ERR_ARG, "server is NULL");
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->stop = true;
+      for (auto& kv : S->sessions) kv.second->closing = true;
+      S->cv.notify_one();
+    }
+    S->worker.join();
+    for (hipStream_t st : S->streams) (void)hipStreamDestroy(st);
+    delete S;
+  });
+}
+
+}  // extern "C"

@@ -54,6 +54,26 @@ class PfResult(ctypes.Structure):
                 ("V", ctypes.c_void_p), ("ldv", ctypes.c_int64), ("info", ctypes.c_void_p)]
 
 
+PF_SERVER_NO_GRAPHS = 0x1
+
+
+class PfServerConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("hbm_budget", ctypes.c_size_t),
+                ("max_active", ctypes.c_int32), ("streams", ctypes.c_int32)]
+
+
+class PfServerEvent(ctypes.Structure):
+    _fields_ = [("session", ctypes.c_int32), ("status", ctypes.c_int32), ("n_pos", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("step", ctypes.c_int64), ("tag", ctypes.c_uint64),
+                ("submit_ns", ctypes.c_int64), ("launch_ns", ctypes.c_int64), ("done_ns", ctypes.c_int64)]
+
+
+class PfServerStats(ctypes.Structure):
+    _fields_ = [("active", ctypes.c_int32), ("waiting", ctypes.c_int32), ("used_bytes", ctypes.c_size_t),
+                ("launched", ctypes.c_int64), ("completed", ctypes.c_int64), ("graph_launches", ctypes.c_int64),
+                ("captures", ctypes.c_int64)]
+
+
 class PfError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{status_string(status)}: {msg}")
@@ -77,6 +97,14 @@ def _load():
         "pf_workspace_size": (i32, [P(PfDesc), P(ctypes.c_size_t)]),
         "pf_profile_set": (i32, [ctypes.c_int]),
         "pf_profile_read": (i32, [ctypes.c_int, P(i64), P(dbl)]),
+        "pf_server_create": (i32, [P(PfServerConfig), P(vp)]),
+        "pf_server_open": (i32, [vp, P(PfDesc), vp, i64, ctypes.c_uint64, ctypes.c_size_t, P(i32)]),
+        "pf_server_submit": (i32, [vp, i32, P(PfMat), P(PfMat), ctypes.c_uint64]),
+        "pf_server_poll": (i32, [vp, P(PfServerEvent), i32, P(i32), i64]),
+        "pf_server_result": (i32, [vp, i32, P(PfResult)]),
+        "pf_server_close": (i32, [vp, i32]),
+        "pf_server_stats_get": (i32, [vp, P(PfServerStats)]),
+        "pf_server_destroy": (i32, [vp]),
         "pf_status_string": (ctypes.c_char_p, [i32]),
         "pf_last_error": (ctypes.c_char_p, []),
         "pf_abi_version": (ctypes.c_int, []),
@@ -186,6 +214,55 @@ def pf_session_wait(h):
 
 def pf_session_close(h):
     _check(LIB.pf_session_close(h))
+
+
+def pf_server_create(hbm_budget, max_active=0, streams=0, flags=0):
+    c = PfServerConfig()
+    c.struct_size = ctypes.sizeof(PfServerConfig)
+    c.flags, c.hbm_budget, c.max_active, c.streams = flags, int(hbm_budget), max_active, streams
+    h = ctypes.c_void_p()
+    _check(LIB.pf_server_create(ctypes.byref(c), ctypes.byref(h)))
+    return h
+
+
+def pf_server_open(h, d, U0=None, seed=0, operator_bytes=0):
+    sid = ctypes.c_int32()
+    _check(LIB.pf_server_open(h, ctypes.byref(d), ctypes.c_void_p(U0.data_ptr()) if U0 is not None else None,
+                              ld_of(U0) if U0 is not None else 0, seed, int(operator_bytes), ctypes.byref(sid)))
+    return sid.value
+
+
+def pf_server_submit(h, session, X_filter, X_rr, tag=0):
+    xf, xr = mat(X_filter), mat(X_rr)
+    _check(LIB.pf_server_submit(h, session, ctypes.byref(xf), ctypes.byref(xr), tag))
+
+
+def pf_server_poll(h, max_events=256, timeout_s=0.0):
+    """Finished-step events (PfServerEvent), waiting up to timeout_s for the first."""
+    buf = (PfServerEvent * max_events)()
+    n = ctypes.c_int32()
+    _check(LIB.pf_server_poll(h, buf, max_events, ctypes.byref(n), int(timeout_s * 1e9)))
+    return [buf[i] for i in range(n.value)]
+
+
+def pf_server_result(h, session):
+    r = PfResult()
+    _check(LIB.pf_server_result(h, session, ctypes.byref(r)))
+    return r
+
+
+def pf_server_close(h, session):
+    _check(LIB.pf_server_close(h, session))
+
+
+def pf_server_stats(h):
+    st = PfServerStats()
+    _check(LIB.pf_server_stats_get(h, ctypes.byref(st)))
+    return st
+
+
+def pf_server_destroy(h):
+    _check(LIB.pf_server_destroy(h))
 
 
 def pf_quantize(dst, tile_scale, tile, dtype, src, stream=None):

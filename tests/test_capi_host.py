@@ -41,7 +41,9 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    structs = {"pf_desc": pf.PfDesc, "pf_mat": pf.PfMat, "pf_info": pf.PfInfo, "pf_result": pf.PfResult}
+    structs = {"pf_desc": pf.PfDesc, "pf_mat": pf.PfMat, "pf_info": pf.PfInfo, "pf_result": pf.PfResult,
+               "pf_server_config": pf.PfServerConfig, "pf_server_event": pf.PfServerEvent,
+               "pf_server_stats": pf.PfServerStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pf.h"', "int main(void){"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -161,3 +163,21 @@ def test_session_and_helpers_reject_nulls():
     d = good_desc()
     h = ctypes.c_void_p()
     assert pf.LIB.pf_session_open(ctypes.byref(d), ctypes.c_void_p(0x1000), 3, 0, ctypes.byref(h)) == pf.PF_ERR_ARG
+
+
+def test_server_rejects_bad_config():
+    """Configuration errors are found before any HIP call."""
+    for kw in (dict(hbm_budget=0), dict(hbm_budget=1 << 30, streams=65), dict(hbm_budget=1 << 30, max_active=-1),
+               dict(hbm_budget=1 << 30, flags=0x80)):
+        with pytest.raises(pf.PfError) as e:
+            pf.pf_server_create(**kw)
+        assert e.value.status == pf.PF_ERR_ARG
+    c = pf.PfServerConfig()
+    c.struct_size = 4
+    c.hbm_budget = 1 << 30
+    h = ctypes.c_void_p()
+    assert pf.LIB.pf_server_create(ctypes.byref(c), ctypes.byref(h)) == pf.PF_ERR_ARG
+    for fn, args in (("pf_server_open", (None, None, None, 0, 0, 0, None)), ("pf_server_submit", (None, 1, None, None, 0)),
+                     ("pf_server_close", (None, 1)), ("pf_server_destroy", (None,)),
+                     ("pf_server_result", (None, 1, None)), ("pf_server_stats_get", (None, None))):
+        assert getattr(pf.LIB, fn)(*args) == pf.PF_ERR_ARG, fn

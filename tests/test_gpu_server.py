@@ -1,0 +1,209 @@
+"""The serving loop (pf_server_*) on the GPU: graph replays and concurrent
+sessions give bitwise the results of eager pf_session stepping on the same
+inputs, a session's results do not depend on what runs beside it, and
+admission keeps the resident footprint within the HBM budget."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1904_10585_amd import workloads as wl
+from gpu_helpers import device_matrix, pf_module
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pf_module()
+
+
+class Case:
+    """One session: planted symmetric X (FP32, device), degree, interval."""
+
+    def __init__(self, n, p, d, idx):
+        self.n, self.p, self.d, self.idx = n, p, d, idx
+        r = max(1, p // 2)
+        X, _, _ = wl.planted(n, r, (4.0, 10.0), (-1.0, 0.5), config=110, index=idx)
+        self.X0 = X.astype(np.float32)
+        self.a, self.b = -1.0, 0.5
+
+    def fresh_x(self):
+        return device_matrix(self.X0, torch.float32)
+
+    def desc(self):
+        pf = pf_module()
+        return pf.desc(self.n, self.p, self.d, self.a, self.b, work=pf.PF_F32)
+
+    def perturb(self, Xd, k):
+        """X_k = X_{k-1} + 1e-3 sym(G)/sqrt(n), seeded by (session, step)."""
+        g = torch.Generator(device="cuda")
+        g.manual_seed(7919 * self.idx + k)
+        G = torch.randn((self.n, self.n), generator=g, device="cuda", dtype=torch.float32)
+        Xd.add_((G + G.t()) * (0.5e-3 / math.sqrt(self.n)))
+
+
+def read_result(pf, r, n, p):
+    th = pf.device_to_numpy(r.theta, (p,), np.float64)
+    V = pf.device_to_numpy(r.V, (p, r.ldv), np.float32).T[:n].copy()
+    return th, V
+
+
+def run_eager(cases, steps):
+    pf = pf_module()
+    out = {}
+    for c in cases:
+        X = c.fresh_x()
+        h = pf.pf_session_open(c.desc(), seed=c.idx)
+        res = []
+        for k in range(steps):
+            if k:
+                c.perturb(X, k)
+            pf.pf_session_step(h, X, X)
+            s, r = pf.pf_session_wait(h)
+            assert s == pf.PF_OK, s
+            res.append(read_result(pf, r, c.n, c.p))
+        torch.cuda.synchronize()
+        pf.pf_session_close(h)
+        out[c.idx] = res
+    return out
+
+
+def run_server(cases, steps, flags=0, streams=0):
+    """All sessions advance in lockstep: submit step k of every session,
+    wait for their events, read results, perturb every X, repeat."""
+    pf = pf_module()
+    srv = pf.pf_server_create(64 << 30, streams=streams, flags=flags)
+    try:
+        Xs = {c.idx: c.fresh_x() for c in cases}
+        ids = {c.idx: pf.pf_server_open(srv, c.desc(), seed=c.idx, operator_bytes=c.n * c.n * 4) for c in cases}
+        out = {c.idx: [] for c in cases}
+        graphs = {c.idx: [] for c in cases}
+        for k in range(steps):
+            torch.cuda.synchronize()
+            for c in cases:
+                pf.pf_server_submit(srv, ids[c.idx], Xs[c.idx], Xs[c.idx], tag=k)
+            got = {}
+            while len(got) < len(cases):
+                for ev in pf.pf_server_poll(srv, timeout_s=5.0):
+                    got[ev.session] = (ev.status, ev.step, ev.tag, ev.graph)
+            for c in cases:
+                st, step, tag, graph = got[ids[c.idx]]
+                assert st == pf.PF_OK and step == k and tag == k, (st, step, tag)
+                graphs[c.idx].append(graph)
+                out[c.idx].append(read_result(pf, pf.pf_server_result(srv, ids[c.idx]), c.n, c.p))
+            for c in cases:
+                if k + 1 < steps:
+                    c.perturb(Xs[c.idx], k + 1)
+        torch.cuda.synchronize()
+        stats = pf.pf_server_stats(srv)
+        for c in cases:
+            pf.pf_server_close(srv, ids[c.idx])
+    finally:
+        pf.pf_server_destroy(srv)
+    return out, graphs, stats
+
+
+CASES = [(1000, 16, 6, 1), (777, 32, 8, 2), (2048, 48, 10, 3), (300, 8, 4, 4), (1536, 96, 6, 5)]
+
+
+def test_server_graphs_match_eager_sessions():
+    """Warm steps replayed from captured graphs, with eager work (the X
+    perturbation, reads of every result) between replays, are bitwise the
+    eager session's steps."""
+    cases = [Case(*c) for c in CASES[:3]]
+    steps = 5
+    eager = run_eager(cases, steps)
+    served, graphs, stats = run_server(cases, steps)
+    for c in cases:
+        assert graphs[c.idx] == [0] + [1] * (steps - 1), graphs[c.idx]
+        for k in range(steps):
+            np.testing.assert_array_equal(served[c.idx][k][0], eager[c.idx][k][0], err_msg=f"theta {c.idx} {k}")
+            np.testing.assert_array_equal(served[c.idx][k][1], eager[c.idx][k][1], err_msg=f"V {c.idx} {k}")
+    assert stats.captures == len(cases) and stats.graph_launches == len(cases) * (steps - 1)
+
+
+def test_server_alone_equals_mix():
+    """A session's results are the same alone and among four others running
+    concurrently on the server's streams."""
+    steps = 4
+    alone, _, _ = run_server([Case(*CASES[0])], steps)
+    mix, _, _ = run_server([Case(*c) for c in CASES], steps)
+    idx = CASES[0][3]
+    for k in range(steps):
+        np.testing.assert_array_equal(alone[idx][k][0], mix[idx][k][0])
+        np.testing.assert_array_equal(alone[idx][k][1], mix[idx][k][1])
+
+
+def test_server_without_graphs_matches():
+    pf = pf_module()
+    cases = [Case(*CASES[1])]
+    a, ga, _ = run_server(cases, 3)
+    b, gb, _ = run_server([Case(*CASES[1])], 3, flags=pf.PF_SERVER_NO_GRAPHS)
+    assert gb[CASES[1][3]] == [0, 0, 0]
+    for k in range(3):
+        np.testing.assert_array_equal(a[CASES[1][3]][k][1], b[CASES[1][3]][k][1])
+
+
+def test_server_admission_within_budget():
+    """With room for two sessions, four sessions are served two at a time:
+    the others wait, and are admitted as closed sessions free memory."""
+    pf = pf_module()
+    n, p, steps = 512, 16, 3
+    d = pf.desc(n, p, 4, -1.0, 0.5, work=pf.PF_F32)
+    declared = 64 << 20                      # operator bytes each session declares
+    fp = pf.pf_workspace_size(d) + declared + (1 << 20)
+    budget = 2 * fp + fp // 2                 # two sessions fit, three do not
+    X = device_matrix(Case(n, p, 4, 9).X0, torch.float32)
+    srv = pf.pf_server_create(budget)
+    try:
+        ids = [pf.pf_server_open(srv, d, seed=i, operator_bytes=declared) for i in range(4)]
+        for sid in ids:
+            for k in range(steps):
+                pf.pf_server_submit(srv, sid, X, X, tag=k)
+        done = {sid: 0 for sid in ids}
+        max_active, saw_waiting = 0, False
+        order = []
+        while sum(done.values()) < 4 * steps:
+            st = pf.pf_server_stats(srv)
+            assert st.used_bytes <= budget
+            max_active = max(max_active, st.active)
+            saw_waiting = saw_waiting or st.waiting > 0
+            for ev in pf.pf_server_poll(srv, timeout_s=5.0):
+                assert ev.status == pf.PF_OK
+                done[ev.session] += 1
+                if done[ev.session] == steps:
+                    order.append(ev.session)
+                    pf.pf_server_close(srv, ev.session)
+        assert max_active == 2 and saw_waiting
+        assert sorted(order[:2]) == ids[:2]           # first come, first admitted
+    finally:
+        pf.pf_server_destroy(srv)
+
+
+def test_server_reports_step_errors_and_continues():
+    """A non-finite operator fails that session's step with its status; the
+    other session's steps are unaffected."""
+    pf = pf_module()
+    good, bad = Case(*CASES[3]), Case(300, 8, 4, 6)
+    Xg, Xb = good.fresh_x(), bad.fresh_x()
+    Xb[3, 5] = float("nan")
+    torch.cuda.synchronize()
+    srv = pf.pf_server_create(8 << 30)
+    try:
+        ig = pf.pf_server_open(srv, good.desc(), seed=1)
+        ib = pf.pf_server_open(srv, bad.desc(), seed=2)
+        for k in range(2):
+            pf.pf_server_submit(srv, ig, Xg, Xg, tag=k)
+            pf.pf_server_submit(srv, ib, Xb, Xb, tag=k)
+        evs = []
+        while len(evs) < 4:
+            evs += pf.pf_server_poll(srv, timeout_s=5.0)
+        for ev in evs:
+            want = pf.PF_OK if ev.session == ig else pf.PF_ERR_NONFINITE
+            assert ev.status == want, (ev.session, ev.status)
+    finally:
+        pf.pf_server_destroy(srv)
