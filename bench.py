@@ -342,6 +342,11 @@ def serve_main(args):
     def perturb(X, i, k):
         X.add_(E[X.shape[0]], alpha=1e-3 * float(zs[i, k]))     # E symmetric: X stays symmetric
 
+    # the client's own GPU work (operator copies and perturbations) runs on
+    # a non-blocking stream of its own and is synchronised per stream: a
+    # device-wide synchronisation could meet a graph capture of the server
+    cs = torch.cuda.Stream()
+
     def run(arrivals, label):
         srv = pf.pf_server_create(int(args.hbm_budget_gb * (1 << 30)), max_active=256, streams=8)
         Xs, ids, left, lat, step_bytes = {}, {}, {}, [], 0.0
@@ -363,13 +368,14 @@ def serve_main(args):
                 nxt += 1
                 n, p, d = int(ns[i]), int(ps[i]), int(ds[i])
                 a, b = wl.serving_interval(d)
-                Xs[i] = session_x(i)
+                with torch.cuda.stream(cs):
+                    Xs[i] = session_x(i)
                 dsc = pf.desc(n, p, d, a, b, work=pf.PF_F32)
                 ids[i] = pf.pf_server_open(srv, dsc, seed=i, operator_bytes=n * n * 4)
                 left[i] = steps
                 opened.append(i)
             if opened:
-                torch.cuda.synchronize()
+                cs.synchronize()
                 for i in opened:
                     pf.pf_server_submit(srv, ids[i], Xs[i], Xs[i], tag=i)
                 if first_submit is None:
@@ -391,13 +397,14 @@ def serve_main(args):
                 last_done = time.perf_counter()
                 left[i] -= 1
                 if left[i] > 0:
-                    perturb(Xs[i], i, steps - left[i])
+                    with torch.cuda.stream(cs):
+                        perturb(Xs[i], i, steps - left[i])
                     resubmit.append(i)
                 else:
                     pf.pf_server_close(srv, ids[i])
                     del Xs[i], ids[i]
             if resubmit:
-                torch.cuda.synchronize()
+                cs.synchronize()
                 for i in resubmit:
                     pf.pf_server_submit(srv, ids[i], Xs[i], Xs[i], tag=i)
             if done_steps and done_steps % 5000 < len(evs):

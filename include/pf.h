@@ -221,7 +221,10 @@ pf_status pf_session_close(pf_session* s);
  *  - Results of a session are bitwise the same whether it runs alone or in
  *    a mix (its kernels are deterministic and touch only its own buffers).
  * All pf_server_* calls are thread-safe.  Operator buffers passed to
- * pf_server_submit must stay valid and unmodified until that step's event. */
+ * pf_server_submit must stay valid and unmodified until that step's event.
+ * While a server runs, other threads synchronise their own streams or
+ * events, not the whole device: hipDeviceSynchronize fails while the worker
+ * is capturing a graph. */
 typedef struct pf_server pf_server;
 
 #define PF_SERVER_NO_GRAPHS 0x1u  /* launch warm steps eagerly, no capture */
