@@ -150,7 +150,10 @@ typedef struct pf_info {
   int32_t sweeps_rr;    /* Jacobi sweeps of the Rayleigh-Ritz eigensolve */
   int32_t sweeps_pre;   /* Jacobi sweeps of the pre-rotation */
   int32_t deficient;    /* columns replaced because the block lost rank */
-  int32_t reserved[3];
+  int32_t refine_rr;    /* refinement iterations of the Rayleigh-Ritz
+                           eigensolve (0 with sweeps_rr > 0: Jacobi ran) */
+  int32_t refine_pre;   /* refinement iterations of the pre-rotation */
+  int32_t reserved;
 } pf_info;
 
 /* One extraction (section 2.1 then eq. RR).

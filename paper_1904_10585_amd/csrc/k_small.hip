@@ -37,16 +37,16 @@ __device__ inline void set_status(pf_info* info, int code) {
 template <int PMAX>
 __global__ __launch_bounds__((PMAX / 4) * (PMAX / 4)) void chol_rinv_kernel(
     const double* __restrict__ G, int ldg, int p, double* __restrict__ Rinv, int ldr,
-    int* __restrict__ deficient, pf_info* info, int pass, double tol) {
+    int* __restrict__ deficient, pf_info* info, int pass, double tol, double near_tol) {
   constexpr int NBK = PMAX / 4;
   constexpr int NT = NBK * NBK;
   __shared__ __align__(16) double s_eq[PMAX], s_piv[PMAX], s_col[2][PMAX], s_row[2][PMAX];
   __shared__ int s_def[PMAX];
-  __shared__ int s_bad;
+  __shared__ int s_bad, s_far;
   const int t = threadIdx.x;
   const int bi = t / NBK, bj = t % NBK;
   const int i0 = 4 * bi, j0 = 4 * bj;
-  if (t == 0) s_bad = 0;
+  if (t == 0) { s_bad = 0; s_far = 0; }
   __syncthreads();
 
   double g[4][4], w[4][4];
@@ -83,6 +83,40 @@ __global__ __launch_bounds__((PMAX / 4) * (PMAX / 4)) void chol_rinv_kernel(
 #pragma unroll
     for (int c = 0; c < 4; ++c)
       if (i0 + r < p && j0 + c < p) g[r][c] *= si[r] * sj[c];
+
+  // Second CholeskyQR pass: the equilibrated Gram matrix of an already
+  // orthonormalised block is I + E with E small.  To first order
+  // chol(I + E) = I + U (U: strict upper part of E, diagonal E_ii / 2) and
+  // (I + U)^{-1} = I - U; the neglected terms are O(|E|^2), below the
+  // working precision when |E| <= near_tol.
+  if (near_tol > 0.0) {
+    double dev = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (i0 + r < p && j0 + c < p) dev = fmax(dev, fabs(g[r][c] - (i0 + r == j0 + c ? 1.0 : 0.0)));
+    if (!(dev <= near_tol)) s_far = 1;
+    __syncthreads();
+    if (!s_far) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int i = i0 + r, j = j0 + c;
+          if (i < p && j < p && i < ldr && j < ldr) {
+            const double u = i == j ? 0.5 * (g[r][c] - 1.0) : (i < j ? g[r][c] : 0.0);
+            Rinv[i + (int64_t)j * ldr] = si[r] * ((i == j ? 1.0 : 0.0) - u);
+          }
+        }
+      for (int idx = t; idx < ldr * ldr; idx += NT) {
+        const int i = idx % ldr, j = idx / ldr;
+        if (i >= p || j >= p) Rinv[idx] = 0.0;
+      }
+      for (int i = t; i < ldr; i += NT) deficient[i] = 0;
+      return;
+    }
+  }
 
   for (int k = 0; k < p; ++k) {
     const int buf = k & 1, kb = k >> 2, kr = k & 3;
@@ -205,7 +239,8 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ 
                                                      double* __restrict__ theta, double* __restrict__ Z,
                                                      int ldz, double* __restrict__ Vglob, pf_info* info,
                                                      int which, int max_sweeps, double tol_rel,
-                                                     int first_order) {
+                                                     int first_order, const int* skip) {
+  if (skip && *skip) return;                     // the refinement solved this matrix
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int pe = (p + 1) & ~1;
   const int half = pe / 2;
@@ -428,21 +463,198 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Eigen-refinement for a nearly diagonal H (the Rayleigh-Ritz matrix of a
+// warm step, the pre-rotation matrix).  Z starts at I and each iteration
+//   A = Z^T H Z,  K_ij = a_ij / (a_jj - a_ii)  (i != j; antisymmetric),
+//   Z <- Z (I + K + K^2 / 2),  Z <- Z (3 I - Z^T Z) / 2,
+// i.e. all plane rotations of a Jacobi sweep at once to first order (the
+// truncated exponential of K), followed by a Newton-Schulz step that
+// restores orthonormality.  Off-diagonal entries go from eps to
+// O(eps^2 / gap): the convergence is quadratic while every |a_ij| is small
+// against its gap.  When some |K_ij| exceeds 0.01 (eigenvalues close
+// against their coupling, or a cold start) the kernel reports failure and
+// the Jacobi kernel that follows solves H from scratch.  Every product is a
+// PP x PP FP64 MFMA contraction (v_mfma_f64_16x16x4f64) on LDS-resident
+// matrices (global scratch for PP = 128).
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// C = op(A) B for PP x PP column-major matrices (leading dimension LD),
+// op(A) = A^T when TA.  Wave w computes the output column blocks w, w+4, ...
+// with all PP/16 row tiles of a block at once: independent accumulators
+// hide the MFMA latency and share one B fragment per K step.
+// Lane l of a 16x16x4 FP64 MFMA holds A[l%16][l/16] and B[l/16][l%16];
+// accumulator j holds D[4j + l/16][l%16].
+template <int PP, int LD, bool TA>
+__device__ inline void gemm_pp(double* __restrict__ C, const double* __restrict__ A, const double* __restrict__ B,
+                               int wave, int lane) {
+  constexpr int NTL = PP / 16;
+  const int r = lane & 15, kq = lane >> 4;
+  for (int tj = wave; tj < NTL; tj += 4) {
+    const int jc = tj * 16 + r;
+    d4v acc[NTL];
+#pragma unroll
+    for (int ti = 0; ti < NTL; ++ti) acc[ti] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int kk = 0; kk < PP; kk += 4) {
+      const int k = kk + kq;
+      const double b = B[k + jc * LD];
+      double a[NTL];
+#pragma unroll
+      for (int ti = 0; ti < NTL; ++ti) {
+        const int i = ti * 16 + r;
+        a[ti] = TA ? A[k + i * LD] : A[i + k * LD];
+      }
+#pragma unroll
+      for (int ti = 0; ti < NTL; ++ti) acc[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b, acc[ti], 0, 0, 0);
+    }
+#pragma unroll
+    for (int ti = 0; ti < NTL; ++ti)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) C[(ti * 16 + 4 * j + kq) + jc * LD] = acc[ti][j];
+  }
+}
+
+template <int PMAX, bool SH>
+__global__ __launch_bounds__(256) void eig_refine_kernel(const double* __restrict__ H, int ldh, int p,
+                                                         double* __restrict__ theta, double* __restrict__ Z,
+                                                         int ldz, double* __restrict__ gscratch, int* refined,
+                                                         pf_info* info, int which, int max_iter) {
+  constexpr int PP = PMAX, LD = PP + 1, MS = PP * LD;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* buf;
+  if constexpr (SH) buf = reinterpret_cast<double*>(smem_raw);
+  else buf = gscratch;
+  double* Hs = buf;
+  double* Zc = buf + MS;
+  double* T1 = buf + 2 * MS;
+  double* T2 = buf + 3 * MS;
+  __shared__ double wsum[4];
+  __shared__ int s_rank[PMAX];
+  __shared__ double s_th[PMAX];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int lane = t & 63, wave = t >> 6;
+
+  double local = 0.0;
+  for (int idx = t; idx < PP * PP; idx += nt) {
+    const int i = idx % PP, j = idx / PP;
+    double v = 0.0;
+    if (i < p && j < p) v = 0.5 * (H[i + (int64_t)j * ldh] + H[j + (int64_t)i * ldh]);   // symmetrise
+    Hs[i + j * LD] = v;
+    Zc[i + j * LD] = i == j ? 1.0 : 0.0;
+    local += v * v;
+  }
+  local = wave_sum(local);
+  if (lane == 0) wsum[wave] = local;
+  __syncthreads();
+  const double fro = sqrt(wsum[0] + wsum[1] + wsum[2] + wsum[3]);
+  // Rayleigh-Ritz: off-diagonal entries below this are at the rounding
+  // level of the PP-term FP64 products that form A; the pre-rotation needs
+  // each column on its eigen-direction to 1e-10 only
+  const double tol = which == 1 ? 64.0 * 2.220446049250313e-16 * fro : 1e-10 * fro;
+
+  bool converged = false;
+  int it = 0;
+  for (;; ++it) {
+    gemm_pp<PP, LD, false>(T1, Hs, Zc, wave, lane);       // T1 = H Z
+    __syncthreads();
+    gemm_pp<PP, LD, true>(T2, Zc, T1, wave, lane);        // T2 = A = Z^T H Z
+    __syncthreads();
+    int above = 0, far = 0;
+    for (int idx = t; idx < PP * PP; idx += nt) {
+      const int i = idx % PP, j = idx / PP;
+      double k = 0.0;
+      if (i != j && i < p && j < p) {
+        const double aij = 0.5 * (T2[i + j * LD] + T2[j + i * LD]);
+        if (fabs(aij) > tol) {
+          above = 1;
+          const double gap = T2[j + j * LD] - T2[i + i * LD];
+          if (!(fabs(aij) <= 0.01 * fabs(gap))) far = 1;
+          else k = aij / gap;
+        }
+      }
+      T1[i + j * LD] = k;                                  // K (antisymmetric)
+    }
+    above = __syncthreads_or(above);
+    far = __syncthreads_or(far);
+    if (!above) { converged = true; break; }
+    if (far || it >= max_iter) break;
+    gemm_pp<PP, LD, false>(T2, T1, T1, wave, lane);       // T2 = K^2
+    __syncthreads();
+    for (int idx = t; idx < PP * PP; idx += nt) {
+      const int i = idx % PP, j = idx / PP;
+      T1[i + j * LD] = (i == j ? 1.0 : 0.0) + T1[i + j * LD] + 0.5 * T2[i + j * LD];   // M = I + K + K^2/2
+    }
+    __syncthreads();
+    gemm_pp<PP, LD, false>(T2, Zc, T1, wave, lane);       // T2 = Z M
+    __syncthreads();
+    gemm_pp<PP, LD, true>(T1, T2, T2, wave, lane);        // T1 = (Z M)^T (Z M)
+    __syncthreads();
+    for (int idx = t; idx < PP * PP; idx += nt) {
+      const int i = idx % PP, j = idx / PP;
+      T1[i + j * LD] = 0.5 * ((i == j ? 3.0 : 0.0) - T1[i + j * LD]);   // (3 I - Z^T Z) / 2
+    }
+    __syncthreads();
+    gemm_pp<PP, LD, false>(Zc, T2, T1, wave, lane);       // Z <- Z M (3 I - ...) / 2
+    __syncthreads();
+  }
+  if (!converged) {
+    if (t == 0) *refined = 0;
+    return;
+  }
+  // theta = diag(A) (Rayleigh quotients of the orthonormal columns of Z),
+  // sorted descending (NaN lowest, ties by index), Z columns permuted alike
+  for (int i = t; i < p; i += nt) s_th[i] = T2[i + i * LD];
+  __syncthreads();
+  for (int i = t; i < p; i += nt) {
+    const double ti = s_th[i];
+    const double ki = isnan(ti) ? -INFINITY : ti;
+    int rank = 0;
+    for (int j = 0; j < p; ++j) {
+      const double kj = isnan(s_th[j]) ? -INFINITY : s_th[j];
+      rank += (kj > ki) || (kj == ki && j < i);
+    }
+    theta[rank] = ti;
+    s_rank[rank] = i;
+  }
+  __syncthreads();
+  for (int idx = t; idx < ldz * ldz; idx += nt) {
+    const int row = idx % ldz, col = idx / ldz;
+    const int src = min(max(col < p ? s_rank[col] : 0, 0), p - 1);
+    Z[idx] = (row < p && col < p) ? Zc[row + src * LD] : (row == col ? 1.0 : 0.0);
+  }
+  if (t == 0) {
+    *refined = 1;
+    if (info) {
+      if (which == 1) {
+        int npos = 0;
+        for (int i = 0; i < p; ++i) npos += s_th[i] > 0.0;
+        info->n_pos = npos;
+        info->sweeps_rr = 0;
+        info->refine_rr = it;
+      } else {
+        info->sweeps_pre = 0;
+        info->refine_pre = it;
+      }
+    }
+  }
+}
+
 }  // namespace
 
 void launch_chol_rinv(const double* G, int ldg, int p, double* Rinv, int ldr, int* deficient,
-                      pf_info* info, int pass, hipStream_t st) {
+                      pf_info* info, int pass, hipStream_t st, double near_tol) {
   // Pivots of the equilibrated Gram are squared sines of the angle between a
   // column and the span of the previous ones.  Below 1e-10 (angle < 1e-5)
   // the column is treated as dependent: CholeskyQR2 reaches working
   // orthogonality only while cond(Y) stays well below 1/sqrt(eps).
   const double tol = 1e-10;
   if (p <= 32) {
-    chol_rinv_kernel<32><<<1, 64, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol);
+    chol_rinv_kernel<32><<<1, 64, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol, near_tol);
   } else if (p <= 64) {
-    chol_rinv_kernel<64><<<1, 256, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol);
+    chol_rinv_kernel<64><<<1, 256, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol, near_tol);
   } else {
-    chol_rinv_kernel<128><<<1, 1024, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol);
+    chol_rinv_kernel<128><<<1, 1024, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol, near_tol);
   }
   PFX_HIP(hipGetLastError());
 }
@@ -462,32 +674,59 @@ size_t jacobi_lds_bytes(int p) {
   return withv <= 160 * 1024 - 256 ? withv : base;   // static LDS: 36 bytes
 }
 
+size_t eig_scratch_bytes(int p) {
+  return p > 64 ? (size_t)4 * 128 * 129 * sizeof(double) + 256 : 256;
+}
+
 void launch_jacobi(const double* H, int ldh, int p, double* theta, double* Z, int ldz,
-                   double* Zwork, pf_info* info, int which, int max_sweeps, hipStream_t st) {
+                   double* Zwork, pf_info* info, int which, int max_sweeps, hipStream_t st, double* escratch,
+                   int* refined) {
   const size_t base = jacobi_base_bytes(p);
   const size_t lds = jacobi_lds_bytes(p);
   const bool v_in_lds = lds > base;
-  static size_t cur32 = 0, cur64 = 0, cur128 = 0, cur128g = 0;
+  static size_t cur32 = 0, cur64 = 0, cur128 = 0, cur128g = 0, ecur32 = 0, ecur64 = 0;
   // Rayleigh-Ritz: converge to FP64 resolution; pre-rotation: a rotation
   // accurate to 1e-10 keeps every FP32 recurrence column on its direction.
   const double tol_rel = which == 1 ? 1e-15 : 1e-10;
   const int fo = which == 0 ? 1 : 0;
+  const int* skip = nullptr;
+  if (refined) {
+    // quadratically convergent refinement first; the Jacobi kernel below
+    // returns at once when it succeeded
+    const int iters = 6;
+    if (p <= 32) {
+      const size_t e = (size_t)4 * 32 * 33 * 8;
+      ensure_lds((const void*)eig_refine_kernel<32, true>, e, ecur32);
+      eig_refine_kernel<32, true><<<1, 256, e, st>>>(H, ldh, p, theta, Z, ldz, escratch, refined, info, which,
+                                                     iters);
+    } else if (p <= 64) {
+      const size_t e = (size_t)4 * 64 * 65 * 8;
+      ensure_lds((const void*)eig_refine_kernel<64, true>, e, ecur64);
+      eig_refine_kernel<64, true><<<1, 256, e, st>>>(H, ldh, p, theta, Z, ldz, escratch, refined, info, which,
+                                                     iters);
+    } else {
+      eig_refine_kernel<128, false><<<1, 256, 0, st>>>(H, ldh, p, theta, Z, ldz, escratch, refined, info, which,
+                                                       iters);
+    }
+    PFX_HIP(hipGetLastError());
+    skip = refined;
+  }
   if (p <= 32) {
     ensure_lds((const void*)jacobi_kernel<32, true>, lds, cur32);
     jacobi_kernel<32, true><<<1, 256, lds, st>>>(H, ldh, p, theta, Z, ldz, Zwork, info, which, max_sweeps,
-                                                 tol_rel, fo);
+                                                 tol_rel, fo, skip);
   } else if (p <= 64) {
     ensure_lds((const void*)jacobi_kernel<64, true>, lds, cur64);
     jacobi_kernel<64, true><<<1, 256, lds, st>>>(H, ldh, p, theta, Z, ldz, Zwork, info, which, max_sweeps,
-                                                 tol_rel, fo);
+                                                 tol_rel, fo, skip);
   } else if (v_in_lds) {
     ensure_lds((const void*)jacobi_kernel<128, true>, lds, cur128);
     jacobi_kernel<128, true><<<1, 256, lds, st>>>(H, ldh, p, theta, Z, ldz, Zwork, info, which, max_sweeps,
-                                                  tol_rel, fo);
+                                                  tol_rel, fo, skip);
   } else {
     ensure_lds((const void*)jacobi_kernel<128, false>, lds, cur128g);
     jacobi_kernel<128, false><<<1, 256, lds, st>>>(H, ldh, p, theta, Z, ldz, Zwork, info, which, max_sweeps,
-                                                   tol_rel, fo);
+                                                   tol_rel, fo, skip);
   }
   PFX_HIP(hipGetLastError());
 }

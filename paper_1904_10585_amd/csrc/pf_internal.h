@@ -87,10 +87,17 @@ void launch_split_planes(const float* src, int64_t lds, int64_t n, int p, uint16
 
 // ---------------------------------------------------------------------------
 // Small dense kernels on p x p matrices (one workgroup each).
+// near_tol > 0: when the equilibrated G is within near_tol of I (a second
+// CholeskyQR pass), R^{-1} is written from the first-order factor directly.
 void launch_chol_rinv(const double* G, int ldg, int p, double* Rinv, int ldr,
-                      int* deficient, pf_info* info, int pass, hipStream_t st);
+                      int* deficient, pf_info* info, int pass, hipStream_t st, double near_tol = 0.0);
+// escratch / refined: scratch of eig_scratch_bytes(p) and one int; when
+// given, a quadratically convergent refinement runs first and the Jacobi
+// sweeps only where it reports failure.
 void launch_jacobi(const double* H, int ldh, int p, double* theta, double* Z, int ldz,
-                   double* Zwork, pf_info* info, int which, int max_sweeps, hipStream_t st);
+                   double* Zwork, pf_info* info, int which, int max_sweeps, hipStream_t st,
+                   double* escratch = nullptr, int* refined = nullptr);
+size_t eig_scratch_bytes(int p);
 size_t jacobi_lds_bytes(int p);
 
 // ---------------------------------------------------------------------------

@@ -21,6 +21,7 @@
 // column (section 2.1: rho(A) (U W) = (rho(A) U) W).
 #include "pf_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -48,6 +49,8 @@ struct Plan {
   double* Rinv;
   double* Zeig;
   double* Zwork;
+  double* Ework;      // scratch of the eigen-refinement (p > 64)
+  int* refined;       // set by the refinement when it converged
   double* theta;
   double* theta_pre;
   int* deficient;
@@ -74,7 +77,7 @@ namespace {
 struct Layout {
   size_t off_Up, off_Ypl[3], off_T = 0, off_Tpl = 0, off_B = 0;
   size_t off_U, off_Z, off_Y[3], off_Q1, off_Q, off_W, off_G, off_Rinv, off_Zeig, off_Zwork, off_theta,
-      off_theta_pre, off_def, off_info, off_part, total, part_bytes;
+      off_theta_pre, off_def, off_info, off_part, total, part_bytes, off_E, off_refined;
 };
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -99,6 +102,8 @@ Layout layout_for(const pf_desc& d) {
   L.off_Rinv = o; o += sq;
   L.off_Zeig = o; o += sq;
   L.off_Zwork = o; o += sq;
+  L.off_E = o; o += align256(eig_scratch_bytes(p_pad));
+  L.off_refined = o; o += 256;
   L.off_theta = o; o += align256((size_t)p_pad * 8);
   L.off_theta_pre = o; o += align256((size_t)p_pad * 8);
   L.off_def = o; o += align256((size_t)p_pad * 4);
@@ -244,6 +249,8 @@ Plan* plan_create(const pf_desc& d, hipStream_t zero_stream, bool async_zero) {
   P->Rinv = reinterpret_cast<double*>(b + L.off_Rinv);
   P->Zeig = reinterpret_cast<double*>(b + L.off_Zeig);
   P->Zwork = reinterpret_cast<double*>(b + L.off_Zwork);
+  P->Ework = reinterpret_cast<double*>(b + L.off_E);
+  P->refined = reinterpret_cast<int*>(b + L.off_refined);
   P->theta = reinterpret_cast<double*>(b + L.off_theta);
   P->theta_pre = reinterpret_cast<double*>(b + L.off_theta_pre);
   P->deficient = reinterpret_cast<int*>(b + L.off_def);
@@ -422,7 +429,7 @@ void filter_product(Plan* P, const pf_mat& Xf, const void* y, void* out, const v
     f.alpha = alpha; f.beta = beta; f.gamma = gamma;
     f.outp = want_planes ? planes_of(P, out) : nullptr; f.ldop = ld; f.oplane = P->plane;
     f.part = P->part; f.part_bytes = P->part_bytes;
-    f.prof_main = PF_PROF_FILTER; f.prof_reduce = PF_PROF_FILTER_REDUCE;
+      f.prof_main = PF_PROF_FILTER; f.prof_reduce = PF_PROF_FILTER_REDUCE;
     filter_bf16x6(f, st);
   } else {
     contract_into(P, Xf.data, Xf.ld, elem_of(Xf.dtype), y, ld, P->work, P->n, P->n, out, ld, P->work, D1, D2, ld,
@@ -492,7 +499,8 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
     void* y_cur;
     if (pass == 0 && !(d.flags & PF_FLAG_NO_PREROTATE)) {
       gram(P, cur, W, P->Z, W, P->G, st);
-      launch_jacobi(P->G, P->p_pad, P->p, P->theta_pre, P->Zeig, P->p_pad, P->Zwork, P->info, 0, 3, st);
+      launch_jacobi(P->G, P->p_pad, P->p, P->theta_pre, P->Zeig, P->p_pad, P->Zwork, P->info, 0, 3, st,
+                    P->Ework, P->refined);
       apply(P, cur, P->Z, P->Zeig, P->Yb[0], ld, P->Yb[1], a1, b1, nullptr, nullptr, st);
       y_prev = P->Yb[0];
       y_cur = P->Yb[1];
@@ -543,7 +551,10 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
   launch_chol_rinv(P->G, P->p_pad, P->p, P->Rinv, P->p_pad, P->deficient, P->info, 1, st);
   apply(P, cur, nullptr, P->Rinv, P->Q1, ld, nullptr, 0.0, 0.0, P->deficient, nullptr, st);
   gram(P, P->Q1, W, P->Q1, W, P->G, st);
-  launch_chol_rinv(P->G, P->p_pad, P->p, P->Rinv, P->p_pad, P->deficient, P->info, 2, st);
+  // the second pass sees I + E, |E| ~ cond(Y) * eps of the work precision:
+  // first order suffices once |E|^2 is below that precision
+  launch_chol_rinv(P->G, P->p_pad, P->p, P->Rinv, P->p_pad, P->deficient, P->info, 2, st,
+                   W == Elem::F64 ? 1e-8 : 3e-4);
   apply(P, P->Q1, nullptr, P->Rinv, P->Q, ld, nullptr, 0.0, 0.0, P->deficient, nullptr, st);
 
   // Rayleigh-Ritz in FP64 (eq. RR)
@@ -558,7 +569,8 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
                   0.0, 0.0, true, st, PF_PROF_RR, -1);
     gram(P, P->Q, W, P->W, Elem::F64, P->G, st);
   }
-  launch_jacobi(P->G, P->p_pad, P->p, P->theta, P->Zeig, P->p_pad, P->Zwork, P->info, 1, max_sweeps, st);
+  launch_jacobi(P->G, P->p_pad, P->p, P->theta, P->Zeig, P->p_pad, P->Zwork, P->info, 1, max_sweeps, st,
+                P->Ework, P->refined);
   apply(P, P->Q, nullptr, P->Zeig, U_out, ldu_out, nullptr, 0.0, 0.0, nullptr, P->info, st);
   if (info_out || theta_out) launch_info_copy(P->info, info_out, P->theta, theta_out, P->p, st);
   if (prof) prof_end(PF_PROF_EXTRACT, st);
