@@ -278,9 +278,16 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(DevArgs a) {
   if (i >= a.M) return;
   const TC* part = static_cast<const TC*>(a.part) + i + j * a.ldp;
   const int64_t slab = a.ldp * a.N;
-  // loads of 8 slabs in flight at a time, summed in slab order
+  // loads of 32 slabs in flight at a time, summed in slab order
   TC sum = TC(0);
   int s = 0;
+  for (; s + 32 <= a.splitk; s += 32) {
+    TC v[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) v[u] = part[(int64_t)(s + u) * slab];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) sum = (s + u == 0) ? v[u] : sum + v[u];
+  }
   for (; s + 8 <= a.splitk; s += 8) {
     TC v[8];
 #pragma unroll
@@ -323,7 +330,9 @@ Split plan_split(const Choice& ch, int64_t K, int64_t M, int64_t N, int requeste
   sp.ntiles = (N + 16 * ch.NB - 1) / (16 * ch.NB);
   const int64_t tiles = sp.mtiles * sp.ntiles;
   const int64_t unit = (int64_t)kWaves * ch.KSTEP;          // kchunk granularity
-  const int64_t min_chunk = unit * 4;                        // >= 4 steps per wave
+  // >= 4 steps per wave for wide outputs; a few-tile output (a p x p Gram
+  // product) needs many K slabs to occupy the GPU
+  const int64_t min_chunk = tiles <= 4 ? unit : unit * 4;
   int64_t S = requested > 0 ? requested : std::max<int64_t>(1, 1024 / std::max<int64_t>(1, tiles));
   S = std::min<int64_t>(S, std::max<int64_t>(1, (K + min_chunk - 1) / min_chunk));
   S = std::max<int64_t>(1, std::min<int64_t>(S, 256));
