@@ -216,6 +216,11 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
 // Pair k of round r of the round-robin order over pe (even) indices: index
 // pe-1 stays, the others rotate; every pair meets once in pe-1 rounds.
 __device__ inline void rr_pair(int r, int k, int pe, int& i, int& j) {
@@ -553,14 +558,24 @@ __global__ __launch_bounds__(256) void eig_refine_kernel(const double* __restric
   // each column on its eigen-direction to 1e-10 only
   const double tol = which == 1 ? 64.0 * 2.220446049250313e-16 * fro : 1e-10 * fro;
 
+  __shared__ double s_kmax[4];
   bool converged = false;
   int it = 0;
   for (;; ++it) {
-    gemm_pp<PP, LD, false>(T1, Hs, Zc, wave, lane);       // T1 = H Z
-    __syncthreads();
-    gemm_pp<PP, LD, true>(T2, Zc, T1, wave, lane);        // T2 = A = Z^T H Z
+    if (it == 0) {
+      // Z = I: A = H
+      for (int idx = t; idx < PP * PP; idx += nt) {
+        const int i = idx % PP, j = idx / PP;
+        T2[i + j * LD] = Hs[i + j * LD];
+      }
+    } else {
+      gemm_pp<PP, LD, false>(T1, Hs, Zc, wave, lane);     // T1 = H Z
+      __syncthreads();
+      gemm_pp<PP, LD, true>(T2, Zc, T1, wave, lane);      // T2 = A = Z^T H Z
+    }
     __syncthreads();
     int above = 0, far = 0;
+    double kmax = 0.0;
     for (int idx = t; idx < PP * PP; idx += nt) {
       const int i = idx % PP, j = idx / PP;
       double k = 0.0;
@@ -573,15 +588,34 @@ __global__ __launch_bounds__(256) void eig_refine_kernel(const double* __restric
           else k = aij / gap;
         }
       }
+      kmax = fmax(kmax, fabs(k));
       T1[i + j * LD] = k;                                  // K (antisymmetric)
     }
+    kmax = wave_max(kmax);
+    if (lane == 0) s_kmax[wave] = kmax;
     above = __syncthreads_or(above);
     far = __syncthreads_or(far);
-    // the pre-rotation only needs every column dominated by one
-    // eigen-direction: one step of the iteration (off-diagonal O(eps^2 /
-    // gap)) is enough once no coupling is large against its gap
-    if (!above || (which == 0 && it >= 1)) { converged = true; break; }
+    kmax = fmax(fmax(s_kmax[0], s_kmax[1]), fmax(s_kmax[2], s_kmax[3]));
+    if (!above) { converged = true; break; }
     if (far || it >= max_iter) break;
+    if (which == 0) {
+      // pre-rotation: the first-order eigenvectors Z = I + K (invertible, so
+      // the span is kept; each column on one eigen-direction to O(K^2)) and
+      // second-order eigenvalues theta_i = a_ii + sum_j a_ij K_ji
+      for (int idx = t; idx < PP * PP; idx += nt) {
+        const int i = idx % PP, j = idx / PP;
+        Zc[i + j * LD] = (i == j ? 1.0 : 0.0) + T1[i + j * LD];
+      }
+      for (int i = t; i < p; i += nt) {
+        double th = T2[i + i * LD];
+        for (int j = 0; j < p; ++j) th += T2[j + i * LD] * T1[j + i * LD];
+        T2[i + i * LD] = th;
+      }
+      __syncthreads();
+      converged = true;
+      break;
+    }
+    const bool small_k = kmax < 1e-4;
     gemm_pp<PP, LD, false>(T2, T1, T1, wave, lane);       // T2 = K^2
     __syncthreads();
     for (int idx = t; idx < PP * PP; idx += nt) {
@@ -589,8 +623,25 @@ __global__ __launch_bounds__(256) void eig_refine_kernel(const double* __restric
       T1[i + j * LD] = (i == j ? 1.0 : 0.0) + T1[i + j * LD] + 0.5 * T2[i + j * LD];   // M = I + K + K^2/2
     }
     __syncthreads();
-    gemm_pp<PP, LD, false>(T2, Zc, T1, wave, lane);       // T2 = Z M
+    if (it == 0) {
+      // Z = I: Z M = M
+      for (int idx = t; idx < PP * PP; idx += nt) {
+        const int i = idx % PP, j = idx / PP;
+        T2[i + j * LD] = T1[i + j * LD];
+      }
+    } else {
+      gemm_pp<PP, LD, false>(T2, Zc, T1, wave, lane);     // T2 = Z M
+    }
     __syncthreads();
+    if (small_k) {
+      // M is orthogonal to O(|K|^4) (M^T M = I + K^4 / 4): no re-orthonormalisation
+      for (int idx = t; idx < PP * PP; idx += nt) {
+        const int i = idx % PP, j = idx / PP;
+        Zc[i + j * LD] = T2[i + j * LD];
+      }
+      __syncthreads();
+      continue;
+    }
     gemm_pp<PP, LD, true>(T1, T2, T2, wave, lane);        // T1 = (Z M)^T (Z M)
     __syncthreads();
     for (int idx = t; idx < PP * PP; idx += nt) {
