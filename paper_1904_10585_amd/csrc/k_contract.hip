@@ -175,14 +175,20 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(DevArgs a) {
     const int64_t nfull = cols_full ? (ke - kb) / KSTEP : 0;
     const int64_t kfull_end = kb + nfull * KSTEP;
     if (nfull > 0) {
-      T cur, nxt;
-      cur.template load<false>(acol, aok, bcol, kb + goff, a.K);
-      for (int64_t k = kb; k < kfull_end; k += KSTEP) {
-        const int64_t kn = k + KSTEP;
-        if (kn < kfull_end) nxt.template load<false>(acol, aok, bcol, kn + goff, a.K);
-        cur.mma(acc);
-        cur = nxt;
+      // two fragment sets, next step's loads in flight during this step's
+      // MFMAs; no branch in the loop (the load past the end repeats the
+      // last step, in range, and is not used)
+      T t0, t1;
+      t0.template load<false>(acol, aok, bcol, kb + goff, a.K);
+      int64_t k = kb;
+      for (; k + 2 * KSTEP <= kfull_end; k += 2 * KSTEP) {
+        t1.template load<false>(acol, aok, bcol, k + KSTEP + goff, a.K);
+        t0.mma(acc);
+        const int64_t k2 = min(k + 2 * KSTEP, kfull_end - KSTEP);
+        t0.template load<false>(acol, aok, bcol, k2 + goff, a.K);
+        t1.mma(acc);
       }
+      if (k < kfull_end) t0.mma(acc);
     }
     for (int64_t k = kfull_end; k < ke; k += KSTEP) {
       T t;
@@ -311,7 +317,10 @@ Choice choose(Elem ta, Elem tb, bool f64_mfma, int64_t N) {
   Choice ch;
   ch.f64 = f64_mfma || ta == Elem::F64 || tb == Elem::F64;
   ch.NB = (int)(N / 16);
-  ch.MB = ch.NB <= 4 ? 4 : 2;
+  // FP64 accumulators take twice the registers: half the rows per wave, so
+  // that two waves fit a SIMD and no accumulator has to leave the registers
+  if (ch.f64) ch.MB = ch.NB <= 4 ? 2 : 1;
+  else ch.MB = ch.NB <= 4 ? 4 : 2;
   ch.VEC = (ta == Elem::F64 || tb == Elem::F64) ? 2 : 4;
   ch.KSTEP = 4 * ch.VEC;
   return ch;
@@ -368,6 +377,20 @@ void launch_tile(const DevArgs& d, const Split& sp, int prof_main, int prof_redu
 
 template <typename TA, typename TB, typename TO, bool F64>
 void dispatch_nb(const DevArgs& d, const Split& sp, int NB, int pm, int pr, hipStream_t st) {
+  if constexpr (F64) {
+    switch (NB) {
+      case 1: launch_tile<TA, TB, TO, F64, 2, 1>(d, sp, pm, pr, st); break;
+      case 2: launch_tile<TA, TB, TO, F64, 2, 2>(d, sp, pm, pr, st); break;
+      case 3: launch_tile<TA, TB, TO, F64, 2, 3>(d, sp, pm, pr, st); break;
+      case 4: launch_tile<TA, TB, TO, F64, 2, 4>(d, sp, pm, pr, st); break;
+      case 5: launch_tile<TA, TB, TO, F64, 1, 5>(d, sp, pm, pr, st); break;
+      case 6: launch_tile<TA, TB, TO, F64, 1, 6>(d, sp, pm, pr, st); break;
+      case 7: launch_tile<TA, TB, TO, F64, 1, 7>(d, sp, pm, pr, st); break;
+      case 8: launch_tile<TA, TB, TO, F64, 1, 8>(d, sp, pm, pr, st); break;
+      default: fail(PF_ERR_UNSUPPORTED, "contract: block width above 128 columns");
+    }
+    return;
+  }
   switch (NB) {
     case 1: launch_tile<TA, TB, TO, F64, 4, 1>(d, sp, pm, pr, st); break;
     case 2: launch_tile<TA, TB, TO, F64, 4, 2>(d, sp, pm, pr, st); break;
