@@ -32,15 +32,23 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 // (lane l holds A1[row0 + l%16][k + l/16] and S[k + l/16][16 nb + l%16];
 // the accumulator element r of lane l is row 4r + l/16, column l%16).
 template <typename T, int NB, bool TWO>
-__global__ __launch_bounds__(64) void apply_kernel(int64_t n, int p, const T* __restrict__ A1, int64_t lda1,
-                                                   const T* __restrict__ A2, int64_t lda2,
-                                                   const double* __restrict__ S, int lds_, T* C1, int64_t ldc1,
-                                                   T* C2, int64_t ldc2, double alpha, double beta,
-                                                   const int* __restrict__ deficient,
-                                                   const pf_info* gate) {
+__global__ __launch_bounds__(256) void apply_kernel(int64_t n, int p, const T* __restrict__ A1, int64_t lda1,
+                                                    const T* __restrict__ A2, int64_t lda2,
+                                                    const double* __restrict__ S, int lds_, T* C1, int64_t ldc1,
+                                                    T* C2, int64_t ldc2, double alpha, double beta,
+                                                    const int* __restrict__ deficient,
+                                                    const pf_info* gate) {
   if (gate && gate->status != 0) return;
-  const int l = threadIdx.x, c = l & 15, g = l >> 4;
-  const int64_t row0 = (int64_t)blockIdx.x * 16;
+  // S staged once per workgroup: row j of sS is column j of S
+  constexpr int PPD = 16 * NB;
+  __shared__ double sS[PPD][PPD + 1];
+  for (int idx = threadIdx.x; idx < PPD * PPD; idx += 256) {
+    const int k = idx % PPD, j = idx / PPD;
+    sS[j][k] = (k < p && j < p) ? S[k + (int64_t)j * lds_] : 0.0;
+  }
+  __syncthreads();
+  const int l = threadIdx.x & 63, c = l & 15, g = l >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * 64 + 16 * (threadIdx.x >> 6);
   const int64_t arow = row0 + c;
   const bool rok = arow < n;
   d4v acc1[NB], acc2[NB];
@@ -58,7 +66,7 @@ __global__ __launch_bounds__(64) void apply_kernel(int64_t n, int p, const T* __
     if constexpr (TWO) a2 = (rok && kok) ? (double)A2[arow + k * lda2] : 0.0;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const double b = kok ? S[k + (int64_t)(16 * nb + c) * lds_] : 0.0;
+      const double b = sS[16 * nb + c][k];          // zero past p
       acc1[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc1[nb], 0, 0, 0);
       if constexpr (TWO) acc2[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b, acc2[nb], 0, 0, 0);
     }
@@ -224,13 +232,13 @@ __global__ __launch_bounds__(256) void psd_dense_kernel(const T* __restrict__ V,
 template <typename T, bool TWO>
 void apply_t(const ApplyArgs& a, hipStream_t st) {
   const int nb = (a.p + 15) / 16;
-  const dim3 grid((unsigned)((a.n + 15) / 16));
+  const dim3 grid((unsigned)((a.n + 63) / 64));
   const T* A1 = static_cast<const T*>(a.A1);
   const T* A2 = static_cast<const T*>(a.A2);
   T* C1 = static_cast<T*>(a.C1);
   T* C2 = static_cast<T*>(a.C2);
 #define PFX_APPLY(NB)                                                                                    \
-  apply_kernel<T, NB, TWO><<<grid, 64, 0, st>>>(a.n, a.p, A1, a.lda1, A2, a.lda2, a.S, a.lds_, C1, a.ldc1, \
+  apply_kernel<T, NB, TWO><<<grid, 256, 0, st>>>(a.n, a.p, A1, a.lda1, A2, a.lda2, a.S, a.lds_, C1, a.ldc1, \
                                                 C2, a.ldc2, a.alpha, a.beta, a.deficient, a.gate)
   switch (nb) {
     case 1: PFX_APPLY(1); break;
