@@ -108,6 +108,10 @@ def main():
 
     if args.workload == "serving":
         return serve_main(args)
+    if args.workload == "planted_16384_bf16":
+        return precision_main(args)
+    if args.workload == "gram_12000x6000_fp8":
+        return gram_main(args)
     w = wl.WORKLOADS[args.workload]
     n, p, d = w.n, w.p, w.degree
     dev = "cuda"
@@ -212,7 +216,7 @@ def main():
                    "steps_chain": "X_k = X_{k-1} + 1e-3 sym(N(0,1))/sqrt(n)"},
         "hbm_GBps_algorithmic": round(bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
         "bytes_per_step_algorithmic": bytes_step,
-        "last_step_info": {"n_pos": int(info[1]), "sweeps_rr": int(info[2]), "sweeps_pre": int(info[3]),
+        "last_step_info": {"n_pos": int(info[1]), "dense_rr": int(info[2]), "dense_pre": int(info[3]),
                            "deficient": int(info[4])},
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
                        "p99": round(float(np.percentile(step_ms, 99)), 4),
@@ -280,6 +284,244 @@ def main():
                          "target": "planted top-64, warm steps, vs FP64 oracle fed the same U_in and X_k",
                          "tolerance": {"ritz_rel": 1e-5, "sin": 1e-4}}
     pf.pf_session_close(sess)
+    print(json.dumps(out), flush=True)
+
+
+def time_session(pf, torch, dsc, U0, ops, W, K, label):
+    """Open a session on U0, run W untimed warm-up steps and K timed steps on
+    the operand list ops[i] = (X_filter, X_rr) (resident); returns
+    (ms_per_step, step latencies ms, final result, session)."""
+    stream = torch.cuda.current_stream()
+    sess = pf.pf_session_open(dsc, U0)
+    for k in range(W):
+        pf.pf_session_step(sess, *ops[k], stream=stream)
+    s, _ = pf.pf_session_wait(sess)
+    if s != pf.PF_OK:
+        raise SystemExit(f"{label}: warm-up step failed: {pf.status_string(s)}")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for k in range(K):
+        pf.pf_session_step(sess, *ops[W + k], stream=stream)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    s, res = pf.pf_session_wait(sess)
+    if s != pf.PF_OK:
+        raise SystemExit(f"{label}: timed step failed: {pf.status_string(s)}")
+    lat = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(K)])
+    ms = ev[0].elapsed_time(ev[K]) / K
+    log(f"{label}: {ms:.3f} ms/step")
+    return ms, lat, res, sess
+
+
+def precision_main(args):
+    """Precision form: n=16384, p=128, degree 12, interval [-10, 0.8].  The
+    filter products read a BF16 copy of X_k (made by pf_quantize, timed on
+    its own as the a0 step), Rayleigh-Ritz reads the FP32 X_k in FP64.  The
+    same chain is run with the plain FP32 form (native FP32 MFMA products)
+    and with the exact BF16-split FP32 form for the speed comparison.
+    Parity: the oracle fed the dequantised copy for the filter and the FP32
+    X_k for Rayleigh-Ritz (same math), and the oracle on the FP32 X_k alone
+    (the quantisation floor)."""
+    import torch
+    from paper_1904_10585_amd import pf
+    from paper_1904_10585_amd import workloads as wl
+    torch.cuda.set_device(0)
+    w = wl.WORKLOADS["planted_16384_bf16"]
+    n, p, d = w.n, w.p, w.degree
+    dev = "cuda"
+    K, W = args.steps, args.warmup
+    # X0 = Q diag(lambda) Q^T built on the device in FP64 (Haar Q from a
+    # seeded normal matrix, lambda from the workload's seeded draw)
+    t0 = time.time()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(wl.SEED_ROOT * 10 + w.config)
+    G = torch.randn((n, n), generator=gen, device=dev, dtype=torch.float64)
+    Q, R = torch.linalg.qr(G)
+    Q = Q * torch.sign(torch.diagonal(R))
+    del G, R
+    lam = torch.from_numpy(wl.planted_eigenvalues(n, w.n_top, w.top, w.rest, wl.rng(w.config, wl.S_LAMBDA))).to(dev)
+    X = (Q * lam) @ Q.t()
+    X0 = (0.5 * (X + X.t())).float()
+    del X, Q
+    torch.cuda.synchronize()
+    log(f"precision form: planted X0 n={n} built on the device in {time.time() - t0:.1f}s")
+    total = W + K + args.cpu_steps + 1
+    Xs, Xb = [], []
+    scale = w.perturb * 0.5 / math.sqrt(n)
+    Xcur = X0
+    ldq = n
+    qa_ms = []
+    for k in range(total):
+        if k:
+            gen.manual_seed(wl.SEED_ROOT * 1000 + k)
+            Gk = torch.randn((n, n), generator=gen, device=dev, dtype=torch.float32)
+            Xcur = Xcur + (Gk + Gk.t()) * scale
+            del Gk
+        Xc = Xcur.t()                          # column-major view of symmetric X_k
+        Xs.append(Xc)
+        b = pf.colmajor(n, n, torch.bfloat16, dev, ld=ldq)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pf.pf_quantize(b, None, 0, pf.PF_BF16, Xc)
+        e1.record()
+        Xb.append(b)
+        torch.cuda.synchronize()
+        qa_ms.append(e0.elapsed_time(e1))
+    log(f"{total} FP32 matrices + BF16 copies resident ({total * n * n * 6 / 2**30:.1f} GiB)")
+    U0 = pf.colmajor(n, p, torch.float32, dev)
+    U0.copy_(torch.from_numpy(wl.start_block(n, p, w.config)).float())
+    forms = {}
+    dsc = pf.desc(n, p, d, w.a, w.b, work=pf.PF_F32)
+    ms_b, lat_b, res_b, sess_b = time_session(pf, torch, dsc, U0, list(zip(Xb, Xs)), W, K, "bf16 X filter")
+    forms["bf16"] = ms_b
+    ms_s, _, _, ss = time_session(pf, torch, dsc, U0, list(zip(Xs, Xs)), W, K, "fp32 (exact BF16 split)")
+    pf.pf_session_close(ss)
+    forms["f32_split"] = ms_s
+    dn = pf.desc(n, p, d, w.a, w.b, work=pf.PF_F32, flags=pf.PF_FLAG_NATIVE_F32)
+    ms_n, _, _, sn = time_session(pf, torch, dn, U0, list(zip(Xs, Xs)), W, K, "fp32 (native FP32 MFMA)")
+    pf.pf_session_close(sn)
+    forms["f32_native"] = ms_n
+    out = {
+        "metric": "extractions/s, BF16-X precision form (n=16384, p=128, d=12) vs the FP32 form",
+        "value": round(1000.0 / ms_b, 3),
+        "unit": "extractions/s",
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(ms_b, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 filter / f64 Rayleigh-Ritz",
+        "data": "synthetic planted-spectrum (seeded), resident in HBM",
+        "config": {"workload": w.name, "n": n, "p": p, "degree": d, "interval": [w.a, w.b]},
+        "forms_ms_per_step": {k: round(v, 4) for k, v in forms.items()},
+        "speedup_vs_native_f32": round(ms_n / ms_b, 3),
+        "speedup_vs_split_f32": round(ms_s / ms_b, 3),
+        "quantize_a0_ms": round(float(np.median(qa_ms)), 4),
+        "latency_ms": {"p50": round(float(np.percentile(lat_b, 50)), 4),
+                       "p99": round(float(np.percentile(lat_b, 99)), 4)},
+    }
+    if not args.no_cpu_baseline and args.cpu_steps > 0:
+        import oracle
+        Vg = pf.device_to_numpy(res_b.V, (p, res_b.ldv), np.float32).T[:n].astype(np.float64)
+        rels, sins, frels, fsins, cpu_t = [], [], [], [], []
+        theta_d = torch.zeros(p, dtype=torch.float64, device=dev)
+        r = w.n_top
+        for j in range(args.cpu_steps):
+            Xk, Bk = Xs[W + K + j], Xb[W + K + j]
+            Xh = Xk.t().contiguous().cpu().numpy().astype(np.float64)
+            Bh = oracle.bf16_round(Xh)                 # the oracle's own BF16 rounding of X_k
+            t1 = time.perf_counter()
+            ref = oracle.extract(Bh, Xh, Vg, d, w.a, w.b)
+            cpu_t.append(time.perf_counter() - t1)
+            floor = oracle.extract(Xh, Xh, Vg, d, w.a, w.b)
+            Ud = pf.colmajor(n, p, torch.float32, dev)
+            Ud.copy_(torch.from_numpy(Vg).float())
+            pf.pf_extract(dsc, Bk, Xk, Ud, theta_d)
+            torch.cuda.synchronize()
+            th = theta_d.cpu().numpy()
+            Vn = Ud.cpu().double().numpy()
+            Qg, _ = np.linalg.qr(Vn[:, :r])
+            rels.append(oracle.ritz_rel_err(th, ref["theta"], r))
+            sins.append(oracle.sin_theta(Qg, ref["V"][:, :r]))
+            frels.append(oracle.ritz_rel_err(th, floor["theta"], r))
+            fsins.append(oracle.sin_theta(Qg, floor["V"][:, :r]))
+            Vg = Vn
+            log(f"parity step {j}: same-math rel {rels[-1]:.2e} sin {sins[-1]:.2e}; "
+                f"vs FP32 X rel {frels[-1]:.2e} sin {fsins[-1]:.2e}")
+        out["cpu_baseline"] = {"value": round(len(cpu_t) / sum(cpu_t), 4), "unit": "extractions/s",
+                               "cores": blas_threads(), "kind": "oracle",
+                               "sample": f"{len(cpu_t)} FP64 oracle extractions (n={n}, p={p}, d={d})"}
+        out["parity"] = {"same_math": {"ritz_rel_max": float(max(rels)), "sin_max": float(max(sins))},
+                         "stated_error_vs_fp32_x": {"ritz_rel_max": float(max(frels)), "sin_max": float(max(fsins))},
+                         "tolerance": {"ritz_rel": 1e-5, "sin": 1e-4}}
+    pf.pf_session_close(sess_b)
+    print(json.dumps(out), flush=True)
+
+
+def gram_main(args):
+    """Gram form: singular pairs of M = A B^T + 0.01 N(0,1) (12000 x 6000,
+    rank 40) through A = M^T M with p=48, degree 8, interval [0, 4], scaled
+    recurrence.  M is held as FP8-E4M3 codes with per-128x128 scales for the
+    filter products (quantised once), Rayleigh-Ritz uses the FP32 M in
+    FP64; the session keeps its transposed copies (M fixed over the chain).
+    Also timed: the same chain with the FP32 M in the filter."""
+    import torch
+    from paper_1904_10585_amd import pf
+    from paper_1904_10585_amd import workloads as wl
+    torch.cuda.set_device(0)
+    w = wl.WORKLOADS["gram_12000x6000_fp8"]
+    m, n, p, d = w.extra["m"], w.n, w.p, w.degree
+    dev = "cuda"
+    K, W = args.steps, args.warmup
+    t0 = time.time()
+    M = wl.lowrank_plus_noise(m, n, w.extra["rank"], w.extra["noise"], w.config).astype(np.float32)
+    log(f"gram form: M {m}x{n} generated on host in {time.time() - t0:.1f}s")
+    Md = pf.colmajor(m, n, torch.float32, dev)
+    Md.copy_(torch.from_numpy(M))
+    ldq = -(-m // 16) * 16
+    codes = pf.colmajor(m, n, torch.uint8, dev, ld=ldq)
+    tm, tn = -(-m // 128), -(-n // 128)
+    scales = torch.zeros((tn, tm), dtype=torch.float32, device=dev).t()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    pf.pf_quantize(codes, scales, 128, pf.PF_F8E4M3, Md)
+    e1.record()
+    torch.cuda.synchronize()
+    qms = e0.elapsed_time(e1)
+    fro2 = float((Md.double() ** 2).sum())          # ||M||_F^2 >= sigma_max^2
+    U0 = pf.colmajor(n, p, torch.float32, dev)
+    U0.copy_(torch.from_numpy(wl.start_block(n, p, w.config)).float())
+    flags = pf.PF_FLAG_SCALED | pf.PF_FLAG_OPERATOR_UNCHANGED
+    dsc = pf.desc(n, p, d, w.a, w.b, work=pf.PF_F32, op=pf.PF_OP_GRAM, m=m, flags=flags, spec_ub=fro2)
+    fp8 = pf.mat(codes, scales, 128)
+    ops8 = [(fp8, Md)] * (W + K)
+    ms8, lat8, res8, s8 = time_session(pf, torch, dsc, U0, ops8, W, K, "gram fp8 M filter")
+    ms32, _, _, s32 = time_session(pf, torch, dsc, U0, [(Md, Md)] * (W + K), W, K, "gram fp32 M filter")
+    pf.pf_session_close(s32)
+    out = {
+        "metric": "extractions/s, nuclear-norm prox route: A = M^T M, M 12000x6000 FP8-E4M3 (p=48, d=8)",
+        "value": round(1000.0 / ms8, 3),
+        "unit": "extractions/s",
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(ms8, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp8 filter / f64 Rayleigh-Ritz",
+        "data": "synthetic rank-40 + noise M (seeded), resident in HBM",
+        "config": {"workload": w.name, "m": m, "n": n, "p": p, "degree": d, "interval": [w.a, w.b],
+                   "scaled": True, "spec_ub": "||M||_F^2"},
+        "forms_ms_per_step": {"fp8": round(ms8, 4), "f32": round(ms32, 4)},
+        "quantize_a0_ms": round(qms, 4),
+        "latency_ms": {"p50": round(float(np.percentile(lat8, 50)), 4),
+                       "p99": round(float(np.percentile(lat8, 99)), 4)},
+    }
+    if not args.no_cpu_baseline and args.cpu_steps > 0:
+        import oracle
+        r = w.n_top
+        Vg = pf.device_to_numpy(res8.V, (p, res8.ldv), np.float32).T[:n].astype(np.float64)
+        Mh = M.astype(np.float64)
+        cq, cs = oracle.fp8_tile_quantize(M, 128)
+        Mq = oracle.fp8_tile_dequantize(cq, cs, 128)
+        # the GPU's last step started from the V of the step before; rerun
+        # one step on the GPU from Vg and on the oracle from the same Vg
+        theta_d = torch.zeros(p, dtype=torch.float64, device=dev)
+        Ud = pf.colmajor(n, p, torch.float32, dev)
+        Ud.copy_(torch.from_numpy(Vg).float())
+        d1 = pf.desc(n, p, d, w.a, w.b, work=pf.PF_F32, op=pf.PF_OP_GRAM, m=m, flags=pf.PF_FLAG_SCALED,
+                     spec_ub=fro2)
+        pf.pf_extract(d1, fp8, Md, Ud, theta_d)
+        torch.cuda.synchronize()
+        th = theta_d.cpu().numpy()
+        t1 = time.perf_counter()
+        ref = oracle.extract_gram(Mq, Mh, Vg, d, w.a, w.b)
+        cpu_s = time.perf_counter() - t1
+        floor = oracle.extract_gram(Mh, Mh, Vg, d, w.a, w.b)
+        sg = np.sqrt(np.maximum(th[:r], 0))
+        out["parity"] = {"same_math_sigma_rel_max": float(np.max(np.abs(sg - ref["sigma"][:r]) / ref["sigma"][:r])),
+                         "stated_error_sigma_rel_max_vs_fp32_m":
+                             float(np.max(np.abs(sg - floor["sigma"][:r]) / floor["sigma"][:r])),
+                         "target": "top-40 singular values", "tolerance": {"ritz_rel": 1e-5}}
+        out["cpu_baseline"] = {"value": round(1.0 / cpu_s, 4), "unit": "extractions/s", "cores": blas_threads(),
+                               "kind": "oracle", "sample": f"1 FP64 oracle extraction (Gram route, m={m}, n={n})"}
+    pf.pf_session_close(s8)
     print(json.dumps(out), flush=True)
 
 

@@ -29,7 +29,7 @@
  *    NULL = the default stream).  They return as soon as the work is
  *    enqueued; argument errors are detected synchronously before any work
  *    is enqueued and leave every output untouched.
- *  - Numerical outcomes (Cholesky breakdown, Jacobi non-convergence,
+ *  - Numerical outcomes (Cholesky breakdown,
  *    non-finite data) are written by the device into a pf_info record
  *    once the stream reaches the end of the extraction.
  *  - No C++ exception crosses this boundary.  pf_last_error() returns a
@@ -55,7 +55,7 @@ typedef enum pf_status {
   PF_ERR_NOMEM = 2,       /* device or host allocation failed */
   PF_ERR_DEVICE = 3,      /* a HIP runtime call failed */
   PF_ERR_BREAKDOWN = 4,   /* Cholesky of the Gram matrix broke down */
-  PF_ERR_NOCONV = 5,      /* Jacobi eigensolver hit its sweep limit */
+  PF_ERR_NOCONV = 5,      /* reserved: the eigensolver is direct and always ends */
   PF_ERR_NONFINITE = 6,   /* Inf/NaN met in the filtered block */
   PF_ERR_BUSY = 7,        /* session has work in flight */
   PF_ERR_UNSUPPORTED = 8  /* valid request this build does not implement */
@@ -140,18 +140,19 @@ typedef struct pf_desc {
                        (> b); ignored otherwise */
   pf_dtype work;    /* PF_F64 or PF_F32: storage of U, Y, Q, V */
   uint32_t flags;
-  int32_t max_sweeps; /* Jacobi sweep limit (0 = default 30) */
+  int32_t reserved;   /* must be 0 */
 } pf_desc;
 
 /* Written by the device at the end of an extraction (device memory). */
 typedef struct pf_info {
   int32_t status;       /* pf_status of the numerical phase */
   int32_t n_pos;        /* #{theta_i > 0} */
-  int32_t sweeps_rr;    /* Jacobi sweeps of the Rayleigh-Ritz eigensolve */
-  int32_t sweeps_pre;   /* Jacobi sweeps of the pre-rotation */
+  int32_t dense_rr;     /* 1: the Rayleigh-Ritz eigensolve needed the dense
+                           solver (the refinement could not converge) */
+  int32_t dense_pre;    /* 1: the pre-rotation needed the dense solver */
   int32_t deficient;    /* columns replaced because the block lost rank */
   int32_t refine_rr;    /* refinement iterations of the Rayleigh-Ritz
-                           eigensolve (0 with sweeps_rr > 0: Jacobi ran) */
+                           eigensolve (meaningless when dense_rr = 1) */
   int32_t refine_pre;   /* refinement iterations of the pre-rotation */
   int32_t reserved;
 } pf_info;
@@ -285,6 +286,22 @@ pf_status pf_server_destroy(pf_server* s);
 pf_status pf_quantize(void* dst, int64_t ld_dst, float* tile_scale, int32_t tile,
                       pf_dtype dtype, const float* src, int64_t rows, int64_t cols,
                       int64_t ld_src, void* stream);
+
+/* The p x p eigenproblem of Rayleigh-Ritz (section 2.2, eq. RR) on its own:
+ * H = Z diag(theta) Z^T for the symmetric part (H + H^T)/2 of an FP64
+ * matrix, 1 <= p <= 128, by the solver an extraction falls back to (a
+ * direct dense solver in one workgroup: Householder tridiagonalisation,
+ * bisection, inverse iteration with reorthogonalisation in clusters).
+ *  H:     device, column-major p x p, ldh >= p; read only.
+ *  theta: device, p values, written in descending order.
+ *  Z:     device, column-major, ldz >= p; columns 0..p-1 (rows 0..p-1)
+ *         written with the orthonormal eigenvectors in theta's order.
+ * H and Z must not overlap.  Asynchronous on stream.  A non-finite entry
+ * in H gives NaN theta and Z = I; H = 0 gives theta = 0 and Z = I.
+ * Accuracy: |theta_i - lambda_i| and ||H z_i - theta_i z_i|| of a few
+ * eps ||H||, Z orthonormal to ~1e-13. */
+pf_status pf_eigh(const double* H, int64_t ldh, int32_t p, double* theta, double* Z, int64_t ldz,
+                  void* stream);
 
 /* Dense PSD projection P_+ = V_+ diag(theta_+) V_+^T (eq. PFAM1) from the
  * Ritz pairs of an extraction: out n-by-n (work dtype), ld_out >= n. */

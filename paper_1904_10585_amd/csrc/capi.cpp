@@ -2,6 +2,7 @@
 // per-stream workspace cache of pf_extract, and sessions.
 #include "pf_internal.h"
 
+#include <cstdint>
 #include <functional>
 #include <map>
 #include <mutex>
@@ -176,7 +177,7 @@ const char* pf_status_string(pf_status s) {
     case PF_ERR_NOMEM: return "PF_ERR_NOMEM: allocation failed";
     case PF_ERR_DEVICE: return "PF_ERR_DEVICE: HIP runtime error";
     case PF_ERR_BREAKDOWN: return "PF_ERR_BREAKDOWN: Cholesky of the Gram matrix broke down";
-    case PF_ERR_NOCONV: return "PF_ERR_NOCONV: Jacobi did not converge";
+    case PF_ERR_NOCONV: return "PF_ERR_NOCONV: an iteration did not converge";
     case PF_ERR_NONFINITE: return "PF_ERR_NONFINITE: non-finite values in the filtered block";
     case PF_ERR_BUSY: return "PF_ERR_BUSY: work in flight";
     case PF_ERR_UNSUPPORTED: return "PF_ERR_UNSUPPORTED: not implemented in this build";
@@ -339,6 +340,21 @@ pf_status pf_psd_dense(const void* V, int64_t ldv, const double* theta, int64_t 
     if (work != PF_F32 && work != PF_F64) fail(PF_ERR_ARG, "work must be F32 or F64");
     launch_psd_dense(V, ldv, work == PF_F64 ? Elem::F64 : Elem::F32, theta, n, p, out, ld_out,
                      static_cast<hipStream_t>(stream));
+  });
+}
+
+pf_status pf_eigh(const double* H, int64_t ldh, int32_t p, double* theta, double* Z, int64_t ldz, void* stream) {
+  return guarded([&] {
+    if (!H || !theta || !Z) fail(PF_ERR_ARG, "NULL argument");
+    if (p < 1 || p > 128) fail(PF_ERR_ARG, "p must be in [1, 128]");
+    if (ldh < p || ldz < p) fail(PF_ERR_ARG, "leading dimension smaller than p");
+    if (ldh > INT32_MAX || ldz > INT32_MAX) fail(PF_ERR_ARG, "leading dimension too large");
+    const char* h0 = reinterpret_cast<const char*>(H);
+    const char* h1 = h0 + ((size_t)(p - 1) * ldh + p) * sizeof(double);
+    const char* z0 = reinterpret_cast<const char*>(Z);
+    const char* z1 = z0 + ((size_t)(p - 1) * ldz + p) * sizeof(double);
+    if (h0 < z1 && z0 < h1) fail(PF_ERR_ARG, "H and Z overlap");
+    launch_eigh(H, (int)ldh, p, theta, Z, (int)ldz, p, nullptr, 1, static_cast<hipStream_t>(stream));
   });
 }
 

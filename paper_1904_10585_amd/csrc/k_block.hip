@@ -113,7 +113,7 @@ __global__ void axpby_kernel(const T* __restrict__ A, const T* __restrict__ B, T
 
 __global__ void info_init_kernel(pf_info* info) {
   if (threadIdx.x == 0) {
-    info->status = 0; info->n_pos = 0; info->sweeps_rr = 0; info->sweeps_pre = 0;
+    info->status = 0; info->n_pos = 0; info->dense_rr = 0; info->dense_pre = 0;
     info->deficient = 0; info->refine_rr = info->refine_pre = info->reserved = 0;
   }
 }

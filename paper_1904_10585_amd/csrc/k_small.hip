@@ -5,11 +5,11 @@
 //    D = diag(G)^{-1/2}, Cholesky D G D = L L^T, and R^{-1} = D L^{-T}.
 //    A pivot below tol marks the column rank-deficient: it is left out of
 //    the elimination and the caller replaces it (see k_block.hip).
-//  * jacobi: symmetric eigendecomposition H = Z diag(theta) Z^T (section
-//    2.2, eq. RR) by cyclic Jacobi in parallel (round-robin) order: each
-//    round rotates p/2 disjoint planes, p-1 rounds make a sweep, sweeps run
-//    until no off-diagonal entry is above the threshold.  Output sorted by
-//    descending theta (the paper's eigenvalue order).
+//  * eig_refine + syev: symmetric eigendecomposition H = Z diag(theta) Z^T
+//    (section 2.2, eq. RR), output sorted by descending theta (the paper's
+//    eigenvalue order).  A quadratically convergent refinement solves the
+//    nearly diagonal matrices of warm steps; a direct dense solver
+//    (tridiagonal reduction, bisection, inverse iteration) takes the rest.
 #include "pf_internal.h"
 
 #include <cmath>
@@ -200,17 +200,33 @@ __global__ __launch_bounds__((PMAX / 4) * (PMAX / 4)) void chol_rinv_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Jacobi.  LDS: A (pe x pe, row stride pe+1 so rows spread over banks),
-// V^T (row i = column i of V, so the plane rotations of V <- V J touch two
-// contiguous rows), rotation parameters per pair (structure of arrays) and
-// the list of 2x2 blocks (P, Q), P <= Q, each updated by one thread.
-//
-// first_order: when every off-diagonal entry is at most 1% of the gap of its
-// two diagonal entries (the pre-rotation of a warm step, where H is the
-// previous Ritz basis projected on a slightly perturbed matrix), the
-// eigenvectors to first order, Z = I + K with K_ij = h_ij / (h_jj - h_ii),
-// replace the sweeps; the pre-rotation needs only that each column is
-// dominated by one eigen-direction, and any invertible Z keeps the span.
+// Dense symmetric eigensolver H = Z diag(theta) Z^T for the p x p matrices of
+// an extraction (p <= PMAX <= 128), one workgroup of 8 * PMAX threads with
+// H in LDS.  It runs where the refinement below cannot (cold steps, guard
+// columns whose Ritz values crowd together), so its cost does not depend on
+// how far H is from diagonal:
+//  1. Householder reduction to tridiagonal T = Q^T H Q (H scaled by a power
+//     of two so that max |h_ij| is in [0.5, 1)).  Step k reflects column k
+//     with P = I - beta v v^T; the trailing block is updated as
+//     A <- A - v w^T - w v^T, y = beta A v, w = y - (beta/2)(v^T y) v.
+//     v overwrites column k below the diagonal.
+//  2. Eigenvalues of T by bisection on Sturm counts (the number of negative
+//     pivots of the LDL^T factorisation of T - x I, pivots kept away from
+//     zero by pivmin), eight-way: the eight lanes of a team count at seven
+//     interior points of the bracket, three bits per round.
+//  3. Eigenvectors of T by inverse iteration (three solves with the
+//     row-pivoted LU of T - lambda I from a fixed pseudo-random start).
+//     Eigenvalues closer than 1e-3 ||T|| form a cluster that one team
+//     takes in order, orthogonalising each iterate against the cluster's
+//     earlier vectors (modified Gram-Schmidt), shifts of coincident
+//     eigenvalues separated by 10 eps |lambda|.  A cluster that is an
+//     eigenspace to working accuracy (spread <= 1e-13 ||T||, e.g. the null
+//     space of a rank-deficient H) shares one shift just above it and is
+//     orthogonalised twice per step.
+//  4. Z = Q Z_T by applying the reflectors in reverse order.
+// Output: theta descending (the paper's order), Z's columns alike; Z holds
+// T's eigenvectors between steps 3 and 4, and its rows and columns p..pad-1
+// (pad >= p, pad <= ldz) are set to the identity.
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
@@ -221,253 +237,537 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-// Pair k of round r of the round-robin order over pe (even) indices: index
-// pe-1 stays, the others rotate; every pair meets once in pe-1 rounds.
-__device__ inline void rr_pair(int r, int k, int pe, int& i, int& j) {
-  if (k == 0) {
-    i = r;
-    j = pe - 1;
-  } else {
-    i = r + k;
-    if (i >= pe - 1) i -= pe - 1;
-    j = r - k;
-    if (j < 0) j += pe - 1;
-  }
-  if (i > j) { const int x = i; i = j; j = x; }
+__device__ inline double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
 }
 
-// VLDS: V^T lives in LDS (p <= 98); otherwise in the global work buffer.
-// Separate instantiations keep every LDS access a ds_* instruction (a
-// pointer that may be either would make them all flat accesses).
-template <int PMAX, bool VLDS>
-__global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ H, int ldh, int p,
-                                                     double* __restrict__ theta, double* __restrict__ Z,
-                                                     int ldz, double* __restrict__ Vglob, pf_info* info,
-                                                     int which, int max_sweeps, double tol_rel,
-                                                     int first_order, const int* skip) {
-  if (skip && *skip) return;                     // the refinement solved this matrix
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int pe = (p + 1) & ~1;
-  const int half = pe / 2;
-  const int nblk = half * (half + 1) / 2;
-  const int lda = pe + 1;
-  const int ldv = VLDS ? pe + 2 : pe;
-  double* A = reinterpret_cast<double*>(smem_raw);
-  double* rc = A + pe * lda;
-  double* rs = rc + half;
-  double* rt = rs + half;
-  double* dg = rt + half;                        // pe values
-  int* perm = reinterpret_cast<int*>(dg + pe);   // pe values
-  unsigned* blk = reinterpret_cast<unsigned*>(perm + pe);
-  double* VT;
-  if constexpr (VLDS) VT = reinterpret_cast<double*>(blk + ((nblk + 1) & ~1));
-  else VT = Vglob;
-  __shared__ double wsum[4];
-  __shared__ int not_diag;
-  const int t = threadIdx.x, nt = blockDim.x;
+// Lane moves inside rows of 16 lanes through DPP (a VALU operand modifier,
+// no LDS round trip): quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E,
+// row_half_mirror = 0x141, row_mirror = 0x140, row_shr:1 = 0x111 (lane i
+// takes lane i-1; the first lane of a row gets 0), row_shl:1 = 0x101.
+template <int CTRL>
+__device__ inline double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
-  double local = 0.0;
-  if (t == 0) not_diag = 0;
-  for (int idx = t; idx < pe * pe; idx += nt) {
-    const int j = idx / pe, i = idx - j * pe;    // coalesced over i
-    double v = 0.0;
-    if (i < p && j < p) v = 0.5 * (H[i + (int64_t)j * ldh] + H[j + (int64_t)i * ldh]);   // symmetrise
-    A[i * lda + j] = v;
-    VT[j * ldv + i] = (i == j) ? 1.0 : 0.0;
-    local += v * v;
-  }
-  for (int b = t; b < half * half; b += nt) {
-    const int P = b / half, Q = b - P * half;
-    if (P <= Q) blk[P * half - P * (P - 1) / 2 + (Q - P)] = ((unsigned)P << 16) | (unsigned)Q;
-  }
-  local = wave_sum(local);
-  if ((t & 63) == 0) wsum[t >> 6] = local;
-  __syncthreads();
-  const double fro = sqrt(wsum[0] + wsum[1] + wsum[2] + wsum[3]);   // fixed order
-  // below this an off-diagonal entry is rounding noise of the rotations
-  const double tol_abs = 2.220446049250313e-16 * fro;
+template <int CTRL>
+__device__ inline int dpp_mov_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
 
-  // the 2x2 blocks (P, Q), P <= Q, of pair space this thread updates
-  constexpr int BMAX = ((PMAX / 2) * (PMAX / 2 + 1) / 2 + 255) / 256;
-  int bP[BMAX], bQ[BMAX];
+// Sums over aligned groups of 8 / 16 lanes and over the wave; every lane of
+// the group gets the same value (each step adds commuting pairs).
+__device__ inline double sum8(double v) {
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x141>(v);
+  return v;
+}
+
+__device__ inline double sum16(double v) {
+  v = sum8(v);
+  v += dpp_mov<0x140>(v);
+  return v;
+}
+
+__device__ inline double sum64(double v) {
+  v = sum16(v);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+__device__ inline double lane0(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), 0);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 0);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 1/q: the hardware estimate and one Newton step (r += r (1 - q r)).
+__device__ inline double rcp_nr(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  return fma(fma(-q, r, 1.0), r, r);
+}
+
+// Number of eigenvalues of T below x (Sturm count on the pivots of T - x I).
+// The loads of four steps are issued ahead of their recurrence steps.
+__device__ inline int sturm_count(const double* d, const double* e2, int p, double x, double pivmin) {
+  double q = d[0] - x;
+  if (fabs(q) <= pivmin) q = -pivmin;
+  int c = q < 0.0;
+  int i = 1;
+  for (; i + 3 < p; i += 4) {
+    double dx[4], f[4];
 #pragma unroll
-  for (int u = 0; u < BMAX; ++u) {
-    const int b = t + u * nt;
-    const unsigned pq = blk[min(b, nblk - 1)];
-    bP[u] = b < nblk ? (int)(pq >> 16) : -1;
-    bQ[u] = (int)(pq & 0xFFFF);
+    for (int u = 0; u < 4; ++u) {
+      dx[u] = d[i + u] - x;
+      f[u] = e2[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      q = dx[u] - f[u] * rcp_nr(q);
+      if (fabs(q) <= pivmin) q = -pivmin;
+      c += q < 0.0;
+    }
   }
+  for (; i < p; ++i) {
+    q = (d[i] - x) - e2[i - 1] * rcp_nr(q);
+    if (fabs(q) <= pivmin) q = -pivmin;
+    c += q < 0.0;
+  }
+  return c;
+}
 
-  bool converged = false;
-  int sweep = 0;
-  if (first_order) {
-    for (int idx = t; idx < p * p; idx += nt) {
-      const int i = idx / p, j = idx - i * p;
-      if (i == j) continue;
-      const double aij = A[i * lda + j];
-      if (fabs(aij) > tol_abs && !(fabs(aij) <= 0.01 * fabs(A[j * lda + j] - A[i * lda + i]))) not_diag = 1;
+// Start vector of inverse iteration: entry i of vector j, uniform in (-1, 1)
+// from an integer mix of (i, j).
+__device__ inline double start_entry(int i, int j) {
+  uint32_t h = (uint32_t)i * 0x9E3779B1u + (uint32_t)j * 0x85EBCA77u + 0x165667B1u;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  h *= 0x297A2D39u;
+  h ^= h >> 15;
+  return (double)h * (2.0 / 4294967296.0) - 1.0;
+}
+
+template <int PMAX>
+__global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict__ H, int ldh, int p,
+                                                        double* __restrict__ theta, double* __restrict__ Z,
+                                                        int ldz, int pad, pf_info* info, int which,
+                                                        const int* skip) {
+  if (skip && *skip) return;                     // the refinement solved this matrix
+  constexpr int NT = 8 * PMAX;
+  constexpr int NW = NT / 64;
+  constexpr int LDA = PMAX + 1;
+  constexpr int R8 = PMAX / 8;                   // rows per lane of an 8-lane team
+  constexpr int R16 = PMAX / 16;                 // rows per lane of a 16-lane team
+  constexpr double EPS = 2.220446049250313e-16;
+  constexpr double SAFMIN = 2.2250738585072014e-308;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* A = reinterpret_cast<double*>(smem_raw);   // PMAX x LDA, row-major
+  __shared__ double s_d[PMAX], s_e[PMAX], s_e2[PMAX], s_beta[PMAX], s_v[PMAX], s_y[PMAX], s_lam[PMAX];
+  __shared__ double s_red[NW];
+  __shared__ double s_par[4];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int team = t >> 3, part = t & 7, base8 = lane & ~7;
+
+  // ---- load sym(H), find max |h_ij| and non-finite entries ----------------
+  double amax = 0.0;
+  int bad = 0;
+  for (int idx = t; idx < PMAX * PMAX; idx += NT) {
+    const int i = idx % PMAX, j = idx / PMAX;
+    double v = 0.0;
+    if (i < p && j < p) {
+      v = 0.5 * (H[i + (int64_t)j * ldh] + H[j + (int64_t)i * ldh]);
+      bad |= !isfinite(v);
+    }
+    A[i * LDA + j] = v;
+    amax = fmax(amax, fabs(v));
+  }
+  amax = wave_max(amax);
+  if (lane == 0) s_red[wave] = amax;
+  bad = __syncthreads_or(bad);
+  amax = 0.0;
+  for (int w = 0; w < NW; ++w) amax = fmax(amax, s_red[w]);
+  if (bad || amax == 0.0) {
+    // non-finite input: NaN Ritz values and a reported status; H = 0: zero
+    // eigenvalues with the identity as eigenvectors
+    for (int idx = t; idx < pad * pad; idx += NT) {
+      const int row = idx % pad, col = idx / pad;
+      Z[row + (int64_t)col * ldz] = row == col ? 1.0 : 0.0;
+    }
+    for (int i = t; i < p; i += NT) theta[i] = bad ? __builtin_nan("") : 0.0;
+    if (t == 0 && info) {
+      if (bad) set_status(info, PF_ERR_NONFINITE);
+      if (which == 1) {
+        info->n_pos = 0;
+        info->dense_rr = 1;
+      } else {
+        info->dense_pre = 1;
+      }
+    }
+    return;
+  }
+  int ex;
+  (void)frexp(amax, &ex);
+  const double scale = ldexp(1.0, ex);           // exact power-of-two scaling
+  const double sinv = ldexp(1.0, -ex);
+  for (int idx = t; idx < PMAX * PMAX; idx += NT) {
+    const int i = idx % PMAX, j = idx / PMAX;
+    A[i * LDA + j] *= sinv;                      // this thread's own entries
+  }
+  __syncthreads();
+
+  // ---- 1. Householder tridiagonalisation ----------------------------------
+  for (int k = 0; k + 2 < p; ++k) {
+    const int m = p - k - 1;                     // trailing size
+    if (wave == 0) {
+      const double xa = lane < m ? A[(k + 1 + lane) * LDA + k] : 0.0;
+      const double xb = lane + 64 < m ? A[(k + 1 + lane + 64) * LDA + k] : 0.0;
+      const double x0 = lane0(xa);
+      const double tail = sum64((lane == 0 ? 0.0 : xa * xa) + xb * xb);
+      double alpha = x0, beta = 0.0, v0 = x0;
+      if (tail != 0.0) {
+        const double nrm = sqrt(x0 * x0 + tail);
+        alpha = x0 >= 0.0 ? -nrm : nrm;
+        beta = 1.0 / (nrm * (nrm + fabs(x0)));
+        v0 = x0 - alpha;
+      }
+      if (lane < m) s_v[lane] = lane == 0 ? v0 : xa;
+      if (lane + 64 < m) s_v[lane + 64] = xb;
+      if (lane == 0) {
+        A[(k + 1) * LDA + k] = v0;
+        s_d[k] = A[k * LDA + k];
+        s_e[k] = alpha;
+        s_beta[k] = beta;
+      }
     }
     __syncthreads();
-    if (!not_diag) {
-      for (int idx = t; idx < p * p; idx += nt) {
-        const int j = idx / p, i = idx - j * p;
-        if (i == j) continue;
-        const double aij = A[i * lda + j];
-        VT[j * ldv + i] = fabs(aij) > tol_abs ? aij / (A[j * lda + j] - A[i * lda + i]) : 0.0;
+    const double beta = s_beta[k];
+    if (beta == 0.0) continue;                   // column already reduced
+    if (team < m) {
+      const double* row = A + (k + 1 + team) * LDA + (k + 1);
+      double acc = 0.0;
+#pragma unroll 4
+      for (int u = 0; u < R8; ++u) {
+        const int j = part + 8 * u;
+        if (j < m) acc += row[j] * s_v[j];
       }
-      for (int j = t; j < p; j += nt) {
-        double d = A[j * lda + j];
-        for (int i = 0; i < p; ++i) {
-          const double aij = A[i * lda + j];
-          if (i != j && fabs(aij) > tol_abs) d += aij * aij / (A[j * lda + j] - A[i * lda + i]);
-        }
-        dg[j] = d;
-      }
-      __syncthreads();
-      for (int j = t; j < p; j += nt) A[j * lda + j] = dg[j];
-      converged = true;
-      __syncthreads();
+      acc = sum8(acc);
+      if (part == 0) s_y[team] = beta * acc;
     }
+    __syncthreads();
+    double kv = (lane < m ? s_v[lane] * s_y[lane] : 0.0) + (lane + 64 < m ? s_v[lane + 64] * s_y[lane + 64] : 0.0);
+    kv = 0.5 * beta * sum64(kv);                 // same value in every wave
+    if (team < m) {
+      double* row = A + (k + 1 + team) * LDA + (k + 1);
+      const double vi = s_v[team], wi = s_y[team] - kv * vi;
+#pragma unroll 4
+      for (int u = 0; u < R8; ++u) {
+        const int j = part + 8 * u;
+        if (j < m) {
+          const double vj = s_v[j];
+          row[j] -= vi * (s_y[j] - kv * vj) + wi * vj;
+        }
+      }
+    }
+    __syncthreads();
   }
-
-  while (!converged) {
-    // a sweep runs only while some off-diagonal entry is above its threshold
-    int above = 0;
-    for (int idx = t; idx < p * p; idx += nt) {
-      const int i = idx / p, j = idx - i * p;
-      if (i < j) {
-        const double thr = fmax(tol_rel * sqrt(fabs(A[i * lda + i]) * fabs(A[j * lda + j])), tol_abs);
-        above |= fabs(A[i * lda + j]) > thr;
-      }
+  if (t == 0) {
+    if (p >= 2) {
+      s_d[p - 2] = A[(p - 2) * LDA + p - 2];
+      s_e[p - 2] = A[(p - 1) * LDA + p - 2];
+      s_beta[p - 2] = 0.0;
     }
-    above = __syncthreads_or(above);
-    if (!above) { converged = true; break; }
-    if (sweep >= max_sweeps) break;
-    ++sweep;
-    for (int r = 0; r < pe - 1; ++r) {
-      // rotation of each pair (one lane per pair, first wave only)
-      if (t < half) {
-        int i, j;
-        rr_pair(r, t, pe, i, j);
-        const double aii = A[i * lda + i], ajj = A[j * lda + j], aij = A[i * lda + j];
-        const double thr = fmax(tol_rel * sqrt(fabs(aii) * fabs(ajj)), tol_abs);
-        double c = 1.0, sn = 0.0, tt = 0.0;
-        if (fabs(aij) > thr) {
-          // tan of the rotation angle, smaller root: t = sign(d) x / (|d| + hypot(d, x))
-          const double d = ajj - aii, x = 2.0 * aij;
-          const double tq = x / (fabs(d) + sqrt(d * d + x * x));
-          tt = d >= 0.0 ? tq : -tq;
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          sn = tt * c;
-        }
-        rc[t] = c; rs[t] = sn; rt[t] = tt;
-      }
-      __syncthreads();
-      // A <- J^T A J on the 2x2 blocks of pairs (upper blocks mirrored): all
-      // loads of this thread's blocks, then the stores
-      {
-        double a11[BMAX], a12[BMAX], a21[BMAX], a22[BMAX];
-        int i1[BMAX], j1[BMAX], i2[BMAX], j2[BMAX], kind[BMAX];
-#pragma unroll
-        for (int u = 0; u < BMAX; ++u) {
-          const int P = max(bP[u], 0), Q = bQ[u];
-          rr_pair(r, P, pe, i1[u], j1[u]);
-          rr_pair(r, Q, pe, i2[u], j2[u]);
-          const double tP = rt[P], tQ = rt[Q];
-          const double c1 = rc[P], s1 = rs[P], c2 = rc[Q], s2 = rs[Q];
-          a11[u] = A[i1[u] * lda + i2[u]]; a12[u] = A[i1[u] * lda + j2[u]];
-          a21[u] = A[j1[u] * lda + i2[u]]; a22[u] = A[j1[u] * lda + j2[u]];
-          kind[u] = (bP[u] < 0 || (tP == 0.0 && tQ == 0.0)) ? 0 : (P == Q ? 1 : 2);
-          if (kind[u] == 1) {
-            a21[u] = tP;                                 // keep t of the pair
-          } else {
-            const double b11 = c2 * a11[u] - s2 * a12[u], b12 = s2 * a11[u] + c2 * a12[u];
-            const double b21 = c2 * a21[u] - s2 * a22[u], b22 = s2 * a21[u] + c2 * a22[u];
-            a11[u] = c1 * b11 - s1 * b21; a21[u] = s1 * b11 + c1 * b21;
-            a12[u] = c1 * b12 - s1 * b22; a22[u] = s1 * b12 + c1 * b22;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < BMAX; ++u) {
-          if (kind[u] == 0) continue;
-          const int x1 = i1[u], y1 = j1[u], x2 = i2[u], y2 = j2[u];
-          if (kind[u] == 1) {
-            // diagonal block of the pair: the rotation zeroes a_{x1 y1}
-            A[x1 * lda + x1] = a11[u] - a21[u] * a12[u];
-            A[y1 * lda + y1] = a22[u] + a21[u] * a12[u];
-            A[x1 * lda + y1] = 0.0;
-            A[y1 * lda + x1] = 0.0;
-          } else {
-            A[x1 * lda + x2] = a11[u]; A[x1 * lda + y2] = a12[u];
-            A[y1 * lda + x2] = a21[u]; A[y1 * lda + y2] = a22[u];
-            A[x2 * lda + x1] = a11[u]; A[y2 * lda + x1] = a12[u];
-            A[x2 * lda + y1] = a21[u]; A[y2 * lda + y1] = a22[u];
-          }
-        }
-      }
-      // V <- V J: eight threads per pair rotate a run of the two rows of V^T
-      {
-        constexpr int CH = PMAX / 8;                 // entries per thread and row
-        const int part = t & 7;
-        const int x0 = part * CH;
-        for (int k = t >> 3; k < half; k += nt >> 3) {
-          if (rt[k] == 0.0) continue;
-          int i, j;
-          rr_pair(r, k, pe, i, j);
-          const double c = rc[k], sn = rs[k];
-          double* __restrict__ vi = VT + i * ldv;
-          double* __restrict__ vj = VT + j * ldv;
-          double va[CH], vb[CH];
-#pragma unroll
-          for (int u = 0; u < CH; ++u) {            // clamped loads, predicated stores
-            const int x = min(x0 + u, pe - 1);
-            va[u] = vi[x];
-            vb[u] = vj[x];
-          }
-#pragma unroll
-          for (int u = 0; u < CH; ++u)
-            if (x0 + u < pe) { vi[x0 + u] = c * va[u] - sn * vb[u]; vj[x0 + u] = sn * va[u] + c * vb[u]; }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  const int sweeps_done = first_order && !not_diag ? 0 : sweep;
-
-  // Sort by descending theta, ties by index.  The key orders NaN below every
-  // number, so (key, index) is a strict total order even for non-finite
-  // input and the ranks are a permutation of 0..p-1.
-  for (int i = t; i < p; i += nt) {
-    const double ti = A[i * lda + i];
-    const double ki = isnan(ti) ? -INFINITY : ti;
-    int rank = 0;
-    for (int j = 0; j < p; ++j) {
-      const double tj = A[j * lda + j];
-      const double kj = isnan(tj) ? -INFINITY : tj;
-      rank += (kj > ki) || (kj == ki && j < i);
-    }
-    theta[rank] = ti;
-    perm[rank] = i;
+    s_d[p - 1] = A[(p - 1) * LDA + p - 1];
+    s_beta[p - 1] = 0.0;
   }
   __syncthreads();
-  for (int idx = t; idx < ldz * ldz; idx += nt) {
-    const int row = idx % ldz, col = idx / ldz;
-    const int src = min(max(col < p ? perm[col] : 0, 0), p - 1);
-    Z[idx] = (row < p && col < p) ? VT[src * ldv + row] : (row == col ? 1.0 : 0.0);
+
+  // ---- 2. eigenvalues: Gershgorin bracket, eight-way bisection -----------
+  if (wave == 0) {
+    double lo = INFINITY, hi = -INFINITY, e2max = 0.0;
+    for (int i = lane; i < p; i += 64) {
+      const double ea = i > 0 ? fabs(s_e[i - 1]) : 0.0;
+      const double eb = i < p - 1 ? fabs(s_e[i]) : 0.0;
+      lo = fmin(lo, s_d[i] - ea - eb);
+      hi = fmax(hi, s_d[i] + ea + eb);
+      if (i < p - 1) {
+        const double e2 = s_e[i] * s_e[i];
+        s_e2[i] = e2;
+        e2max = fmax(e2max, e2);
+      }
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    e2max = wave_max(e2max);
+    if (lane == 0) {
+      const double tnorm = fmax(fabs(lo), fabs(hi));
+      const double pivmin = SAFMIN * fmax(1.0, e2max);
+      const double widen = 2.1 * tnorm * EPS * p + 4.2 * pivmin;
+      s_par[0] = lo - widen;
+      s_par[1] = hi + widen;
+      s_par[2] = pivmin;
+      s_par[3] = tnorm;
+    }
+  }
+  __syncthreads();
+  const double pivmin = s_par[2], tnorm = s_par[3];
+  if (team < p) {
+    double lo = s_par[0], hi = s_par[1];
+    for (int it = 0; it < 40; ++it) {
+      if (hi - lo <= fmax(2.0 * EPS * fmax(fabs(lo), fabs(hi)), EPS * tnorm)) break;
+      const double w8 = (hi - lo) * 0.125;
+      const int cnt = part < 7 ? sturm_count(s_d, s_e2, p, lo + w8 * (double)(part + 1), pivmin) : p;
+      // first point with more than `team` eigenvalues below it
+      const unsigned bits = (unsigned)(__ballot(cnt > team) >> base8) & 0x7Fu;
+      const int first = bits ? __builtin_ctz(bits) : 7;
+      const double nlo = first == 0 ? lo : lo + w8 * (double)first;
+      const double nhi = first == 7 ? hi : lo + w8 * (double)(first + 1);
+      lo = nlo;
+      hi = nhi;
+    }
+    if (part == 0) s_lam[team] = 0.5 * (lo + hi);   // ascending
+  }
+  __syncthreads();
+
+  // ---- 3. inverse iteration: 16-lane teams, R16 rows per lane ------------
+  {
+    const int part16 = t & 15, r0 = part16 * R16;
+    const double ortol = 1e-3 * tnorm;
+    const double tiny = EPS * tnorm;
+    const int ldt = ldz;                         // T's eigenvectors go to Z first
+    double ur[R16], lm[R16], zr[R16];
+    unsigned pv = 0;
+    double sig = 0.0;
+    // row-pivoted LU of T - sig I, rows r0..r0+R16-1 on this lane:
+    // ur = 1/u_ii, lm = multiplier, pv = rows i, i+1 swapped.  The rest of U
+    // follows from these: u_{i,i+1} = d_{i+1} - sig after a swap, else the
+    // running super-diagonal (e_i, or -l_{i-1} e_i after a swap at i-1);
+    // u_{i,i+2} = e_{i+1} after a swap, else 0.
+    auto factor = [&]() {
+      pv = 0;
+      double ca = 0.0, cb = 0.0;
+#pragma unroll 1
+      for (int s = 0; s < 16; ++s) {
+        if (part16 == s) {
+          double a = s == 0 ? s_d[0] - sig : ca;
+          double b = s == 0 ? (p > 1 ? s_e[0] : 0.0) : cb;
+#pragma unroll
+          for (int u = 0; u < R16; ++u) {
+            const int i = r0 + u;
+            ur[u] = 0.0;
+            lm[u] = 0.0;
+            if (i < p - 1) {
+              const double c = s_e[i], an = s_d[i + 1] - sig;
+              const double bn = i + 1 < p - 1 ? s_e[i + 1] : 0.0;
+              if (fabs(a) >= fabs(c)) {
+                if (fabs(a) <= tiny) a = a >= 0.0 ? tiny : -tiny;
+                const double r = rcp_nr(a);
+                const double l = c * r;
+                ur[u] = r;
+                lm[u] = l;
+                a = an - l * b;
+                b = bn;
+              } else {
+                const double r = rcp_nr(c);
+                const double l = a * r;
+                ur[u] = r;
+                lm[u] = l;
+                pv |= 1u << u;
+                a = b - l * an;
+                b = -l * bn;
+              }
+            } else if (i == p - 1) {
+              if (fabs(a) <= tiny) a = a >= 0.0 ? tiny : -tiny;
+              ur[u] = rcp_nr(a);
+            }
+          }
+          ca = a;
+          cb = b;
+        }
+        ca = dpp_mov<0x111>(ca);                 // lane s+1 receives lane s's state
+        cb = dpp_mov<0x111>(cb);
+      }
+    };
+    // zr <- (T - sig I)^{-1} zr with the factors above
+    auto solve = [&]() {
+      // forward: y = L^{-1} P z (carry w = the running value of z_i)
+      const double znext = dpp_mov<0x101>(zr[0]);  // first row of the next lane
+      double w = 0.0;
+#pragma unroll 1
+      for (int s = 0; s < 16; ++s) {
+        if (part16 == s) {
+          double wi = s == 0 ? zr[0] : w;
+#pragma unroll
+          for (int u = 0; u < R16; ++u) {
+            const int i = r0 + u;
+            if (i < p - 1) {
+              double zn = u + 1 < R16 ? zr[u + 1] : znext;
+              double zi = wi;
+              if (pv & (1u << u)) {
+                const double tmp = zi;
+                zi = zn;
+                zn = tmp;
+              }
+              zr[u] = zi;
+              wi = zn - lm[u] * zi;
+            } else if (i == p - 1) {
+              zr[u] = wi;
+            }
+          }
+          w = wi;
+        }
+        w = dpp_mov<0x111>(w);
+      }
+      // back: x_i = (y_i - u2_i x_{i+1} - u3_i x_{i+2}) / u_ii
+      const double lprev = dpp_mov<0x111>(lm[R16 - 1]);   // last row of the previous lane
+      const unsigned pprev = ((unsigned)dpp_mov_i<0x111>((int)pv) >> (R16 - 1)) & 1u;
+      double x1 = 0.0, x2 = 0.0;
+#pragma unroll 1
+      for (int s = 15; s >= 0; --s) {
+        if (part16 == s) {
+          double a1 = x1, a2 = x2;
+#pragma unroll
+          for (int u = R16 - 1; u >= 0; --u) {
+            const int i = r0 + u;
+            if (i < p) {
+              const bool sw = (pv >> u) & 1u;
+              const bool swp = u > 0 ? ((pv >> (u - 1)) & 1u) : (i > 0 && pprev);
+              const double lp = u > 0 ? lm[u > 0 ? u - 1 : 0] : lprev;
+              double u2 = 0.0, u3 = 0.0;
+              if (i < p - 1) {
+                u2 = sw ? s_d[i + 1] - sig : (swp ? -lp * s_e[i] : s_e[i]);
+                if (sw && i + 1 < p - 1) u3 = s_e[i + 1];
+              }
+              const double xi = (zr[u] - u2 * a1 - u3 * a2) * ur[u];
+              zr[u] = xi;
+              a2 = a1;
+              a1 = xi;
+            }
+          }
+          x1 = a1;
+          x2 = a2;
+        }
+        x1 = dpp_mov<0x101>(x1);                 // lane s-1 receives lane s's rows
+        x2 = dpp_mov<0x101>(x2);
+      }
+    };
+    auto start = [&](int mm, int salt) {
+#pragma unroll
+      for (int u = 0; u < R16; ++u) zr[u] = r0 + u < p ? start_entry(r0 + u, mm + salt) : 0.0;
+    };
+    // orthogonalise zr against columns j..mm-1 (modified Gram-Schmidt,
+    // `passes` times), then normalise
+    auto orthonormalise = [&](int j, int mm, int passes, int it) {
+      for (int ps = 0; ps < passes; ++ps) {
+        for (int q = j; q < mm; ++q) {
+          const double* col = Z + (int64_t)q * ldt;
+          double dot = 0.0;
+#pragma unroll
+          for (int u = 0; u < R16; ++u)
+            if (r0 + u < p) dot += col[r0 + u] * zr[u];
+          dot = sum16(dot);
+#pragma unroll
+          for (int u = 0; u < R16; ++u)
+            if (r0 + u < p) zr[u] -= dot * col[r0 + u];
+        }
+      }
+      double ss = 0.0;
+#pragma unroll
+      for (int u = 0; u < R16; ++u) ss += zr[u] * zr[u];
+      ss = sum16(ss);
+      if (ss > 0.0 && ss < INFINITY) {
+        const double inv = 1.0 / sqrt(ss);
+#pragma unroll
+        for (int u = 0; u < R16; ++u) zr[u] *= inv;
+      } else {
+        start(mm, 7919 * (it + 1));
+      }
+    };
+    for (int pass = 0; pass < 2; ++pass) {
+      const int j = (t >> 4) + pass * (PMAX / 2);
+      if (j >= p) continue;
+      if (!(j == 0 || s_lam[j] - s_lam[j - 1] > ortol)) continue;   // not the first of its cluster
+      int end = j + 1;
+      while (end < p && !(s_lam[end] - s_lam[end - 1] > ortol)) ++end;
+      // A cluster whose eigenvalues agree to 1e-13 ||T|| is an eigenspace to
+      // working accuracy: one shift just above it amplifies the whole
+      // eigenspace alike (so successive iterates do not collapse onto one
+      // direction) and damps everything else by at least 1e-9 per solve.
+      const double spread = s_lam[end - 1] - s_lam[j];
+      const bool degen = end - j > 1 && spread <= 1e-13 * tnorm;
+      double sprev = 0.0;
+      for (int mm = j; mm < end; ++mm) {
+        if (!degen || mm == j) {
+          sig = s_lam[mm];
+          if (degen) sig = s_lam[end - 1] + 1e3 * fmax(spread, EPS * tnorm);
+          else if (mm > j && sig - sprev < 10.0 * EPS * fabs(sig)) sig = sprev + 10.0 * EPS * fabs(sig);
+          sprev = sig;
+          factor();
+        }
+        start(mm, 0);
+        const int nit = degen || end - j == 1 ? 2 : 3;   // isolated: two solves
+        for (int it = 0; it < nit; ++it) {
+          solve();
+          orthonormalise(j, mm, degen ? 2 : 1, it);
+        }
+#pragma unroll
+        for (int u = 0; u < R16; ++u)
+          if (r0 + u < p) Z[r0 + u + (int64_t)mm * ldt] = zr[u];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- 4. back-transform Z = Q Z_T, columns in descending order ----------
+  // 16-lane teams, columns j0 and j0 + PMAX/2 together; rows r = part16 + 16 u
+  {
+    const int part16 = t & 15;
+    const int j0 = t >> 4, j1 = j0 + PMAX / 2;
+    double z0[R16], z1[R16];
+#pragma unroll
+    for (int u = 0; u < R16; ++u) {
+      const int r = part16 + 16 * u;
+      z0[u] = j0 < p && r < p ? Z[r + (int64_t)j0 * ldz] : 0.0;
+      z1[u] = j1 < p && r < p ? Z[r + (int64_t)j1 * ldz] : 0.0;
+    }
+    __syncthreads();                             // every column read before any is rewritten
+    if (j0 < p) {
+      for (int k = p - 3; k >= 0; --k) {
+        const double b = s_beta[k];
+        if (b == 0.0) continue;
+        double a[R16];
+        double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+        for (int u = 0; u < R16; ++u) {
+          const int r = part16 + 16 * u;
+          a[u] = r > k && r < p ? A[r * LDA + k] : 0.0;
+          d0 += a[u] * z0[u];
+          d1 += a[u] * z1[u];
+        }
+        d0 = b * sum16(d0);
+        d1 = b * sum16(d1);
+#pragma unroll
+        for (int u = 0; u < R16; ++u) {
+          z0[u] -= d0 * a[u];
+          z1[u] -= d1 * a[u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < R16; ++u) {
+        const int r = part16 + 16 * u;
+        if (r < p) {
+          Z[r + (int64_t)(p - 1 - j0) * ldz] = z0[u];
+          if (j1 < p) Z[r + (int64_t)(p - 1 - j1) * ldz] = z1[u];
+        }
+      }
+      if (part16 == 0) {
+        theta[p - 1 - j0] = s_lam[j0] * scale;
+        if (j1 < p) theta[p - 1 - j1] = s_lam[j1] * scale;
+      }
+    }
+  }
+  for (int idx = t; idx < pad * pad; idx += NT) {
+    const int row = idx % pad, col = idx / pad;
+    if (row >= p || col >= p) Z[row + (int64_t)col * ldz] = row == col ? 1.0 : 0.0;
   }
   if (t == 0 && info) {
     if (which == 1) {
       int npos = 0;
-      for (int i = 0; i < p; ++i) npos += A[i * lda + i] > 0.0;
+      for (int i = 0; i < p; ++i) npos += s_lam[i] > 0.0;
       info->n_pos = npos;
-      info->sweeps_rr = sweeps_done;
-      if (!converged) set_status(info, PF_ERR_NOCONV);
+      info->dense_rr = 1;
     } else {
-      info->sweeps_pre = sweeps_done;
+      info->dense_pre = 1;
     }
   }
 }
-
 // ---------------------------------------------------------------------------
 // Eigen-refinement for a nearly diagonal H (the Rayleigh-Ritz matrix of a
 // warm step, the pre-rotation matrix).  Z starts at I and each iteration
@@ -479,7 +779,12 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ 
 // O(eps^2 / gap): the convergence is quadratic while every |a_ij| is small
 // against its gap.  When some |K_ij| exceeds 0.01 (eigenvalues close
 // against their coupling, or a cold start) the kernel reports failure and
-// the Jacobi kernel that follows solves H from scratch.  Every product is a
+// the dense solver that follows solves H from scratch.  The pre-rotation
+// leaves such a pair coupled instead when its two diagonal entries lie
+// within 1e-3 ||H||_F: columns with nearly equal Ritz values are amplified
+// alike by the filter, so mixing them costs no conditioning, and guard
+// columns in the dense unwanted part of the spectrum do crowd together.
+// Every product is a
 // PP x PP FP64 MFMA contraction (v_mfma_f64_16x16x4f64) on LDS-resident
 // matrices (global scratch for PP = 128).
 typedef double d4v __attribute__((ext_vector_type(4)));
@@ -584,8 +889,8 @@ __global__ __launch_bounds__(256) void eig_refine_kernel(const double* __restric
         if (fabs(aij) > tol) {
           above = 1;
           const double gap = T2[j + j * LD] - T2[i + i * LD];
-          if (!(fabs(aij) <= 0.01 * fabs(gap))) far = 1;
-          else k = aij / gap;
+          if (fabs(aij) <= 0.01 * fabs(gap)) k = aij / gap;
+          else if (!(which == 0 && fabs(gap) <= 1e-3 * fro)) far = 1;   // else: left coupled
         }
       }
       kmax = fmax(kmax, fabs(k));
@@ -684,10 +989,10 @@ __global__ __launch_bounds__(256) void eig_refine_kernel(const double* __restric
         int npos = 0;
         for (int i = 0; i < p; ++i) npos += s_th[i] > 0.0;
         info->n_pos = npos;
-        info->sweeps_rr = 0;
+        info->dense_rr = 0;
         info->refine_rr = it;
       } else {
-        info->sweeps_pre = 0;
+        info->dense_pre = 0;
         info->refine_pre = it;
       }
     }
@@ -713,39 +1018,16 @@ void launch_chol_rinv(const double* G, int ldg, int p, double* Rinv, int ldr, in
   PFX_HIP(hipGetLastError());
 }
 
-static size_t jacobi_base_bytes(int p) {
-  const int pe = (p + 1) & ~1;
-  const int half = pe / 2;
-  const int nblk = half * (half + 1) / 2;
-  return (size_t)pe * (pe + 1) * 8 + (size_t)half * 3 * 8 + (size_t)pe * (8 + 4) +
-         (size_t)((nblk + 1) & ~1) * 4;
-}
-
-size_t jacobi_lds_bytes(int p) {
-  const int pe = (p + 1) & ~1;
-  const size_t base = jacobi_base_bytes(p);
-  const size_t withv = base + (size_t)pe * (pe + 2) * 8;
-  return withv <= 160 * 1024 - 256 ? withv : base;   // static LDS: 36 bytes
-}
-
 size_t eig_scratch_bytes(int p) {
   return p > 64 ? (size_t)4 * 128 * 129 * sizeof(double) + 256 : 256;
 }
 
-void launch_jacobi(const double* H, int ldh, int p, double* theta, double* Z, int ldz,
-                   double* Zwork, pf_info* info, int which, int max_sweeps, hipStream_t st, double* escratch,
-                   int* refined) {
-  const size_t base = jacobi_base_bytes(p);
-  const size_t lds = jacobi_lds_bytes(p);
-  const bool v_in_lds = lds > base;
-  static size_t cur32 = 0, cur64 = 0, cur128 = 0, cur128g = 0, ecur32 = 0, ecur64 = 0;
-  // Rayleigh-Ritz: converge to FP64 resolution; pre-rotation: a rotation
-  // accurate to 1e-10 keeps every FP32 recurrence column on its direction.
-  const double tol_rel = which == 1 ? 1e-15 : 1e-10;
-  const int fo = which == 0 ? 1 : 0;
+void launch_eigh(const double* H, int ldh, int p, double* theta, double* Z, int ldz, int pad, pf_info* info,
+                 int which, hipStream_t st, double* escratch, int* refined) {
+  static size_t ecur32 = 0, ecur64 = 0, scur64 = 0, scur128 = 0;
   const int* skip = nullptr;
   if (refined) {
-    // quadratically convergent refinement first; the Jacobi kernel below
+    // quadratically convergent refinement first; the dense solver below
     // returns at once when it succeeded
     const int iters = 6;
     if (p <= 32) {
@@ -766,21 +1048,15 @@ void launch_jacobi(const double* H, int ldh, int p, double* theta, double* Z, in
     skip = refined;
   }
   if (p <= 32) {
-    ensure_lds((const void*)jacobi_kernel<32, true>, lds, cur32);
-    jacobi_kernel<32, true><<<1, 256, lds, st>>>(H, ldh, p, theta, Z, ldz, Zwork, info, which, max_sweeps,
-                                                 tol_rel, fo, skip);
+    syev_kernel<32><<<1, 256, (size_t)32 * 33 * 8, st>>>(H, ldh, p, theta, Z, ldz, pad, info, which, skip);
   } else if (p <= 64) {
-    ensure_lds((const void*)jacobi_kernel<64, true>, lds, cur64);
-    jacobi_kernel<64, true><<<1, 256, lds, st>>>(H, ldh, p, theta, Z, ldz, Zwork, info, which, max_sweeps,
-                                                 tol_rel, fo, skip);
-  } else if (v_in_lds) {
-    ensure_lds((const void*)jacobi_kernel<128, true>, lds, cur128);
-    jacobi_kernel<128, true><<<1, 256, lds, st>>>(H, ldh, p, theta, Z, ldz, Zwork, info, which, max_sweeps,
-                                                  tol_rel, fo, skip);
+    const size_t lds = (size_t)64 * 65 * 8;
+    ensure_lds((const void*)syev_kernel<64>, lds, scur64);
+    syev_kernel<64><<<1, 512, lds, st>>>(H, ldh, p, theta, Z, ldz, pad, info, which, skip);
   } else {
-    ensure_lds((const void*)jacobi_kernel<128, false>, lds, cur128g);
-    jacobi_kernel<128, false><<<1, 256, lds, st>>>(H, ldh, p, theta, Z, ldz, Zwork, info, which, max_sweeps,
-                                                   tol_rel, fo, skip);
+    const size_t lds = (size_t)128 * 129 * 8;
+    ensure_lds((const void*)syev_kernel<128>, lds, scur128);
+    syev_kernel<128><<<1, 1024, lds, st>>>(H, ldh, p, theta, Z, ldz, pad, info, which, skip);
   }
   PFX_HIP(hipGetLastError());
 }

@@ -91,14 +91,15 @@ void launch_split_planes(const float* src, int64_t lds, int64_t n, int p, uint16
 // CholeskyQR pass), R^{-1} is written from the first-order factor directly.
 void launch_chol_rinv(const double* G, int ldg, int p, double* Rinv, int ldr,
                       int* deficient, pf_info* info, int pass, hipStream_t st, double near_tol = 0.0);
-// escratch / refined: scratch of eig_scratch_bytes(p) and one int; when
-// given, a quadratically convergent refinement runs first and the Jacobi
-// sweeps only where it reports failure.
-void launch_jacobi(const double* H, int ldh, int p, double* theta, double* Z, int ldz,
-                   double* Zwork, pf_info* info, int which, int max_sweeps, hipStream_t st,
-                   double* escratch = nullptr, int* refined = nullptr);
+// Symmetric eigendecomposition of a p x p FP64 matrix (p <= 128), theta
+// descending, Z (ldz >= pad >= p) its eigenvectors, rows and columns
+// p..pad-1 of Z set to the identity.  escratch / refined: scratch of
+// eig_scratch_bytes(p) and one int; when given, a quadratically convergent
+// refinement runs first and the dense solver only where it reports failure.
+// which: 1 = Rayleigh-Ritz, 0 = pre-rotation (info fields and tolerances).
+void launch_eigh(const double* H, int ldh, int p, double* theta, double* Z, int ldz, int pad, pf_info* info,
+                 int which, hipStream_t st, double* escratch = nullptr, int* refined = nullptr);
 size_t eig_scratch_bytes(int p);
-size_t jacobi_lds_bytes(int p);
 
 // ---------------------------------------------------------------------------
 // Tall-skinny block operations (n x p blocks, p <= 128).
@@ -161,7 +162,7 @@ void plan_validate(const pf_desc& d, const pf_mat* Xf, const pf_mat* Xr);
 void enqueue_extraction(Plan* plan, const pf_mat& Xf, const pf_mat& Xr, const void* U_in,
                         int64_t ldu_in, void* U_out, int64_t ldu_out, double* theta_out,
                         pf_info* info_out, hipStream_t st);
-// refresh the numeric fields (interval, flags, sweeps) of a cached plan
+// refresh the numeric fields (interval, flags) of a cached plan
 void plan_set_desc(Plan* P, const pf_desc& d);
 // plan-owned buffers (for sessions)
 double* plan_theta(Plan* p);

@@ -48,7 +48,6 @@ struct Plan {
   double* G;
   double* Rinv;
   double* Zeig;
-  double* Zwork;
   double* Ework;      // scratch of the eigen-refinement (p > 64)
   int* refined;       // set by the refinement when it converged
   double* theta;
@@ -76,7 +75,7 @@ namespace {
 
 struct Layout {
   size_t off_Up, off_Ypl[3], off_T = 0, off_Tpl = 0, off_B = 0;
-  size_t off_U, off_Z, off_Y[3], off_Q1, off_Q, off_W, off_G, off_Rinv, off_Zeig, off_Zwork, off_theta,
+  size_t off_U, off_Z, off_Y[3], off_Q1, off_Q, off_W, off_G, off_Rinv, off_Zeig, off_theta,
       off_theta_pre, off_def, off_info, off_part, total, part_bytes, off_E, off_refined;
 };
 
@@ -101,7 +100,6 @@ Layout layout_for(const pf_desc& d) {
   L.off_G = o; o += sq;
   L.off_Rinv = o; o += sq;
   L.off_Zeig = o; o += sq;
-  L.off_Zwork = o; o += sq;
   L.off_E = o; o += align256(eig_scratch_bytes(p_pad));
   L.off_refined = o; o += 256;
   L.off_theta = o; o += align256((size_t)p_pad * 8);
@@ -194,7 +192,7 @@ void plan_validate(const pf_desc& d, const pf_mat* Xf, const pf_mat* Xr) {
   if (d.flags & ~(PF_FLAG_NO_PREROTATE | PF_FLAG_SCALED | PF_FLAG_COLD | PF_FLAG_NATIVE_F32 |
                   PF_FLAG_OPERATOR_UNCHANGED))
     fail(PF_ERR_ARG, "unknown bits in pf_desc.flags");
-  if (d.max_sweeps < 0) fail(PF_ERR_ARG, "pf_desc.max_sweeps must be >= 0");
+  if (d.reserved != 0) fail(PF_ERR_ARG, "pf_desc.reserved must be 0");
   if (Xf || Xr) {
     const int64_t rows = d.op == PF_OP_GRAM ? d.m : d.n;
     check_mat(Xf, "X_filter", rows);
@@ -248,7 +246,6 @@ Plan* plan_create(const pf_desc& d, hipStream_t zero_stream, bool async_zero) {
   P->G = reinterpret_cast<double*>(b + L.off_G);
   P->Rinv = reinterpret_cast<double*>(b + L.off_Rinv);
   P->Zeig = reinterpret_cast<double*>(b + L.off_Zeig);
-  P->Zwork = reinterpret_cast<double*>(b + L.off_Zwork);
   P->Ework = reinterpret_cast<double*>(b + L.off_E);
   P->refined = reinterpret_cast<int*>(b + L.off_refined);
   P->theta = reinterpret_cast<double*>(b + L.off_theta);
@@ -467,7 +464,6 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
   host_coefficients(d, tau);
   const Elem W = P->work;
   const Elem tr = elem_of(Xr.dtype);
-  const int max_sweeps = d.max_sweeps > 0 ? d.max_sweeps : 30;
   const int64_t ld = P->n_pad;
 
   const bool prof = prof_enabled();
@@ -499,8 +495,8 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
     void* y_cur;
     if (pass == 0 && !(d.flags & PF_FLAG_NO_PREROTATE)) {
       gram(P, cur, W, P->Z, W, P->G, st);
-      launch_jacobi(P->G, P->p_pad, P->p, P->theta_pre, P->Zeig, P->p_pad, P->Zwork, P->info, 0, 3, st,
-                    P->Ework, P->refined);
+      launch_eigh(P->G, P->p_pad, P->p, P->theta_pre, P->Zeig, P->p_pad, P->p_pad, P->info, 0, st, P->Ework,
+                  P->refined);
       apply(P, cur, P->Z, P->Zeig, P->Yb[0], ld, P->Yb[1], a1, b1, nullptr, nullptr, st);
       y_prev = P->Yb[0];
       y_cur = P->Yb[1];
@@ -569,8 +565,7 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
                   0.0, 0.0, true, st, PF_PROF_RR, -1);
     gram(P, P->Q, W, P->W, Elem::F64, P->G, st);
   }
-  launch_jacobi(P->G, P->p_pad, P->p, P->theta, P->Zeig, P->p_pad, P->Zwork, P->info, 1, max_sweeps, st,
-                P->Ework, P->refined);
+  launch_eigh(P->G, P->p_pad, P->p, P->theta, P->Zeig, P->p_pad, P->p_pad, P->info, 1, st, P->Ework, P->refined);
   apply(P, P->Q, nullptr, P->Zeig, U_out, ldu_out, nullptr, 0.0, 0.0, nullptr, P->info, st);
   if (info_out || theta_out) launch_info_copy(P->info, info_out, P->theta, theta_out, P->p, st);
   if (prof) prof_end(PF_PROF_EXTRACT, st);

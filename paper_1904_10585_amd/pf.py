@@ -40,12 +40,12 @@ class PfDesc(ctypes.Structure):
                 ("m", ctypes.c_int64), ("p", ctypes.c_int32), ("degree", ctypes.c_int32),
                 ("q", ctypes.c_int32), ("a", ctypes.c_double), ("b", ctypes.c_double),
                 ("spec_ub", ctypes.c_double), ("work", ctypes.c_int), ("flags", ctypes.c_uint32),
-                ("max_sweeps", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32)]
 
 
 class PfInfo(ctypes.Structure):
-    _fields_ = [("status", ctypes.c_int32), ("n_pos", ctypes.c_int32), ("sweeps_rr", ctypes.c_int32),
-                ("sweeps_pre", ctypes.c_int32), ("deficient", ctypes.c_int32),
+    _fields_ = [("status", ctypes.c_int32), ("n_pos", ctypes.c_int32), ("dense_rr", ctypes.c_int32),
+                ("dense_pre", ctypes.c_int32), ("deficient", ctypes.c_int32),
                 ("refine_rr", ctypes.c_int32), ("refine_pre", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
@@ -94,6 +94,7 @@ def _load():
         "pf_session_close": (i32, [vp]),
         "pf_quantize": (i32, [vp, i64, vp, i32, ctypes.c_int, vp, i64, i64, i64, vp]),
         "pf_psd_dense": (i32, [vp, i64, vp, i64, i32, ctypes.c_int, vp, i64, vp]),
+        "pf_eigh": (i32, [vp, i64, i32, vp, vp, i64, vp]),
         "pf_workspace_size": (i32, [P(PfDesc), P(ctypes.c_size_t)]),
         "pf_profile_set": (i32, [ctypes.c_int]),
         "pf_profile_read": (i32, [ctypes.c_int, P(i64), P(dbl)]),
@@ -133,12 +134,12 @@ def _check(s):
         raise PfError(s, last_error())
 
 
-def desc(n, p, degree, a, b, *, q=1, work=PF_F32, op=PF_OP_SYM, m=0, flags=0, spec_ub=0.0, max_sweeps=0):
+def desc(n, p, degree, a, b, *, q=1, work=PF_F32, op=PF_OP_SYM, m=0, flags=0, spec_ub=0.0):
     d = PfDesc()
     d.struct_size = ctypes.sizeof(PfDesc)
     d.op, d.n, d.m, d.p, d.degree, d.q = op, n, m, p, degree, q
     d.a, d.b, d.spec_ub = float(a), float(b), float(spec_ub)
-    d.work, d.flags, d.max_sweeps = work, flags, max_sweeps
+    d.work, d.flags, d.reserved = work, flags, 0
     return d
 
 
@@ -275,6 +276,13 @@ def pf_quantize(dst, tile_scale, tile, dtype, src, stream=None):
 def pf_psd_dense(V, theta, n, p, work, out, stream=None):
     _check(LIB.pf_psd_dense(ctypes.c_void_p(V.data_ptr()), ld_of(V), ctypes.c_void_p(theta.data_ptr()), n, p, work,
                             ctypes.c_void_p(out.data_ptr()), ld_of(out), _stream(stream)))
+
+
+def pf_eigh(H, theta, Z, stream=None):
+    """theta (descending), Z = eigenpairs of sym(H); H, Z column-major FP64 p x p."""
+    p = H.shape[0]
+    _check(LIB.pf_eigh(ctypes.c_void_p(H.data_ptr()), ld_of(H), p, ctypes.c_void_p(theta.data_ptr()),
+                       ctypes.c_void_p(Z.data_ptr()), ld_of(Z), _stream(stream)))
 
 
 def pf_workspace_size(d):

@@ -20,7 +20,7 @@ def device_matrix(A, dtype, ld=None):
     return t
 
 
-def run_extract(X, U, degree, a, b, work="f64", q=1, flags=0, Xrr=None, ld_pad=0, max_sweeps=0):
+def run_extract(X, U, degree, a, b, work="f64", q=1, flags=0, Xrr=None, ld_pad=0):
     """One pf_extract on host arrays; returns (theta, V, info dict)."""
     pf = pf_module()
     n, p = U.shape
@@ -32,13 +32,13 @@ def run_extract(X, U, degree, a, b, work="f64", q=1, flags=0, Xrr=None, ld_pad=0
     Ud = device_matrix(U, tdt, ld=n + ld_pad)
     theta = torch.zeros(p, dtype=torch.float64, device="cuda")
     info = torch.zeros(8, dtype=torch.int32, device="cuda")
-    d = pf.desc(n, p, degree, a, b, q=q, work=wk, flags=flags, max_sweeps=max_sweeps)
+    d = pf.desc(n, p, degree, a, b, q=q, work=wk, flags=flags)
     pf.pf_extract(d, Xd, Xr, Ud, theta, info)
     torch.cuda.synchronize()
     inf = info.cpu().numpy()
     return (theta.cpu().numpy(), Ud.cpu().double().numpy(),
-            {"status": int(inf[0]), "n_pos": int(inf[1]), "sweeps_rr": int(inf[2]),
-             "sweeps_pre": int(inf[3]), "deficient": int(inf[4])})
+            {"status": int(inf[0]), "n_pos": int(inf[1]), "dense_rr": int(inf[2]),
+             "dense_pre": int(inf[3]), "deficient": int(inf[4])})
 
 
 def compare(theta_g, V_g, ref, r):

@@ -70,7 +70,7 @@ def good_desc(**kw):
 
 @pytest.mark.parametrize("field,value", [
     ("n", 0), ("p", 0), ("p", 129), ("p", 300), ("degree", 0), ("q", 0),
-    ("a", 1.0), ("b", -2.0), ("work", 7), ("flags", 0x100), ("max_sweeps", -1), ("op", 5),
+    ("a", 1.0), ("b", -2.0), ("work", 7), ("flags", 0x100), ("reserved", 1), ("op", 5),
 ])
 def test_workspace_size_rejects(field, value):
     d = good_desc()
@@ -181,3 +181,16 @@ def test_server_rejects_bad_config():
                      ("pf_server_close", (None, 1)), ("pf_server_destroy", (None,)),
                      ("pf_server_result", (None, 1, None)), ("pf_server_stats_get", (None, None))):
         assert getattr(pf.LIB, fn)(*args) == pf.PF_ERR_ARG, fn
+
+
+def test_eigh_rejects_before_launch():
+    """pf_eigh argument errors are returned before any HIP call (the
+    pointers below are never dereferenced)."""
+    H, th, Z = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x80000), ctypes.c_void_p(0x100000)
+    assert pf.LIB.pf_eigh(None, 4, 4, th, Z, 4, None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_eigh(H, 4, 0, th, Z, 4, None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_eigh(H, 129, 129, th, Z, 129, None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_eigh(H, 3, 4, th, Z, 4, None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_eigh(H, 4, 4, th, Z, 2, None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_eigh(H, 8, 8, th, ctypes.c_void_p(0x10000 + 8 * 8), 8, None) == pf.PF_ERR_ARG
+    assert "overlap" in pf.last_error()

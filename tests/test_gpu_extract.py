@@ -42,7 +42,7 @@ def test_tiny_fp64_every_step():
         th, V, info = run_extract(X, U, w.degree, w.a, w.b, work="f64", flags=(4 if k == 0 else 0))
         assert info["status"] == 0, info
         rel, sin = compare(th, V, ref, w.n_top)
-        print(f"tiny fp64 step {k}: rel {rel:.2e} sin {sin:.2e} sweeps {info['sweeps_rr']}/{info['sweeps_pre']}"
+        print(f"tiny fp64 step {k}: rel {rel:.2e} sin {sin:.2e} dense {info['dense_rr']}/{info['dense_pre']}"
               f" deficient {info['deficient']}")
         if not (rel <= 1e-10 and sin <= 1e-10):
             bad.append((k, rel, sin))
