@@ -209,7 +209,8 @@ __global__ __launch_bounds__((PMAX / 4) * (PMAX / 4)) void chol_rinv_kernel(
 //     of two so that max |h_ij| is in [0.5, 1)).  Step k reflects column k
 //     with P = I - beta v v^T; the trailing block is updated as
 //     A <- A - v w^T - w v^T, y = beta A v, w = y - (beta/2)(v^T y) v.
-//     v overwrites column k below the diagonal.
+//     The matrix lives in registers (R8 entries of one row per lane); the
+//     reflectors are kept in LDS.
 //  2. Eigenvalues of T by bisection on Sturm counts (the number of negative
 //     pivots of the LDL^T factorisation of T - x I, pivots kept away from
 //     zero by pivmin), eight-way: the eight lanes of a team count at seven
@@ -349,24 +350,28 @@ __global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict
   constexpr double EPS = 2.220446049250313e-16;
   constexpr double SAFMIN = 2.2250738585072014e-308;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* A = reinterpret_cast<double*>(smem_raw);   // PMAX x LDA, row-major
-  __shared__ double s_d[PMAX], s_e[PMAX], s_e2[PMAX], s_beta[PMAX], s_v[PMAX], s_y[PMAX], s_lam[PMAX];
+  double* A = reinterpret_cast<double*>(smem_raw);   // Householder vectors: v_k in column k
+  __shared__ double s_d[PMAX], s_e[PMAX], s_e2[PMAX], s_beta[PMAX], s_v[PMAX], s_y[PMAX], s_lam[PMAX], s_x[PMAX];
   __shared__ double s_red[NW];
   __shared__ double s_par[4];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int team = t >> 3, part = t & 7, base8 = lane & ~7;
 
-  // ---- load sym(H), find max |h_ij| and non-finite entries ----------------
+  // ---- load sym(H) into registers: lane (row team, part) holds row `team`,
+  // columns R8*part .. R8*part+R8-1; find max |h_ij| and non-finite entries
+  const int c0 = R8 * part;
+  double a[R8];
   double amax = 0.0;
   int bad = 0;
-  for (int idx = t; idx < PMAX * PMAX; idx += NT) {
-    const int i = idx % PMAX, j = idx / PMAX;
+#pragma unroll
+  for (int u = 0; u < R8; ++u) {
+    const int j = c0 + u;
     double v = 0.0;
-    if (i < p && j < p) {
-      v = 0.5 * (H[i + (int64_t)j * ldh] + H[j + (int64_t)i * ldh]);
+    if (team < p && j < p) {
+      v = 0.5 * (H[team + (int64_t)j * ldh] + H[j + (int64_t)team * ldh]);
       bad |= !isfinite(v);
     }
-    A[i * LDA + j] = v;
+    a[u] = v;
     amax = fmax(amax, fabs(v));
   }
   amax = wave_max(amax);
@@ -397,18 +402,28 @@ __global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict
   (void)frexp(amax, &ex);
   const double scale = ldexp(1.0, ex);           // exact power-of-two scaling
   const double sinv = ldexp(1.0, -ex);
-  for (int idx = t; idx < PMAX * PMAX; idx += NT) {
-    const int i = idx % PMAX, j = idx / PMAX;
-    A[i * LDA + j] *= sinv;                      // this thread's own entries
-  }
+#pragma unroll
+  for (int u = 0; u < R8; ++u) a[u] *= sinv;
+  // entry (team, col) of this lane's registers, 0 if it holds other columns
+  auto entry = [&](int col) {
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < R8; ++u)
+      if (c0 + u == col) v = a[u];
+    return v;
+  };
+  if (part == 0 && team < p) s_x[team] = a[0];  // column 0
   __syncthreads();
 
   // ---- 1. Householder tridiagonalisation ----------------------------------
+  // The trailing matrix stays in registers; a step publishes v (s_v), y
+  // (s_y) and the next column (s_x) through LDS.  v also goes to column k of
+  // the LDS array A, kept for the back-transform.
   for (int k = 0; k + 2 < p; ++k) {
     const int m = p - k - 1;                     // trailing size
     if (wave == 0) {
-      const double xa = lane < m ? A[(k + 1 + lane) * LDA + k] : 0.0;
-      const double xb = lane + 64 < m ? A[(k + 1 + lane + 64) * LDA + k] : 0.0;
+      const double xa = lane < m ? s_x[k + 1 + lane] : 0.0;
+      const double xb = lane + 64 < m ? s_x[k + 1 + lane + 64] : 0.0;
       const double x0 = lane0(xa);
       const double tail = sum64((lane == 0 ? 0.0 : xa * xa) + xb * xb);
       double alpha = x0, beta = 0.0, v0 = x0;
@@ -418,53 +433,62 @@ __global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict
         beta = 1.0 / (nrm * (nrm + fabs(x0)));
         v0 = x0 - alpha;
       }
-      if (lane < m) s_v[lane] = lane == 0 ? v0 : xa;
-      if (lane + 64 < m) s_v[lane + 64] = xb;
+      if (lane < m) {
+        const double vv = lane == 0 ? v0 : xa;
+        s_v[k + 1 + lane] = vv;
+        A[(k + 1 + lane) * LDA + k] = vv;
+      }
+      if (lane + 64 < m) {
+        s_v[k + 65 + lane] = xb;
+        A[(k + 65 + lane) * LDA + k] = xb;
+      }
       if (lane == 0) {
-        A[(k + 1) * LDA + k] = v0;
-        s_d[k] = A[k * LDA + k];
+        s_d[k] = s_x[k];
         s_e[k] = alpha;
         s_beta[k] = beta;
       }
     }
     __syncthreads();
     const double beta = s_beta[k];
-    if (beta == 0.0) continue;                   // column already reduced
-    if (team < m) {
-      const double* row = A + (k + 1 + team) * LDA + (k + 1);
-      double acc = 0.0;
-#pragma unroll 4
+    const bool row_on = team > k && team < p;
+    if (beta != 0.0) {
+      double vj[R8];
+#pragma unroll
       for (int u = 0; u < R8; ++u) {
-        const int j = part + 8 * u;
-        if (j < m) acc += row[j] * s_v[j];
+        const int j = c0 + u;
+        vj[u] = j > k && j < p ? s_v[j] : 0.0;
       }
-      acc = sum8(acc);
-      if (part == 0) s_y[team] = beta * acc;
-    }
-    __syncthreads();
-    double kv = (lane < m ? s_v[lane] * s_y[lane] : 0.0) + (lane + 64 < m ? s_v[lane + 64] * s_y[lane + 64] : 0.0);
-    kv = 0.5 * beta * sum64(kv);                 // same value in every wave
-    if (team < m) {
-      double* row = A + (k + 1 + team) * LDA + (k + 1);
-      const double vi = s_v[team], wi = s_y[team] - kv * vi;
-#pragma unroll 4
-      for (int u = 0; u < R8; ++u) {
-        const int j = part + 8 * u;
-        if (j < m) {
-          const double vj = s_v[j];
-          row[j] -= vi * (s_y[j] - kv * vj) + wi * vj;
+      if (row_on) {
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < R8; ++u) acc += a[u] * vj[u];
+        acc = sum8(acc);
+        if (part == 0) s_y[team] = beta * acc;
+      }
+      __syncthreads();
+      double kv = (lane < m ? s_v[k + 1 + lane] * s_y[k + 1 + lane] : 0.0) +
+                  (lane + 64 < m ? s_v[k + 65 + lane] * s_y[k + 65 + lane] : 0.0);
+      kv = 0.5 * beta * sum64(kv);               // same value in every wave
+      if (row_on) {
+        const double vi = s_v[team], wi = s_y[team] - kv * vi;
+#pragma unroll
+        for (int u = 0; u < R8; ++u) {
+          const int j = c0 + u;
+          if (j > k && j < p) a[u] -= vi * (s_y[j] - kv * vj[u]) + wi * vj[u];
         }
       }
     }
+    // publish column k+1 (rows k+1.., the diagonal included)
+    if (team > k && team < p && c0 <= k + 1 && k + 1 < c0 + R8) s_x[team] = entry(k + 1);
     __syncthreads();
   }
+  if (team == p - 1 && c0 <= p - 1 && p - 1 < c0 + R8) s_d[p - 1] = entry(p - 1);
   if (t == 0) {
     if (p >= 2) {
-      s_d[p - 2] = A[(p - 2) * LDA + p - 2];
-      s_e[p - 2] = A[(p - 1) * LDA + p - 2];
+      s_d[p - 2] = s_x[p - 2];
+      s_e[p - 2] = s_x[p - 1];
       s_beta[p - 2] = 0.0;
     }
-    s_d[p - 1] = A[(p - 1) * LDA + p - 1];
     s_beta[p - 1] = 0.0;
   }
   __syncthreads();
@@ -670,40 +694,114 @@ __global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict
         start(mm, 7919 * (it + 1));
       }
     };
+    // cluster of eigenvalue jj: [cs, ce) chained by gaps <= ortol; kind 0 =
+    // alone, 1 = loose (every gap >= 1e-9 ||T||), 2 = tight, 3 = an
+    // eigenspace to working accuracy (spread <= 1e-13 ||T||)
+    auto cluster_of = [&](int jj, int& cs, int& ce) {
+      cs = jj;
+      while (cs > 0 && !(s_lam[cs] - s_lam[cs - 1] > ortol)) --cs;
+      ce = jj + 1;
+      while (ce < p && !(s_lam[ce] - s_lam[ce - 1] > ortol)) ++ce;
+      if (ce - cs == 1) return 0;
+      if (s_lam[ce - 1] - s_lam[cs] <= 1e-13 * tnorm) return 3;
+      for (int q = cs + 1; q < ce; ++q)
+        if (s_lam[q] - s_lam[q - 1] < 1e-9 * tnorm) return 2;
+      return 1;
+    };
     for (int pass = 0; pass < 2; ++pass) {
       const int j = (t >> 4) + pass * (PMAX / 2);
       if (j >= p) continue;
-      if (!(j == 0 || s_lam[j] - s_lam[j - 1] > ortol)) continue;   // not the first of its cluster
-      int end = j + 1;
-      while (end < p && !(s_lam[end] - s_lam[end - 1] > ortol)) ++end;
-      // A cluster whose eigenvalues agree to 1e-13 ||T|| is an eigenspace to
-      // working accuracy: one shift just above it amplifies the whole
-      // eigenspace alike (so successive iterates do not collapse onto one
-      // direction) and damps everything else by at least 1e-9 per solve.
-      const double spread = s_lam[end - 1] - s_lam[j];
-      const bool degen = end - j > 1 && spread <= 1e-13 * tnorm;
+      int cs, ce;
+      const int kind = cluster_of(j, cs, ce);
+      if (kind <= 1) {
+        // alone or in a loose cluster: two solves from the exact shift (the
+        // loose clusters are orthonormalised together below)
+        sig = s_lam[j];
+        factor();
+        start(j, 0);
+        for (int it = 0; it < 2; ++it) {
+          solve();
+          orthonormalise(j, j, 0, it);
+        }
+#pragma unroll
+        for (int u = 0; u < R16; ++u)
+          if (r0 + u < p) Z[r0 + u + (int64_t)j * ldt] = zr[u];
+        continue;
+      }
+      if (j != cs) continue;                     // the cluster's first team takes it in order
+      // An eigenspace to working accuracy shares one shift just above it:
+      // it amplifies the whole eigenspace alike (so successive iterates do
+      // not collapse onto one direction) and damps the rest by >= 1e-9 per
+      // solve.  A tight cluster uses separated shifts and Gram-Schmidt.
+      const bool degen = kind == 3;
+      const double spread = s_lam[ce - 1] - s_lam[cs];
       double sprev = 0.0;
-      for (int mm = j; mm < end; ++mm) {
-        if (!degen || mm == j) {
+      for (int mm = cs; mm < ce; ++mm) {
+        if (!degen || mm == cs) {
           sig = s_lam[mm];
-          if (degen) sig = s_lam[end - 1] + 1e3 * fmax(spread, EPS * tnorm);
-          else if (mm > j && sig - sprev < 10.0 * EPS * fabs(sig)) sig = sprev + 10.0 * EPS * fabs(sig);
+          if (degen) sig = s_lam[ce - 1] + 1e3 * fmax(spread, EPS * tnorm);
+          else if (mm > cs && sig - sprev < 10.0 * EPS * fabs(sig)) sig = sprev + 10.0 * EPS * fabs(sig);
           sprev = sig;
           factor();
         }
         start(mm, 0);
-        const int nit = degen || end - j == 1 ? 2 : 3;   // isolated: two solves
+        const int nit = degen ? 2 : 3;
         for (int it = 0; it < nit; ++it) {
           solve();
-          orthonormalise(j, mm, degen ? 2 : 1, it);
+          orthonormalise(cs, mm, degen ? 2 : 1, it);
         }
 #pragma unroll
         for (int u = 0; u < R16; ++u)
           if (r0 + u < p) Z[r0 + u + (int64_t)mm * ldt] = zr[u];
       }
     }
+    __syncthreads();
+    // loose clusters: independent inverse iteration leaves inner products
+    // of order eps ||T|| / gap between members; two Newton-Schulz steps
+    // Z_c <- Z_c (3 I - Z_c^T Z_c) / 2 make the block orthonormal (the
+    // mixing is of the same order, so residuals stay at eps ||T||)
+    for (int ns = 0; ns < 2; ++ns) {
+      double nz[2][R16];
+      bool has[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int j = (t >> 4) + h * (PMAX / 2);
+        int cs = 0, ce = 0;
+        has[h] = j < p && cluster_of(j, cs, ce) == 1;
+        if (!has[h]) continue;
+        double zj[R16], acc[R16];
+#pragma unroll
+        for (int u = 0; u < R16; ++u) {
+          zj[u] = r0 + u < p ? Z[r0 + u + (int64_t)j * ldt] : 0.0;
+          acc[u] = 0.0;
+        }
+        for (int q = cs; q < ce; ++q) {
+          double zq[R16];
+          double dot = 0.0;
+#pragma unroll
+          for (int u = 0; u < R16; ++u) {
+            zq[u] = r0 + u < p ? Z[r0 + u + (int64_t)q * ldt] : 0.0;
+            dot += zq[u] * zj[u];
+          }
+          dot = sum16(dot);
+#pragma unroll
+          for (int u = 0; u < R16; ++u) acc[u] += dot * zq[u];
+        }
+#pragma unroll
+        for (int u = 0; u < R16; ++u) nz[h][u] = 1.5 * zj[u] - 0.5 * acc[u];
+      }
+      __syncthreads();                           // every member read before any is rewritten
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int j = (t >> 4) + h * (PMAX / 2);
+        if (!has[h]) continue;
+#pragma unroll
+        for (int u = 0; u < R16; ++u)
+          if (r0 + u < p) Z[r0 + u + (int64_t)j * ldt] = nz[h][u];
+      }
+      __syncthreads();
+    }
   }
-  __syncthreads();
 
   // ---- 4. back-transform Z = Q Z_T, columns in descending order ----------
   // 16-lane teams, columns j0 and j0 + PMAX/2 together; rows r = part16 + 16 u

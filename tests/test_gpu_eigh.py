@@ -80,6 +80,11 @@ SPECTRA = {
     "tight_cluster": lambda r: 1.0 + 1e-9 * r.standard_normal(80),
     "cluster_steps": lambda r: np.concatenate([1.0 + 1e-6 * np.arange(40), r.uniform(-1, 0.5, 88)]),
     "tiny_scale": lambda r: 1e-200 * r.uniform(-1, 1, 64),
+    # Rayleigh-Ritz matrix with guard columns: the guard Ritz values crowd
+    # within ~0.1 (a loose cluster) or ~1e-5 / 1e-8 (tight) below the top block
+    "guard_cluster": lambda r: np.concatenate([r.uniform(1, 20, 64), -0.6 + 0.1 * r.standard_normal(64)]),
+    "guard_cluster_1e-5": lambda r: np.concatenate([r.uniform(1, 20, 64), -0.6 + 1e-5 * r.standard_normal(64)]),
+    "guard_cluster_1e-8": lambda r: np.concatenate([r.uniform(1, 20, 64), -0.6 + 1e-8 * r.standard_normal(64)]),
     "huge_scale": lambda r: 1e150 * r.uniform(-1, 1, 64),
 }
 
