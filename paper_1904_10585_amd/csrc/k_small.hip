@@ -213,8 +213,10 @@ __global__ __launch_bounds__((PMAX / 4) * (PMAX / 4)) void chol_rinv_kernel(
 //     reflectors are kept in LDS.
 //  2. Eigenvalues of T by bisection on Sturm counts (the number of negative
 //     pivots of the LDL^T factorisation of T - x I, pivots kept away from
-//     zero by pivmin), eight-way: the eight lanes of a team count at seven
-//     interior points of the bracket, three bits per round.
+//     zero by pivmin): one count per thread at 8 PMAX points of the
+//     Gershgorin interval brackets every eigenvalue, then eight-way
+//     bisection (the eight lanes of a team count at the seven interior
+//     points of the bracket, three bits per round).
 //  3. Eigenvectors of T by inverse iteration (three solves with the
 //     row-pivoted LU of T - lambda I from a fixed pseudo-random start).
 //     Eigenvalues closer than 1e-3 ||T|| form a cluster that one team
@@ -275,18 +277,33 @@ __device__ inline double sum16(double v) {
   return v;
 }
 
-__device__ inline double sum64(double v) {
-  v = sum16(v);
-  v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 32);
-  return v;
+template <int LANE>
+__device__ inline double read_lane(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), LANE);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), LANE);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ inline double lane0(double v) {
+__device__ inline double lane0(double v) { return read_lane<0>(v); }
+
+// Sum over the wave (all lanes active): row sums, then row_bcast:15 adds
+// row 0 into row 1 and row 2 into row 3 (row mask 0xA), row_bcast:31 adds
+// rows 0-1 into rows 2-3 (row mask 0xC); lane 63 holds the total, read
+// into a uniform value.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_rows(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), 0);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 0);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double sum64(double v) {
+  v = sum16(v);
+  v += dpp_rows<0x142, 0xA>(v);
+  v += dpp_rows<0x143, 0xC>(v);
+  return read_lane<63>(v);
 }
 
 // 1/q: the hardware estimate and one Newton step (r += r (1 - q r)).
@@ -352,6 +369,7 @@ __global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* A = reinterpret_cast<double*>(smem_raw);   // Householder vectors: v_k in column k
   __shared__ double s_d[PMAX], s_e[PMAX], s_e2[PMAX], s_beta[PMAX], s_v[PMAX], s_y[PMAX], s_lam[PMAX], s_x[PMAX];
+  __shared__ int s_cnt[NT];
   __shared__ double s_red[NW];
   __shared__ double s_par[4];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -459,10 +477,10 @@ __global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict
         vj[u] = j > k && j < p ? s_v[j] : 0.0;
       }
       if (row_on) {
-        double acc = 0.0;
+        double acc4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int u = 0; u < R8; ++u) acc += a[u] * vj[u];
-        acc = sum8(acc);
+        for (int u = 0; u < R8; ++u) acc4[u & 3] += a[u] * vj[u];
+        double acc = sum8((acc4[0] + acc4[1]) + (acc4[2] + acc4[3]));
         if (part == 0) s_y[team] = beta * acc;
       }
       __syncthreads();
@@ -470,11 +488,12 @@ __global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict
                   (lane + 64 < m ? s_v[k + 65 + lane] * s_y[k + 65 + lane] : 0.0);
       kv = 0.5 * beta * sum64(kv);               // same value in every wave
       if (row_on) {
-        const double vi = s_v[team], wi = s_y[team] - kv * vi;
+        // v_i w_j + w_i v_j = v_i y_j + (y_i - 2 kv v_i) v_j
+        const double vi = s_v[team], ci = s_y[team] - 2.0 * kv * vi;
 #pragma unroll
         for (int u = 0; u < R8; ++u) {
           const int j = c0 + u;
-          if (j > k && j < p) a[u] -= vi * (s_y[j] - kv * vj[u]) + wi * vj[u];
+          if (j > k && j < p) a[u] -= vi * s_y[j] + ci * vj[u];
         }
       }
     }
@@ -493,7 +512,7 @@ __global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict
   }
   __syncthreads();
 
-  // ---- 2. eigenvalues: Gershgorin bracket, eight-way bisection -----------
+  // ---- 2. eigenvalues: Gershgorin bracket, coarse counts, 8-way bisection -
   if (wave == 0) {
     double lo = INFINITY, hi = -INFINITY, e2max = 0.0;
     for (int i = lane; i < p; i += 64) {
@@ -522,15 +541,30 @@ __global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict
   }
   __syncthreads();
   const double pivmin = s_par[2], tnorm = s_par[3];
+  // coarse pass: every thread counts at one of NT points splitting the
+  // Gershgorin interval into NT + 1 parts
+  const double glo = s_par[0], gw = (s_par[1] - s_par[0]) / (double)(NT + 1);
+  s_cnt[t] = sturm_count(s_d, s_e2, p, glo + gw * (double)(t + 1), pivmin);
+  __syncthreads();
   if (team < p) {
-    double lo = s_par[0], hi = s_par[1];
+    // the first point with more than `team` eigenvalues below it brackets
+    // eigenvalue `team` (counts rise with x)
+    int lo_i = 0, hi_i = NT;                     // search [lo_i, hi_i) for that point
+    while (lo_i < hi_i) {
+      const int mid = (lo_i + hi_i) >> 1;
+      if (s_cnt[mid] > team) hi_i = mid;
+      else lo_i = mid + 1;
+    }
+    double lo = lo_i == 0 ? s_par[0] : glo + gw * (double)lo_i;
+    double hi = lo_i == NT ? s_par[1] : glo + gw * (double)(lo_i + 1);
+    // eight-way bisection: the lanes of a team count at the seven interior
+    // points of the bracket
     for (int it = 0; it < 40; ++it) {
       if (hi - lo <= fmax(2.0 * EPS * fmax(fabs(lo), fabs(hi)), EPS * tnorm)) break;
       const double w8 = (hi - lo) * 0.125;
       const int cnt = part < 7 ? sturm_count(s_d, s_e2, p, lo + w8 * (double)(part + 1), pivmin) : p;
-      // first point with more than `team` eigenvalues below it
       const unsigned bits = (unsigned)(__ballot(cnt > team) >> base8) & 0x7Fu;
-      const int first = bits ? __builtin_ctz(bits) : 7;
+      const int first = bits ? __builtin_ctz(bits) : 7;   // point first+1 is the first above
       const double nlo = first == 0 ? lo : lo + w8 * (double)first;
       const double nhi = first == 7 ? hi : lo + w8 * (double)(first + 1);
       lo = nlo;
@@ -540,10 +574,28 @@ __global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict
   }
   __syncthreads();
 
+  const double ortol = 1e-3 * tnorm;
+  // cluster of eigenvalue jj: [cs, ce) chained by gaps <= ortol; kind 0 =
+  // alone, 1 = loose (every gap >= 1e-11 ||T||), 2 = tight, 3 = an
+  // eigenspace to working accuracy (spread <= 1e-13 ||T||)
+  auto cluster_of = [&](int jj, int& cs, int& ce) {
+    cs = jj;
+    while (cs > 0 && !(s_lam[cs] - s_lam[cs - 1] > ortol)) --cs;
+    ce = jj + 1;
+    while (ce < p && !(s_lam[ce] - s_lam[ce - 1] > ortol)) ++ce;
+    if (ce - cs == 1) return 0;
+    if (s_lam[ce - 1] - s_lam[cs] <= 1e-13 * tnorm) return 3;
+    for (int q = cs + 1; q < ce; ++q)
+      if (s_lam[q] - s_lam[q - 1] < 1e-11 * tnorm) return 2;
+    return 1;
+  };
+  __shared__ int s_loose;
+  if (t == 0) s_loose = 0;
+  __syncthreads();
+
   // ---- 3. inverse iteration: 16-lane teams, R16 rows per lane ------------
   {
     const int part16 = t & 15, r0 = part16 * R16;
-    const double ortol = 1e-3 * tnorm;
     const double tiny = EPS * tnorm;
     const int ldt = ldz;                         // T's eigenvectors go to Z first
     double ur[R16], lm[R16], zr[R16];
@@ -694,20 +746,6 @@ __global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict
         start(mm, 7919 * (it + 1));
       }
     };
-    // cluster of eigenvalue jj: [cs, ce) chained by gaps <= ortol; kind 0 =
-    // alone, 1 = loose (every gap >= 1e-9 ||T||), 2 = tight, 3 = an
-    // eigenspace to working accuracy (spread <= 1e-13 ||T||)
-    auto cluster_of = [&](int jj, int& cs, int& ce) {
-      cs = jj;
-      while (cs > 0 && !(s_lam[cs] - s_lam[cs - 1] > ortol)) --cs;
-      ce = jj + 1;
-      while (ce < p && !(s_lam[ce] - s_lam[ce - 1] > ortol)) ++ce;
-      if (ce - cs == 1) return 0;
-      if (s_lam[ce - 1] - s_lam[cs] <= 1e-13 * tnorm) return 3;
-      for (int q = cs + 1; q < ce; ++q)
-        if (s_lam[q] - s_lam[q - 1] < 1e-9 * tnorm) return 2;
-      return 1;
-    };
     for (int pass = 0; pass < 2; ++pass) {
       const int j = (t >> 4) + pass * (PMAX / 2);
       if (j >= p) continue;
@@ -715,7 +753,8 @@ __global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict
       const int kind = cluster_of(j, cs, ce);
       if (kind <= 1) {
         // alone or in a loose cluster: two solves from the exact shift (the
-        // loose clusters are orthonormalised together below)
+        // loose clusters are orthonormalised together after step 4)
+        if (kind == 1) s_loose = 1;
         sig = s_lam[j];
         factor();
         start(j, 0);
@@ -755,53 +794,8 @@ __global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict
           if (r0 + u < p) Z[r0 + u + (int64_t)mm * ldt] = zr[u];
       }
     }
-    __syncthreads();
-    // loose clusters: independent inverse iteration leaves inner products
-    // of order eps ||T|| / gap between members; two Newton-Schulz steps
-    // Z_c <- Z_c (3 I - Z_c^T Z_c) / 2 make the block orthonormal (the
-    // mixing is of the same order, so residuals stay at eps ||T||)
-    for (int ns = 0; ns < 2; ++ns) {
-      double nz[2][R16];
-      bool has[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int j = (t >> 4) + h * (PMAX / 2);
-        int cs = 0, ce = 0;
-        has[h] = j < p && cluster_of(j, cs, ce) == 1;
-        if (!has[h]) continue;
-        double zj[R16], acc[R16];
-#pragma unroll
-        for (int u = 0; u < R16; ++u) {
-          zj[u] = r0 + u < p ? Z[r0 + u + (int64_t)j * ldt] : 0.0;
-          acc[u] = 0.0;
-        }
-        for (int q = cs; q < ce; ++q) {
-          double zq[R16];
-          double dot = 0.0;
-#pragma unroll
-          for (int u = 0; u < R16; ++u) {
-            zq[u] = r0 + u < p ? Z[r0 + u + (int64_t)q * ldt] : 0.0;
-            dot += zq[u] * zj[u];
-          }
-          dot = sum16(dot);
-#pragma unroll
-          for (int u = 0; u < R16; ++u) acc[u] += dot * zq[u];
-        }
-#pragma unroll
-        for (int u = 0; u < R16; ++u) nz[h][u] = 1.5 * zj[u] - 0.5 * acc[u];
-      }
-      __syncthreads();                           // every member read before any is rewritten
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int j = (t >> 4) + h * (PMAX / 2);
-        if (!has[h]) continue;
-#pragma unroll
-        for (int u = 0; u < R16; ++u)
-          if (r0 + u < p) Z[r0 + u + (int64_t)j * ldt] = nz[h][u];
-      }
-      __syncthreads();
-    }
   }
+  __syncthreads();
 
   // ---- 4. back-transform Z = Q Z_T, columns in descending order ----------
   // 16-lane teams, columns j0 and j0 + PMAX/2 together; rows r = part16 + 16 u
@@ -849,6 +843,52 @@ __global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict
         theta[p - 1 - j0] = s_lam[j0] * scale;
         if (j1 < p) theta[p - 1 - j1] = s_lam[j1] * scale;
       }
+    }
+  }
+  // ---- loose clusters: independent inverse iteration leaves inner products
+  // of order eps ||T|| / gap between members; two Newton-Schulz steps
+  // Z_c <- Z_c (3 I - Z_c^T Z_c) / 2 on the final vectors (Q is orthogonal,
+  // so this equals orthonormalising Z_T) make the block orthonormal, the
+  // mixing being of the same order, so residuals stay at eps ||T||.  Each
+  // step stages Z in the LDS array the reflectors no longer need.
+  __syncthreads();
+  if (s_loose) {
+    const int part16 = t & 15, r0 = part16 * R16;
+    for (int ns = 0; ns < 2; ++ns) {
+      for (int idx = t; idx < p * p; idx += NT) {
+        const int r = idx % p, c = idx / p;
+        A[c * LDA + r] = Z[r + (int64_t)c * ldz];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int j = (t >> 4) + h * (PMAX / 2);
+        int cs = 0, ce = 0;
+        if (j >= p || cluster_of(j, cs, ce) != 1) continue;
+        const int cj = p - 1 - j;                // final column of eigenvalue j
+        double zj[R16], acc[R16];
+#pragma unroll
+        for (int u = 0; u < R16; ++u) {
+          zj[u] = r0 + u < p ? A[cj * LDA + r0 + u] : 0.0;
+          acc[u] = 0.0;
+        }
+        for (int q = p - ce; q < p - cs; ++q) {  // the cluster's final columns
+          double zq[R16];
+          double dot = 0.0;
+#pragma unroll
+          for (int u = 0; u < R16; ++u) {
+            zq[u] = r0 + u < p ? A[q * LDA + r0 + u] : 0.0;
+            dot += zq[u] * zj[u];
+          }
+          dot = sum16(dot);
+#pragma unroll
+          for (int u = 0; u < R16; ++u) acc[u] += dot * zq[u];
+        }
+#pragma unroll
+        for (int u = 0; u < R16; ++u)
+          if (r0 + u < p) Z[r0 + u + (int64_t)cj * ldz] = 1.5 * zj[u] - 0.5 * acc[u];
+      }
+      __syncthreads();
     }
   }
   for (int idx = t; idx < pad * pad; idx += NT) {
