@@ -150,7 +150,7 @@ struct FCfg {
 // The four stage buffers are file-scope LDS objects (sized for the largest
 // tile): the compiler gives each its own alias scope, so the LDS reads of one
 // stage wait only for the direct loads into that stage.
-constexpr int kStageChunks = 2048;                 // 32 KiB per stage
+constexpr int kStageChunks = 2560;                 // 40 KiB per stage, 160 KiB for the ring
 __shared__ u4v g_st0[kStageChunks], g_st1[kStageChunks], g_st2[kStageChunks], g_st3[kStageChunks];
 
 // One 16-byte direct global->LDS load per lane (global_load_lds_dwordx4).
@@ -491,9 +491,16 @@ void launch_f(FArgs& a, const FSplit& sp, int pm, int pr, hipStream_t st) {
   }
 }
 
-// Rows per workgroup: two 16-row blocks per wave where the stage fits the
-// 32 KiB LDS slot (an FP32 X stage is twice a BF16 one).
-int mb_for(int xk, int NB) { return xk == XK_F32 && NB > 4 ? 1 : 2; }
+// Rows per workgroup (16-row blocks per wave): every workgroup reloads the
+// Y planes of its K slab, so wide blocks want tall tiles.  Four blocks per
+// wave for a BF16 X with more than 64 columns (the stage then holds 16 KiB
+// of X and 24 KiB of Y); two where the stage fits otherwise (an FP32 X stage
+// is twice a BF16 one; an FP8 workgroup must stay in one 128-row scale tile).
+int mb_for(int xk, int NB) {
+  if (xk == XK_F32) return NB > 4 ? 1 : 2;
+  if (xk == XK_BF16) return NB > 4 ? 4 : 2;
+  return 2;
+}
 
 int xk_of(pf_dtype t) {
   switch (t) {
@@ -524,10 +531,10 @@ void launch_xk(FArgs& a, const FSplit& sp, int NB, int pm, int pr, hipStream_t s
       case 2: launch_f<XK, 2, 2>(a, sp, pm, pr, st); break;
       case 3: launch_f<XK, 2, 3>(a, sp, pm, pr, st); break;
       case 4: launch_f<XK, 2, 4>(a, sp, pm, pr, st); break;
-      case 5: launch_f<XK, 2, 5>(a, sp, pm, pr, st); break;
-      case 6: launch_f<XK, 2, 6>(a, sp, pm, pr, st); break;
-      case 7: launch_f<XK, 2, 7>(a, sp, pm, pr, st); break;
-      default: launch_f<XK, 2, 8>(a, sp, pm, pr, st); break;
+      case 5: launch_f<XK, XK == XK_BF16 ? 4 : 2, 5>(a, sp, pm, pr, st); break;
+      case 6: launch_f<XK, XK == XK_BF16 ? 4 : 2, 6>(a, sp, pm, pr, st); break;
+      case 7: launch_f<XK, XK == XK_BF16 ? 4 : 2, 7>(a, sp, pm, pr, st); break;
+      default: launch_f<XK, XK == XK_BF16 ? 4 : 2, 8>(a, sp, pm, pr, st); break;
     }
   }
 }
