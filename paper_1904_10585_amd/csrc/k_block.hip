@@ -28,9 +28,15 @@ __device__ inline double u01(uint64_t h) { return ((double)(h >> 11) + 0.5) * (1
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 
-// One wave per 16 rows: C1[16 x p] = A1[16 x p] S with FP64 MFMA 16x16x4
-// (lane l holds A1[row0 + l%16][k + l/16] and S[k + l/16][16 nb + l%16];
+// One wave per 16 rows and one 16-column block jb of the result:
+// C1[16 x 16] = A1[16 x p] S[:, 16 jb .. 16 jb + 15] with FP64 MFMA 16x16x4
+// (lane l holds A1[row0 + l%16][k + l/16] and S[k + l/16][16 jb + l%16];
 // the accumulator element r of lane l is row 4r + l/16, column l%16).
+// Operands come straight from memory (S and the block are L2-resident);
+// every load of a lane is issued before the first product, so one memory
+// latency covers the kernel, and the K steps alternate between two
+// accumulators to halve the dependent MFMA chain.  Workgroups of one row
+// block read the same A rows and write disjoint columns: C must not alias A.
 template <typename T, int NB, bool TWO>
 __global__ __launch_bounds__(256) void apply_kernel(int64_t n, int p, const T* __restrict__ A1, int64_t lda1,
                                                     const T* __restrict__ A2, int64_t lda2,
@@ -38,58 +44,45 @@ __global__ __launch_bounds__(256) void apply_kernel(int64_t n, int p, const T* _
                                                     T* C2, int64_t ldc2, double alpha, double beta,
                                                     const int* __restrict__ deficient,
                                                     const pf_info* gate) {
-  if (gate && gate->status != 0) return;
-  // S staged once per workgroup: row j of sS is column j of S
-  constexpr int PPD = 16 * NB;
-  __shared__ double sS[PPD][PPD + 1];
-  for (int idx = threadIdx.x; idx < PPD * PPD; idx += 256) {
-    const int k = idx % PPD, j = idx / PPD;
-    sS[j][k] = (k < p && j < p) ? S[k + (int64_t)j * lds_] : 0.0;
-  }
-  __syncthreads();
+  constexpr int KS = 4 * NB;                         // K steps of 4 cover the padded width 16 NB
   const int l = threadIdx.x & 63, c = l & 15, g = l >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * 64 + 16 * (threadIdx.x >> 6);
+  const int j = 16 * (int)blockIdx.y + c;            // B column of this lane = its output column
   const int64_t arow = row0 + c;
-  const bool rok = arow < n;
-  d4v acc1[NB], acc2[NB];
+  const bool rok = arow < n, jok = j < p;
+  const int gst = gate ? gate->status : 0;
+  const bool defj = deficient && jok && deficient[j];
+  double a1[KS], a2[KS], b[KS];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) { acc1[nb] = d4v{0, 0, 0, 0}; acc2[nb] = d4v{0, 0, 0, 0}; }
-  // compile-time trip count (4 NB steps of 4 cover the padded width 16 NB),
-  // fully unrolled up to 64 columns so all loads are in flight together
-  constexpr int UNROLL = NB <= 4 ? 16 : 8;
-#pragma unroll UNROLL
-  for (int ks = 0; ks < 4 * NB; ++ks) {
+  for (int ks = 0; ks < KS; ++ks) {
     const int k = 4 * ks + g;
     const bool kok = k < p;
-    const double a1 = (rok && kok) ? (double)A1[arow + k * lda1] : 0.0;
-    double a2 = 0.0;
-    if constexpr (TWO) a2 = (rok && kok) ? (double)A2[arow + k * lda2] : 0.0;
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const double b = sS[16 * nb + c][k];          // zero past p
-      acc1[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc1[nb], 0, 0, 0);
-      if constexpr (TWO) acc2[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b, acc2[nb], 0, 0, 0);
-    }
+    a1[ks] = (rok && kok) ? (double)A1[arow + k * lda1] : 0.0;
+    if constexpr (TWO) a2[ks] = (rok && kok) ? (double)A2[arow + k * lda2] : 0.0;
+    b[ks] = (kok && jok) ? S[k + (int64_t)j * lds_] : 0.0;
   }
+  d4v acc1[2] = {d4v{0, 0, 0, 0}, d4v{0, 0, 0, 0}};
+  d4v acc2[2] = {d4v{0, 0, 0, 0}, d4v{0, 0, 0, 0}};
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    const int j = 16 * nb + c;
-    if (j >= p) continue;
-    const bool defj = deficient && deficient[j];
+  for (int ks = 0; ks < KS; ++ks) {
+    acc1[ks & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[ks], b[ks], acc1[ks & 1], 0, 0, 0);
+    if constexpr (TWO) acc2[ks & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[ks], b[ks], acc2[ks & 1], 0, 0, 0);
+  }
+  if (gst != 0 || !jok) return;
+  const d4v r1 = acc1[0] + acc1[1];
+  const d4v r2 = acc2[0] + acc2[1];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = row0 + 4 * r + g;
-      if (row >= n) continue;
-      double v1 = acc1[nb][r];
-      if (defj) {
-        // rank-deficient column: a fixed pseudo-random direction, which the
-        // next CholeskyQR pass orthogonalises against the others
-        v1 = (2.0 * u01(mix64(((uint64_t)row << 8) ^ (uint64_t)j ^ 0x5DEECE66Dull)) - 1.0) /
-             sqrt((double)n);
-      }
-      C1[row + j * ldc1] = (T)v1;
-      if constexpr (TWO) C2[row + j * ldc2] = (T)(alpha * acc2[nb][r] + beta * (double)(T)v1);
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = row0 + 4 * r + g;
+    if (row >= n) continue;
+    double v1 = r1[r];
+    if (defj) {
+      // rank-deficient column: a fixed pseudo-random direction, which the
+      // next CholeskyQR pass orthogonalises against the others
+      v1 = (2.0 * u01(mix64(((uint64_t)row << 8) ^ (uint64_t)j ^ 0x5DEECE66Dull)) - 1.0) / sqrt((double)n);
     }
+    C1[row + j * ldc1] = (T)v1;
+    if constexpr (TWO) C2[row + j * ldc2] = (T)(alpha * r2[r] + beta * (double)(T)v1);
   }
 }
 
@@ -232,7 +225,7 @@ __global__ __launch_bounds__(256) void psd_dense_kernel(const T* __restrict__ V,
 template <typename T, bool TWO>
 void apply_t(const ApplyArgs& a, hipStream_t st) {
   const int nb = (a.p + 15) / 16;
-  const dim3 grid((unsigned)((a.n + 63) / 64));
+  const dim3 grid((unsigned)((a.n + 63) / 64), (unsigned)nb);
   const T* A1 = static_cast<const T*>(a.A1);
   const T* A2 = static_cast<const T*>(a.A2);
   T* C1 = static_cast<T*>(a.C1);
@@ -282,6 +275,9 @@ void launch_apply(const ApplyArgs& a, hipStream_t st) {
   if (a.ta1 != a.tc1 || (a.A2 && (a.ta2 != a.ta1 || a.tc2 != a.tc1)))
     fail(PF_ERR_UNSUPPORTED, "apply: mixed element types");
   const bool two = a.A2 != nullptr;
+  // workgroups of one row block share A rows and write disjoint columns
+  if (a.C1 == a.A1 || (two && (a.C1 == a.A2 || a.C2 == a.A1 || a.C2 == a.A2)))
+    fail(PF_ERR_ARG, "apply: output aliases an input");
   if (a.ta1 == Elem::F64) { if (two) apply_t<double, true>(a, st); else apply_t<double, false>(a, st); }
   else { if (two) apply_t<float, true>(a, st); else apply_t<float, false>(a, st); }
 }

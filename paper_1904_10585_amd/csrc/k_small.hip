@@ -34,6 +34,19 @@ __device__ inline void set_status(pf_info* info, int code) {
 // R = D^{1/2} L_1^T (of the equilibrated matrix) and
 //     R^{-1}[i][j] = s_i W[j][i] / sqrt(d_j),   i <= j,
 // with s = diag(G)^{-1/2} the equilibration.
+// 1/q for q in a normal range: the hardware estimate refined by two Newton
+// steps r += r (1 - q r), each squaring the relative error.
+__device__ inline double rcp_nr2(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(fma(-q, r, 1.0), r, r);
+  return fma(fma(-q, r, 1.0), r, r);
+}
+
+template <int V>
+struct IntC {
+  static constexpr int value = V;
+};
+
 template <int PMAX>
 __global__ __launch_bounds__((PMAX / 4) * (PMAX / 4)) void chol_rinv_kernel(
     const double* __restrict__ G, int ldg, int p, double* __restrict__ Rinv, int ldr,
@@ -118,53 +131,56 @@ __global__ __launch_bounds__((PMAX / 4) * (PMAX / 4)) void chol_rinv_kernel(
     }
   }
 
-  for (int k = 0; k < p; ++k) {
-    const int buf = k & 1, kb = k >> 2, kr = k & 3;
-    // owners publish column k of G and row k of W (kr is uniform: a scalar
-    // branch picks the registers)
-    if (bj == kb) {
-      switch (kr) {
-        case 0: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][0]; break;
-        case 1: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][1]; break;
-        case 2: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][2]; break;
-        default: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][3]; break;
+  // Steps k = 4 kb + kr, the four of a block unrolled so that the published
+  // register column is a compile-time choice.  Steps past p (at most three)
+  // meet the identity padding: unit pivot, zero multipliers, no change.
+  const int nkb = (p + 3) / 4;
+  for (int kb = 0; kb < nkb; ++kb) {
+    const auto step = [&](auto krc) {
+      constexpr int kr = decltype(krc)::value;
+      constexpr int buf = kr & 1;
+      const int k = 4 * kb + kr;
+      // owners publish column k of G and row k of W
+      if (bj == kb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][kr];
       }
-    }
-    if (bi == kb) {
-      switch (kr) {
-        case 0: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[0][c]; break;
-        case 1: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[1][c]; break;
-        case 2: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[2][c]; break;
-        default: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[3][c]; break;
+      if (bi == kb) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[kr][c];
       }
-    }
-    __syncthreads();
-    const double pk = s_col[buf][k];
-    double ci[4], cj[4], wk[4];
+      __syncthreads();
+      const double pk = s_col[buf][k];
+      double ci[4], cj[4], wk[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      ci[u] = s_col[buf][i0 + u];
-      cj[u] = s_col[buf][j0 + u];
-      wk[u] = s_row[buf][j0 + u];
-    }
-    // a dependent column (equilibrated pivot <= tol; a zero column has pivot
-    // 0) is left out of the elimination
-    const bool ok = pk > tol;
-    if (t == 0) { s_piv[k] = ok ? pk : 1.0; s_def[k] = ok ? 0 : 1; }
-    const double inv = ok ? 1.0 / pk : 0.0;
-    double li[4], gj[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      li[u] = (i0 + u > k) ? ci[u] * inv : 0.0;
-      gj[u] = (j0 + u > k) ? cj[u] : 0.0;
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        g[r][c] -= li[r] * gj[c];
-        w[r][c] -= li[r] * wk[c];
+      for (int u = 0; u < 4; ++u) {
+        ci[u] = s_col[buf][i0 + u];
+        cj[u] = s_col[buf][j0 + u];
+        wk[u] = s_row[buf][j0 + u];
       }
+      // a dependent column (equilibrated pivot <= tol; a zero column has
+      // pivot 0) is left out of the elimination
+      const bool ok = pk > tol;
+      if (t == 0) { s_piv[k] = ok ? pk : 1.0; s_def[k] = ok ? 0 : 1; }
+      const double inv = ok ? rcp_nr2(pk) : 0.0;
+      double li[4], gj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        li[u] = (i0 + u > k) ? ci[u] * inv : 0.0;
+        gj[u] = (j0 + u > k) ? cj[u] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          g[r][c] -= li[r] * gj[c];
+          w[r][c] -= li[r] * wk[c];
+        }
+    };
+    step(IntC<0>{});
+    step(IntC<1>{});
+    step(IntC<2>{});
+    step(IntC<3>{});
   }
   __syncthreads();
 
