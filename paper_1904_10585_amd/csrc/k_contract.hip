@@ -317,9 +317,10 @@ Choice choose(Elem ta, Elem tb, bool f64_mfma, int64_t N) {
   Choice ch;
   ch.f64 = f64_mfma || ta == Elem::F64 || tb == Elem::F64;
   ch.NB = (int)(N / 16);
-  // FP64 accumulators take twice the registers: half the rows per wave, so
-  // that two waves fit a SIMD and no accumulator has to leave the registers
-  if (ch.f64) ch.MB = ch.NB <= 4 ? 2 : 1;
+  // FP64 accumulators take twice the registers: half the rows per wave.
+  // Wide blocks keep two 16-row blocks as well (one wave per SIMD, 16 MFMA
+  // chains): with one, every 16 rows of A re-read the whole K x N block B
+  if (ch.f64) ch.MB = 2;
   else ch.MB = ch.NB <= 4 ? 4 : 2;
   ch.VEC = (ta == Elem::F64 || tb == Elem::F64) ? 2 : 4;
   ch.KSTEP = 4 * ch.VEC;
@@ -383,10 +384,10 @@ void dispatch_nb(const DevArgs& d, const Split& sp, int NB, int pm, int pr, hipS
       case 2: launch_tile<TA, TB, TO, F64, 2, 2>(d, sp, pm, pr, st); break;
       case 3: launch_tile<TA, TB, TO, F64, 2, 3>(d, sp, pm, pr, st); break;
       case 4: launch_tile<TA, TB, TO, F64, 2, 4>(d, sp, pm, pr, st); break;
-      case 5: launch_tile<TA, TB, TO, F64, 1, 5>(d, sp, pm, pr, st); break;
-      case 6: launch_tile<TA, TB, TO, F64, 1, 6>(d, sp, pm, pr, st); break;
-      case 7: launch_tile<TA, TB, TO, F64, 1, 7>(d, sp, pm, pr, st); break;
-      case 8: launch_tile<TA, TB, TO, F64, 1, 8>(d, sp, pm, pr, st); break;
+      case 5: launch_tile<TA, TB, TO, F64, 2, 5>(d, sp, pm, pr, st); break;
+      case 6: launch_tile<TA, TB, TO, F64, 2, 6>(d, sp, pm, pr, st); break;
+      case 7: launch_tile<TA, TB, TO, F64, 2, 7>(d, sp, pm, pr, st); break;
+      case 8: launch_tile<TA, TB, TO, F64, 2, 8>(d, sp, pm, pr, st); break;
       default: fail(PF_ERR_UNSUPPORTED, "contract: block width above 128 columns");
     }
     return;

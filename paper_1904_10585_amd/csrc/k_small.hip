@@ -21,19 +21,6 @@ __device__ inline void set_status(pf_info* info, int code) {
   if (info) atomicCAS(&info->status, 0, code);
 }
 
-// ---------------------------------------------------------------------------
-// Cholesky + triangular inverse, register resident.  Thread (bi, bj) of a
-// (PMAX/4)^2 grid holds the 4x4 blocks (bi, bj) of the equilibrated Gram
-// matrix G and of W, which starts as I.  Step k of the right-looking
-// elimination in L D L^T form broadcasts column k of G and row k of W
-// through LDS (double-buffered: one barrier per step) and applies
-//     G[i][j] -= G[i][k] G[k][j] / d_k   (i, j > k)
-//     W[i][:] -= G[i][k] / d_k * W[k][:] (i > k),
-// the same row operations on W as on G, so that at the end
-// G = L_1 D L_1^T with L_1 unit lower triangular and W = L_1^{-1}.  Then
-// R = D^{1/2} L_1^T (of the equilibrated matrix) and
-//     R^{-1}[i][j] = s_i W[j][i] / sqrt(d_j),   i <= j,
-// with s = diag(G)^{-1/2} the equilibration.
 // 1/q for q in a normal range: the hardware estimate refined by two Newton
 // steps r += r (1 - q r), each squaring the relative error.
 __device__ inline double rcp_nr2(double q) {
@@ -47,27 +34,50 @@ struct IntC {
   static constexpr int value = V;
 };
 
-template <int PMAX>
-__global__ __launch_bounds__((PMAX / 4) * (PMAX / 4)) void chol_rinv_kernel(
+// f(IntC<K>{}) for K = B .. E - 1 in order.
+template <int B, int E, typename F>
+__device__ __attribute__((always_inline)) inline void static_for(F& f) {
+  if constexpr (B < E) {
+    f(IntC<B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky + triangular inverse, register resident.  Thread (bi, bj) of a
+// (PMAX/BR) x (PMAX/BC) grid holds the BR x BC blocks (bi, bj) of the equilibrated Gram
+// matrix G and of W, which starts as I.  Step k of the right-looking
+// elimination in L D L^T form broadcasts column k of G and row k of W
+// through LDS (double-buffered: one barrier per step) and applies
+//     G[i][j] -= G[i][k] G[k][j] / d_k   (i, j > k)
+//     W[i][:] -= G[i][k] / d_k * W[k][:] (i > k),
+// the same row operations on W as on G, so that at the end
+// G = L_1 D L_1^T with L_1 unit lower triangular and W = L_1^{-1}.  Then
+// R = D^{1/2} L_1^T (of the equilibrated matrix) and
+//     R^{-1}[i][j] = s_i W[j][i] / sqrt(d_j),   i <= j,
+// with s = diag(G)^{-1/2} the equilibration.
+template <int PMAX, int BR, int BC, bool UNROLL>
+__global__ __launch_bounds__((PMAX / BR) * (PMAX / BC)) void chol_rinv_kernel(
     const double* __restrict__ G, int ldg, int p, double* __restrict__ Rinv, int ldr,
     int* __restrict__ deficient, pf_info* info, int pass, double tol, double near_tol) {
-  constexpr int NBK = PMAX / 4;
-  constexpr int NT = NBK * NBK;
+  static_assert(BC % BR == 0 && BC % 2 == 0, "a step block spans whole row blocks");
+  constexpr int NBR = PMAX / BR, NBC = PMAX / BC;
+  constexpr int NT = NBR * NBC;
   __shared__ __align__(16) double s_eq[PMAX], s_piv[PMAX], s_col[2][PMAX], s_row[2][PMAX];
   __shared__ int s_def[PMAX];
   __shared__ int s_bad, s_far;
   const int t = threadIdx.x;
-  const int bi = t / NBK, bj = t % NBK;
-  const int i0 = 4 * bi, j0 = 4 * bj;
+  const int bi = t / NBC, bj = t % NBC;
+  const int i0 = BR * bi, j0 = BC * bj;
   if (t == 0) { s_bad = 0; s_far = 0; }
   __syncthreads();
 
-  double g[4][4], w[4][4];
+  double g[BR][BC], w[BR][BC];
   bool bad = false;
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int r = 0; r < BR; ++r)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < BC; ++c) {
       const int i = i0 + r, j = j0 + c;
       double v = i == j ? 1.0 : 0.0;                 // identity padding past p
       if (i < p && j < p) {
@@ -78,23 +88,26 @@ __global__ __launch_bounds__((PMAX / 4) * (PMAX / 4)) void chol_rinv_kernel(
       w[r][c] = i == j ? 1.0 : 0.0;
     }
   if (bad) s_bad = 1;
-  if (bi == bj) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) s_eq[i0 + r] = g[r][r] > 0.0 ? 1.0 / sqrt(g[r][r]) : 0.0;
-  }
+  for (int r = 0; r < BR; ++r)
+#pragma unroll
+    for (int c = 0; c < BC; ++c)
+      if (i0 + r == j0 + c) s_eq[i0 + r] = g[r][c] > 0.0 ? 1.0 / sqrt(g[r][c]) : 0.0;
   __syncthreads();
   if (s_bad) {
     if (t == 0) set_status(info, PF_ERR_NONFINITE);
     for (int idx = t; idx < ldr * ldr; idx += NT) Rinv[idx] = 0.0;
     return;
   }
-  double si[4], sj[4];
+  double si[BR], sj[BC];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) { si[u] = s_eq[i0 + u]; sj[u] = s_eq[j0 + u]; }
+  for (int u = 0; u < BR; ++u) si[u] = s_eq[i0 + u];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int u = 0; u < BC; ++u) sj[u] = s_eq[j0 + u];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+  for (int r = 0; r < BR; ++r)
+#pragma unroll
+    for (int c = 0; c < BC; ++c)
       if (i0 + r < p && j0 + c < p) g[r][c] *= si[r] * sj[c];
 
   // Second CholeskyQR pass: the equilibrated Gram matrix of an already
@@ -105,17 +118,17 @@ __global__ __launch_bounds__((PMAX / 4) * (PMAX / 4)) void chol_rinv_kernel(
   if (near_tol > 0.0) {
     double dev = 0.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < BR; ++r)
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+      for (int c = 0; c < BC; ++c)
         if (i0 + r < p && j0 + c < p) dev = fmax(dev, fabs(g[r][c] - (i0 + r == j0 + c ? 1.0 : 0.0)));
     if (!(dev <= near_tol)) s_far = 1;
     __syncthreads();
     if (!s_far) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < BR; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < BC; ++c) {
           const int i = i0 + r, j = j0 + c;
           if (i < p && j < p && i < ldr && j < ldr) {
             const double u = i == j ? 0.5 * (g[r][c] - 1.0) : (i < j ? g[r][c] : 0.0);
@@ -131,23 +144,81 @@ __global__ __launch_bounds__((PMAX / 4) * (PMAX / 4)) void chol_rinv_kernel(
     }
   }
 
-  // Steps k = 4 kb + kr, the four of a block unrolled so that the published
-  // register column is a compile-time choice.  Steps past p (at most three)
-  // meet the identity padding: unit pivot, zero multipliers, no change.
-  const int nkb = (p + 3) / 4;
-  for (int kb = 0; kb < nkb; ++kb) {
-    const auto step = [&](auto krc) {
-      constexpr int kr = decltype(krc)::value;
-      constexpr int buf = kr & 1;
-      const int k = 4 * kb + kr;
-      // owners publish column k of G and row k of W
-      if (bj == kb) {
+  if constexpr (UNROLL) {
+    // Steps k = BC kb + kr, the BC steps of a column block unrolled so that
+    // the published register column is a compile-time choice.  Steps past p
+    // (fewer than BC) meet the identity padding: unit pivot, zero
+    // multipliers, no change.
+    const int nkb = (p + BC - 1) / BC;
+    for (int kb = 0; kb < nkb; ++kb) {
+      const auto step = [&](auto krc) __attribute__((always_inline)) {
+        constexpr int kr = decltype(krc)::value;
+        constexpr int buf = kr & 1;
+        const int k = BC * kb + kr;
+        // owners publish column k of G and row k of W
+        if (bj == kb) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][kr];
+          for (int r = 0; r < BR; ++r) s_col[buf][i0 + r] = g[r][kr];
+        }
+        if (bi == k / BR) {
+#pragma unroll
+          for (int c = 0; c < BC; ++c) s_row[buf][j0 + c] = w[kr % BR][c];
+        }
+        __syncthreads();
+        const double pk = s_col[buf][k];
+        double ci[BR], cj[BC], wk[BC];
+#pragma unroll
+        for (int u = 0; u < BR; ++u) ci[u] = s_col[buf][i0 + u];
+#pragma unroll
+        for (int u = 0; u < BC; ++u) {
+          cj[u] = s_col[buf][j0 + u];
+          wk[u] = s_row[buf][j0 + u];
+        }
+        // a dependent column (equilibrated pivot <= tol; a zero column has
+        // pivot 0) is left out of the elimination
+        const bool ok = pk > tol;
+        if (t == 0) { s_piv[k] = ok ? pk : 1.0; s_def[k] = ok ? 0 : 1; }
+        const double inv = ok ? rcp_nr2(pk) : 0.0;
+        double li[BR], gj[BC];
+#pragma unroll
+        for (int u = 0; u < BR; ++u) li[u] = (i0 + u > k) ? ci[u] * inv : 0.0;
+#pragma unroll
+        for (int u = 0; u < BC; ++u) gj[u] = (j0 + u > k) ? cj[u] : 0.0;
+#pragma unroll
+        for (int r = 0; r < BR; ++r)
+#pragma unroll
+          for (int c = 0; c < BC; ++c) {
+            g[r][c] -= li[r] * gj[c];
+            w[r][c] -= li[r] * wk[c];
+          }
+        // keep each step's updates inside the step: sunk past the next
+        // barrier they keep several steps' multipliers live
+        __builtin_amdgcn_sched_barrier(0);
+      };
+      static_for<0, BC>(step);
+    }
+  } else {
+    // One step per iteration (at 1024 threads a lane has 128 registers: the
+    // unrolled form spills inside the loop).  kr is uniform: a scalar branch
+    // picks the published registers.
+    static_assert(BR == 4 && BC == 4, "rolled steps take 4 x 4 blocks");
+    for (int k = 0; k < p; ++k) {
+      const int buf = k & 1, kb = k >> 2, kr = k & 3;
+      if (bj == kb) {
+        switch (kr) {
+          case 0: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][0]; break;
+          case 1: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][1]; break;
+          case 2: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][2]; break;
+          default: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][3]; break;
+        }
       }
       if (bi == kb) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[kr][c];
+        switch (kr) {
+          case 0: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[0][c]; break;
+          case 1: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[1][c]; break;
+          case 2: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[2][c]; break;
+          default: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[3][c]; break;
+        }
       }
       __syncthreads();
       const double pk = s_col[buf][k];
@@ -158,11 +229,9 @@ __global__ __launch_bounds__((PMAX / 4) * (PMAX / 4)) void chol_rinv_kernel(
         cj[u] = s_col[buf][j0 + u];
         wk[u] = s_row[buf][j0 + u];
       }
-      // a dependent column (equilibrated pivot <= tol; a zero column has
-      // pivot 0) is left out of the elimination
       const bool ok = pk > tol;
       if (t == 0) { s_piv[k] = ok ? pk : 1.0; s_def[k] = ok ? 0 : 1; }
-      const double inv = ok ? rcp_nr2(pk) : 0.0;
+      const double inv = ok ? 1.0 / pk : 0.0;
       double li[4], gj[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -176,26 +245,24 @@ __global__ __launch_bounds__((PMAX / 4) * (PMAX / 4)) void chol_rinv_kernel(
           g[r][c] -= li[r] * gj[c];
           w[r][c] -= li[r] * wk[c];
         }
-    };
-    step(IntC<0>{});
-    step(IntC<1>{});
-    step(IntC<2>{});
-    step(IntC<3>{});
+    }
   }
+  __syncthreads();
+  for (int k = t; k < p; k += NT) s_piv[k] = 1.0 / sqrt(s_piv[k]);   // now 1 / sqrt(d_k)
   __syncthreads();
 
   // R^{-1}[i][j] = s_i W[j][i] / sqrt(d_j) for i <= j: this thread's W block
   // (rows i0.., columns j0..) lands transposed at rows j0.., columns i0..
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int r = 0; r < BR; ++r)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < BC; ++c) {
       const int wr = i0 + r, wc = j0 + c;          // W[wr][wc] -> Rinv[wc][wr]
       if (wr < p && wc < p && wc < ldr && wr < ldr) {
         double v = 0.0;
         if (wc <= wr) {
           const double s = s_def[wc] ? 1.0 : s_eq[wc];
-          v = s * w[r][c] / sqrt(s_piv[wr]);
+          v = s * w[r][c] * s_piv[wr];
         }
         Rinv[wc + (int64_t)wr * ldr] = v;
       }
@@ -1163,11 +1230,13 @@ void launch_chol_rinv(const double* G, int ldg, int p, double* Rinv, int ldr, in
   // orthogonality only while cond(Y) stays well below 1/sqrt(eps).
   const double tol = 1e-10;
   if (p <= 32) {
-    chol_rinv_kernel<32><<<1, 64, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol, near_tol);
+    chol_rinv_kernel<32, 4, 4, true><<<1, 64, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol, near_tol);
   } else if (p <= 64) {
-    chol_rinv_kernel<64><<<1, 256, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol, near_tol);
+    chol_rinv_kernel<64, 4, 4, true><<<1, 256, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol, near_tol);
   } else {
-    chol_rinv_kernel<128><<<1, 1024, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol, near_tol);
+    // 128 registers a lane at 1024 threads: the steps stay rolled
+    chol_rinv_kernel<128, 4, 4, false><<<1, 1024, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol,
+                                                           near_tol);
   }
   PFX_HIP(hipGetLastError());
 }

@@ -260,13 +260,16 @@ def test_guard_columns_chain(work):
         pf.pf_session_close(h)
 
 
-@pytest.mark.parametrize("shape", [(256, 256), (300, 200), (1000, 700)])
-def test_quantize_matches_oracle(shape):
+# (1003, 300) with a padded BF16 leading dimension takes the eight-row
+# vector path with a partial last group; (300, 200) the element-wise one
+@pytest.mark.parametrize("shape,ldd", [((256, 256), None), ((300, 200), None), ((1000, 700), None),
+                                       ((1003, 300), 1008)])
+def test_quantize_matches_oracle(shape, ldd):
     pf = pf_module()
     g = np.random.default_rng(shape[0])
     A = (g.standard_normal(shape) * np.exp(g.uniform(-3, 3, shape))).astype(np.float32)
     src = device_matrix(A, torch.float32)
-    dst16 = pf.colmajor(shape[0], shape[1], torch.int16, "cuda")
+    dst16 = pf.colmajor(shape[0], shape[1], torch.int16, "cuda", ld=ldd)
     pf.pf_quantize(dst16, None, 0, pf.PF_BF16, src)
     dst8 = pf.colmajor(shape[0], shape[1], torch.uint8, "cuda")
     tm, tn = -(-shape[0] // 128), -(-shape[1] // 128)
