@@ -43,7 +43,8 @@ __global__ __launch_bounds__(256) void apply_kernel(int64_t n, int p, const T* _
                                                     const double* __restrict__ S, int lds_, T* C1, int64_t ldc1,
                                                     T* C2, int64_t ldc2, double alpha, double beta,
                                                     const int* __restrict__ deficient,
-                                                    const pf_info* gate) {
+                                                    const pf_info* gate, pf_info* info_out,
+                                                    const double* __restrict__ theta, double* theta_out) {
   constexpr int KS = 4 * NB;                         // K steps of 4 cover the padded width 16 NB
   const int l = threadIdx.x & 63, c = l & 15, g = l >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * 64 + 16 * (threadIdx.x >> 6);
@@ -67,6 +68,11 @@ __global__ __launch_bounds__(256) void apply_kernel(int64_t n, int p, const T* _
   for (int ks = 0; ks < KS; ++ks) {
     acc1[ks & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[ks], b[ks], acc1[ks & 1], 0, 0, 0);
     if constexpr (TWO) acc2[ks & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[ks], b[ks], acc2[ks & 1], 0, 0, 0);
+  }
+  if (gate && blockIdx.x == 0 && blockIdx.y == 0) {
+    if (info_out && threadIdx.x == 0) *info_out = *gate;
+    if (theta_out && gst == 0)
+      for (int i = threadIdx.x; i < p; i += 256) theta_out[i] = theta[i];
   }
   if (gst != 0 || !jok) return;
   const d4v r1 = acc1[0] + acc1[1];
@@ -102,13 +108,6 @@ __global__ void axpby_kernel(const T* __restrict__ A, const T* __restrict__ B, T
   const int j = blockIdx.y;
   if (i >= n || j >= p) return;
   dst[i + j * ld] = (T)(alpha * (double)A[i + j * ld] + beta * (double)B[i + j * ld]);
-}
-
-__global__ void info_init_kernel(pf_info* info) {
-  if (threadIdx.x == 0) {
-    info->status = 0; info->n_pos = 0; info->dense_rr = 0; info->dense_pre = 0;
-    info->deficient = 0; info->refine_rr = info->refine_pre = info->reserved = 0;
-  }
 }
 
 __global__ void info_copy_kernel(const pf_info* src, pf_info* dst, const double* th, double* thd, int p) {
@@ -259,7 +258,8 @@ void apply_t(const ApplyArgs& a, hipStream_t st) {
   T* C2 = static_cast<T*>(a.C2);
 #define PFX_APPLY(NB)                                                                                    \
   apply_kernel<T, NB, TWO><<<grid, 256, 0, st>>>(a.n, a.p, A1, a.lda1, A2, a.lda2, a.S, a.lds_, C1, a.ldc1, \
-                                                C2, a.ldc2, a.alpha, a.beta, a.deficient, a.gate)
+                                                C2, a.ldc2, a.alpha, a.beta, a.deficient, a.gate, a.info_out,     \
+                                                a.theta, a.theta_out)
   switch (nb) {
     case 1: PFX_APPLY(1); break;
     case 2: PFX_APPLY(2); break;
@@ -302,6 +302,7 @@ void launch_apply(const ApplyArgs& a, hipStream_t st) {
   if (a.ta1 != a.tc1 || (a.A2 && (a.ta2 != a.ta1 || a.tc2 != a.tc1)))
     fail(PF_ERR_UNSUPPORTED, "apply: mixed element types");
   const bool two = a.A2 != nullptr;
+  if ((a.info_out || a.theta_out) && !a.gate) fail(PF_ERR_ARG, "apply: output copies need the gate");
   // workgroups of one row block share A rows and write disjoint columns
   if (a.C1 == a.A1 || (two && (a.C1 == a.A2 || a.C2 == a.A1 || a.C2 == a.A2)))
     fail(PF_ERR_ARG, "apply: output aliases an input");
@@ -331,16 +332,6 @@ void launch_axpby(const void* A, const void* B, void* dst, int64_t ld, Elem t, i
   else
     axpby_kernel<float><<<grid, 256, 0, st>>>(static_cast<const float*>(A), static_cast<const float*>(B),
                                               static_cast<float*>(dst), ld, n, p, alpha, beta);
-  PFX_HIP(hipGetLastError());
-}
-
-void launch_info_init(pf_info* info, hipStream_t st) {
-  info_init_kernel<<<1, 64, 0, st>>>(info);
-  PFX_HIP(hipGetLastError());
-}
-
-void launch_info_copy(const pf_info* src, pf_info* dst, const double* th, double* thd, int p, hipStream_t st) {
-  info_copy_kernel<<<1, 128, 0, st>>>(src, dst, th, thd, p);
   PFX_HIP(hipGetLastError());
 }
 

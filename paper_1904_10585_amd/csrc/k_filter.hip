@@ -448,6 +448,31 @@ __global__ void split_planes_kernel(const float* __restrict__ src, int64_t lds_,
   o[2 * plane] = p3;
 }
 
+// Start of an extraction in one launch: the n x p start block copied into
+// the padded work buffer (zero padding up to n_pad x p_pad), its three BF16
+// planes when `planes` is set, and the step's pf_info cleared.
+template <typename T>
+__global__ void begin_block_kernel(const T* __restrict__ src, int64_t lds_, T* __restrict__ dst, int64_t ldd,
+                                   int64_t n, int p, int64_t n_pad, uint16_t* __restrict__ planes, int64_t plane,
+                                   pf_info* info) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (info && i == 0 && j == 0) *info = pf_info{};
+  if (i >= n_pad) return;
+  const T v = (i < n && j < p) ? src[i + j * lds_] : T(0);
+  dst[i + j * ldd] = v;
+  if constexpr (std::is_same<T, float>::value) {
+    if (planes) {
+      uint16_t p1, p2, p3;
+      split1(v, p1, p2, p3);
+      uint16_t* o = planes + i + j * ldd;
+      o[0] = p1;
+      o[plane] = p2;
+      o[2 * plane] = p3;
+    }
+  }
+}
+
 struct FSplit {
   int S;
   int64_t kchunk, ldp, mtiles;
@@ -570,6 +595,20 @@ void filter_bf16x6(const FilterArgs& x, hipStream_t st) {
     case XK_BF16: launch_xk<XK_BF16>(a, sp, NB, x.prof_main, x.prof_reduce, st); break;
     default: launch_xk<XK_FP8>(a, sp, NB, x.prof_main, x.prof_reduce, st); break;
   }
+}
+
+void launch_begin_block(const void* src, int64_t lds, Elem t, void* dst, int64_t ldd, int64_t n, int p,
+                        int64_t n_pad, int p_pad, uint16_t* planes, int64_t plane, pf_info* info, hipStream_t st) {
+  dim3 grid((unsigned)((n_pad + 255) / 256), (unsigned)p_pad);
+  if (t == Elem::F64) {
+    if (planes) fail(PF_ERR_ARG, "begin_block: BF16 planes need FP32 work");
+    begin_block_kernel<double><<<grid, 256, 0, st>>>(static_cast<const double*>(src), lds, static_cast<double*>(dst),
+                                                     ldd, n, p, n_pad, nullptr, 0, info);
+  } else {
+    begin_block_kernel<float><<<grid, 256, 0, st>>>(static_cast<const float*>(src), lds, static_cast<float*>(dst), ldd,
+                                                    n, p, n_pad, planes, plane, info);
+  }
+  PFX_HIP(hipGetLastError());
 }
 
 void launch_split_planes(const float* src, int64_t lds, int64_t n, int p, uint16_t* dst, int64_t ldd,

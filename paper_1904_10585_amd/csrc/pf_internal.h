@@ -82,6 +82,11 @@ struct FilterArgs {
 };
 void filter_bf16x6(const FilterArgs& a, hipStream_t st);
 size_t filter_bf16x6_part_bytes(pf_dtype xdt, int64_t K, int64_t M, int64_t N);
+// Start of an extraction: copy the start block into the padded work buffer
+// (element type t), write its BF16 planes if planes is set (FP32 only) and
+// clear *info, in one launch.
+void launch_begin_block(const void* src, int64_t lds, Elem t, void* dst, int64_t ldd, int64_t n, int p,
+                        int64_t n_pad, int p_pad, uint16_t* planes, int64_t plane, pf_info* info, hipStream_t st);
 void launch_split_planes(const float* src, int64_t lds, int64_t n, int p, uint16_t* dst, int64_t ldd,
                          int64_t plane, int64_t n_pad, int p_pad, hipStream_t st);
 
@@ -115,6 +120,11 @@ struct ApplyArgs {
   double alpha, beta;
   const int* deficient;      // replace flagged columns of C1 (CholQR)
   const pf_info* gate;       // if non-null: skip writes unless gate->status == 0
+  // with gate: *info_out = *gate, and theta_out[0..p) = theta when the
+  // status is 0 (the step's outputs, in the same launch)
+  pf_info* info_out = nullptr;
+  const double* theta = nullptr;
+  double* theta_out = nullptr;
 };
 void launch_apply(const ApplyArgs& a, hipStream_t st);
 
@@ -125,9 +135,6 @@ void launch_copy_block(const void* src, int64_t lds, Elem ts, void* dst, int64_t
 // dst = alpha * A + beta * B (n x p blocks, same element type)
 void launch_axpby(const void* A, const void* B, void* dst, int64_t ld, Elem t, int64_t n, int p,
                   double alpha, double beta, hipStream_t st);
-void launch_info_init(pf_info* info, hipStream_t st);
-void launch_info_copy(const pf_info* src, pf_info* dst, const double* theta_src, double* theta_dst,
-                      int p, hipStream_t st);
 void launch_normal_block(void* dst, int64_t ld, Elem t, int64_t n, int p, uint64_t seed,
                          hipStream_t st);
 

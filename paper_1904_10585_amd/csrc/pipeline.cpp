@@ -440,7 +440,8 @@ void gram(Plan* P, const void* A, Elem ta, const void* B, Elem tb, double* out, 
 }
 
 void apply(Plan* P, const void* A1, const void* A2, const double* S, void* C1, int64_t ldc1, void* C2,
-           double alpha, double beta, const int* deficient, const pf_info* gate, hipStream_t st) {
+           double alpha, double beta, const int* deficient, const pf_info* gate, hipStream_t st,
+           pf_info* info_out = nullptr, double* theta_out = nullptr) {
   ApplyArgs a;
   a.n = P->n; a.p = P->p;
   a.A1 = A1; a.lda1 = P->n_pad; a.ta1 = P->work;
@@ -451,6 +452,9 @@ void apply(Plan* P, const void* A1, const void* A2, const double* S, void* C1, i
   a.alpha = alpha; a.beta = beta;
   a.deficient = deficient;
   a.gate = gate;
+  a.info_out = info_out;
+  a.theta = theta_out ? P->theta : nullptr;
+  a.theta_out = theta_out;
   launch_apply(a, st);
 }
 
@@ -468,8 +472,11 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
 
   const bool prof = prof_enabled();
   if (prof) prof_begin(PF_PROF_EXTRACT, st);
-  launch_info_init(P->info, st);
-  launch_copy_block(U_in, ldu_in, W, P->U, ld, W, P->n, P->p, P->n_pad, P->p_pad, st);
+  const bool split = W == Elem::F32 && !(d.flags & PF_FLAG_NATIVE_F32);
+  // U_in into the work buffer (with the planes of Y_0 = U for the split
+  // filter) and pf_info cleared, in one launch
+  launch_begin_block(U_in, ldu_in, W, P->U, ld, P->n, P->p, P->n_pad, P->p_pad, split ? planes_of(P, P->U) : nullptr,
+                     P->plane, P->info, st);
   const Plan::Copy* rr_copy = nullptr;
   if (d.op == PF_OP_GRAM) {
     ensure_copy(P, P->mft, Xf, st);
@@ -481,13 +488,10 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
     }
   }
 
-  const bool split = W == Elem::F32 && !(d.flags & PF_FLAG_NATIVE_F32);
   void* cur = P->U;
   for (int pass = 0; pass < d.q; ++pass) {
-    if (split) {
-      if (pass == 0) refresh_planes(P, cur, st);
-      // later passes start from Y_d, whose planes the last step wrote
-    }
+    // the planes of Y_0 come with the copy of U; later passes start from
+    // Y_d, whose planes the last step wrote
     // first product Z = A Y_0
     filter_product(P, Xf, cur, P->Z, nullptr, nullptr, 1.0, 0.0, 0.0, false, st);
     const double a1 = 1.0 / (e * tau[1]), b1 = -c / (e * tau[1]);
@@ -566,8 +570,8 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
     gram(P, P->Q, W, P->W, Elem::F64, P->G, st);
   }
   launch_eigh(P->G, P->p_pad, P->p, P->theta, P->Zeig, P->p_pad, P->p_pad, P->info, 1, st, P->Ework, P->refined);
-  apply(P, P->Q, nullptr, P->Zeig, U_out, ldu_out, nullptr, 0.0, 0.0, nullptr, P->info, st);
-  if (info_out || theta_out) launch_info_copy(P->info, info_out, P->theta, theta_out, P->p, st);
+  // Ritz vectors, with pf_info and theta copied out in the same launch
+  apply(P, P->Q, nullptr, P->Zeig, U_out, ldu_out, nullptr, 0.0, 0.0, nullptr, P->info, st, info_out, theta_out);
   if (prof) prof_end(PF_PROF_EXTRACT, st);
 }
 
