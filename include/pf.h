@@ -308,6 +308,57 @@ pf_status pf_eigh(const double* H, int64_t ldh, int32_t p, double* theta, double
 pf_status pf_psd_dense(const void* V, int64_t ldv, const double* theta, int64_t n, int32_t p,
                        pf_dtype work, void* out, int64_t ld_out, void* stream);
 
+/* Spectrum bounds by block Lanczos: the estimate of the smallest eigenvalue
+ * that places the left end a of the damping interval (section 4.1, which
+ * names the Lanczos method for it).  The start block V0 (n-by-16 FP64,
+ * device, ld ldv0 >= n; the caller draws it) spans the first block of the
+ * Krylov space K = span{V0, X V0, ..., X^(steps-1) V0}; each block step is
+ * one pass over X (products accumulated in FP64), the new block is
+ * orthogonalised against all earlier ones (classical Gram-Schmidt twice)
+ * and orthonormalised by CholeskyQR (a dependent column becomes a fixed
+ * pseudo-random direction, orthogonalised in turn); the Rayleigh-Ritz
+ * values of X on K (16 * steps of them, via pf_eigh's solver) give
+ *   theta_min >= lambda_min and theta_max <= lambda_max (Cauchy interlacing),
+ * and the residual norms ||X y - theta y|| of their Ritz vectors y give
+ * intervals [theta - res, theta + res] that each hold an eigenvalue.
+ *  X:     n-by-n symmetric, FP32 or FP64 (column-major, ld >= n).
+ *  steps: 1..8 block steps, 16 * steps <= n.
+ *  out:   device pf_bounds, written stream-ordered (status 0, or
+ *         PF_ERR_NONFINITE when X or V0 holds Inf/NaN).
+ * Scratch (about 8 n (32 + 16 steps) bytes) is allocated and freed
+ * stream-ordered on the stream. */
+typedef struct pf_bounds {
+  double theta_min, theta_max;  /* extreme Ritz values of X on K */
+  double res_min, res_max;      /* their residual norms */
+  int32_t status;               /* pf_status of the run (0 = PF_OK) */
+  int32_t replaced;             /* dependent columns replaced (an invariant subspace reached) */
+} pf_bounds;
+pf_status pf_lanczos_bounds(const pf_mat* X, int64_t n, const double* V0, int64_t ldv0, int32_t steps,
+                            pf_bounds* out, void* stream);
+
+/* Damping interval of section 4.1, host arithmetic.  a = lam_min - margin
+ * (lam_min an estimate of the smallest eigenvalue, e.g. pf_bounds'
+ * theta_min; margin >= 0, e.g. its res_min, keeps a below the spectrum).
+ *  top_r <= 0 (all positive eigenvalues wanted): b = eta * a, which needs
+ *      a < 0;
+ *  top_r > 0 (the r largest wanted): b = (1 - eta) * theta_r + eta * a,
+ *      theta_r the r-th largest Ritz value of the previous iterate.
+ * eta in (0, 1) (the paper uses 0.1 to 0.2).  PF_ERR_ARG unless a < b and
+ * every input is finite. */
+pf_status pf_interval_policy(double lam_min, double margin, double eta, int32_t top_r, double theta_r,
+                             double* a, double* b);
+
+/* Block size of section 4.2, host arithmetic.  top_r > 0: p = 5 + q * r
+ * (rounded up; q > 1 the guard factor); top_r <= 0 (all positive wanted):
+ * p = n_pos + guards, n_pos the positive Ritz count of the previous iterate
+ * (pf_info.n_pos).  The result is clamped to [1, 128]; PF_ERR_ARG for
+ * q <= 1, negative counts or non-finite q. */
+pf_status pf_block_size_policy(int32_t top_r, double q, int32_t n_pos, int32_t guards, int32_t* p);
+
+/* Move a session's damping interval [a, b] (a < b, finite) for its next
+ * steps, as the interval policy of section 4.1 follows the iterates. */
+pf_status pf_session_set_interval(pf_session* s, double a, double b);
+
 /* Kernel timing hooks (diagnostics).  While enabled, the library records a
  * HIP event pair on the launch stream around every kernel launch of the
  * given class; pf_profile_read synchronises on the recorded events and

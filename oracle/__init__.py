@@ -13,6 +13,8 @@ unoptimised reference of what one extraction computes (Li, Liu, Wen, Yuan,
   * the SVD route through A^T A (section 5.2.1),
   * the BF16 / FP8-E4M3 quantisers that define the low-precision copies
     of X the GPU filter reads.
+  * the Lanczos estimate of the smallest eigenvalue and the damping
+    interval / block size rules of sections 4.1-4.2.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import it.  It shares no code with the HIP path (no common
@@ -30,6 +32,7 @@ from .extract import (orthonormalize, rayleigh_ritz, extract, extract_gram,
                       psd_projection, lowrank_projection, ritz_residuals)
 from .metrics import sin_theta, projector_distance, ritz_rel_err, orth_error
 from .jacobi import jacobi_eigh
+from .lanczos import block_krylov_ritz, lanczos_bounds, interval_policy, block_size_policy
 from .quantize import (bf16_round, fp8_e4m3_round, fp8_tile_quantize,
                        fp8_tile_dequantize)
 
@@ -38,6 +41,7 @@ __all__ = [
     "orthonormalize", "rayleigh_ritz", "extract", "extract_gram",
     "psd_projection", "lowrank_projection", "ritz_residuals",
     "sin_theta", "projector_distance", "ritz_rel_err", "orth_error",
+    "block_krylov_ritz", "lanczos_bounds", "interval_policy", "block_size_policy",
     "jacobi_eigh",
     "bf16_round", "fp8_e4m3_round", "fp8_tile_quantize", "fp8_tile_dequantize",
 ]

@@ -2,6 +2,7 @@
 // per-stream workspace cache of pf_extract, and sessions.
 #include "pf_internal.h"
 
+#include <cmath>
 #include <cstdint>
 #include <functional>
 #include <map>
@@ -355,6 +356,67 @@ pf_status pf_eigh(const double* H, int64_t ldh, int32_t p, double* theta, double
     const char* z1 = z0 + ((size_t)(p - 1) * ldz + p) * sizeof(double);
     if (h0 < z1 && z0 < h1) fail(PF_ERR_ARG, "H and Z overlap");
     launch_eigh(H, (int)ldh, p, theta, Z, (int)ldz, p, nullptr, 1, static_cast<hipStream_t>(stream));
+  });
+}
+
+pf_status pf_lanczos_bounds(const pf_mat* X, int64_t n, const double* V0, int64_t ldv0, int32_t steps,
+                            pf_bounds* out, void* stream) {
+  return guarded([&] {
+    if (!X || !X->data || !V0 || !out) fail(PF_ERR_ARG, "NULL argument");
+    if (X->dtype != PF_F32 && X->dtype != PF_F64) fail(PF_ERR_ARG, "X must be FP32 or FP64");
+    if (steps < 1 || steps > 8) fail(PF_ERR_ARG, "steps must be in [1, 8]");
+    if (n < 16 * (int64_t)steps) fail(PF_ERR_ARG, "n must be at least 16 * steps");
+    if (X->ld < n || ldv0 < n) fail(PF_ERR_ARG, "leading dimension smaller than n");
+    const size_t esz = X->dtype == PF_F64 ? 8 : 4;
+    if (reinterpret_cast<uintptr_t>(X->data) % 16 != 0) fail(PF_ERR_ARG, "X.data must be 16-byte aligned");
+    if (((size_t)X->ld * esz) % 16 != 0) fail(PF_ERR_ARG, "X.ld * element size must be a multiple of 16 bytes");
+    enqueue_lanczos(*X, n, V0, ldv0, steps, out, static_cast<hipStream_t>(stream));
+  });
+}
+
+pf_status pf_interval_policy(double lam_min, double margin, double eta, int32_t top_r, double theta_r, double* a,
+                             double* b) {
+  return guarded([&] {
+    if (!a || !b) fail(PF_ERR_ARG, "NULL argument");
+    if (!std::isfinite(lam_min) || !std::isfinite(margin) || margin < 0.0) fail(PF_ERR_ARG, "lam_min and margin >= 0 must be finite");
+    if (!(eta > 0.0 && eta < 1.0)) fail(PF_ERR_ARG, "eta must be in (0, 1)");
+    const double lo = lam_min - margin;
+    double hi;
+    if (top_r <= 0) {
+      hi = eta * lo;                                  // all positive eigenvalues
+    } else {
+      if (!std::isfinite(theta_r)) fail(PF_ERR_ARG, "theta_r must be finite");
+      hi = (1.0 - eta) * theta_r + eta * lo;          // the r largest
+    }
+    if (!(lo < hi)) fail(PF_ERR_ARG, "the policy gives a >= b (all-positive case needs a < 0; top-r needs theta_r > a)");
+    *a = lo;
+    *b = hi;
+  });
+}
+
+pf_status pf_block_size_policy(int32_t top_r, double q, int32_t n_pos, int32_t guards, int32_t* p) {
+  return guarded([&] {
+    if (!p) fail(PF_ERR_ARG, "NULL argument");
+    double v;
+    if (top_r > 0) {
+      if (!std::isfinite(q) || !(q > 1.0)) fail(PF_ERR_ARG, "q must be a finite number above 1");
+      v = std::ceil(5.0 + q * top_r);
+    } else {
+      if (n_pos < 0 || guards < 0) fail(PF_ERR_ARG, "n_pos and guards must be non-negative");
+      v = (double)n_pos + guards;
+    }
+    *p = (int32_t)std::min(128.0, std::max(1.0, v));
+  });
+}
+
+pf_status pf_session_set_interval(pf_session* s, double a, double b) {
+  return guarded([&] {
+    if (!s) fail(PF_ERR_ARG, "session is NULL");
+    pf_desc d = s->core->desc;
+    d.a = a;
+    d.b = b;
+    plan_validate(d, nullptr, nullptr);             // finite a < b; spec_ub > b when scaled
+    s->core->desc = d;
   });
 }
 

@@ -295,6 +295,39 @@ __global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ sr
   }
 }
 
+// Block-upper H (m x m, column blocks of s filled in rows 0 .. (j+1)s-1)
+// completed to the full symmetric matrix: entries below the diagonal
+// blocks take their mirror images.
+__global__ void sym_from_block_upper_kernel(double* H, int ldh, int m, int s) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r >= m || r / s <= c / s) return;
+  H[r + (int64_t)c * ldh] = H[c + (int64_t)r * ldh];
+}
+
+// Lanczos outputs from the Ritz values theta (descending, m of them), the
+// eigenvectors Z (ld ldz) and the Gram G (s x s) of the residual block:
+// the residual of Ritz vector i is ||Wr z_i|| with z_i its last s entries.
+__global__ void lanczos_out_kernel(const double* theta, const double* Z, int ldz, int m, int s,
+                                   const double* G, const pf_info* info, pf_bounds* out) {
+  if (threadIdx.x != 0) return;
+  double res[2];
+  const int cols[2] = {m - 1, 0};
+  for (int t = 0; t < 2; ++t) {
+    const double* z = Z + (int64_t)cols[t] * ldz + (m - s);
+    double q = 0.0;
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b < s; ++b) q += z[a] * G[a + b * s] * z[b];
+    res[t] = sqrt(fmax(q, 0.0));
+  }
+  out->theta_min = theta[m - 1];
+  out->theta_max = theta[0];
+  out->res_min = res[0];
+  out->res_max = res[1];
+  out->status = info->status;
+  out->replaced = info->deficient;
+}
+
 }  // namespace
 
 void launch_apply(const ApplyArgs& a, hipStream_t st) {
@@ -402,6 +435,18 @@ void launch_transpose(const void* src, int64_t lds_, int64_t rows, int64_t cols,
                                                       static_cast<uint8_t*>(dst), ldd);
       break;
   }
+  PFX_HIP(hipGetLastError());
+}
+
+void launch_sym_from_block_upper(double* H, int ldh, int m, int s, hipStream_t st) {
+  dim3 grid((unsigned)((m + 255) / 256), (unsigned)m);
+  sym_from_block_upper_kernel<<<grid, 256, 0, st>>>(H, ldh, m, s);
+  PFX_HIP(hipGetLastError());
+}
+
+void launch_lanczos_out(const double* theta, const double* Z, int ldz, int m, int s, const double* G,
+                        const pf_info* info, pf_bounds* out, hipStream_t st) {
+  lanczos_out_kernel<<<1, 64, 0, st>>>(theta, Z, ldz, m, s, G, info, out);
   PFX_HIP(hipGetLastError());
 }
 

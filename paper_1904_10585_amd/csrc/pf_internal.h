@@ -105,6 +105,17 @@ void launch_chol_rinv(const double* G, int ldg, int p, double* Rinv, int ldr,
 void launch_eigh(const double* H, int ldh, int p, double* theta, double* Z, int ldz, int pad, pf_info* info,
                  int which, hipStream_t st, double* escratch = nullptr, int* refined = nullptr);
 size_t eig_scratch_bytes(int p);
+// H (m x m) whose column blocks of s hold rows 0 .. (j+1)s-1 completed to the
+// symmetric matrix (entries below the diagonal blocks mirrored).
+void launch_sym_from_block_upper(double* H, int ldh, int m, int s, hipStream_t st);
+// Lanczos outputs (extreme Ritz values, residual norms from the residual
+// block's Gram G (s x s), status and replaced-column count of *info).
+void launch_lanczos_out(const double* theta, const double* Z, int ldz, int m, int s, const double* G,
+                        const pf_info* info, pf_bounds* out, hipStream_t st);
+// Block Lanczos bounds (pf_lanczos_bounds), stream-ordered on st; scratch
+// allocated and freed stream-ordered.
+void enqueue_lanczos(const pf_mat& X, int64_t n, const double* V0, int64_t ldv0, int steps, pf_bounds* out,
+                     hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Tall-skinny block operations (n x p blocks, p <= 128).

@@ -54,6 +54,11 @@ class PfResult(ctypes.Structure):
                 ("V", ctypes.c_void_p), ("ldv", ctypes.c_int64), ("info", ctypes.c_void_p)]
 
 
+class PfBounds(ctypes.Structure):
+    _fields_ = [("theta_min", ctypes.c_double), ("theta_max", ctypes.c_double), ("res_min", ctypes.c_double),
+                ("res_max", ctypes.c_double), ("status", ctypes.c_int32), ("replaced", ctypes.c_int32)]
+
+
 PF_SERVER_NO_GRAPHS = 0x1
 
 
@@ -96,6 +101,10 @@ def _load():
         "pf_psd_dense": (i32, [vp, i64, vp, i64, i32, ctypes.c_int, vp, i64, vp]),
         "pf_eigh": (i32, [vp, i64, i32, vp, vp, i64, vp]),
         "pf_workspace_size": (i32, [P(PfDesc), P(ctypes.c_size_t)]),
+        "pf_lanczos_bounds": (i32, [P(PfMat), i64, vp, i64, i32, vp, vp]),
+        "pf_interval_policy": (i32, [dbl, dbl, dbl, i32, dbl, P(dbl), P(dbl)]),
+        "pf_block_size_policy": (i32, [i32, dbl, i32, i32, P(i32)]),
+        "pf_session_set_interval": (i32, [vp, dbl, dbl]),
         "pf_profile_set": (i32, [ctypes.c_int]),
         "pf_profile_read": (i32, [ctypes.c_int, P(i64), P(dbl)]),
         "pf_server_create": (i32, [P(PfServerConfig), P(vp)]),
@@ -283,6 +292,50 @@ def pf_eigh(H, theta, Z, stream=None):
     p = H.shape[0]
     _check(LIB.pf_eigh(ctypes.c_void_p(H.data_ptr()), ld_of(H), p, ctypes.c_void_p(theta.data_ptr()),
                        ctypes.c_void_p(Z.data_ptr()), ld_of(Z), _stream(stream)))
+
+
+def pf_lanczos_bounds(X, V0, steps, stream=None, out=None):
+    """Block Lanczos bounds of a symmetric n x n device matrix X (FP32 or
+    FP64) from the n x 16 FP64 start block V0.  Without ``out``: waits for
+    the stream and returns the PfBounds.  With ``out`` (a device uint8 tensor
+    of ctypes.sizeof(PfBounds) bytes): only enqueues; read it with
+    ``bounds_of(out)`` once the stream is done."""
+    import torch
+    n = X.shape[0]
+    dst = out if out is not None else torch.zeros(ctypes.sizeof(PfBounds), dtype=torch.uint8, device=X.device)
+    m = mat(X)
+    _check(LIB.pf_lanczos_bounds(ctypes.byref(m), n, ctypes.c_void_p(V0.data_ptr()), ld_of(V0), steps,
+                                 ctypes.c_void_p(dst.data_ptr()), _stream(stream)))
+    if out is not None:
+        return None
+    if stream is not None:
+        stream.synchronize()
+    else:
+        torch.cuda.synchronize(X.device)
+    return bounds_of(dst)
+
+
+def bounds_of(out):
+    """PfBounds from the device buffer pf_lanczos_bounds wrote."""
+    return PfBounds.from_buffer_copy(bytes(out.cpu().numpy()))
+
+
+def pf_interval_policy(lam_min, margin, eta, top_r=0, theta_r=0.0):
+    """(a, b) of the section 4.1 rule (host arithmetic)."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(LIB.pf_interval_policy(lam_min, margin, eta, top_r, theta_r, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def pf_block_size_policy(top_r, q=2.0, n_pos=0, guards=0):
+    """p of the section 4.2 rule (host arithmetic)."""
+    p = ctypes.c_int32()
+    _check(LIB.pf_block_size_policy(top_r, q, n_pos, guards, ctypes.byref(p)))
+    return p.value
+
+
+def pf_session_set_interval(h, a, b):
+    _check(LIB.pf_session_set_interval(h, a, b))
 
 
 def pf_workspace_size(d):

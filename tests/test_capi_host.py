@@ -194,3 +194,49 @@ def test_eigh_rejects_before_launch():
     assert pf.LIB.pf_eigh(H, 4, 4, th, Z, 2, None) == pf.PF_ERR_ARG
     assert pf.LIB.pf_eigh(H, 8, 8, th, ctypes.c_void_p(0x10000 + 8 * 8), 8, None) == pf.PF_ERR_ARG
     assert "overlap" in pf.last_error()
+
+
+def test_interval_and_block_size_policies_match_the_oracle():
+    """The host rules of sections 4.1-4.2 in the C ABI agree with the
+    oracle's statement of them over a grid of inputs, errors included."""
+    import oracle
+    for lam in (-7.5, -1.0, 0.3):
+        for margin in (0.0, 0.25):
+            for eta in (0.1, 0.2):
+                for top_r, th in ((0, 0.0), (5, 2.0), (12, -0.2)):
+                    try:
+                        want = oracle.interval_policy(lam, margin, eta, top_r, th)
+                    except ValueError:
+                        want = None
+                    if want is None:
+                        with pytest.raises(pf.PfError) as e:
+                            pf.pf_interval_policy(lam, margin, eta, top_r, th)
+                        assert e.value.status == pf.PF_ERR_ARG
+                    else:
+                        got = pf.pf_interval_policy(lam, margin, eta, top_r, th)
+                        assert abs(got[0] - want[0]) <= 1e-15 and abs(got[1] - want[1]) <= 1e-14
+    for r, q in ((1, 1.5), (3, 2.2), (40, 1.5), (100, 2.0)):
+        assert pf.pf_block_size_policy(r, q) == oracle.block_size_policy(r, q)
+    for n_pos, guards in ((0, 0), (37, 8), (200, 4)):
+        assert pf.pf_block_size_policy(0, 2.0, n_pos, guards) == oracle.block_size_policy(0, 2.0, n_pos, guards)
+    for args in ((4, 1.0, 0, 0), (0, 2.0, -1, 0), (3, float("nan"), 0, 0)):
+        with pytest.raises(pf.PfError):
+            pf.pf_block_size_policy(*args)
+    with pytest.raises(pf.PfError):
+        pf.pf_interval_policy(-1.0, 0.0, 1.5)
+
+
+def test_lanczos_rejects_before_launch():
+    """pf_lanczos_bounds argument errors are returned before any HIP call."""
+    m = fake_mat(ld=256)
+    V0, out = ctypes.c_void_p(0x40000), ctypes.c_void_p(0x80000)
+    assert pf.LIB.pf_lanczos_bounds(ctypes.byref(m), 256, None, 256, 4, out, None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_lanczos_bounds(ctypes.byref(m), 256, V0, 256, 0, out, None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_lanczos_bounds(ctypes.byref(m), 256, V0, 256, 9, out, None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_lanczos_bounds(ctypes.byref(m), 40, V0, 256, 3, out, None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_lanczos_bounds(ctypes.byref(m), 300, V0, 300, 4, out, None) == pf.PF_ERR_ARG   # ld < n
+    bf = fake_mat(dtype=pf.PF_BF16, ld=256)
+    assert pf.LIB.pf_lanczos_bounds(ctypes.byref(bf), 256, V0, 256, 4, out, None) == pf.PF_ERR_ARG
+    odd = fake_mat(ld=257)
+    assert pf.LIB.pf_lanczos_bounds(ctypes.byref(odd), 256, V0, 257, 4, out, None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_session_set_interval(None, -1.0, 1.0) == pf.PF_ERR_ARG
