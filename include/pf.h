@@ -314,8 +314,8 @@ pf_status pf_psd_dense(const void* V, int64_t ldv, const double* theta, int64_t 
  * device, ld ldv0 >= n; the caller draws it) spans the first block of the
  * Krylov space K = span{V0, X V0, ..., X^(steps-1) V0}; each block step is
  * one pass over X (products accumulated in FP64), the new block is
- * orthogonalised against all earlier ones (classical Gram-Schmidt twice)
- * and orthonormalised by CholeskyQR (a dependent column becomes a fixed
+ * orthogonalised against all earlier ones and orthonormalised by block
+ * Gram-Schmidt and CholeskyQR, twice (a dependent column becomes a fixed
  * pseudo-random direction, orthogonalised in turn); the Rayleigh-Ritz
  * values of X on K (16 * steps of them, via pf_eigh's solver) give
  *   theta_min >= lambda_min and theta_max <= lambda_max (Cauchy interlacing),

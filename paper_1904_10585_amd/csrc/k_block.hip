@@ -37,20 +37,24 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 // latency covers the kernel, and the K steps alternate between two
 // accumulators to halve the dependent MFMA chain.  Workgroups of one row
 // block read the same A rows and write disjoint columns: C must not alias A.
+// S may be rectangular (p x q, q output columns), and with D the result is
+// C1 = D - A1 S (D may be C1 itself: each element is read, then written, by
+// one lane) -- a Gram-Schmidt update Y -= V C in one launch.
 template <typename T, int NB, bool TWO>
-__global__ __launch_bounds__(256) void apply_kernel(int64_t n, int p, const T* __restrict__ A1, int64_t lda1,
+__global__ __launch_bounds__(256) void apply_kernel(int64_t n, int p, int q, const T* __restrict__ A1, int64_t lda1,
                                                     const T* __restrict__ A2, int64_t lda2,
                                                     const double* __restrict__ S, int lds_, T* C1, int64_t ldc1,
                                                     T* C2, int64_t ldc2, double alpha, double beta,
                                                     const int* __restrict__ deficient,
                                                     const pf_info* gate, pf_info* info_out,
-                                                    const double* __restrict__ theta, double* theta_out) {
+                                                    const double* __restrict__ theta, double* theta_out,
+                                                    const T* D, int64_t ldd) {
   constexpr int KS = 4 * NB;                         // K steps of 4 cover the padded width 16 NB
   const int l = threadIdx.x & 63, c = l & 15, g = l >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * 64 + 16 * (threadIdx.x >> 6);
   const int j = 16 * (int)blockIdx.y + c;            // B column of this lane = its output column
   const int64_t arow = row0 + c;
-  const bool rok = arow < n, jok = j < p;
+  const bool rok = arow < n, jok = j < q;
   const int gst = gate ? gate->status : 0;
   const bool defj = deficient && jok && deficient[j];
   double a1[KS], a2[KS], b[KS];
@@ -87,6 +91,7 @@ __global__ __launch_bounds__(256) void apply_kernel(int64_t n, int p, const T* _
       // next CholeskyQR pass orthogonalises against the others
       v1 = (2.0 * u01(mix64(((uint64_t)row << 8) ^ (uint64_t)j ^ 0x5DEECE66Dull)) - 1.0) / sqrt((double)n);
     }
+    if (D) v1 = (double)D[row + j * ldd] - v1;
     C1[row + j * ldc1] = (T)v1;
     if constexpr (TWO) C2[row + j * ldc2] = (T)(alpha * r2[r] + beta * (double)(T)v1);
   }
@@ -251,15 +256,17 @@ __global__ __launch_bounds__(256) void psd_dense_kernel(const T* __restrict__ V,
 template <typename T, bool TWO>
 void apply_t(const ApplyArgs& a, hipStream_t st) {
   const int nb = (a.p + 15) / 16;
-  const dim3 grid((unsigned)((a.n + 63) / 64), (unsigned)nb);
+  const int q = a.q > 0 ? a.q : a.p;
+  const dim3 grid((unsigned)((a.n + 63) / 64), (unsigned)((q + 15) / 16));
+  const T* D = static_cast<const T*>(a.D);
   const T* A1 = static_cast<const T*>(a.A1);
   const T* A2 = static_cast<const T*>(a.A2);
   T* C1 = static_cast<T*>(a.C1);
   T* C2 = static_cast<T*>(a.C2);
 #define PFX_APPLY(NB)                                                                                    \
-  apply_kernel<T, NB, TWO><<<grid, 256, 0, st>>>(a.n, a.p, A1, a.lda1, A2, a.lda2, a.S, a.lds_, C1, a.ldc1, \
-                                                C2, a.ldc2, a.alpha, a.beta, a.deficient, a.gate, a.info_out,     \
-                                                a.theta, a.theta_out)
+  apply_kernel<T, NB, TWO><<<grid, 256, 0, st>>>(a.n, a.p, q, A1, a.lda1, A2, a.lda2, a.S, a.lds_, C1, a.ldc1, \
+                                                C2, a.ldc2, a.alpha, a.beta, a.deficient, a.gate, a.info_out,        \
+                                                a.theta, a.theta_out, D, a.ldd)
   switch (nb) {
     case 1: PFX_APPLY(1); break;
     case 2: PFX_APPLY(2); break;
@@ -336,6 +343,8 @@ void launch_apply(const ApplyArgs& a, hipStream_t st) {
     fail(PF_ERR_UNSUPPORTED, "apply: mixed element types");
   const bool two = a.A2 != nullptr;
   if ((a.info_out || a.theta_out) && !a.gate) fail(PF_ERR_ARG, "apply: output copies need the gate");
+  if (a.q < 0 || a.q > 128) fail(PF_ERR_ARG, "apply: q out of range");
+  if (a.D && (a.D == a.A1 || a.D == a.A2 || two)) fail(PF_ERR_ARG, "apply: D must not alias an input, nor come with A2");
   // workgroups of one row block share A rows and write disjoint columns
   if (a.C1 == a.A1 || (two && (a.C1 == a.A2 || a.C2 == a.A1 || a.C2 == a.A2)))
     fail(PF_ERR_ARG, "apply: output aliases an input");

@@ -5,16 +5,16 @@
 // it.  Here the Krylov space K = span{V0, X V0, ..., X^(s-1) V0} of a
 // 16-column start block is built one block per pass over X (products
 // accumulated in FP64 by the contraction kernel), each new block
-// orthogonalised against all earlier ones (classical Gram-Schmidt twice)
-// and orthonormalised by CholeskyQR; a dependent column becomes a fixed
-// pseudo-random direction, which a third Gram-Schmidt pass and a second
-// CholeskyQR put back into the orthogonal complement.  The Rayleigh-Ritz
-// matrix H = V^T X V is assembled from the first Gram-Schmidt coefficients
-// of every step (block j of H's columns is V^T (X V_j)) and decomposed by
-// the dense p x p solver.  The residual of a Ritz vector y = V z is
-// (I - V V^T) X V z = W_r z_r (W_r the last step's block after
-// orthogonalisation, z_r the last 16 entries of z), so its norm comes from
-// the 16 x 16 Gram matrix of W_r.
+// orthogonalised against all earlier ones by block classical Gram-Schmidt
+// with re-orthogonalisation: Gram-Schmidt, CholeskyQR, Gram-Schmidt,
+// CholeskyQR (a dependent column, which CholeskyQR turns into a fixed
+// pseudo-random direction, is put back into the orthogonal complement by
+// the second pair).  The Rayleigh-Ritz matrix H = V^T X V is assembled
+// from the first Gram-Schmidt coefficients of every step (block j of H's
+// columns is V^T (X V_j)) and decomposed by the dense p x p solver.  The
+// residual of a Ritz vector y = V z is (I - V V^T) X V z = W_r z_r (W_r the
+// last step's block after orthogonalisation, z_r the last 16 entries of z),
+// so its norm comes from the 16 x 16 Gram matrix of W_r.
 #include "pf_internal.h"
 
 #include <algorithm>
@@ -48,12 +48,11 @@ void enqueue_lanczos(const pf_mat& X, int64_t n, const double* V0, int64_t ldv0,
                                 contract_part_bytes(n, m, kS, Elem::F64, Elem::F64, true, 0),
                                 contract_part_bytes(n, kS, kS, Elem::F64, Elem::F64, true, 0)});
   // sizes first (a null arena counts), then one stream-ordered allocation
-  auto carve = [&](Arena& a, double*& V, double*& W, double*& W1, double*& T, double*& H, double*& S, double*& G,
+  auto carve = [&](Arena& a, double*& V, double*& W, double*& W1, double*& H, double*& S, double*& G,
                    double*& R, double*& Gl, double*& Z, double*& th, int*& def, pf_info*& info, void*& pb) {
     V = a.take<double>((size_t)ld * m);
     W = a.take<double>((size_t)ld * kS);
     W1 = a.take<double>((size_t)ld * kS);
-    T = a.take<double>((size_t)ld * m);
     H = a.take<double>((size_t)m * m);
     S = a.take<double>((size_t)m * m);
     G = a.take<double>(kS * kS);
@@ -65,12 +64,12 @@ void enqueue_lanczos(const pf_mat& X, int64_t n, const double* V0, int64_t ldv0,
     info = a.take<pf_info>(1);
     pb = a.take<char>(std::max<size_t>(part, 256));
   };
-  double *V, *W, *W1, *T, *H, *S, *G, *R, *Gl, *Z, *th;
+  double *V, *W, *W1, *H, *S, *G, *R, *Gl, *Z, *th;
   int* def;
   pf_info* info;
   void* pb;
   Arena a;
-  carve(a, V, W, W1, T, H, S, G, R, Gl, Z, th, def, info, pb);
+  carve(a, V, W, W1, H, S, G, R, Gl, Z, th, def, info, pb);
   void* mem = nullptr;
   if (hipMallocAsync(&mem, a.used, st) != hipSuccess) {
     (void)hipGetLastError();
@@ -78,7 +77,7 @@ void enqueue_lanczos(const pf_mat& X, int64_t n, const double* V0, int64_t ldv0,
   }
   a.base = static_cast<char*>(mem);
   a.used = 0;
-  carve(a, V, W, W1, T, H, S, G, R, Gl, Z, th, def, info, pb);
+  carve(a, V, W, W1, H, S, G, R, Gl, Z, th, def, info, pb);
   PFX_HIP(hipMemsetAsync(info, 0, sizeof(pf_info), st));
 
   // C (M x N, ld ldc) = A^T B, contracted over n rows in FP64
@@ -108,24 +107,23 @@ void enqueue_lanczos(const pf_mat& X, int64_t n, const double* V0, int64_t ldv0,
     ap.gate = nullptr;
     launch_apply(ap, st);
   };
-  // Y <- Y - V_{0..j} C, C ((j+1) kS x kS) already in S (ld m) with zero
-  // columns kS .. (j+1) kS - 1
-  auto subtract = [&](double* Y, int j) {
-    rotate(V, (j + 1) * kS, S, m, T, nullptr);
-    launch_axpby(Y, T, Y, ld, Elem::F64, n, kS, 1.0, -1.0, st);
-  };
-  // one Gram-Schmidt pass of Y against V_{0..j}; the coefficients go to
-  // S (and, when Hcol is given, to that column block of H first)
-  auto gs_pass = [&](double* Y, int j, double* Hcol) {
+  // one Gram-Schmidt pass of Y against V_{0..j}: C = V^T Y ((j+1) kS x kS,
+  // ld ldc), then Y -= V C in one rectangular apply
+  auto gs_pass = [&](double* Y, int j, double* C, int ldc) {
     const int rows = (j + 1) * kS;
-    if (Hcol) {
-      product(V, ld, Elem::F64, rows, Y, ld, Hcol, m);
-      launch_copy_block(Hcol, m, Elem::F64, S, m, Elem::F64, rows, kS, rows, rows, st);
-    } else {
-      launch_copy_block(S, m, Elem::F64, S, m, Elem::F64, 0, 0, rows, rows, st);   // zero the square
-      product(V, ld, Elem::F64, rows, Y, ld, S, m);
-    }
-    subtract(Y, j);
+    product(V, ld, Elem::F64, rows, Y, ld, C, ldc);
+    ApplyArgs ap;
+    ap.n = n; ap.p = rows; ap.q = kS;
+    ap.A1 = V; ap.lda1 = ld; ap.ta1 = Elem::F64;
+    ap.A2 = nullptr; ap.lda2 = ld; ap.ta2 = Elem::F64;
+    ap.S = C; ap.lds_ = ldc;
+    ap.C1 = Y; ap.ldc1 = ld; ap.tc1 = Elem::F64;
+    ap.C2 = nullptr; ap.ldc2 = ld; ap.tc2 = Elem::F64;
+    ap.alpha = 0.0; ap.beta = 0.0;
+    ap.deficient = nullptr;
+    ap.gate = nullptr;
+    ap.D = Y; ap.ldd = ld;
+    launch_apply(ap, st);
   };
   // CholeskyQR pass: dst = src R^{-1}, dependent columns replaced
   auto cholqr = [&](const double* src, double* dst) {
@@ -141,13 +139,13 @@ void enqueue_lanczos(const pf_mat& X, int64_t n, const double* V0, int64_t ldv0,
   for (int j = 0; j < steps; ++j) {
     const double* Vj = V + (int64_t)j * kS * ld;
     product(X.data, X.ld, tx, n, Vj, ld, W, ld);      // W = X V_j (X symmetric: X^T V_j)
-    gs_pass(W, j, H + (int64_t)j * kS * m);           // H[0..(j+1)kS, block j] = V^T X V_j
-    gs_pass(W, j, nullptr);
+    gs_pass(W, j, H + (int64_t)j * kS * m, m);        // H[0..(j+1)kS, block j] = V^T X V_j
     if (j + 1 < steps) {
       cholqr(W, W1);
-      gs_pass(W1, j, nullptr);
+      gs_pass(W1, j, S, m);
       cholqr(W1, V + (int64_t)(j + 1) * kS * ld);
     } else {
+      gs_pass(W, j, S, m);
       product(W, ld, Elem::F64, kS, W, ld, Gl, kS);   // Gram of the residual block
     }
   }

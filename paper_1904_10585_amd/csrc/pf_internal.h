@@ -136,6 +136,11 @@ struct ApplyArgs {
   pf_info* info_out = nullptr;
   const double* theta = nullptr;
   double* theta_out = nullptr;
+  // q output columns (0: p), S then p x q; with D (element type of C1,
+  // ld ldd, may be C1 itself): C1 = D - A1 S
+  int q = 0;
+  const void* D = nullptr;
+  int64_t ldd = 0;
 };
 void launch_apply(const ApplyArgs& a, hipStream_t st);
 
