@@ -359,6 +359,25 @@ pf_status pf_block_size_policy(int32_t top_r, double q, int32_t n_pos, int32_t g
  * steps, as the interval policy of section 4.1 follows the iterates. */
 pf_status pf_session_set_interval(pf_session* s, double a, double b);
 
+/* Filter degree for a tolerance (section 3, Lemma ctr1), host arithmetic.
+ * A wanted eigenvalue theta_r > b maps to 1 + l past the damping interval,
+ * l = 2 (theta_r - b) / (b - a); the unwanted part maps into [-1, 1].  After
+ * one filtered step (power q) the subspace error is bounded by a factor of
+ * the start angle times 1 / T_d(1 + l)^q (the step of the proof before
+ * Lemma cheb-est's lower bound on T_d is used), so sin <= eps needs
+ *   T_d(1 + l)^q >= 1 / eps,  d = ceil(acosh(eps^(-1/q)) / acosh(1 + l)).
+ * The result is clamped to [d_min, d_max].  The O(log k) degree schedule of
+ * Theorem conv1 is this rule with eps = eps_0 / k at outer iteration k.
+ * PF_ERR_ARG unless a < b < theta_r, 0 < eps < 1, q >= 1 and
+ * 1 <= d_min <= d_max. */
+pf_status pf_degree_policy(double theta_r, double a, double b, int32_t q, double eps, int32_t d_min,
+                           int32_t d_max, int32_t* degree);
+
+/* Change a session's filter degree d and power q for its next steps (the
+ * degree schedule of Theorem conv1, q_k of eq. pfpg2); validated like
+ * pf_desc. */
+pf_status pf_session_set_filter(pf_session* s, int32_t degree, int32_t q);
+
 /* Kernel timing hooks (diagnostics).  While enabled, the library records a
  * HIP event pair on the launch stream around every kernel launch of the
  * given class; pf_profile_read synchronises on the recorded events and

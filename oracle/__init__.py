@@ -32,7 +32,7 @@ from .extract import (orthonormalize, rayleigh_ritz, extract, extract_gram,
                       psd_projection, lowrank_projection, ritz_residuals)
 from .metrics import sin_theta, projector_distance, ritz_rel_err, orth_error
 from .jacobi import jacobi_eigh
-from .lanczos import block_krylov_ritz, lanczos_bounds, interval_policy, block_size_policy
+from .lanczos import block_krylov_ritz, lanczos_bounds, interval_policy, block_size_policy, degree_policy
 from .quantize import (bf16_round, fp8_e4m3_round, fp8_tile_quantize,
                        fp8_tile_dequantize)
 
@@ -41,7 +41,7 @@ __all__ = [
     "orthonormalize", "rayleigh_ritz", "extract", "extract_gram",
     "psd_projection", "lowrank_projection", "ritz_residuals",
     "sin_theta", "projector_distance", "ritz_rel_err", "orth_error",
-    "block_krylov_ritz", "lanczos_bounds", "interval_policy", "block_size_policy",
+    "block_krylov_ritz", "lanczos_bounds", "interval_policy", "block_size_policy", "degree_policy",
     "jacobi_eigh",
     "bf16_round", "fp8_e4m3_round", "fp8_tile_quantize", "fp8_tile_dequantize",
 ]

@@ -1,4 +1,5 @@
-"""Spectrum estimate and interval / block-size rules (section 4.1, 4.2).
+"""Spectrum estimate, interval / block-size rules (section 4.1, 4.2) and
+the filter-degree rule (section 3, Lemma ctr1 and Theorem conv1).
 
 Test infrastructure (see ``oracle/__init__``).
 
@@ -74,3 +75,17 @@ def block_size_policy(top_r, q=2.0, n_pos=0, guards=0):
     else:
         p = n_pos + guards
     return int(min(128, max(1, p)))
+
+
+def degree_policy(theta_r, a, b, q=1, eps=1e-6, d_min=1, d_max=64):
+    """Degree for sin <= eps after one filtered step (Lemma ctr1): theta_r
+    maps to 1 + l, l = 2 (theta_r - b) / (b - a), the unwanted spectrum into
+    [-1, 1]; the error after one step is bounded by a start-angle factor over
+    T_d(1 + l)^q (the step of the proof before Lemma cheb-est bounds T_d from
+    below), so the smallest d with T_d(1 + l)^q >= 1 / eps, from
+    T_d(x) = cosh(d acosh x) for x >= 1.  Clamped to [d_min, d_max]."""
+    if not (a < b < theta_r) or not (0.0 < eps < 1.0) or q < 1 or not (1 <= d_min <= d_max):
+        raise ValueError("need a < b < theta_r, 0 < eps < 1, q >= 1, 1 <= d_min <= d_max")
+    x = 1.0 + 2.0 * (theta_r - b) / (b - a)
+    d = int(np.ceil(np.arccosh(eps ** (-1.0 / q)) / np.arccosh(x)))
+    return int(min(d_max, max(d_min, d)))

@@ -420,4 +420,31 @@ pf_status pf_session_set_interval(pf_session* s, double a, double b) {
   });
 }
 
+pf_status pf_degree_policy(double theta_r, double a, double b, int32_t q, double eps, int32_t d_min,
+                           int32_t d_max, int32_t* degree) {
+  return guarded([&] {
+    if (!degree) fail(PF_ERR_ARG, "NULL argument");
+    if (!std::isfinite(theta_r) || !std::isfinite(a) || !std::isfinite(b) || !(a < b) || !(b < theta_r))
+      fail(PF_ERR_ARG, "need finite a < b < theta_r");
+    if (!(eps > 0.0 && eps < 1.0)) fail(PF_ERR_ARG, "eps must be in (0, 1)");
+    if (q < 1) fail(PF_ERR_ARG, "q must be >= 1");
+    if (d_min < 1 || d_max < d_min) fail(PF_ERR_ARG, "need 1 <= d_min <= d_max");
+    const double l = 2.0 * (theta_r - b) / (b - a);
+    // T_d(1 + l) = cosh(d acosh(1 + l)) >= eps^(-1/q)
+    const double d = std::ceil(std::acosh(std::pow(eps, -1.0 / q)) / std::acosh(1.0 + l));
+    *degree = (int32_t)std::min<double>(d_max, std::max<double>(d_min, d));
+  });
+}
+
+pf_status pf_session_set_filter(pf_session* s, int32_t degree, int32_t q) {
+  return guarded([&] {
+    if (!s) fail(PF_ERR_ARG, "session is NULL");
+    pf_desc d = s->core->desc;
+    d.degree = degree;
+    d.q = q;
+    plan_validate(d, nullptr, nullptr);             // degree >= 1, q >= 1
+    s->core->desc = d;
+  });
+}
+
 }  // extern "C"

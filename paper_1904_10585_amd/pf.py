@@ -105,6 +105,8 @@ def _load():
         "pf_interval_policy": (i32, [dbl, dbl, dbl, i32, dbl, P(dbl), P(dbl)]),
         "pf_block_size_policy": (i32, [i32, dbl, i32, i32, P(i32)]),
         "pf_session_set_interval": (i32, [vp, dbl, dbl]),
+        "pf_degree_policy": (i32, [dbl, dbl, dbl, i32, dbl, i32, i32, P(i32)]),
+        "pf_session_set_filter": (i32, [vp, i32, i32]),
         "pf_profile_set": (i32, [ctypes.c_int]),
         "pf_profile_read": (i32, [ctypes.c_int, P(i64), P(dbl)]),
         "pf_server_create": (i32, [P(PfServerConfig), P(vp)]),
@@ -336,6 +338,17 @@ def pf_block_size_policy(top_r, q=2.0, n_pos=0, guards=0):
 
 def pf_session_set_interval(h, a, b):
     _check(LIB.pf_session_set_interval(h, a, b))
+
+
+def pf_degree_policy(theta_r, a, b, q=1, eps=1e-6, d_min=1, d_max=64):
+    """Filter degree of the tolerance rule (host arithmetic)."""
+    d = ctypes.c_int32()
+    _check(LIB.pf_degree_policy(theta_r, a, b, q, eps, d_min, d_max, ctypes.byref(d)))
+    return d.value
+
+
+def pf_session_set_filter(h, degree, q=1):
+    _check(LIB.pf_session_set_filter(h, degree, q))
 
 
 def pf_workspace_size(d):

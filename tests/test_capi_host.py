@@ -240,3 +240,18 @@ def test_lanczos_rejects_before_launch():
     odd = fake_mat(ld=257)
     assert pf.LIB.pf_lanczos_bounds(ctypes.byref(odd), 256, V0, 257, 4, out, None) == pf.PF_ERR_ARG
     assert pf.LIB.pf_session_set_interval(None, -1.0, 1.0) == pf.PF_ERR_ARG
+
+
+def test_degree_policy_matches_the_oracle():
+    import oracle
+    for th, a, b in ((1.0, -5.0, 0.8), (1.0, -2.0, 0.8), (5.0, -1.0, 0.5), (20.0, -10.0, 0.8)):
+        for q in (1, 2, 3):
+            for eps in (1e-2, 1e-6, 1e-10):
+                for dmin, dmax in ((1, 64), (8, 12)):
+                    assert pf.pf_degree_policy(th, a, b, q, eps, dmin, dmax) == \
+                        oracle.degree_policy(th, a, b, q, eps, dmin, dmax)
+    for args in ((0.5, -1.0, 0.8, 1, 1e-3, 1, 64), (1.0, -1.0, 0.8, 0, 1e-3, 1, 64),
+                 (1.0, -1.0, 0.8, 1, 1.5, 1, 64), (1.0, -1.0, 0.8, 1, 1e-3, 5, 4)):
+        with pytest.raises(pf.PfError):
+            pf.pf_degree_policy(*args)
+    assert pf.LIB.pf_session_set_filter(None, 8, 1) == pf.PF_ERR_ARG

@@ -118,3 +118,47 @@ def test_session_interval_policy_chain(work):
             U = V
     finally:
         pf.pf_session_close(h)
+
+
+@pytest.mark.parametrize("work", ["f64", "f32"])
+def test_session_degree_schedule_chain(work):
+    """Theorem conv1's schedule driving a chain: at outer step k the degree
+    is the Lemma ctr1 rule with eps_k = eps_0 / k (theta_r from the previous
+    step), the power alternates 1, 2, moved into the session with
+    pf_session_set_filter.  Every step matches the oracle run with the same
+    degree and power on the same U and X_k."""
+    pf = pf_module()
+    # 12 planted top eigenvalues, the 12th at 1.07 just above b; the rule
+    # and the comparison use the 10th (6.7), which stays clear of b
+    n, p, r, a, b = 1500, 24, 10, -5.0, 0.8
+    X, _, _ = wl.planted(n, 12, (1.0, 20.0), (-2.0, 0.8), config=135)
+    U = wl.start_block(n, p, config=135)
+    f64 = work == "f64"
+    tdt, wk = (torch.float64, pf.PF_F64) if f64 else (torch.float32, pf.PF_F32)
+    d, q = 8, 1
+    h = pf.pf_session_open(pf.desc(n, p, d, a, b, work=wk), device_matrix(U, tdt), seed=0)
+    try:
+        for k in range(1, 6):
+            if k > 1:
+                X = X + wl.perturbation(n, 135, k)
+            Xs = X if f64 else X.astype(np.float32).astype(np.float64)
+            Xd = device_matrix(Xs, tdt)
+            pf.pf_session_step(h, Xd, Xd)
+            s, res = pf.pf_session_wait(h)
+            assert s == pf.PF_OK and res.status == 0
+            ref = oracle.extract(Xs, Xs, U, d, a, b, q=q)
+            th = pf.device_to_numpy(res.theta, (p,), np.float64)
+            V = pf.device_to_numpy(res.V, (p, res.ldv), np.float64 if f64 else np.float32).T[:n].astype(np.float64)
+            rel, sin = compare(th, V, ref, r)
+            print(f"degree schedule {work} step {k}: d={d} q={q} rel {rel:.2e} sin {sin:.2e}")
+            if f64:
+                assert rel <= 1e-10 and sin <= (1e-7 if k == 1 else 1e-9), (k, rel, sin)
+            elif k >= 3:
+                assert rel <= 1e-5 and sin <= 1e-4, (k, rel, sin)
+            q = 1 + (k % 2)
+            d = pf.pf_degree_policy(float(th[r - 1]), a, b, q, 1e-3 / (k + 1), 4, 16)
+            assert d == oracle.degree_policy(float(th[r - 1]), a, b, q, 1e-3 / (k + 1), 4, 16)
+            pf.pf_session_set_filter(h, d, q)
+            U = V
+    finally:
+        pf.pf_session_close(h)

@@ -86,3 +86,27 @@ def test_block_size_rules_worked_examples():
     assert oracle.block_size_policy(100, 2.0) == 128
     with pytest.raises(ValueError):
         oracle.block_size_policy(10, 1.0)
+
+
+@pytest.mark.parametrize("theta_r,a,b,q,eps", [(1.0, -5.0, 0.8, 1, 1e-6), (1.0, -2.0, 0.8, 2, 1e-8),
+                                               (5.0, -1.0, 0.5, 1, 1e-3), (1.2, -5.0, 0.8, 3, 1e-2)])
+def test_degree_rule_is_the_smallest_sufficient_degree(theta_r, a, b, q, eps):
+    """Lemma ctr1's requirement T_d(1 + l)^q >= 1/eps, checked with the
+    oracle's Chebyshev polynomial (pinned on its own): the rule's degree
+    meets it and one less does not."""
+    d = oracle.degree_policy(theta_r, a, b, q, eps, d_min=1, d_max=10_000)
+    x = 1.0 + 2.0 * (theta_r - b) / (b - a)
+    assert oracle.cheb_T(d, x) ** q >= (1.0 - 1e-12) / eps
+    assert oracle.cheb_T(d - 1, x) ** q < 1.0 / eps
+    assert oracle.interval_map(theta_r, a, b) == pytest.approx(x)
+
+
+def test_degree_schedule_grows_like_log_k():
+    """Theorem conv1: eps_k = eps_0 / k gives d_k = O(log k): nondecreasing,
+    and d_k - d_1 stays within log(k) / acosh(1 + l) + 1."""
+    a, b, th = -5.0, 0.8, 1.5
+    x = 1.0 + 2.0 * (th - b) / (b - a)
+    ds = [oracle.degree_policy(th, a, b, 1, 1e-2 / k, d_min=1, d_max=10_000) for k in range(1, 2001)]
+    assert all(d1 <= d2 for d1, d2 in zip(ds, ds[1:]))
+    for k in (10, 100, 1000, 2000):
+        assert ds[k - 1] - ds[0] <= np.log(k) / np.arccosh(x) + 1
