@@ -58,7 +58,7 @@ typedef enum pf_status {
   PF_ERR_NOCONV = 5,      /* reserved: the eigensolver is direct and always ends */
   PF_ERR_NONFINITE = 6,   /* Inf/NaN met in the filtered block */
   PF_ERR_BUSY = 7,        /* session has work in flight */
-  PF_ERR_UNSUPPORTED = 8  /* valid request this build does not implement */
+  PF_ERR_UNSUPPORTED = 8  /* valid request the library does not implement */
 } pf_status;
 
 typedef enum pf_dtype {

@@ -181,7 +181,7 @@ const char* pf_status_string(pf_status s) {
     case PF_ERR_NOCONV: return "PF_ERR_NOCONV: an iteration did not converge";
     case PF_ERR_NONFINITE: return "PF_ERR_NONFINITE: non-finite values in the filtered block";
     case PF_ERR_BUSY: return "PF_ERR_BUSY: work in flight";
-    case PF_ERR_UNSUPPORTED: return "PF_ERR_UNSUPPORTED: not implemented in this build";
+    case PF_ERR_UNSUPPORTED: return "PF_ERR_UNSUPPORTED: not implemented by the library";
   }
   return "unknown pf_status";
 }
