@@ -178,6 +178,30 @@ pf_status pf_extract(const pf_desc* desc, const pf_mat* X_filter, const pf_mat* 
                      void* U_inout, int64_t ldu, double* theta_out, pf_info* info_out,
                      void* stream);
 
+/* A caller-supplied symmetric operator in place of a dense X (matrix-free
+ * or sparse A; the paper's extraction only ever needs the products A Y).
+ * apply(ctx, Y, ldy, AY, lday, cols, stream) enqueues AY = A Y on stream for
+ * an n-by-cols device block Y in the work dtype (column-major; cols is p
+ * rounded up to a multiple of 16, the columns past p are zero) into AY of
+ * the same shape and dtype, and returns PF_OK once enqueued (any other
+ * value aborts the extraction with that status).  The library calls it d q
+ * + 1 times per extraction (every filter product and the Rayleigh-Ritz
+ * product) from the calling thread; the recurrence, CholeskyQR,
+ * Rayleigh-Ritz Gram and p x p eigensolve stay in the library's kernels
+ * (the Gram accumulated in FP64; the product's own precision is the
+ * caller's).  Forms: PF_OP_SYM with work FP32 or FP64; PF_FLAG_NATIVE_F32
+ * is implied (no BF16 split). */
+typedef pf_status (*pf_apply_fn)(void* ctx, const void* Y, int64_t ldy, void* AY, int64_t lday, int32_t cols,
+                                 void* stream);
+typedef struct pf_operator {
+  pf_apply_fn apply;
+  void* ctx;
+} pf_operator;
+
+/* pf_extract with the operator in place of X_filter and X_rr. */
+pf_status pf_extract_op(const pf_desc* desc, const pf_operator* op, void* U_inout, int64_t ldu,
+                        double* theta_out, pf_info* info_out, void* stream);
+
 /* Sessions: a warm-started chain of extractions (eq. pfpg2 / eq. PFAM2:
  * U^{k+1} = orth(rho(X^{k+1}) U^k)), whose subspace stays on the device.
  *  U0: device n-by-p block in the work dtype (ld ldu0), or NULL for an
@@ -354,6 +378,9 @@ pf_status pf_interval_policy(double lam_min, double margin, double eta, int32_t 
  * (pf_info.n_pos).  The result is clamped to [1, 128]; PF_ERR_ARG for
  * q <= 1, negative counts or non-finite q. */
 pf_status pf_block_size_policy(int32_t top_r, double q, int32_t n_pos, int32_t guards, int32_t* p);
+
+/* pf_session_step with a caller-supplied operator (see pf_operator). */
+pf_status pf_session_step_op(pf_session* s, const pf_operator* op, pf_result* out, void* stream);
 
 /* Move a session's damping interval [a, b] (a < b, finite) for its next
  * steps, as the interval policy of section 4.1 follows the iterates. */

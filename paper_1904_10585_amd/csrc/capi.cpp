@@ -63,11 +63,12 @@ void session_destroy(SessionCore* s) {
   delete s;
 }
 
-void session_enqueue_step(SessionCore* s, const pf_mat& Xf, const pf_mat& Xr, hipStream_t st) {
+void session_enqueue_step(SessionCore* s, const pf_mat& Xf, const pf_mat& Xr, hipStream_t st,
+                          const pf_operator* op) {
   pf_desc d = s->desc;
   if (s->steps == 0) d.flags |= PF_FLAG_COLD;        // first step starts from U0
   plan_set_desc(s->plan, d);
-  enqueue_extraction(s->plan, Xf, Xr, s->U, s->ldu, s->U, s->ldu, s->theta, s->info, st);
+  enqueue_extraction(s->plan, Xf, Xr, s->U, s->ldu, s->U, s->ldu, s->theta, s->info, st, op);
   s->steps++;
 }
 
@@ -239,6 +240,31 @@ pf_status pf_extract(const pf_desc* desc, const pf_mat* X_filter, const pf_mat* 
   });
 }
 
+namespace {
+// the operator forms: a symmetric operator given by its products
+void check_operator(const pf_desc& d, const pf_operator* op) {
+  if (!op || !op->apply) fail(PF_ERR_ARG, "operator or its apply callback is NULL");
+  if (d.op != PF_OP_SYM) fail(PF_ERR_ARG, "an operator extraction takes pf_desc.op = PF_OP_SYM");
+}
+}  // namespace
+
+pf_status pf_extract_op(const pf_desc* desc, const pf_operator* op, void* U_inout, int64_t ldu, double* theta_out,
+                        pf_info* info_out, void* stream) {
+  return guarded([&] {
+    if (!desc) fail(PF_ERR_ARG, "desc is NULL");
+    plan_validate(*desc, nullptr, nullptr);
+    check_operator(*desc, op);
+    if (!U_inout) fail(PF_ERR_ARG, "U_inout is NULL");
+    if (ldu < desc->n) fail(PF_ERR_ARG, "ldu is smaller than n");
+    if (!theta_out) fail(PF_ERR_ARG, "theta_out is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Plan* P = cached_plan(*desc, st);
+    plan_set_desc(P, *desc);
+    const pf_mat none{};
+    enqueue_extraction(P, none, none, U_inout, ldu, U_inout, ldu, theta_out, info_out, st, op);
+  });
+}
+
 pf_status pf_session_open(const pf_desc* desc, const void* U0, int64_t ldu0, uint64_t seed, pf_session** out) {
   return guarded([&] {
     if (!desc || !out) fail(PF_ERR_ARG, "NULL argument");
@@ -264,6 +290,26 @@ pf_status pf_session_step(pf_session* s, const pf_mat* X_filter, const pf_mat* X
     plan_validate(s->core->desc, X_filter, X_rr);
     hipStream_t st = static_cast<hipStream_t>(stream);
     session_enqueue_step(s->core, *X_filter, *X_rr, st);
+    PFX_HIP(hipEventRecord(s->done, st));
+    s->stepped = true;
+    if (out) {
+      out->status = 0;
+      out->n_pos = 0;
+      out->theta = s->core->theta;
+      out->V = s->core->U;
+      out->ldv = s->core->ldu;
+      out->info = s->core->info;
+    }
+  });
+}
+
+pf_status pf_session_step_op(pf_session* s, const pf_operator* op, pf_result* out, void* stream) {
+  return guarded([&] {
+    if (!s) fail(PF_ERR_ARG, "session is NULL");
+    check_operator(s->core->desc, op);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const pf_mat none{};
+    session_enqueue_step(s->core, none, none, st, op);
     PFX_HIP(hipEventRecord(s->done, st));
     s->stepped = true;
     if (out) {

@@ -106,6 +106,21 @@ __global__ void copy_block_kernel(const T* __restrict__ src, int64_t lds_, T* __
   dst[i + j * ldd] = (i < n && j < p) ? src[i + j * lds_] : T(0);
 }
 
+// out = alpha A + beta D1 + gamma D2 on rows < n (D1, D2 optional): the
+// recurrence step around a caller-supplied product A = X Y.
+template <typename T>
+__global__ void combine_kernel(const T* __restrict__ A, const T* __restrict__ D1, const T* __restrict__ D2, T* out,
+                               int64_t ld, int64_t n, int p, double alpha, double beta, double gamma) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n || j >= p) return;
+  const int64_t o = i + j * ld;
+  double v = alpha * (double)A[o];
+  if (D1) v += beta * (double)D1[o];
+  if (D2) v += gamma * (double)D2[o];
+  out[o] = (T)v;
+}
+
 template <typename T>
 __global__ void axpby_kernel(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ dst, int64_t ld,
                              int64_t n, int p, double alpha, double beta) {
@@ -456,6 +471,20 @@ void launch_sym_from_block_upper(double* H, int ldh, int m, int s, hipStream_t s
 void launch_lanczos_out(const double* theta, const double* Z, int ldz, int m, int s, const double* G,
                         const pf_info* info, pf_bounds* out, hipStream_t st) {
   lanczos_out_kernel<<<1, 64, 0, st>>>(theta, Z, ldz, m, s, G, info, out);
+  PFX_HIP(hipGetLastError());
+}
+
+void launch_combine(const void* A, const void* D1, const void* D2, void* out, int64_t ld, Elem t, int64_t n, int p,
+                    double alpha, double beta, double gamma, hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)p);
+  if (t == Elem::F64)
+    combine_kernel<double><<<grid, 256, 0, st>>>(static_cast<const double*>(A), static_cast<const double*>(D1),
+                                                 static_cast<const double*>(D2), static_cast<double*>(out), ld, n, p,
+                                                 alpha, beta, gamma);
+  else
+    combine_kernel<float><<<grid, 256, 0, st>>>(static_cast<const float*>(A), static_cast<const float*>(D1),
+                                                static_cast<const float*>(D2), static_cast<float*>(out), ld, n, p,
+                                                alpha, beta, gamma);
   PFX_HIP(hipGetLastError());
 }
 

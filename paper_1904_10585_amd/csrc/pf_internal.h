@@ -148,6 +148,10 @@ void launch_apply(const ApplyArgs& a, hipStream_t st);
 // p_pad columns, zero fill of padding columns and rows up to n_pad).
 void launch_copy_block(const void* src, int64_t lds, Elem ts, void* dst, int64_t ldd, Elem td,
                        int64_t n, int p, int64_t n_pad, int p_pad, hipStream_t st);
+// out = alpha * A + beta * D1 + gamma * D2 on rows < n (D1, D2 optional;
+// n x p blocks of one ld and element type)
+void launch_combine(const void* A, const void* D1, const void* D2, void* out, int64_t ld, Elem t, int64_t n, int p,
+                    double alpha, double beta, double gamma, hipStream_t st);
 // dst = alpha * A + beta * B (n x p blocks, same element type)
 void launch_axpby(const void* A, const void* B, void* dst, int64_t ld, Elem t, int64_t n, int p,
                   double alpha, double beta, hipStream_t st);
@@ -182,9 +186,11 @@ void plan_destroy(Plan* p);
 size_t plan_bytes(const pf_desc& d);
 void plan_validate(const pf_desc& d, const pf_mat* Xf, const pf_mat* Xr);
 // Enqueue one extraction.  U_in (ld ldu_in) may alias U_out.
+// With op, the caller's operator takes the place of Xf and Xr (PF_OP_SYM;
+// no BF16 split).
 void enqueue_extraction(Plan* plan, const pf_mat& Xf, const pf_mat& Xr, const void* U_in,
                         int64_t ldu_in, void* U_out, int64_t ldu_out, double* theta_out,
-                        pf_info* info_out, hipStream_t st);
+                        pf_info* info_out, hipStream_t st, const pf_operator* op = nullptr);
 // refresh the numeric fields (interval, flags) of a cached plan
 void plan_set_desc(Plan* P, const pf_desc& d);
 // plan-owned buffers (for sessions)
@@ -213,7 +219,8 @@ SessionCore* session_create(const pf_desc& d, const void* U0, int64_t ldu0, uint
                             bool sync);
 void session_destroy(SessionCore* s);
 // Enqueue one step on st (the first step of a session runs as a cold start).
-void session_enqueue_step(SessionCore* s, const pf_mat& Xf, const pf_mat& Xr, hipStream_t st);
+void session_enqueue_step(SessionCore* s, const pf_mat& Xf, const pf_mat& Xr, hipStream_t st,
+                          const pf_operator* op = nullptr);
 // Copy the info record of the last step to host-visible memory (a mapped
 // pinned buffer), stream-ordered: the host reads it once the step is done.
 void launch_info_to_host(const pf_info* src, pf_info* host_mapped, hipStream_t st);

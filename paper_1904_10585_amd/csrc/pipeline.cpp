@@ -390,10 +390,26 @@ void split_product(Plan* P, const void* A, int64_t lda, pf_dtype adt, const floa
 // One filter product out = alpha X Y + beta D1 + gamma D2 on the split-BF16
 // path (FP32 work) or on the native MFMA path (FP32 with PF_FLAG_NATIVE_F32,
 // or FP64).  want_planes: also write the planes of out for the next product.
+// Caller-supplied product AY = A Y (pf_operator) into AY, checked.
+void operator_product(Plan* P, const pf_operator* op, const void* Y, void* AY, hipStream_t st) {
+  const pf_status s = op->apply(op->ctx, Y, P->n_pad, AY, P->n_pad, P->p_pad, st);
+  if (s != PF_OK) fail(s, "the operator's apply callback returned an error");
+}
+
 void filter_product(Plan* P, const pf_mat& Xf, const void* y, void* out, const void* D1, const void* D2,
-                    double alpha, double beta, double gamma, bool want_planes, hipStream_t st) {
-  const bool split = P->work == Elem::F32 && !(P->d.flags & PF_FLAG_NATIVE_F32);
+                    double alpha, double beta, double gamma, bool want_planes, hipStream_t st,
+                    const pf_operator* op) {
   const int64_t ld = P->n_pad;
+  if (op) {
+    // the caller's product, then the recurrence step around it (W is free
+    // until the Rayleigh-Ritz product)
+    const bool plain = !D1 && !D2 && alpha == 1.0;
+    void* AY = plain ? out : P->W;
+    operator_product(P, op, y, AY, st);
+    if (!plain) launch_combine(AY, D1, D2, out, ld, P->work, P->n, P->p_pad, alpha, beta, gamma, st);
+    return;
+  }
+  const bool split = P->work == Elem::F32 && !(P->d.flags & PF_FLAG_NATIVE_F32);
   if (P->d.op == PF_OP_GRAM) {
     // T = M Y (contraction over the n columns of M: the transposed copy),
     // then out = alpha M^T T + beta D1 + gamma D2 (contraction over m)
@@ -461,7 +477,8 @@ void apply(Plan* P, const void* A1, const void* A2, const double* S, void* C1, i
 }  // namespace
 
 void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void* U_in, int64_t ldu_in,
-                        void* U_out, int64_t ldu_out, double* theta_out, pf_info* info_out, hipStream_t st) {
+                        void* U_out, int64_t ldu_out, double* theta_out, pf_info* info_out, hipStream_t st,
+                        const pf_operator* op) {
   const pf_desc& d = P->d;
   const double c = 0.5 * (d.a + d.b), e = 0.5 * (d.b - d.a);
   std::vector<double> tau;
@@ -472,7 +489,7 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
 
   const bool prof = prof_enabled();
   if (prof) prof_begin(PF_PROF_EXTRACT, st);
-  const bool split = W == Elem::F32 && !(d.flags & PF_FLAG_NATIVE_F32);
+  const bool split = W == Elem::F32 && !(d.flags & PF_FLAG_NATIVE_F32) && !op;
   // U_in into the work buffer (with the planes of Y_0 = U for the split
   // filter) and pf_info cleared, in one launch
   launch_begin_block(U_in, ldu_in, W, P->U, ld, P->n, P->p, P->n_pad, P->p_pad, split ? planes_of(P, P->U) : nullptr,
@@ -493,7 +510,7 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
     // the planes of Y_0 come with the copy of U; later passes start from
     // Y_d, whose planes the last step wrote
     // first product Z = A Y_0
-    filter_product(P, Xf, cur, P->Z, nullptr, nullptr, 1.0, 0.0, 0.0, false, st);
+    filter_product(P, Xf, cur, P->Z, nullptr, nullptr, 1.0, 0.0, 0.0, false, st, op);
     const double a1 = 1.0 / (e * tau[1]), b1 = -c / (e * tau[1]);
     void* y_prev;
     void* y_cur;
@@ -526,7 +543,7 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
       const bool reorth = cold && (k + 1) % 2 == 0 && k + 1 < d.degree;
       // planes of Y_{k+1} feed the next product (or the next pass)
       const bool want = split && ((k + 1 < d.degree && !reorth) || (k + 1 == d.degree && pass + 1 < d.q));
-      filter_product(P, Xf, y_cur, y_next, y_cur, y_prev, al, be, ga, want, st);
+      filter_product(P, Xf, y_cur, y_next, y_cur, y_prev, al, be, ga, want, st, op);
       y_prev = y_cur;
       y_cur = y_next;
       if (reorth) {
@@ -564,6 +581,10 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
                   nullptr, P->m_pad, 1.0, 0.0, 0.0, true, st, PF_PROF_RR, -1);
     contract_into(P, P->B, P->m_pad, Elem::F64, P->B, P->m_pad, Elem::F64, P->m, P->p_pad, P->G, P->p_pad,
                   Elem::F64, nullptr, nullptr, 0, 1.0, 0.0, 0.0, true, st, -1, -1);
+  } else if (op) {
+    // W = A Q by the caller's operator (work dtype), H = Q^T W in FP64
+    operator_product(P, op, P->Q, P->W, st);
+    gram(P, P->Q, W, P->W, W, P->G, st);
   } else {
     contract_into(P, Xr.data, Xr.ld, tr, P->Q, ld, W, P->n, P->n, P->W, ld, Elem::F64, nullptr, nullptr, ld, 1.0,
                   0.0, 0.0, true, st, PF_PROF_RR, -1);

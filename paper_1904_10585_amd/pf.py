@@ -54,6 +54,14 @@ class PfResult(ctypes.Structure):
                 ("V", ctypes.c_void_p), ("ldv", ctypes.c_int64), ("info", ctypes.c_void_p)]
 
 
+APPLY_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                            ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p)
+
+
+class PfOperator(ctypes.Structure):
+    _fields_ = [("apply", APPLY_FN), ("ctx", ctypes.c_void_p)]
+
+
 class PfBounds(ctypes.Structure):
     _fields_ = [("theta_min", ctypes.c_double), ("theta_max", ctypes.c_double), ("res_min", ctypes.c_double),
                 ("res_max", ctypes.c_double), ("status", ctypes.c_int32), ("replaced", ctypes.c_int32)]
@@ -102,6 +110,8 @@ def _load():
         "pf_eigh": (i32, [vp, i64, i32, vp, vp, i64, vp]),
         "pf_workspace_size": (i32, [P(PfDesc), P(ctypes.c_size_t)]),
         "pf_lanczos_bounds": (i32, [P(PfMat), i64, vp, i64, i32, vp, vp]),
+        "pf_extract_op": (i32, [P(PfDesc), P(PfOperator), vp, i64, vp, vp, vp]),
+        "pf_session_step_op": (i32, [vp, P(PfOperator), P(PfResult), vp]),
         "pf_interval_policy": (i32, [dbl, dbl, dbl, i32, dbl, P(dbl), P(dbl)]),
         "pf_block_size_policy": (i32, [i32, dbl, i32, i32, P(i32)]),
         "pf_session_set_interval": (i32, [vp, dbl, dbl]),
@@ -320,6 +330,57 @@ def pf_lanczos_bounds(X, V0, steps, stream=None, out=None):
 def bounds_of(out):
     """PfBounds from the device buffer pf_lanczos_bounds wrote."""
     return PfBounds.from_buffer_copy(bytes(out.cpu().numpy()))
+
+
+class _DeviceArray:
+    """A column-major rows x cols device block at a raw pointer, exposed
+    through __cuda_array_interface__ (zero-copy views for operator callbacks)."""
+
+    def __init__(self, ptr, rows, cols, ld, typestr, esz):
+        self.__cuda_array_interface__ = {"shape": (rows, cols), "typestr": typestr, "data": (ptr, False),
+                                         "strides": (esz, ld * esz), "version": 2}
+
+
+def device_view(ptr, rows, cols, ld, dtype):
+    """torch view of a column-major device block (float32 / float64)."""
+    import torch
+    typestr, esz = ("<f8", 8) if dtype == torch.float64 else ("<f4", 4)
+    return torch.as_tensor(_DeviceArray(ptr, rows, cols, ld, typestr, esz), device="cuda")
+
+
+def make_operator(fn, n, dtype):
+    """PfOperator from fn(Y, AY): torch views of the n x cols blocks (column
+    major, dtype the work dtype); fn must write AY = A Y with torch work on
+    the current stream (the callback makes the library's stream current).
+    The returned object keeps the ctypes callback alive."""
+    import torch
+
+    def _apply(ctx, Y, ldy, AY, lday, cols, stream):
+        try:
+            st = torch.cuda.ExternalStream(stream) if stream else torch.cuda.current_stream()
+            with torch.cuda.stream(st):
+                fn(device_view(Y, n, cols, ldy, dtype), device_view(AY, n, cols, lday, dtype))
+            return PF_OK
+        except Exception:                                    # reported as a device error
+            return PF_ERR_DEVICE
+
+    cb = APPLY_FN(_apply)
+    op = PfOperator(cb, None)
+    op._keep = cb
+    return op
+
+
+def pf_extract_op(d, op, U, theta, info=None, stream=None):
+    """pf_extract with a PfOperator (make_operator) in place of X."""
+    _check(LIB.pf_extract_op(ctypes.byref(d), ctypes.byref(op), ctypes.c_void_p(U.data_ptr()), ld_of(U),
+                             ctypes.c_void_p(theta.data_ptr()),
+                             ctypes.c_void_p(info.data_ptr()) if info is not None else None, _stream(stream)))
+
+
+def pf_session_step_op(h, op, stream=None):
+    r = PfResult()
+    _check(LIB.pf_session_step_op(h, ctypes.byref(op), ctypes.byref(r), _stream(stream)))
+    return r
 
 
 def pf_interval_policy(lam_min, margin, eta, top_r=0, theta_r=0.0):

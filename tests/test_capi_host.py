@@ -16,6 +16,7 @@ pf = pytest.importorskip("paper_1904_10585_amd.pf")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"typedef[^;]*;", "", text)                 # function-pointer types are not symbols
     return sorted(set(re.findall(r"\b(pf_[a-z_]+)\s*\(", text)))
 
 
@@ -255,3 +256,19 @@ def test_degree_policy_matches_the_oracle():
         with pytest.raises(pf.PfError):
             pf.pf_degree_policy(*args)
     assert pf.LIB.pf_session_set_filter(None, 8, 1) == pf.PF_ERR_ARG
+
+
+def test_operator_entry_points_reject_before_launch():
+    """pf_extract_op / pf_session_step_op argument errors before any HIP
+    call: no operator, no callback, a Gram descriptor."""
+    d = good_desc()
+    U, theta = ctypes.c_void_p(0x20000), ctypes.c_void_p(0x30000)
+    assert pf.LIB.pf_extract_op(ctypes.byref(d), None, U, 256, theta, None, None) == pf.PF_ERR_ARG
+    op = pf.PfOperator()
+    assert pf.LIB.pf_extract_op(ctypes.byref(d), ctypes.byref(op), U, 256, theta, None, None) == pf.PF_ERR_ARG
+    good = pf.make_operator(lambda Y, AY: None, 256, None)
+    g = good_desc(op=pf.PF_OP_GRAM, m=300)
+    assert pf.LIB.pf_extract_op(ctypes.byref(g), ctypes.byref(good), U, 256, theta, None, None) == pf.PF_ERR_ARG
+    assert "PF_OP_SYM" in pf.last_error()
+    assert pf.LIB.pf_extract_op(ctypes.byref(d), ctypes.byref(good), None, 256, theta, None, None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_session_step_op(None, ctypes.byref(good), None, None) == pf.PF_ERR_ARG
