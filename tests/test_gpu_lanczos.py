@@ -162,3 +162,37 @@ def test_session_degree_schedule_chain(work):
             U = V
     finally:
         pf.pf_session_close(h)
+
+
+def test_session_setters_validate():
+    """The per-step setters check like pf_desc: a scaled session keeps
+    spec_ub > b, degree and power stay >= 1; a rejected call leaves the
+    session as it was (the next step still runs)."""
+    pf = pf_module()
+    n, p = 400, 16
+    X, _, _ = wl.planted(n, 8, (2.0, 9.0), (-1.0, 0.5), config=136)
+    U = wl.start_block(n, p, config=136)
+    dsc = pf.desc(n, p, 6, -1.2, 0.6, work=pf.PF_F64, flags=pf.PF_FLAG_SCALED, spec_ub=12.0)
+    h = pf.pf_session_open(dsc, device_matrix(U, torch.float64), seed=0)
+    try:
+        for bad in ((-1.2, 13.0), (0.6, -1.2), (float("nan"), 0.6)):
+            with pytest.raises(pf.PfError) as e:
+                pf.pf_session_set_interval(h, *bad)
+            assert e.value.status == pf.PF_ERR_ARG
+        for bad in ((0, 1), (6, 0)):
+            with pytest.raises(pf.PfError) as e:
+                pf.pf_session_set_filter(h, *bad)
+            assert e.value.status == pf.PF_ERR_ARG
+        pf.pf_session_set_interval(h, -1.3, 0.55)
+        pf.pf_session_set_filter(h, 7, 2)
+        Xd = device_matrix(X, torch.float64)
+        pf.pf_session_step(h, Xd, Xd)
+        s, res = pf.pf_session_wait(h)
+        assert s == pf.PF_OK and res.status == 0
+        ref = oracle.extract(X, X, U, 7, -1.3, 0.55, q=2)
+        th = pf.device_to_numpy(res.theta, (p,), np.float64)
+        V = pf.device_to_numpy(res.V, (p, res.ldv), np.float64).T[:n]
+        rel, sin = compare(th, V, ref, 8)
+        assert rel <= 1e-10 and sin <= 1e-7, (rel, sin)
+    finally:
+        pf.pf_session_close(h)
