@@ -36,50 +36,14 @@ struct Arena {
   }
 };
 
-}  // namespace
-
-void enqueue_lanczos(const pf_mat& X, int64_t n, const double* V0, int64_t ldv0, int steps, pf_bounds* out,
-                     hipStream_t st) {
+// The block steps on carved scratch (see enqueue_lanczos).
+void lanczos_steps(const pf_mat& X, int64_t n, const double* V0, int64_t ldv0, int steps, pf_bounds* out,
+                   hipStream_t st, double* V, double* W, double* W1, double* H, double* S, double* G, double* R,
+                   double* Gl, double* Z, double* th, int* def, pf_info* info, void* pb, size_t part) {
   const Elem tx = X.dtype == PF_F64 ? Elem::F64 : Elem::F32;
   const int m = kS * steps;
   const int64_t ld = round_up(n, 16);
-
-  const size_t part = std::max({contract_part_bytes(n, n, kS, tx, Elem::F64, true, 0),
-                                contract_part_bytes(n, m, kS, Elem::F64, Elem::F64, true, 0),
-                                contract_part_bytes(n, kS, kS, Elem::F64, Elem::F64, true, 0)});
-  // sizes first (a null arena counts), then one stream-ordered allocation
-  auto carve = [&](Arena& a, double*& V, double*& W, double*& W1, double*& H, double*& S, double*& G,
-                   double*& R, double*& Gl, double*& Z, double*& th, int*& def, pf_info*& info, void*& pb) {
-    V = a.take<double>((size_t)ld * m);
-    W = a.take<double>((size_t)ld * kS);
-    W1 = a.take<double>((size_t)ld * kS);
-    H = a.take<double>((size_t)m * m);
-    S = a.take<double>((size_t)m * m);
-    G = a.take<double>(kS * kS);
-    R = a.take<double>(kS * kS);
-    Gl = a.take<double>(kS * kS);
-    Z = a.take<double>((size_t)m * m);
-    th = a.take<double>(m);
-    def = a.take<int>(kS);
-    info = a.take<pf_info>(1);
-    pb = a.take<char>(std::max<size_t>(part, 256));
-  };
-  double *V, *W, *W1, *H, *S, *G, *R, *Gl, *Z, *th;
-  int* def;
-  pf_info* info;
-  void* pb;
-  Arena a;
-  carve(a, V, W, W1, H, S, G, R, Gl, Z, th, def, info, pb);
-  void* mem = nullptr;
-  if (hipMallocAsync(&mem, a.used, st) != hipSuccess) {
-    (void)hipGetLastError();
-    fail(PF_ERR_NOMEM, "lanczos: scratch allocation failed");
-  }
-  a.base = static_cast<char*>(mem);
-  a.used = 0;
-  carve(a, V, W, W1, H, S, G, R, Gl, Z, th, def, info, pb);
   PFX_HIP(hipMemsetAsync(info, 0, sizeof(pf_info), st));
-
   // C (M x N, ld ldc) = A^T B, contracted over n rows in FP64
   auto product = [&](const void* A, int64_t lda, Elem ta, int64_t M, const double* B, int64_t ldb, double* C,
                      int64_t ldc) {
@@ -152,6 +116,56 @@ void enqueue_lanczos(const pf_mat& X, int64_t n, const double* V0, int64_t ldv0,
   launch_sym_from_block_upper(H, m, m, kS, st);
   launch_eigh(H, m, m, th, Z, m, m, nullptr, 1, st);
   launch_lanczos_out(th, Z, m, m, kS, Gl, info, out, st);
+}
+
+}  // namespace
+
+void enqueue_lanczos(const pf_mat& X, int64_t n, const double* V0, int64_t ldv0, int steps, pf_bounds* out,
+                     hipStream_t st) {
+  const Elem tx = X.dtype == PF_F64 ? Elem::F64 : Elem::F32;
+  const int m = kS * steps;
+  const int64_t ld = round_up(n, 16);
+
+  const size_t part = std::max({contract_part_bytes(n, n, kS, tx, Elem::F64, true, 0),
+                                contract_part_bytes(n, m, kS, Elem::F64, Elem::F64, true, 0),
+                                contract_part_bytes(n, kS, kS, Elem::F64, Elem::F64, true, 0)});
+  // sizes first (a null arena counts), then one stream-ordered allocation
+  auto carve = [&](Arena& a, double*& V, double*& W, double*& W1, double*& H, double*& S, double*& G,
+                   double*& R, double*& Gl, double*& Z, double*& th, int*& def, pf_info*& info, void*& pb) {
+    V = a.take<double>((size_t)ld * m);
+    W = a.take<double>((size_t)ld * kS);
+    W1 = a.take<double>((size_t)ld * kS);
+    H = a.take<double>((size_t)m * m);
+    S = a.take<double>((size_t)m * m);
+    G = a.take<double>(kS * kS);
+    R = a.take<double>(kS * kS);
+    Gl = a.take<double>(kS * kS);
+    Z = a.take<double>((size_t)m * m);
+    th = a.take<double>(m);
+    def = a.take<int>(kS);
+    info = a.take<pf_info>(1);
+    pb = a.take<char>(std::max<size_t>(part, 256));
+  };
+  double *V, *W, *W1, *H, *S, *G, *R, *Gl, *Z, *th;
+  int* def;
+  pf_info* info;
+  void* pb;
+  Arena a;
+  carve(a, V, W, W1, H, S, G, R, Gl, Z, th, def, info, pb);
+  void* mem = nullptr;
+  if (hipMallocAsync(&mem, a.used, st) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(PF_ERR_NOMEM, "lanczos: scratch allocation failed");
+  }
+  a.base = static_cast<char*>(mem);
+  a.used = 0;
+  carve(a, V, W, W1, H, S, G, R, Gl, Z, th, def, info, pb);
+  try {
+    lanczos_steps(X, n, V0, ldv0, steps, out, st, V, W, W1, H, S, G, R, Gl, Z, th, def, info, pb, part);
+  } catch (...) {
+    (void)hipFreeAsync(mem, st);                       // the scratch goes back with the error
+    throw;
+  }
   PFX_HIP(hipFreeAsync(mem, st));
 }
 
