@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--workload", default="planted_8192")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle extractions in the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-interval-policy", action="store_true",
+                    help="skip the Lanczos interval-policy leg (keeps kernel traces to the extraction)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event hooks")
     ap.add_argument("--sessions", type=int, default=2000, help="serving: sessions in the Poisson stream")
     ap.add_argument("--session-steps", type=int, default=30, help="serving: steps per session")
@@ -199,27 +201,29 @@ def main():
     # ---- damping-interval policy of section 4.1 on the chain's last timed
     # matrix: block Lanczos bounds, 8 block steps of 16 columns (one pass
     # over X each), after the timed region
-    import ctypes
-    V0l = pf.colmajor(n, 16, torch.float64, dev)
-    V0l.copy_(torch.from_numpy(wl.start_block(n, 16, w.config, index=1)))
-    Xl = Xs[W + K - 1]
-    lz_out = torch.zeros(ctypes.sizeof(pf.PfBounds), dtype=torch.uint8, device=dev)
-    pf.pf_lanczos_bounds(Xl, V0l, 8, stream=stream, out=lz_out)          # first call: pool warm-up
-    lz_ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    lz_reps = 5
-    torch.cuda.synchronize()
-    lz_ev[0].record(stream)
-    for _ in range(lz_reps):
-        pf.pf_lanczos_bounds(Xl, V0l, 8, stream=stream, out=lz_out)
-    lz_ev[1].record(stream)
-    torch.cuda.synchronize()
-    lz_ms = lz_ev[0].elapsed_time(lz_ev[1]) / lz_reps
-    lzb = pf.bounds_of(lz_out)
-    # the r-largest rule of section 4.1 with theta_r from the chain's last Ritz values
-    th_last = pf.device_to_numpy(res.theta, (p,), np.float64)
-    lz_a, lz_b = pf.pf_interval_policy(lzb.theta_min, lzb.res_min, 0.15, w.n_top, float(th_last[w.n_top - 1]))
-    log(f"lanczos bounds (8 x 16): {lz_ms:.3f} ms, theta_min {lzb.theta_min:.4f} res {lzb.res_min:.3e} "
-        f"(planted lambda_min of X0 {float(lam.min()):.4f})")
+    lz_ms = None
+    if not args.no_interval_policy:
+        import ctypes
+        V0l = pf.colmajor(n, 16, torch.float64, dev)
+        V0l.copy_(torch.from_numpy(wl.start_block(n, 16, w.config, index=1)))
+        Xl = Xs[W + K - 1]
+        lz_out = torch.zeros(ctypes.sizeof(pf.PfBounds), dtype=torch.uint8, device=dev)
+        pf.pf_lanczos_bounds(Xl, V0l, 8, stream=stream, out=lz_out)          # first call: pool warm-up
+        lz_ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        lz_reps = 5
+        torch.cuda.synchronize()
+        lz_ev[0].record(stream)
+        for _ in range(lz_reps):
+            pf.pf_lanczos_bounds(Xl, V0l, 8, stream=stream, out=lz_out)
+        lz_ev[1].record(stream)
+        torch.cuda.synchronize()
+        lz_ms = lz_ev[0].elapsed_time(lz_ev[1]) / lz_reps
+        lzb = pf.bounds_of(lz_out)
+        # the r-largest rule of section 4.1 with theta_r from the chain's last Ritz values
+        th_last = pf.device_to_numpy(res.theta, (p,), np.float64)
+        lz_a, lz_b = pf.pf_interval_policy(lzb.theta_min, lzb.res_min, 0.15, w.n_top, float(th_last[w.n_top - 1]))
+        log(f"lanczos bounds (8 x 16): {lz_ms:.3f} ms, theta_min {lzb.theta_min:.4f} res {lzb.res_min:.3e} "
+            f"(planted lambda_min of X0 {float(lam.min()):.4f})")
     ms_per_step = total_ms / K
     log(f"timed {K} steps: {ms_per_step:.3f} ms/step (wall {wall * 1e3 / K:.3f} ms/step)")
 
@@ -245,15 +249,16 @@ def main():
         "bytes_per_step_algorithmic": bytes_step,
         "last_step_info": {"n_pos": int(info[1]), "dense_rr": int(info[2]), "dense_pre": int(info[3]),
                            "deficient": int(info[4])},
-        "interval_policy": {"lanczos_ms": round(lz_ms, 4), "block_steps": 8, "block": 16,
-                            "hbm_GBps_per_pass": round(8 * 4.0 * n * n / (lz_ms * 1e-3) / 1e9, 1),
-                            "theta_min": round(lzb.theta_min, 6), "res_min": round(lzb.res_min, 6),
-                            "planted_lambda_min_X0": round(float(lam.min()), 6),
-                            "a": round(lz_a, 6), "b_top_r_rule": round(lz_b, 6), "status": int(lzb.status)},
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
                        "p99": round(float(np.percentile(step_ms, 99)), 4),
                        "max": round(float(step_ms.max()), 4)},
     }
+    if lz_ms is not None:
+        out["interval_policy"] = {"lanczos_ms": round(lz_ms, 4), "block_steps": 8, "block": 16,
+                                  "hbm_GBps_per_pass": round(8 * 4.0 * n * n / (lz_ms * 1e-3) / 1e9, 1),
+                                  "theta_min": round(lzb.theta_min, 6), "res_min": round(lzb.res_min, 6),
+                                  "planted_lambda_min_X0": round(float(lam.min()), 6),
+                                  "a": round(lz_a, 6), "b_top_r_rule": round(lz_b, 6), "status": int(lzb.status)}
     if prof:
         cnt, ms = prof["filter"]
         avg_us = ms / max(cnt, 1) * 1e3
