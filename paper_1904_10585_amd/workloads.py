@@ -9,14 +9,15 @@ stands in for the SVD route.
 
 Seeds: numpy PCG64 keyed by SeedSequence([10585, config, stream, index]);
 streams 0 = Q, 1 = lambda, 2 = U0, 3 = perturbation E_k (index k),
-4 = session parameters, 5 = arrivals, 6 = factors of M, 7 = noise of M.
+4 = session parameters, 5 = arrivals, 6 = factors of M, 7 = noise of M,
+8 = off-diagonal entries of an NCE matrix G.
 """
 from dataclasses import dataclass, field
 
 import numpy as np
 
 SEED_ROOT = 10585
-S_Q, S_LAMBDA, S_U0, S_PERTURB, S_SESSION, S_ARRIVAL, S_MFACT, S_MNOISE = range(8)
+S_Q, S_LAMBDA, S_U0, S_PERTURB, S_SESSION, S_ARRIVAL, S_MFACT, S_MNOISE, S_NCE = range(9)
 
 
 def rng(config, stream, index=0):
@@ -119,6 +120,18 @@ def lowrank_plus_noise(m, n, r, noise, config, index=0):
     B = gf.standard_normal((n, r))
     N = rng(config, S_MNOISE, index).standard_normal((m, n))
     return A @ B.T + noise * N
+
+
+def nce_matrix(n, example, config, index=0):
+    """Symmetric G of the nearest correlation examples of section 5.1: unit
+    diagonal, off-diagonal entries i.i.d. uniform in [-1, 1] (example 6) or
+    [0, 2] (example 7); the upper triangle is drawn and mirrored."""
+    lo, hi = {6: (-1.0, 1.0), 7: (0.0, 2.0)}[int(example)]
+    T = rng(config, S_NCE, index).uniform(lo, hi, (n, n))
+    G = np.triu(T, 1)
+    G = G + G.T
+    np.fill_diagonal(G, 1.0)
+    return G
 
 
 def workload_matrices(w, index=0):
