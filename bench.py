@@ -116,6 +116,8 @@ def main():
         return gram_main(args)
     if args.workload == "operator_sparse":
         return operator_main(args)
+    if args.workload.startswith("nce_ex"):
+        return nce_main(args)
     w = wl.WORKLOADS[args.workload]
     n, p, d = w.n, w.p, w.degree
     dev = "cuda"
@@ -563,6 +565,93 @@ def operator_main(args):
         "speedup_vs_dense": round(ms_dense / ms_op, 2),
         "parity_operator_vs_dense": {"ritz_rel_max": rel, "sin_max": sin, "target": f"top-{r}"},
     }
+    print(json.dumps(out), flush=True)
+
+
+def nce_main(args):
+    """Nearest correlation estimation (section 5.1): PFPG on the dual of
+    min 1/2 ||G - X||_F^2, diag(X) = 1, X PSD, for G of example 5.6 or 5.7
+    (``--workload nce_ex7_2000``: unit diagonal, off-diagonal entries uniform
+    in [0, 2], n = 2000) from x0 = 1 - diag(G) to ||grad F|| <= 1e-7
+    ||grad F(x0)||.  One FP64 extraction per step (degree 10; 4 for example
+    5.7, whose outlying eigenvalue near n would otherwise dominate the
+    filtered block; interval from
+    the block Lanczos bound, block = positive count + 8 guards within 128),
+    the extrapolation of section 4.3 every 4 steps.  A "step" here is one
+    whole solve; value = solves/s.  The oracle's exact gradient method
+    (a full FP64 eigendecomposition per iteration) is timed on three
+    iterations beside it, and the oracle's PFPG on three."""
+    import time
+    import torch
+    from paper_1904_10585_amd import pf
+    from paper_1904_10585_amd import workloads as wl
+    torch.cuda.set_device(0)
+    parts = args.workload.split("_")
+    example, n = int(parts[1][2:]), int(parts[2])
+    p_max = 128
+    # example 5.7 has an eigenvalue near n far above the bulk: degree 4 keeps
+    # the filter's growth ratio between it and the wanted bulk near 1e5
+    degree = 4 if example == 7 else 10
+    G = wl.nce_matrix(n, example, config=170, index=n)
+    U0h = wl.start_block(n, p_max, config=170, index=n)
+    V0h = wl.start_block(n, 16, config=171, index=n)
+    x0 = 1.0 - np.diag(G)
+    Gd = pf.colmajor(n, n, torch.float64, "cuda")
+    Gd.copy_(torch.from_numpy(G))
+    U0 = pf.colmajor(n, p_max, torch.float64, "cuda")
+    U0.copy_(torch.from_numpy(U0h))
+    V0 = pf.colmajor(n, 16, torch.float64, "cuda")
+    V0.copy_(torch.from_numpy(V0h))
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    K, W = max(1, args.steps // 10), max(1, args.warmup // 5)
+    log(f"nce example 5.{example}, n={n}: {W} warm-up solve(s), {K} timed")
+
+    def solve():
+        x.copy_(torch.from_numpy(x0))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res, hist = pf.pf_nce_pfpg(Gd, x, U0, V0, p_max=p_max, degree=degree)
+        return time.perf_counter() - t, res, hist
+
+    for _ in range(W):
+        solve()
+    times = []
+    for _ in range(K):
+        dt, res, hist = solve()
+        times.append(dt)
+        log(f"solve: {dt * 1e3:.1f} ms, {res.iters} iterations, F {res.F:.6e}, |g|/|g0| {res.gnorm / res.gnorm0:.2e}, "
+            f"p {res.p}, n_pos {res.n_pos}, {res.extrapolations} extrapolations")
+    sec = float(np.median(times))
+    out = {
+        "metric": f"NCE solves/s (example 5.{example}, n={n}, PFPG to 1e-7 relative gradient)",
+        "value": round(1.0 / sec, 4), "unit": "solves/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(sec * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic NCE matrix (seeded), resident in HBM",
+        "config": {"workload": args.workload, "n": n, "example": example, "degree": degree, "p_max": p_max, "guards": 8,
+                   "tau": 1.6, "eta": 0.1, "extrapolation_len": 3, "lanczos_every": 10},
+        "iterations": res.iters, "ms_per_iteration": round(sec * 1e3 / max(res.iters + 1, 1), 4),
+        "F": res.F, "converged": bool(res.converged), "p_final": res.p, "n_pos_final": res.n_pos,
+        "block_size_trace": [int(v) for v in hist[:, 3]],
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = len(os.sched_getaffinity(0))
+        t = time.perf_counter()
+        g3 = oracle.nce_grad(G, max_iter=3)
+        t_grad = (time.perf_counter() - t) / 3
+        t = time.perf_counter()
+        oracle.nce_pfpg(G, U0h, V0h, p_max=p_max, degree=degree, max_iter=3)
+        t_pf = (time.perf_counter() - t) / 3
+        # the exact method's iteration count from the GPU-independent oracle
+        # is not run to the end here (minutes at n=2000): its solve time is
+        # per-iteration time x the PFPG iteration count, labelled as such
+        out["cpu_baseline"] = {"value": round(1.0 / (t_grad * (res.iters + 1)), 6), "unit": "solves/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"3 iterations of the oracle's exact gradient method (full FP64 eigh, "
+                                         f"{t_grad:.3f} s/iteration) scaled to {res.iters + 1} iterations; the "
+                                         f"oracle PFPG takes {t_pf:.3f} s/iteration"}
+        log(f"oracle: exact gradient {t_grad:.3f} s/iteration, PFPG {t_pf:.3f} s/iteration "
+            f"(first F {g3['history'][0][0]:.6e})")
     print(json.dumps(out), flush=True)
 
 

@@ -405,6 +405,68 @@ pf_status pf_degree_policy(double theta_r, double a, double b, int32_t q, double
  * pf_desc. */
 pf_status pf_session_set_filter(pf_session* s, int32_t degree, int32_t q);
 
+/* Nearest correlation estimation by PFPG (section 5.1; eq. pfpg1-pfpg2
+ * with R = 0 on the dual of eq. NCE-dual): minimise
+ *   F(x) = 1/2 sum_i max(lambda_i(G + Diag(x)), 0)^2 - 1^T x
+ * by x <- x - tau (diag(P_+(P_U(B(x)))) - 1), B(x) = G + Diag(x), where
+ * P_U(B) = V Theta V^T is the Rayleigh-Ritz projection of one extraction
+ * (filter degree d on [a, b], FP64) warm-started from the previous one.
+ * Every extrapolation_len + 1 steps the last points are combined by the
+ * regularised extrapolation of section 4.3 (coefficients from the Gram of
+ * their successive differences, lambda relative to its Frobenius norm).
+ * The interval follows section 4.1 for all positive eigenvalues:
+ * a = theta_min - res_min of pf_lanczos_bounds on B(x) (start block V0),
+ * b = eta a, refreshed every lanczos_every steps (0: once).  The block size
+ * follows section 4.2: the previous positive count plus guards, rounded up
+ * to a multiple of 16, within [16, p_max]; while more than p_max
+ * eigenvalues are positive the gradient uses the p_max largest Ritz pairs.
+ * Columns added when the block grows are the next columns of U0.
+ * Stops when ||g|| <= tol ||g_0|| (the paper's criterion) or after
+ * max_iter steps.
+ *  G:       device n-by-n FP64 symmetric (ld ldg), not modified.
+ *  x:       device n FP64: in the start point (the paper takes
+ *           1 - diag(G)), out the last iterate (the point whose gradient
+ *           met the test, when converged).
+ *  U0:      device n-by-p_max FP64 start block (ld ldu0).
+ *  V0:      device n-by-16 FP64 Lanczos start block (ld ldv0).
+ *  out:     host result.  history: host, max_iter x 6 doubles (row k:
+ *           F, ||g||, n_pos, p, a, b at step k), or NULL.
+ * Synchronous: returns when the loop ends (the host reads ||g|| and the
+ * positive count after every step).  Device scratch (about
+ * 8 n (n + 2 p_max + extrapolation_len + 8) bytes plus one extraction
+ * workspace per block size) is allocated stream-ordered and freed before
+ * return.  PF_ERR_ARG for invalid options; a failed extraction or
+ * Lanczos run stops the loop with its status in out->status (and as the
+ * return value), x holding the last good iterate. */
+typedef struct pf_nce_opts {
+  uint32_t struct_size;     /* sizeof(pf_nce_opts) */
+  int32_t degree;           /* Chebyshev degree d >= 1 */
+  int32_t guards;           /* guard columns >= 0 */
+  int32_t p_max;            /* 16 <= p_max <= min(n, 128) */
+  int32_t max_iter;         /* >= 1 */
+  int32_t extrapolation_len;  /* l of section 4.3, 0 (off) .. 7 */
+  int32_t lanczos_steps;    /* 1..8 block steps, 16 steps <= n */
+  int32_t lanczos_every;    /* >= 0 */
+  double tau;               /* step size > 0 (F has a 1-Lipschitz gradient: tau < 2) */
+  double eta;               /* b = eta a, 0 < eta < 1 */
+  double tol;               /* > 0 */
+  double extrapolation_lambda;  /* >= 0 */
+} pf_nce_opts;
+typedef struct pf_nce_result {
+  int32_t status;           /* pf_status of the run */
+  int32_t iters;            /* steps taken (the index of the last evaluated iterate) */
+  int32_t converged;        /* 1: ||g|| <= tol ||g_0|| */
+  int32_t n_pos;            /* positive Ritz values at the last iterate */
+  int32_t p;                /* block size at the last iterate */
+  int32_t extrapolations;   /* extrapolation steps taken */
+  double F;                 /* F at the last iterate (from its Ritz values) */
+  double gnorm, gnorm0;     /* ||g|| there and at x0 */
+  double a, b;              /* the last damping interval */
+} pf_nce_result;
+pf_status pf_nce_pfpg(const pf_nce_opts* opts, int64_t n, const double* G, int64_t ldg, double* x,
+                      const double* U0, int64_t ldu0, const double* V0, int64_t ldv0, pf_nce_result* out,
+                      double* history, void* stream);
+
 /* Kernel timing hooks (diagnostics).  While enabled, the library records a
  * HIP event pair on the launch stream around every kernel launch of the
  * given class; pf_profile_read synchronises on the recorded events and

@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpfx.so")
-SOURCES = ["k_contract.hip", "k_filter.hip", "k_small.hip", "k_block.hip", "pipeline.cpp", "capi.cpp", "server.cpp",
-           "lanczos.cpp"]
+SOURCES = ["k_contract.hip", "k_filter.hip", "k_small.hip", "k_block.hip", "k_nce.hip", "pipeline.cpp", "capi.cpp",
+           "server.cpp", "lanczos.cpp", "nce.cpp"]
 ARCH = "gfx950"
 
 

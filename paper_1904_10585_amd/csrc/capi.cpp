@@ -493,4 +493,31 @@ pf_status pf_session_set_filter(pf_session* s, int32_t degree, int32_t q) {
   });
 }
 
+pf_status pf_nce_pfpg(const pf_nce_opts* opts, int64_t n, const double* G, int64_t ldg, double* x, const double* U0,
+                      int64_t ldu0, const double* V0, int64_t ldv0, pf_nce_result* out, double* history,
+                      void* stream) {
+  if (out) *out = pf_nce_result{};
+  const pf_status s = guarded([&] {
+    if (!opts || !G || !x || !U0 || !V0 || !out) fail(PF_ERR_ARG, "NULL argument");
+    const pf_nce_opts& o = *opts;
+    if (o.struct_size != sizeof(pf_nce_opts)) fail(PF_ERR_ARG, "opts.struct_size must be sizeof(pf_nce_opts)");
+    if (o.p_max < 16 || o.p_max > 128 || o.p_max > n) fail(PF_ERR_ARG, "p_max must be in [16, min(n, 128)]");
+    if (o.degree < 1 || o.guards < 0 || o.max_iter < 1) fail(PF_ERR_ARG, "need degree >= 1, guards >= 0, max_iter >= 1");
+    if (o.extrapolation_len < 0 || o.extrapolation_len > kNceMaxRna) fail(PF_ERR_ARG, "extrapolation_len must be in [0, 7]");
+    if (o.lanczos_steps < 1 || o.lanczos_steps > 8 || n < 16 * (int64_t)o.lanczos_steps)
+      fail(PF_ERR_ARG, "lanczos_steps must be in [1, 8] with 16 * lanczos_steps <= n");
+    if (o.lanczos_every < 0) fail(PF_ERR_ARG, "lanczos_every must be >= 0");
+    if (!(o.tau > 0.0) || !std::isfinite(o.tau)) fail(PF_ERR_ARG, "tau must be positive and finite");
+    if (!(o.eta > 0.0 && o.eta < 1.0)) fail(PF_ERR_ARG, "eta must be in (0, 1)");
+    if (!(o.tol > 0.0) || !std::isfinite(o.tol)) fail(PF_ERR_ARG, "tol must be positive and finite");
+    if (!(o.extrapolation_lambda >= 0.0) || !std::isfinite(o.extrapolation_lambda))
+      fail(PF_ERR_ARG, "extrapolation_lambda must be >= 0 and finite");
+    if (ldg < n || ldu0 < n || ldv0 < n) fail(PF_ERR_ARG, "leading dimension smaller than n");
+    run_nce_pfpg(o, n, G, ldg, x, U0, ldu0, V0, ldv0, out, history, static_cast<hipStream_t>(stream));
+    if (out->status != 0) fail((pf_status)out->status, "nce: an extraction reported a numerical failure");
+  });
+  if (s != PF_OK && out && out->status == 0) out->status = s;
+  return s;
+}
+
 }  // extern "C"

@@ -177,6 +177,23 @@ void prof_begin(int cls, hipStream_t st);
 void prof_end(int cls, hipStream_t st);
 
 // ---------------------------------------------------------------------------
+// Nearest-correlation PFPG loop (k_nce.hip, nce.cpp).
+constexpr int kNceMaxRna = 7;   // longest extrapolation window l
+int nce_partial_blocks(int64_t n);
+void launch_nce_init(const double* x, double* gd, double* B, int64_t ldb, int64_t n, double* hist, hipStream_t st);
+// g, per-block partials (2 doubles per block) and stats[4] =
+// (||g||^2, sum x, 1/2 sum max(theta,0)^2, #{theta > 0})
+void launch_nce_grad(const double* V, int64_t ldv, int p, const double* theta, const double* x, double* g, int64_t n,
+                     const pf_info* info, double* partial, double* stats, hipStream_t st);
+void launch_nce_step(double* x, const double* g, double tau, const double* gd, double* B, int64_t ldb, int64_t n,
+                     double* hist, int64_t ldh, int slot, hipStream_t st);
+void launch_nce_diff_gram(const double* hist, int64_t ldh, int64_t n, int m, double* M, hipStream_t st);
+void launch_nce_combine(const double* c, int m, double* hist, int64_t ldh, double* x, const double* gd, double* B,
+                        int64_t ldb, int64_t n, hipStream_t st);
+void run_nce_pfpg(const pf_nce_opts& o, int64_t n, const double* G, int64_t ldg, double* x, const double* U0,
+                  int64_t ldu0, const double* V0, int64_t ldv0, pf_nce_result* out, double* history, hipStream_t st);
+
+// ---------------------------------------------------------------------------
 // The extraction pipeline.
 struct Plan;
 // zero_stream: clear the workspace with hipMemsetAsync on that stream (the

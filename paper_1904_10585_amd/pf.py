@@ -67,6 +67,20 @@ class PfBounds(ctypes.Structure):
                 ("res_max", ctypes.c_double), ("status", ctypes.c_int32), ("replaced", ctypes.c_int32)]
 
 
+class PfNceOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("degree", ctypes.c_int32), ("guards", ctypes.c_int32),
+                ("p_max", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("extrapolation_len", ctypes.c_int32),
+                ("lanczos_steps", ctypes.c_int32), ("lanczos_every", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("eta", ctypes.c_double), ("tol", ctypes.c_double), ("extrapolation_lambda", ctypes.c_double)]
+
+
+class PfNceResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("n_pos", ctypes.c_int32), ("p", ctypes.c_int32), ("extrapolations", ctypes.c_int32),
+                ("F", ctypes.c_double), ("gnorm", ctypes.c_double), ("gnorm0", ctypes.c_double),
+                ("a", ctypes.c_double), ("b", ctypes.c_double)]
+
+
 PF_SERVER_NO_GRAPHS = 0x1
 
 
@@ -110,6 +124,7 @@ def _load():
         "pf_eigh": (i32, [vp, i64, i32, vp, vp, i64, vp]),
         "pf_workspace_size": (i32, [P(PfDesc), P(ctypes.c_size_t)]),
         "pf_lanczos_bounds": (i32, [P(PfMat), i64, vp, i64, i32, vp, vp]),
+        "pf_nce_pfpg": (i32, [P(PfNceOpts), i64, vp, i64, vp, vp, i64, vp, i64, P(PfNceResult), vp, vp]),
         "pf_extract_op": (i32, [P(PfDesc), P(PfOperator), vp, i64, vp, vp, vp]),
         "pf_session_step_op": (i32, [vp, P(PfOperator), P(PfResult), vp]),
         "pf_interval_policy": (i32, [dbl, dbl, dbl, i32, dbl, P(dbl), P(dbl)]),
@@ -325,6 +340,34 @@ def pf_lanczos_bounds(X, V0, steps, stream=None, out=None):
     else:
         torch.cuda.synchronize(X.device)
     return bounds_of(dst)
+
+
+def pf_nce_pfpg(G, x, U0, V0, *, degree=10, guards=8, p_max=128, max_iter=500, extrapolation_len=3,
+                lanczos_steps=4, lanczos_every=10, tau=1.6, eta=0.1, tol=1e-7, extrapolation_lambda=1e-8,
+                stream=None, history=True):
+    """Nearest correlation PFPG loop on the device (FP64 column-major G
+    n x n, x n (in: start, out: last iterate), U0 n x p_max, V0 n x 16).
+    Returns (PfNceResult, history) with history an (iters + 1) x 6 array of
+    (F, ||g||, n_pos, p, a, b) rows, or None.  Raises PfError on failure
+    (the result is then in the exception's ``result`` attribute)."""
+    import numpy as np
+    n = G.shape[0]
+    o = PfNceOpts()
+    o.struct_size = ctypes.sizeof(PfNceOpts)
+    o.degree, o.guards, o.p_max, o.max_iter = degree, guards, p_max, max_iter
+    o.extrapolation_len, o.lanczos_steps, o.lanczos_every = extrapolation_len, lanczos_steps, lanczos_every
+    o.tau, o.eta, o.tol, o.extrapolation_lambda = tau, eta, tol, extrapolation_lambda
+    res = PfNceResult()
+    hist = np.zeros((max_iter, 6)) if history else None
+    hp = ctypes.c_void_p(hist.ctypes.data) if history else ctypes.c_void_p(0)
+    s = LIB.pf_nce_pfpg(ctypes.byref(o), n, ctypes.c_void_p(G.data_ptr()), ld_of(G), ctypes.c_void_p(x.data_ptr()),
+                        ctypes.c_void_p(U0.data_ptr()), ld_of(U0), ctypes.c_void_p(V0.data_ptr()), ld_of(V0),
+                        ctypes.byref(res), hp, _stream(stream))
+    if s != PF_OK:
+        e = PfError(s, last_error())
+        e.result = res
+        raise e
+    return res, (hist[: res.iters + 1] if history else None)
 
 
 def bounds_of(out):

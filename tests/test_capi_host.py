@@ -272,3 +272,39 @@ def test_operator_entry_points_reject_before_launch():
     assert "PF_OP_SYM" in pf.last_error()
     assert pf.LIB.pf_extract_op(ctypes.byref(d), ctypes.byref(good), None, 256, theta, None, None) == pf.PF_ERR_ARG
     assert pf.LIB.pf_session_step_op(None, ctypes.byref(good), None, None) == pf.PF_ERR_ARG
+
+
+def test_nce_rejects_before_launch():
+    """pf_nce_pfpg option and argument errors are returned before any HIP
+    call, with the status also in the result record."""
+    P = ctypes.c_void_p
+
+    def opts(**kw):
+        o = pf.PfNceOpts()
+        o.struct_size = ctypes.sizeof(pf.PfNceOpts)
+        o.degree, o.guards, o.p_max, o.max_iter = 10, 8, 128, 50
+        o.extrapolation_len, o.lanczos_steps, o.lanczos_every = 3, 4, 10
+        o.tau, o.eta, o.tol, o.extrapolation_lambda = 1.6, 0.1, 1e-7, 1e-8
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def call(o, n=512, lds=512, G=P(0x40000)):
+        r = pf.PfNceResult()
+        s = pf.LIB.pf_nce_pfpg(ctypes.byref(o), n, G, lds, P(0x80000), P(0xC0000), lds, P(0x100000), lds,
+                               ctypes.byref(r), None, None)
+        assert r.status == s
+        return s
+
+    bad = [dict(struct_size=8), dict(p_max=8), dict(p_max=129), dict(degree=0), dict(guards=-1), dict(max_iter=0),
+           dict(extrapolation_len=8), dict(extrapolation_len=-1), dict(lanczos_steps=0), dict(lanczos_steps=9),
+           dict(lanczos_every=-1), dict(tau=0.0), dict(tau=float("inf")), dict(eta=0.0), dict(eta=1.0),
+           dict(tol=0.0), dict(extrapolation_lambda=-1.0), dict(extrapolation_lambda=float("nan"))]
+    for kw in bad:
+        assert call(opts(**kw)) == pf.PF_ERR_ARG, kw
+    assert call(opts(), n=100) == pf.PF_ERR_ARG                      # p_max > n
+    assert call(opts(p_max=32, lanczos_steps=8), n=100) == pf.PF_ERR_ARG   # 16 * steps > n
+    assert call(opts(), lds=500) == pf.PF_ERR_ARG                    # ld < n
+    assert call(opts(), G=None) == pf.PF_ERR_ARG
+    r = pf.PfNceResult()
+    assert pf.LIB.pf_nce_pfpg(None, 512, P(1), 512, P(1), P(1), 512, P(1), 512, ctypes.byref(r), None, None) == pf.PF_ERR_ARG
