@@ -114,7 +114,8 @@ def nce_pfpg(G, U0, V0, x0=None, tau=1.6, degree=10, guards=8, p_max=128, eta=0.
     the module docstring.  U0: n x p_max start block; V0: n x 16 Lanczos
     start block.  Returns dict(x, F, gnorm, iters, n_pos, p, history) with
     history rows (F, ||g||, n_pos, p, a, b) per evaluated iterate, F and g
-    from the Ritz pairs (the values the method itself sees)."""
+    from the Ritz pairs (the values the method itself sees).  x is the last
+    evaluated iterate (no step after the last evaluation)."""
     G = np.asarray(G, dtype=np.float64)
     n = G.shape[0]
     U0 = np.asarray(U0, dtype=np.float64)
@@ -143,8 +144,9 @@ def nce_pfpg(G, U0, V0, x0=None, tau=1.6, degree=10, guards=8, p_max=128, eta=0.
         g0 = gn if g0 is None else g0
         npos = r["n_pos"]
         rows.append((F, gn, npos, p, a, b))
-        if gn <= tol * g0:
-            return {"x": x, "F": F, "gnorm": gn, "g0": g0, "iters": k, "n_pos": npos, "p": p, "history": rows}
+        if gn <= tol * g0 or k + 1 == max_iter:
+            return {"x": x, "F": F, "gnorm": gn, "g0": g0, "iters": k, "n_pos": npos, "p": p, "history": rows,
+                    "converged": gn <= tol * g0}
         x = _history_step(hist, x - tau * g, rna_l, rna_lam)
         B = G + np.diag(x)
         p_new = int(min(p_max, max(16, -(-(npos + guards) // 16) * 16)))
@@ -152,4 +154,3 @@ def nce_pfpg(G, U0, V0, x0=None, tau=1.6, degree=10, guards=8, p_max=128, eta=0.
         p = p_new
         if lanczos_every > 0 and (k + 1) % lanczos_every == 0:
             a, b = interval(B)
-    return {"x": x, "F": F, "gnorm": gn, "g0": g0, "iters": max_iter, "n_pos": npos, "p": p, "history": rows}
