@@ -606,32 +606,41 @@ def nce_main(args):
     K, W = max(1, args.steps // 10), max(1, args.warmup // 5)
     log(f"nce example 5.{example}, n={n}: {W} warm-up solve(s), {K} timed")
 
-    def solve():
+    def solve(flags):
         x.copy_(torch.from_numpy(x0))
         torch.cuda.synchronize()
         t = time.perf_counter()
-        res, hist = pf.pf_nce_pfpg(Gd, x, U0, V0, p_max=p_max, degree=degree)
+        res, hist = pf.pf_nce_pfpg(Gd, x, U0, V0, p_max=p_max, degree=degree, flags=flags)
         return time.perf_counter() - t, res, hist
 
-    for _ in range(W):
-        solve()
-    times = []
-    for _ in range(K):
-        dt, res, hist = solve()
-        times.append(dt)
-        log(f"solve: {dt * 1e3:.1f} ms, {res.iters} iterations, F {res.F:.6e}, |g|/|g0| {res.gnorm / res.gnorm0:.2e}, "
-            f"p {res.p}, n_pos {res.n_pos}, {res.extrapolations} extrapolations")
-    sec = float(np.median(times))
+    # two forms: with the pre-rotation of every extraction (the library's
+    # default) and without it (FP64 work does not need it; one p x p
+    # eigensolve less per step); the second is the reported one
+    forms = {}
+    for name, flags in (("prerotate", 0), ("no_prerotate", pf.PF_FLAG_NO_PREROTATE)):
+        for _ in range(W):
+            solve(flags)
+        times = []
+        for _ in range(K):
+            dt, res, hist = solve(flags)
+            times.append(dt)
+            log(f"{name} solve: {dt * 1e3:.1f} ms, {res.iters} iterations, F {res.F:.6e}, "
+                f"|g|/|g0| {res.gnorm / res.gnorm0:.2e}, p {res.p}, n_pos {res.n_pos}, "
+                f"{res.extrapolations} extrapolations")
+        forms[name] = (float(np.median(times)), res, hist)
+    sec, res, hist = forms["no_prerotate"]
     out = {
         "metric": f"NCE solves/s (example 5.{example}, n={n}, PFPG to 1e-7 relative gradient)",
         "value": round(1.0 / sec, 4), "unit": "solves/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": round(sec * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic NCE matrix (seeded), resident in HBM",
         "config": {"workload": args.workload, "n": n, "example": example, "degree": degree, "p_max": p_max, "guards": 8,
-                   "tau": 1.6, "eta": 0.1, "extrapolation_len": 3, "lanczos_every": 10},
+                   "tau": 1.6, "eta": 0.1, "extrapolation_len": 3, "lanczos_every": 10, "prerotate": False},
         "iterations": res.iters, "ms_per_iteration": round(sec * 1e3 / max(res.iters + 1, 1), 4),
         "F": res.F, "converged": bool(res.converged), "p_final": res.p, "n_pos_final": res.n_pos,
         "block_size_trace": [int(v) for v in hist[:, 3]],
+        "forms_ms_per_solve": {k: round(v[0] * 1e3, 3) for k, v in forms.items()},
+        "forms_iterations": {k: v[1].iters for k, v in forms.items()},
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -640,7 +649,7 @@ def nce_main(args):
         g3 = oracle.nce_grad(G, max_iter=3)
         t_grad = (time.perf_counter() - t) / 3
         t = time.perf_counter()
-        oracle.nce_pfpg(G, U0h, V0h, p_max=p_max, degree=degree, max_iter=3)
+        oracle.nce_pfpg(G, U0h, V0h, p_max=p_max, degree=degree, max_iter=3)   # never pre-rotates
         t_pf = (time.perf_counter() - t) / 3
         # the exact method's iteration count from the GPU-independent oracle
         # is not run to the end here (minutes at n=2000): its solve time is

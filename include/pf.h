@@ -451,6 +451,11 @@ typedef struct pf_nce_opts {
   double eta;               /* b = eta a, 0 < eta < 1 */
   double tol;               /* > 0 */
   double extrapolation_lambda;  /* >= 0 */
+  uint32_t flags;           /* extraction flags of every step: 0 or
+                               PF_FLAG_NO_PREROTATE (the pre-rotation is a
+                               precision aid of the FP32 forms; in FP64 it
+                               costs a second p x p eigensolve per step) */
+  int32_t reserved;         /* must be 0 */
 } pf_nce_opts;
 typedef struct pf_nce_result {
   int32_t status;           /* pf_status of the run */

@@ -512,6 +512,8 @@ pf_status pf_nce_pfpg(const pf_nce_opts* opts, int64_t n, const double* G, int64
     if (!(o.tol > 0.0) || !std::isfinite(o.tol)) fail(PF_ERR_ARG, "tol must be positive and finite");
     if (!(o.extrapolation_lambda >= 0.0) || !std::isfinite(o.extrapolation_lambda))
       fail(PF_ERR_ARG, "extrapolation_lambda must be >= 0 and finite");
+    if ((o.flags & ~PF_FLAG_NO_PREROTATE) != 0 || o.reserved != 0)
+      fail(PF_ERR_ARG, "opts.flags may hold only PF_FLAG_NO_PREROTATE; opts.reserved must be 0");
     if (ldg < n || ldu0 < n || ldv0 < n) fail(PF_ERR_ARG, "leading dimension smaller than n");
     run_nce_pfpg(o, n, G, ldg, x, U0, ldu0, V0, ldv0, out, history, static_cast<hipStream_t>(stream));
     if (out->status != 0) fail((pf_status)out->status, "nce: an extraction reported a numerical failure");

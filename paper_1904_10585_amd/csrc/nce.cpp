@@ -151,7 +151,7 @@ void run_nce_pfpg(const pf_nce_opts& o, int64_t n, const double* G, int64_t ldg,
     d.struct_size = sizeof(pf_desc);
     d.op = PF_OP_SYM; d.n = n; d.p = p; d.degree = o.degree; d.q = 1;
     d.a = a; d.b = b; d.work = PF_F64;
-    d.flags = cold ? PF_FLAG_COLD : 0u;
+    d.flags = (cold ? PF_FLAG_COLD : 0u) | o.flags;
     Plan* P = plan_for(p);
     plan_set_desc(P, d);
     enqueue_extraction(P, Bm, Bm, U, ld, U, ld, theta, info, st);

@@ -71,7 +71,8 @@ class PfNceOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("degree", ctypes.c_int32), ("guards", ctypes.c_int32),
                 ("p_max", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("extrapolation_len", ctypes.c_int32),
                 ("lanczos_steps", ctypes.c_int32), ("lanczos_every", ctypes.c_int32), ("tau", ctypes.c_double),
-                ("eta", ctypes.c_double), ("tol", ctypes.c_double), ("extrapolation_lambda", ctypes.c_double)]
+                ("eta", ctypes.c_double), ("tol", ctypes.c_double), ("extrapolation_lambda", ctypes.c_double),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
 
 
 class PfNceResult(ctypes.Structure):
@@ -344,7 +345,7 @@ def pf_lanczos_bounds(X, V0, steps, stream=None, out=None):
 
 def pf_nce_pfpg(G, x, U0, V0, *, degree=10, guards=8, p_max=128, max_iter=500, extrapolation_len=3,
                 lanczos_steps=4, lanczos_every=10, tau=1.6, eta=0.1, tol=1e-7, extrapolation_lambda=1e-8,
-                stream=None, history=True):
+                flags=0, stream=None, history=True):
     """Nearest correlation PFPG loop on the device (FP64 column-major G
     n x n, x n (in: start, out: last iterate), U0 n x p_max, V0 n x 16).
     Returns (PfNceResult, history) with history an (iters + 1) x 6 array of
@@ -357,6 +358,7 @@ def pf_nce_pfpg(G, x, U0, V0, *, degree=10, guards=8, p_max=128, max_iter=500, e
     o.degree, o.guards, o.p_max, o.max_iter = degree, guards, p_max, max_iter
     o.extrapolation_len, o.lanczos_steps, o.lanczos_every = extrapolation_len, lanczos_steps, lanczos_every
     o.tau, o.eta, o.tol, o.extrapolation_lambda = tau, eta, tol, extrapolation_lambda
+    o.flags = flags
     res = PfNceResult()
     hist = np.zeros((max_iter, 6)) if history else None
     hp = ctypes.c_void_p(hist.ctypes.data) if history else ctypes.c_void_p(0)

@@ -299,7 +299,8 @@ def test_nce_rejects_before_launch():
     bad = [dict(struct_size=8), dict(p_max=8), dict(p_max=129), dict(degree=0), dict(guards=-1), dict(max_iter=0),
            dict(extrapolation_len=8), dict(extrapolation_len=-1), dict(lanczos_steps=0), dict(lanczos_steps=9),
            dict(lanczos_every=-1), dict(tau=0.0), dict(tau=float("inf")), dict(eta=0.0), dict(eta=1.0),
-           dict(tol=0.0), dict(extrapolation_lambda=-1.0), dict(extrapolation_lambda=float("nan"))]
+           dict(tol=0.0), dict(extrapolation_lambda=-1.0), dict(extrapolation_lambda=float("nan")),
+           dict(flags=pf.PF_FLAG_SCALED), dict(reserved=1)]
     for kw in bad:
         assert call(opts(**kw)) == pf.PF_ERR_ARG, kw
     assert call(opts(), n=100) == pf.PF_ERR_ARG                      # p_max > n

@@ -19,11 +19,13 @@ def run_both(pf, G, p_max, **kw):
     x0 = 1.0 - np.diag(G)
     okw = dict(kw)
     rna = okw.pop("extrapolation_len", 3)                   # the oracle calls it rna_l
+    gkw = dict(okw)
+    okw.pop("flags", None)                                  # extraction flags: GPU only
     ref = oracle.nce_pfpg(G, U0, V0, x0=x0, p_max=p_max, rna_l=rna, **okw)
     x = torch.from_numpy(x0.copy()).cuda()
     print(f"nce n={n} p_max={p_max} {kw}", flush=True)
     res, hist = pf.pf_nce_pfpg(device_matrix(G, torch.float64), x, device_matrix(U0, torch.float64),
-                               device_matrix(V0, torch.float64), p_max=p_max, extrapolation_len=rna, **okw)
+                               device_matrix(V0, torch.float64), p_max=p_max, extrapolation_len=rna, **gkw)
     return ref, res, hist, x.cpu().numpy()
 
 
@@ -54,17 +56,20 @@ def check_history(ref, res, hist, x, G):
 # within a few steps (the oracle against itself).  Step-by-step parity on
 # example 5.7 therefore runs at degree 4 (ratio ~1e3, trajectories stable
 # to 1e-6); degree 10 is checked on the solution it reaches.
-@pytest.mark.parametrize("example,n,p_max,degree", [(6, 300, 128, 10), (7, 400, 128, 4), (6, 257, 96, 10),
-                                                    (7, 640, 64, 4)])
-def test_nce_pfpg_matches_oracle(example, n, p_max, degree):
+@pytest.mark.parametrize("example,n,p_max,degree,flags", [(6, 300, 128, 10, 0), (7, 400, 128, 4, 0),
+                                                          (6, 257, 96, 10, 0), (7, 640, 64, 4, 0),
+                                                          (6, 300, 128, 10, 1), (7, 2000, 128, 4, 1)])
+def test_nce_pfpg_matches_oracle(example, n, p_max, degree, flags):
     """Every step's F, ||g||, positive count, block size and interval, and
     the final x, against the oracle; the converged F equals the exact
     gradient method's.  (6, 300): the block starts truncated (about 150
     positive eigenvalues) and shrinks; (6, 257): ragged n; (7, 640): a
-    64-column limit."""
+    64-column limit; flags 1: without the pre-rotation (the oracle never
+    pre-rotates); (7, 2000): the size the benchmark times."""
     pf = pf_module()
     G = wl.nce_matrix(n, example, config=162, index=n)
-    ref, res, hist, x = run_both(pf, G, p_max, degree=degree)
+    kw = {"flags": pf.PF_FLAG_NO_PREROTATE} if flags else {}
+    ref, res, hist, x = run_both(pf, G, p_max, degree=degree, **kw)
     check_history(ref, res, hist, x, G)
     assert res.converged == 1 and res.gnorm <= 1e-7 * res.gnorm0
     exact = oracle.nce_grad(G)
