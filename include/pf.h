@@ -435,7 +435,10 @@ pf_status pf_session_set_filter(pf_session* s, int32_t degree, int32_t q);
  * positive count after every step).  Device scratch (about
  * 8 n (n + 2 p_max + extrapolation_len + 8) bytes plus one extraction
  * workspace per block size) is allocated stream-ordered and freed before
- * return.  PF_ERR_ARG for invalid options; a failed extraction or
+ * return.  PF_ERR_ARG for invalid options, and when the Lanczos bound finds
+ * no negative eigenvalue of B(x) (the all-positive interval rule needs
+ * a < 0; then P_+(B) = B, no extraction is needed, and at x = 1 - diag(G)
+ * G is already a correlation matrix); a failed extraction or
  * Lanczos run stops the loop with its status in out->status (and as the
  * return value), x holding the last good iterate. */
 typedef struct pf_nce_opts {
