@@ -16,7 +16,8 @@ unoptimised reference of what one extraction computes (Li, Liu, Wen, Yuan,
   * the Lanczos estimate of the smallest eigenvalue and the damping
     interval / block size rules of sections 4.1-4.2.
   * the nearest correlation dual of section 5.1 by the exact gradient
-    method and by PFPG, with the extrapolation of section 4.3.
+    method and by PFPG, with the extrapolation of section 4.3, and its
+    primal by DRS with the exact PSD projection and by PFAM.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import it.  It shares no code with the HIP path (no common
@@ -35,7 +36,7 @@ from .extract import (orthonormalize, rayleigh_ritz, extract, extract_gram,
 from .metrics import sin_theta, projector_distance, ritz_rel_err, orth_error
 from .jacobi import jacobi_eigh
 from .lanczos import block_krylov_ritz, lanczos_bounds, interval_policy, block_size_policy, degree_policy
-from .nce import nce_dual, nce_primal, rna_extrapolate, nce_grad, nce_pfpg
+from .nce import nce_dual, nce_primal, rna_extrapolate, nce_grad, nce_pfpg, nce_drs, nce_pfam
 from .quantize import (bf16_round, fp8_e4m3_round, fp8_tile_quantize,
                        fp8_tile_dequantize)
 
@@ -46,6 +47,6 @@ __all__ = [
     "sin_theta", "projector_distance", "ritz_rel_err", "orth_error",
     "block_krylov_ritz", "lanczos_bounds", "interval_policy", "block_size_policy", "degree_policy",
     "jacobi_eigh",
-    "nce_dual", "nce_primal", "rna_extrapolate", "nce_grad", "nce_pfpg",
+    "nce_dual", "nce_primal", "rna_extrapolate", "nce_grad", "nce_pfpg", "nce_drs", "nce_pfam",
     "bf16_round", "fp8_e4m3_round", "fp8_tile_quantize", "fp8_tile_dequantize",
 ]

@@ -1,5 +1,6 @@
 """Nearest correlation estimation by the dual gradient method, exact and
-polynomial-filtered (section 5.1 with section 2.2 and section 4).
+polynomial-filtered (section 5.1 with section 2.2 and section 4), and by
+DRS on the primal, exact and polynomial-filtered (PFAM, eq. PFAM1-PFAM2).
 
 Test infrastructure (see ``oracle/__init__``).
 
@@ -37,7 +38,8 @@ of F, the fixed point of a correlation matrix, the KKT conditions and
 strong duality at the solution, agreement with an independent solver
 (alternating projections with Dykstra's correction), the objective values
 printed in the paper's NCE table, the extrapolation's exactness on a linear
-iteration, and PFPG reaching the exact method's solution.
+iteration, PFPG reaching the exact method's solution, and the primal DRS
+and PFAM reaching the dual method's nearest correlation matrix.
 """
 import numpy as np
 
@@ -154,3 +156,82 @@ def nce_pfpg(G, U0, V0, x0=None, tau=1.6, degree=10, guards=8, p_max=128, eta=0.
         p = p_new
         if lanczos_every > 0 and (k + 1) % lanczos_every == 0:
             a, b = interval(B)
+
+
+def _drs_update(Z, P, G, t):
+    """One step of the DRS map of the PFAM section on the NCE primal with
+    F the indicator of the PSD cone (prox_tF = P_+) and G(X) = 1/2 ||X -
+    G||_F^2 plus the indicator of diag(X) = 1, whose prox is entrywise:
+    (t G_ij + Y_ij) / (1 + t) off the diagonal, 1 on it.  Returns dZ with
+    Z^{k+1} = prox_tG(2 P - Z) - P + Z = Z + dZ (eq. PFAM1, P the PSD
+    projection of Z or of its projection onto the subspace)."""
+    prox = (t * G + (2.0 * P - Z)) / (1.0 + t)
+    np.fill_diagonal(prox, 1.0)
+    return prox - P
+
+
+def nce_drs(G, Z0=None, t=0.5, tol=1e-7, max_iter=5000):
+    """The DRS iteration with the exact P_+ (full eigendecomposition of Z
+    each step).  Stops when ||dZ||_F <= tol ||dZ_0||_F.  Returns dict(Z, X,
+    iters, residual, residual0) with X = P_+(Z) of the last evaluated
+    iterate."""
+    G = np.asarray(G, dtype=np.float64)
+    Z = G.copy() if Z0 is None else np.array(Z0, dtype=np.float64)
+    r0 = None
+    for k in range(max_iter):
+        w, Q = np.linalg.eigh(Z)
+        P = (Q * np.maximum(w, 0.0)) @ Q.T
+        dZ = _drs_update(Z, P, G, t)
+        r = float(np.linalg.norm(dZ))
+        r0 = r if r0 is None else r0
+        Z = Z + dZ
+        if r <= tol * r0:
+            break
+    return {"Z": Z, "X": P, "iters": k, "residual": r, "residual0": r0}
+
+
+def nce_pfam(G, U0, V0, Z0=None, t=0.5, degree=10, guards=8, p_max=128, eta=0.1, tol=1e-7, max_iter=500,
+             lanczos_steps=4, lanczos_every=10):
+    """PFAM (eq. PFAM1-PFAM2) on the NCE primal: the DRS step above with
+    P = P_+(P_U(Z)) = V_+ Theta_+ V_+^T from one extraction on Z per step,
+    warm-started; interval, block size and U0 columns as in ``nce_pfpg``.
+    Every step: P from the extraction on Z, dZ, then Z += dZ; stops when
+    ||dZ|| <= tol ||dZ_0|| or at max_iter (Z then holds the step taken, X =
+    P the projection it was taken from).  History rows: (||dZ||,
+    1/2 ||G - P||_F^2, n_pos, p, a, b, max |diag(P) - 1|)."""
+    G = np.asarray(G, dtype=np.float64)
+    n = G.shape[0]
+    U0 = np.asarray(U0, dtype=np.float64)
+    p_max = min(p_max, n, U0.shape[1])
+    Z = G.copy() if Z0 is None else np.array(Z0, dtype=np.float64)
+
+    def interval(M):
+        lo, _, res, _ = lanczos_bounds(M, V0, lanczos_steps)
+        a = lo - res
+        if not a < 0.0:
+            raise ValueError("the all-positive interval rule needs a negative smallest eigenvalue")
+        return a, eta * a
+
+    a, b = interval(Z)
+    p = p_max
+    U = U0[:, :p]
+    rows, r0 = [], None
+    for k in range(max_iter):
+        r = extract(Z, Z, U, degree, a, b)
+        theta, V = r["theta"], r["V"]
+        P = (V * np.maximum(theta, 0.0)) @ V.T
+        dZ = _drs_update(Z, P, G, t)
+        res = float(np.linalg.norm(dZ))
+        r0 = res if r0 is None else r0
+        npos = r["n_pos"]
+        rows.append((res, 0.5 * float(np.linalg.norm(G - P) ** 2), npos, p, a, b,
+                     float(np.abs(np.diag(P) - 1.0).max())))
+        Z = Z + dZ
+        if res <= tol * r0 or k + 1 == max_iter:
+            return {"Z": Z, "X": P, "iters": k, "residual": res, "residual0": r0, "n_pos": npos, "p": p,
+                    "history": rows, "converged": res <= tol * r0}
+        p_new = int(min(p_max, max(16, -(-(npos + guards) // 16) * 16)))
+        U = V[:, :p_new] if p_new <= p else np.hstack([V, U0[:, p:p_new]])
+        p = p_new
+        if lanczos_every > 0 and (k + 1) % lanczos_every == 0:
+            a, b = interval(Z)

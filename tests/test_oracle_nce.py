@@ -117,3 +117,29 @@ def test_pfpg_reaches_the_exact_solution(example, n):
     assert abs(f["F"] - e["F"]) <= 1e-9 * abs(e["F"])
     assert np.abs(f["x"] - e["x"]).max() <= 1e-3
     assert f["n_pos"] == e["n_pos"] and f["p"] < 128 and f["p"] >= f["n_pos"]
+
+
+@pytest.mark.parametrize("example,n", [(6, 40), (7, 30)])
+def test_primal_drs_reaches_the_dual_solution(example, n):
+    """DRS on the primal (PSD projection, entrywise prox of the affine part)
+    and the dual gradient method are different algorithms on the same
+    problem: the same nearest correlation matrix, unit diagonal, PSD."""
+    G = wl.nce_matrix(n, example, config=155, index=n)
+    Xd = oracle.nce_primal(G, oracle.nce_grad(G, tol=1e-12, max_iter=5000)["x"])
+    r = oracle.nce_drs(G, tol=1e-12, max_iter=20000)
+    assert np.abs(r["X"] - Xd).max() < 1e-8
+    assert np.abs(np.diag(r["X"]) - 1.0).max() < 1e-8 and np.linalg.eigvalsh(r["X"]).min() > -1e-10
+
+
+def test_pfam_reaches_the_nearest_correlation_matrix():
+    """PFAM's projections from the extracted subspace converge to the dual
+    method's nearest correlation matrix (the block starts truncated: about
+    n / 2 positive eigenvalues against 128 columns)."""
+    n = 300
+    G = wl.nce_matrix(n, 6, config=156, index=n)
+    Xd = oracle.nce_primal(G, oracle.nce_grad(G, tol=1e-10)["x"])
+    f = oracle.nce_pfam(G, wl.start_block(n, 128, config=156, index=n), wl.start_block(n, 16, config=157, index=n))
+    assert f["converged"] and f["p"] < 128
+    assert np.abs(f["X"] - Xd).max() < 1e-5
+    h = np.array(f["history"])
+    assert h[-1, 6] < 1e-5                              # unit diagonal at the end
