@@ -475,6 +475,58 @@ pf_status pf_nce_pfpg(const pf_nce_opts* opts, int64_t n, const double* G, int64
                       const double* U0, int64_t ldu0, const double* V0, int64_t ldv0, pf_nce_result* out,
                       double* history, void* stream);
 
+/* Nearest correlation estimation on the primal by PFAM (eq. PFAM1-PFAM2):
+ * Douglas-Rachford splitting of min 1/2 ||X - G||_F^2 + indicator(diag(X)
+ * = 1) + indicator(X PSD), the PSD projection taken in the extracted
+ * subspace:
+ *   P = P_+(P_U(Z)) = V_+ Theta_+ V_+^T   (one FP64 extraction on Z,
+ *                                          warm-started from the last one)
+ *   Z <- prox_tG(2 P - Z) - P + Z, prox_tG(Y)_ij = (t G_ij + Y_ij)/(1 + t)
+ *        off the diagonal and 1 on it.
+ * Interval, block size and U0 columns follow the rules of pf_nce_pfpg,
+ * applied to Z.  Stops when ||dZ||_F <= tol ||dZ_0||_F or after max_iter
+ * steps.
+ *  G:  device n-by-n FP64 symmetric (ld ldg), not modified.
+ *  Z:  device n-by-n FP64 symmetric (ld ldz, 16-byte aligned, ldz * 8 a
+ *      multiple of 16): in the start (G itself is the usual one), out Z
+ *      after the last step.
+ *  X:  device n-by-n FP64 (ld ldx), out: P of the last evaluated step,
+ *      the primal iterate (PSD by construction; its diagonal converges to 1).
+ *  U0, V0: start blocks as in pf_nce_pfpg.
+ *  out: host result.  history: host, max_iter x 7 doubles (row k:
+ *      ||dZ||, 1/2 ||G - P||_F^2, n_pos, p, a, b, max |diag(P) - 1|), or NULL.
+ * Synchronous, with device scratch allocated stream-ordered and freed before
+ * return (about 8 (n p_max + 3 n^2 / 256) bytes plus one extraction
+ * workspace per block size).  Errors as pf_nce_pfpg. */
+typedef struct pf_pfam_opts {
+  uint32_t struct_size;     /* sizeof(pf_pfam_opts) */
+  int32_t degree;           /* Chebyshev degree d >= 1 */
+  int32_t guards;           /* guard columns >= 0 */
+  int32_t p_max;            /* 16 <= p_max <= min(n, 128) */
+  int32_t max_iter;         /* >= 1 */
+  int32_t lanczos_steps;    /* 1..8 block steps, 16 steps <= n */
+  int32_t lanczos_every;    /* >= 0 */
+  uint32_t flags;           /* 0 or PF_FLAG_NO_PREROTATE */
+  double t;                 /* DRS step > 0 */
+  double eta;               /* b = eta a, 0 < eta < 1 */
+  double tol;               /* > 0 */
+} pf_pfam_opts;
+typedef struct pf_pfam_result {
+  int32_t status;           /* pf_status of the run */
+  int32_t iters;            /* index of the last evaluated step */
+  int32_t converged;        /* 1: ||dZ|| <= tol ||dZ_0|| */
+  int32_t n_pos;            /* positive Ritz values at the last step */
+  int32_t p;                /* block size at the last step */
+  int32_t reserved;
+  double residual, residual0;  /* ||dZ||_F at the last and the first step */
+  double objective;         /* 1/2 ||G - X||_F^2 */
+  double diag_err;          /* max |diag(X) - 1| */
+  double a, b;              /* the last damping interval */
+} pf_pfam_result;
+pf_status pf_nce_pfam(const pf_pfam_opts* opts, int64_t n, const double* G, int64_t ldg, double* Z, int64_t ldz,
+                      double* X, int64_t ldx, const double* U0, int64_t ldu0, const double* V0, int64_t ldv0,
+                      pf_pfam_result* out, double* history, void* stream);
+
 /* Kernel timing hooks (diagnostics).  While enabled, the library records a
  * HIP event pair on the launch stream around every kernel launch of the
  * given class; pf_profile_read synchronises on the recorded events and

@@ -522,4 +522,42 @@ pf_status pf_nce_pfpg(const pf_nce_opts* opts, int64_t n, const double* G, int64
   return s;
 }
 
+pf_status pf_nce_pfam(const pf_pfam_opts* opts, int64_t n, const double* G, int64_t ldg, double* Z, int64_t ldz,
+                      double* X, int64_t ldx, const double* U0, int64_t ldu0, const double* V0, int64_t ldv0,
+                      pf_pfam_result* out, double* history, void* stream) {
+  if (out) *out = pf_pfam_result{};
+  const pf_status s = guarded([&] {
+    if (!opts || !G || !Z || !X || !U0 || !V0 || !out) fail(PF_ERR_ARG, "NULL argument");
+    const pf_pfam_opts& o = *opts;
+    if (o.struct_size != sizeof(pf_pfam_opts)) fail(PF_ERR_ARG, "opts.struct_size must be sizeof(pf_pfam_opts)");
+    if (o.p_max < 16 || o.p_max > 128 || o.p_max > n) fail(PF_ERR_ARG, "p_max must be in [16, min(n, 128)]");
+    if (o.degree < 1 || o.guards < 0 || o.max_iter < 1) fail(PF_ERR_ARG, "need degree >= 1, guards >= 0, max_iter >= 1");
+    if (o.lanczos_steps < 1 || o.lanczos_steps > 8 || n < 16 * (int64_t)o.lanczos_steps)
+      fail(PF_ERR_ARG, "lanczos_steps must be in [1, 8] with 16 * lanczos_steps <= n");
+    if (o.lanczos_every < 0) fail(PF_ERR_ARG, "lanczos_every must be >= 0");
+    if ((o.flags & ~PF_FLAG_NO_PREROTATE) != 0) fail(PF_ERR_ARG, "opts.flags may hold only PF_FLAG_NO_PREROTATE");
+    if (!(o.t > 0.0) || !std::isfinite(o.t)) fail(PF_ERR_ARG, "t must be positive and finite");
+    if (!(o.eta > 0.0 && o.eta < 1.0)) fail(PF_ERR_ARG, "eta must be in (0, 1)");
+    if (!(o.tol > 0.0) || !std::isfinite(o.tol)) fail(PF_ERR_ARG, "tol must be positive and finite");
+    if (n > 65535) fail(PF_ERR_ARG, "n must be at most 65535");
+    if (ldg < n || ldz < n || ldx < n || ldu0 < n || ldv0 < n) fail(PF_ERR_ARG, "leading dimension smaller than n");
+    if (Z == X || Z == G || X == G) fail(PF_ERR_ARG, "G, Z and X must be distinct buffers");
+    if (reinterpret_cast<uintptr_t>(Z) % 16 != 0 || ((size_t)ldz * 8) % 16 != 0)
+      fail(PF_ERR_ARG, "Z must be 16-byte aligned with ldz * 8 a multiple of 16");
+    {
+      // the extraction's own checks on Z at the largest block
+      pf_desc d{};
+      d.struct_size = sizeof(pf_desc);
+      d.op = PF_OP_SYM; d.n = n; d.p = o.p_max; d.degree = o.degree; d.q = 1;
+      d.a = -1.0; d.b = 0.0; d.work = PF_F64; d.flags = o.flags;
+      const pf_mat zm{Z, PF_F64, ldz, nullptr, 0};
+      plan_validate(d, &zm, &zm);
+    }
+    run_nce_pfam(o, n, G, ldg, Z, ldz, X, ldx, U0, ldu0, V0, ldv0, out, history, static_cast<hipStream_t>(stream));
+    if (out->status != 0) fail((pf_status)out->status, "pfam: an extraction reported a numerical failure");
+  });
+  if (s != PF_OK && out && out->status == 0) out->status = s;
+  return s;
+}
+
 }  // extern "C"

@@ -147,9 +147,93 @@ __global__ void nce_combine_kernel(Coef cf, int m, double* __restrict__ hist, in
   hist[i] = v;
 }
 
+// One DRS step of the PFAM section on the NCE primal, entrywise over the
+// n x n matrices (thread i of block (bx, j) takes entry (i, j)):
+//   y = 2 P - Z,  prox = (t G + y) / (1 + t) off the diagonal, 1 on it,
+//   dZ = prox - P,  Z += dZ,
+// P = P_+(P_U(Z)) from the extraction.  Per-block partials: sum dZ^2,
+// sum (G - P)^2, max |P_ii - 1|.  Nothing is written when the extraction
+// reported a numerical failure.
+__global__ void drs_step_kernel(double* __restrict__ Z, int64_t ldz, const double* __restrict__ P, int64_t ldp,
+                                const double* __restrict__ G, int64_t ldg, int64_t n, double t,
+                                const pf_info* __restrict__ info, double* __restrict__ partial) {
+  __shared__ double sh[kT];
+  const bool ok = info->status == 0;
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  double d2 = 0.0, o2 = 0.0, de = 0.0;
+  if (ok && i < n) {
+    const double pij = P[i + j * ldp];
+    const double z = Z[i + j * ldz];
+    const double gij = G[i + j * ldg];
+    const double prox = (i == j) ? 1.0 : (t * gij + (2.0 * pij - z)) / (1.0 + t);
+    const double dz = prox - pij;
+    Z[i + j * ldz] = z + dz;
+    d2 = dz * dz;
+    o2 = (gij - pij) * (gij - pij);
+    if (i == j) de = fabs(pij - 1.0);
+  }
+  d2 = block_sum(d2, sh);
+  o2 = block_sum(o2, sh);
+  // max over the block (fixed tree order)
+  sh[threadIdx.x] = de;
+  __syncthreads();
+  for (int s = kT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    partial[3 * b] = d2;
+    partial[3 * b + 1] = o2;
+    partial[3 * b + 2] = sh[0];
+  }
+}
+
+// stats = (sum dZ^2, sum (G - P)^2, max |P_ii - 1|, #{theta > 0}) over the
+// block partials, in block order
+__global__ void drs_stats_kernel(const double* __restrict__ partial, int64_t blocks, const double* __restrict__ theta,
+                                 int p, double* __restrict__ stats) {
+  __shared__ double sh[kT];
+  double d2 = 0.0, o2 = 0.0, de = 0.0, np = 0.0;
+  for (int64_t b = threadIdx.x; b < blocks; b += kT) {
+    d2 += partial[3 * b];
+    o2 += partial[3 * b + 1];
+    de = fmax(de, partial[3 * b + 2]);
+  }
+  for (int j = threadIdx.x; j < p; j += kT) np += theta[j] > 0.0 ? 1.0 : 0.0;
+  d2 = block_sum(d2, sh);
+  o2 = block_sum(o2, sh);
+  np = block_sum(np, sh);
+  sh[threadIdx.x] = de;
+  __syncthreads();
+  for (int s = kT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    stats[0] = d2;
+    stats[1] = o2;
+    stats[2] = sh[0];
+    stats[3] = np;
+  }
+}
+
 unsigned blocks_of(int64_t n) { return (unsigned)((n + kT - 1) / kT); }
 
 }  // namespace
+
+int64_t drs_partial_blocks(int64_t n) { return (int64_t)blocks_of(n) * n; }
+
+void launch_drs_step(double* Z, int64_t ldz, const double* P, int64_t ldp, const double* G, int64_t ldg, int64_t n,
+                     double t, const pf_info* info, const double* theta, int p, double* partial, double* stats,
+                     hipStream_t st) {
+  if (n > 65535) fail(PF_ERR_ARG, "drs: n exceeds the grid's y extent");
+  drs_step_kernel<<<dim3(blocks_of(n), (unsigned)n), kT, 0, st>>>(Z, ldz, P, ldp, G, ldg, n, t, info, partial);
+  PFX_HIP(hipGetLastError());
+  drs_stats_kernel<<<1, kT, 0, st>>>(partial, drs_partial_blocks(n), theta, p, stats);
+  PFX_HIP(hipGetLastError());
+}
 
 int nce_partial_blocks(int64_t n) { return (int)blocks_of(n); }
 

@@ -224,4 +224,116 @@ void run_nce_pfpg(const pf_nce_opts& o, int64_t n, const double* G, int64_t ldg,
   }
 }
 
+// PFAM (eq. PFAM1-PFAM2) on the NCE primal: per step one FP64 extraction on
+// Z (warm-started), P = V_+ Theta_+ V_+^T into X, then the DRS step on Z
+// entrywise; the host reads ||dZ|| and the positive count.  Interval and
+// block size as in the PFPG loop, applied to Z.
+void run_nce_pfam(const pf_pfam_opts& o, int64_t n, const double* G, int64_t ldg, double* Z, int64_t ldz, double* X,
+                  int64_t ldx, const double* U0, int64_t ldu0, const double* V0, int64_t ldv0, pf_pfam_result* out,
+                  double* history, hipStream_t st) {
+  const int64_t ld = round_up(n, 16);
+  const int64_t nblk = drs_partial_blocks(n);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t at = off; off += (size_t)round_up((int64_t)bytes, 256); return at; };
+  const size_t oU = take(sizeof(double) * ld * o.p_max);
+  const size_t opart = take(sizeof(double) * 3 * nblk);
+  const size_t ostats = take(sizeof(double) * 4);
+  const size_t oth = take(sizeof(double) * 128);
+  const size_t oinfo = take(sizeof(pf_info));
+  const size_t obnd = take(sizeof(pf_bounds));
+  Scratch S;
+  S.st = st;
+  if (hipMallocAsync(&S.mem, off, st) != hipSuccess) {
+    (void)hipGetLastError();
+    S.mem = nullptr;
+    fail(PF_ERR_NOMEM, "pfam: scratch allocation failed");
+  }
+  char* base = static_cast<char*>(S.mem);
+  double* U = reinterpret_cast<double*>(base + oU);
+  double* part = reinterpret_cast<double*>(base + opart);
+  double* stats = reinterpret_cast<double*>(base + ostats);
+  double* theta = reinterpret_cast<double*>(base + oth);
+  pf_info* info = reinterpret_cast<pf_info*>(base + oinfo);
+  pf_bounds* bnd = reinterpret_cast<pf_bounds*>(base + obnd);
+  PFX_HIP(hipMemcpy2DAsync(U, ld * sizeof(double), U0, ldu0 * sizeof(double), n * sizeof(double), o.p_max,
+                           hipMemcpyDeviceToDevice, st));
+  const pf_mat Zm{Z, PF_F64, ldz, nullptr, 0};
+
+  double a = 0.0, b = 0.0;
+  auto interval = [&]() {
+    enqueue_lanczos(Zm, n, V0, ldv0, o.lanczos_steps, bnd, st);
+    pf_bounds hb{};
+    PFX_HIP(hipMemcpyAsync(&hb, bnd, sizeof(hb), hipMemcpyDeviceToHost, st));
+    PFX_HIP(hipStreamSynchronize(st));
+    if (hb.status != 0) fail((pf_status)hb.status, "pfam: Lanczos bound failed on Z");
+    a = hb.theta_min - hb.res_min;
+    if (!(a < 0.0)) fail(PF_ERR_ARG, "pfam: the all-positive interval rule needs a negative smallest eigenvalue");
+    b = o.eta * a;
+  };
+  auto desc_for = [&](int p, bool cold) {
+    pf_desc d{};
+    d.struct_size = sizeof(pf_desc);
+    d.op = PF_OP_SYM; d.n = n; d.p = p; d.degree = o.degree; d.q = 1;
+    d.a = a; d.b = b; d.work = PF_F64;
+    d.flags = (cold ? PF_FLAG_COLD : 0u) | o.flags;
+    return d;
+  };
+
+  interval();
+  *out = pf_pfam_result{};
+  int p = o.p_max;
+  bool cold = true;
+  double r0 = 0.0;
+  for (int k = 0;; ++k) {
+    const pf_desc d = desc_for(p, cold);
+    auto it = S.plans.find(p);
+    Plan* P = it != S.plans.end() ? it->second : (S.plans[p] = plan_create(d, st, true));
+    plan_set_desc(P, d);
+    enqueue_extraction(P, Zm, Zm, U, ld, U, ld, theta, info, st);
+    launch_psd_dense(U, ld, Elem::F64, theta, n, p, X, ldx, st);
+    launch_drs_step(Z, ldz, X, ldx, G, ldg, n, o.t, info, theta, p, part, stats, st);
+    double hs[4];
+    pf_info hi{};
+    PFX_HIP(hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, st));
+    PFX_HIP(hipMemcpyAsync(&hi, info, sizeof(hi), hipMemcpyDeviceToHost, st));
+    PFX_HIP(hipStreamSynchronize(st));
+    out->iters = k;
+    out->p = p;
+    out->a = a;
+    out->b = b;
+    if (hi.status != 0) {
+      out->status = hi.status;
+      out->residual0 = r0;
+      return;
+    }
+    const double r = std::sqrt(hs[0]);
+    const int npos = hi.n_pos;
+    if (k == 0) r0 = r;
+    if (history) {
+      double* row = history + (size_t)7 * k;
+      row[0] = r; row[1] = 0.5 * hs[1]; row[2] = npos; row[3] = p; row[4] = a; row[5] = b; row[6] = hs[2];
+    }
+    out->n_pos = npos;
+    out->residual = r;
+    out->residual0 = r0;
+    out->objective = 0.5 * hs[1];
+    out->diag_err = hs[2];
+    if (r <= o.tol * r0) {
+      out->converged = 1;
+      return;
+    }
+    if (k + 1 >= o.max_iter) return;
+    int p_new = (int)round_up((int64_t)npos + o.guards, 16);
+    p_new = std::max(16, std::min(o.p_max, p_new));
+    cold = false;
+    if (p_new > p) {
+      PFX_HIP(hipMemcpy2DAsync(U + (size_t)p * ld, ld * sizeof(double), U0 + (size_t)p * ldu0, ldu0 * sizeof(double),
+                               n * sizeof(double), p_new - p, hipMemcpyDeviceToDevice, st));
+      cold = true;
+    }
+    p = p_new;
+    if (o.lanczos_every > 0 && (k + 1) % o.lanczos_every == 0) interval();
+  }
+}
+
 }  // namespace pfx

@@ -190,6 +190,15 @@ void launch_nce_step(double* x, const double* g, double tau, const double* gd, d
 void launch_nce_diff_gram(const double* hist, int64_t ldh, int64_t n, int m, double* M, hipStream_t st);
 void launch_nce_combine(const double* c, int m, double* hist, int64_t ldh, double* x, const double* gd, double* B,
                         int64_t ldb, int64_t n, hipStream_t st);
+int64_t drs_partial_blocks(int64_t n);
+// one DRS step on the NCE primal (Z += prox(2P - Z) - P, entrywise) and
+// stats[4] = (||dZ||^2, ||G - P||^2, max |diag(P) - 1|, #{theta > 0})
+void launch_drs_step(double* Z, int64_t ldz, const double* P, int64_t ldp, const double* G, int64_t ldg, int64_t n,
+                     double t, const pf_info* info, const double* theta, int p, double* partial, double* stats,
+                     hipStream_t st);
+void run_nce_pfam(const pf_pfam_opts& o, int64_t n, const double* G, int64_t ldg, double* Z, int64_t ldz, double* X,
+                  int64_t ldx, const double* U0, int64_t ldu0, const double* V0, int64_t ldv0, pf_pfam_result* out,
+                  double* history, hipStream_t st);
 void run_nce_pfpg(const pf_nce_opts& o, int64_t n, const double* G, int64_t ldg, double* x, const double* U0,
                   int64_t ldu0, const double* V0, int64_t ldv0, pf_nce_result* out, double* history, hipStream_t st);
 

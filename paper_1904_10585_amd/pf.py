@@ -82,6 +82,20 @@ class PfNceResult(ctypes.Structure):
                 ("a", ctypes.c_double), ("b", ctypes.c_double)]
 
 
+class PfPfamOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("degree", ctypes.c_int32), ("guards", ctypes.c_int32),
+                ("p_max", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
+                ("lanczos_every", ctypes.c_int32), ("flags", ctypes.c_uint32), ("t", ctypes.c_double),
+                ("eta", ctypes.c_double), ("tol", ctypes.c_double)]
+
+
+class PfPfamResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("n_pos", ctypes.c_int32), ("p", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("residual", ctypes.c_double), ("residual0", ctypes.c_double), ("objective", ctypes.c_double),
+                ("diag_err", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double)]
+
+
 PF_SERVER_NO_GRAPHS = 0x1
 
 
@@ -126,6 +140,8 @@ def _load():
         "pf_workspace_size": (i32, [P(PfDesc), P(ctypes.c_size_t)]),
         "pf_lanczos_bounds": (i32, [P(PfMat), i64, vp, i64, i32, vp, vp]),
         "pf_nce_pfpg": (i32, [P(PfNceOpts), i64, vp, i64, vp, vp, i64, vp, i64, P(PfNceResult), vp, vp]),
+        "pf_nce_pfam": (i32, [P(PfPfamOpts), i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, P(PfPfamResult), vp,
+                              vp]),
         "pf_extract_op": (i32, [P(PfDesc), P(PfOperator), vp, i64, vp, vp, vp]),
         "pf_session_step_op": (i32, [vp, P(PfOperator), P(PfResult), vp]),
         "pf_interval_policy": (i32, [dbl, dbl, dbl, i32, dbl, P(dbl), P(dbl)]),
@@ -365,6 +381,34 @@ def pf_nce_pfpg(G, x, U0, V0, *, degree=10, guards=8, p_max=128, max_iter=500, e
     s = LIB.pf_nce_pfpg(ctypes.byref(o), n, ctypes.c_void_p(G.data_ptr()), ld_of(G), ctypes.c_void_p(x.data_ptr()),
                         ctypes.c_void_p(U0.data_ptr()), ld_of(U0), ctypes.c_void_p(V0.data_ptr()), ld_of(V0),
                         ctypes.byref(res), hp, _stream(stream))
+    if s != PF_OK:
+        e = PfError(s, last_error())
+        e.result = res
+        raise e
+    return res, (hist[: res.iters + 1] if history else None)
+
+
+def pf_nce_pfam(G, Z, X, U0, V0, *, degree=10, guards=8, p_max=128, max_iter=500, lanczos_steps=4,
+                lanczos_every=10, t=0.5, eta=0.1, tol=1e-7, flags=0, stream=None, history=True):
+    """PFAM on the nearest correlation primal on the device (FP64
+    column-major G, Z (in: start, out: last), X (out: primal iterate), all
+    n x n; U0 n x p_max, V0 n x 16).  Returns (PfPfamResult, history) with
+    history an (iters + 1) x 7 array of (||dZ||, 1/2 ||G - X||^2, n_pos, p,
+    a, b, max |diag X - 1|) rows, or None.  Raises PfError on failure (the
+    result in the exception's ``result`` attribute)."""
+    import numpy as np
+    n = G.shape[0]
+    o = PfPfamOpts()
+    o.struct_size = ctypes.sizeof(PfPfamOpts)
+    o.degree, o.guards, o.p_max, o.max_iter = degree, guards, p_max, max_iter
+    o.lanczos_steps, o.lanczos_every, o.flags = lanczos_steps, lanczos_every, flags
+    o.t, o.eta, o.tol = t, eta, tol
+    res = PfPfamResult()
+    hist = np.zeros((max_iter, 7)) if history else None
+    hp = ctypes.c_void_p(hist.ctypes.data) if history else ctypes.c_void_p(0)
+    s = LIB.pf_nce_pfam(ctypes.byref(o), n, ctypes.c_void_p(G.data_ptr()), ld_of(G), ctypes.c_void_p(Z.data_ptr()),
+                        ld_of(Z), ctypes.c_void_p(X.data_ptr()), ld_of(X), ctypes.c_void_p(U0.data_ptr()), ld_of(U0),
+                        ctypes.c_void_p(V0.data_ptr()), ld_of(V0), ctypes.byref(res), hp, _stream(stream))
     if s != PF_OK:
         e = PfError(s, last_error())
         e.result = res

@@ -309,3 +309,38 @@ def test_nce_rejects_before_launch():
     assert call(opts(), G=None) == pf.PF_ERR_ARG
     r = pf.PfNceResult()
     assert pf.LIB.pf_nce_pfpg(None, 512, P(1), 512, P(1), P(1), 512, P(1), 512, ctypes.byref(r), None, None) == pf.PF_ERR_ARG
+
+
+def test_pfam_rejects_before_launch():
+    """pf_nce_pfam option and argument errors are returned before any HIP
+    call, with the status also in the result record."""
+    P = ctypes.c_void_p
+
+    def opts(**kw):
+        o = pf.PfPfamOpts()
+        o.struct_size = ctypes.sizeof(pf.PfPfamOpts)
+        o.degree, o.guards, o.p_max, o.max_iter = 10, 8, 128, 50
+        o.lanczos_steps, o.lanczos_every, o.flags = 4, 10, 0
+        o.t, o.eta, o.tol = 0.5, 0.1, 1e-7
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def call(o, n=512, ld=512, Z=P(0x80000), X=P(0xC0000)):
+        r = pf.PfPfamResult()
+        s = pf.LIB.pf_nce_pfam(ctypes.byref(o), n, P(0x40000), ld, Z, ld, X, ld, P(0x100000), ld, P(0x140000), ld,
+                               ctypes.byref(r), None, None)
+        assert r.status == s
+        return s
+
+    bad = [dict(struct_size=8), dict(p_max=8), dict(p_max=129), dict(degree=0), dict(guards=-1), dict(max_iter=0),
+           dict(lanczos_steps=0), dict(lanczos_steps=9), dict(lanczos_every=-1), dict(flags=pf.PF_FLAG_SCALED),
+           dict(t=0.0), dict(t=float("nan")), dict(eta=0.0), dict(eta=1.0), dict(tol=0.0)]
+    for kw in bad:
+        assert call(opts(**kw)) == pf.PF_ERR_ARG, kw
+    assert call(opts(), n=100) == pf.PF_ERR_ARG                      # p_max > n
+    assert call(opts(), ld=500) == pf.PF_ERR_ARG                     # ld < n
+    assert call(opts(), Z=P(0x80008)) == pf.PF_ERR_ARG               # Z not 16-byte aligned
+    assert call(opts(), X=P(0x80000)) == pf.PF_ERR_ARG               # X aliases Z
+    assert call(opts(), Z=None) == pf.PF_ERR_ARG
+    assert call(opts(p_max=16), n=70000, ld=70000) == pf.PF_ERR_ARG  # grid extent

@@ -128,3 +128,40 @@ def test_nce_nonfinite_reports_status():
                        device_matrix(wl.start_block(n, 16, config=165), torch.float64), p_max=64)
     assert e.value.status == pf.PF_ERR_NONFINITE and e.value.result.status == pf.PF_ERR_NONFINITE
     np.testing.assert_array_equal(x.cpu().numpy(), x0)
+
+
+def run_pfam(pf, G, p_max, flags=0, **kw):
+    n = G.shape[0]
+    U0 = wl.start_block(n, p_max, config=166, index=n)
+    V0 = wl.start_block(n, 16, config=167, index=n)
+    ref = oracle.nce_pfam(G, U0, V0, p_max=p_max, **kw)
+    Z = device_matrix(G, torch.float64)
+    X = device_matrix(np.zeros_like(G), torch.float64)
+    print(f"pfam n={n} p_max={p_max} flags={flags} {kw}", flush=True)
+    res, hist = pf.pf_nce_pfam(device_matrix(G, torch.float64), Z, X, device_matrix(U0, torch.float64),
+                               device_matrix(V0, torch.float64), p_max=p_max, flags=flags, **kw)
+    return ref, res, hist, Z.cpu().numpy(), X.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,p_max,flags", [(300, 128, 0), (257, 96, 0), (500, 128, 1)])
+def test_pfam_matches_oracle(n, p_max, flags):
+    """PFAM on the NCE primal (example 5.6): every step's ||dZ||, objective,
+    positive count, block size, interval and diagonal error against the
+    oracle's loop on the same inputs; the final Z and X; X against the
+    dual method's nearest correlation matrix."""
+    pf = pf_module()
+    G = wl.nce_matrix(n, 6, config=168, index=n)
+    ref, res, hist, Z, X = run_pfam(pf, G, p_max, flags=pf.PF_FLAG_NO_PREROTATE if flags else 0)
+    rh = np.array(ref["history"])
+    print(f"  gpu iters {res.iters} residual {res.residual:.3e} objective {res.objective:.10e} p {res.p}; "
+          f"oracle iters {ref['iters']}")
+    assert res.status == 0 and res.converged == 1 and res.iters == ref["iters"] and len(hist) == len(rh)
+    np.testing.assert_array_equal(hist[:, 2:4], rh[:, 2:4])                              # n_pos, p
+    np.testing.assert_allclose(hist[:, 0], rh[:, 0], rtol=1e-6, atol=1e-9 * rh[0, 0])    # ||dZ||
+    np.testing.assert_allclose(hist[:, 1], rh[:, 1], rtol=1e-10)                          # objective
+    np.testing.assert_allclose(hist[:, 6], rh[:, 6], rtol=1e-6, atol=1e-10)              # diagonal error
+    nb = float(np.abs(np.linalg.eigvalsh(G)).max())
+    np.testing.assert_allclose(hist[:, 4:6], rh[:, 4:6], rtol=0, atol=1e-7 * nb)         # a, b (Lanczos parity)
+    assert np.abs(X - ref["X"]).max() <= 1e-9 and np.abs(Z - ref["Z"]).max() <= 1e-9
+    Xd = oracle.nce_primal(G, oracle.nce_grad(G, tol=1e-10)["x"])
+    assert np.abs(X - Xd).max() <= 1e-5 and res.diag_err <= 1e-5
