@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event hooks")
     ap.add_argument("--sessions", type=int, default=2000, help="serving: sessions in the Poisson stream")
     ap.add_argument("--session-steps", type=int, default=30, help="serving: steps per session")
+    ap.add_argument("--gram-share", type=float, default=0.05,
+                    help="serving: share of sessions in the Gram form (FP8 M 12000x6000, p=48, d=8, M fixed)")
     ap.add_argument("--load", type=float, default=0.7, help="serving: arrival rate / saturated session rate")
     ap.add_argument("--hbm-budget-gb", type=float, default=160.0, help="serving: HBM budget of the server")
     ap.add_argument("--calib-copy", action="store_true",
@@ -826,7 +828,8 @@ def gram_main(args):
 
 def serve_main(args):
     """Serving form: a Poisson stream of warm-started extraction sessions of
-    mixed n, p and degree through the library's server (admission by HBM
+    mixed n, p and degree, a share of them (--gram-share) in the Gram form on
+    a fixed FP8 M, through the library's server (admission by HBM
     footprint, concurrent sessions over HIP streams, graph replay of warm
     steps).  Each session is a chain of steps on its own device copy of a
     planted matrix, perturbed in place between steps (the client's work,
@@ -876,6 +879,27 @@ def serve_main(args):
     torch.cuda.synchronize()
     log(f"serving: {len(base)} base matrices built on the device in {time.time() - t0:.1f}s")
     zs = wl.rng(4, wl.S_PERTURB).standard_normal((nS, steps))
+    # a share of the arrivals are sessions of the Gram form (singular pairs of
+    # a fixed M through M^T M): FP8-E4M3 M in the filter, FP32 M for
+    # Rayleigh-Ritz, quantised once; all of them read the same M
+    is_gram = wl.rng(4, wl.S_SESSION, 1).random(nS) < args.gram_share
+    gw = wl.WORKLOADS["gram_12000x6000_fp8"]
+    gm, gn, gp, gd = gw.extra["m"], gw.n, gw.p, gw.degree
+    gram_ops, gram_desc = None, None
+    if is_gram.any():
+        Mh = wl.lowrank_plus_noise(gm, gn, gw.extra["rank"], gw.extra["noise"], gw.config).astype(np.float32)
+        Mg = pf.colmajor(gm, gn, torch.float32, dev)
+        Mg.copy_(torch.from_numpy(Mh))
+        del Mh
+        codes = pf.colmajor(gm, gn, torch.uint8, dev, ld=-(-gm // 16) * 16)
+        scales = torch.zeros((-(-gn // 128), -(-gm // 128)), dtype=torch.float32, device=dev).t()
+        pf.pf_quantize(codes, scales, 128, pf.PF_F8E4M3, Mg)
+        fro2 = float((Mg.double() ** 2).sum())
+        gram_ops = (pf.mat(codes, scales, 128), Mg)
+        gram_desc = pf.desc(gn, gp, gd, gw.a, gw.b, work=pf.PF_F32, op=pf.PF_OP_GRAM, m=gm,
+                            flags=pf.PF_FLAG_SCALED | pf.PF_FLAG_OPERATOR_UNCHANGED, spec_ub=fro2)
+        torch.cuda.synchronize()
+        log(f"serving: {int(is_gram.sum())} of {nS} sessions in the Gram form (M {gm}x{gn}, FP8 filter)")
 
     def session_x(i):
         return base[(int(ns[i]), i % 2, int(ps[i]))].clone().t()   # column-major view of symmetric X
@@ -907,18 +931,23 @@ def serve_main(args):
             while nxt < nS and arrivals[pending[nxt]] <= now and len(opened) < room:
                 i = pending[nxt]
                 nxt += 1
-                n, p, d = int(ns[i]), int(ps[i]), int(ds[i])
-                a, b = wl.serving_interval(d)
-                with torch.cuda.stream(cs):
-                    Xs[i] = session_x(i)
-                dsc = pf.desc(n, p, d, a, b, work=pf.PF_F32)
-                ids[i] = pf.pf_server_open(srv, dsc, seed=i, operator_bytes=n * n * 4)
+                if is_gram[i]:
+                    Xs[i] = gram_ops
+                    # the library's transposed copies of M (FP8 and FP32)
+                    ids[i] = pf.pf_server_open(srv, gram_desc, seed=i, operator_bytes=gm * gn * 5)
+                else:
+                    n, p, d = int(ns[i]), int(ps[i]), int(ds[i])
+                    a, b = wl.serving_interval(d)
+                    with torch.cuda.stream(cs):
+                        Xs[i] = (session_x(i),) * 2
+                    dsc = pf.desc(n, p, d, a, b, work=pf.PF_F32)
+                    ids[i] = pf.pf_server_open(srv, dsc, seed=i, operator_bytes=n * n * 4)
                 left[i] = steps
                 opened.append(i)
             if opened:
                 cs.synchronize()
                 for i in opened:
-                    pf.pf_server_submit(srv, ids[i], Xs[i], Xs[i], tag=i)
+                    pf.pf_server_submit(srv, ids[i], Xs[i][0], Xs[i][1], tag=i)
                 if first_submit is None:
                     first_submit = time.perf_counter()
             wait = 0.002
@@ -932,14 +961,18 @@ def serve_main(args):
                     raise SystemExit(f"serving step failed: {pf.status_string(ev.status)}")
                 i = by_id[ev.session]
                 lat.append((ev.done_ns - ev.submit_ns) * 1e-6)
-                n, d = int(ns[i]), int(ds[i])
-                step_bytes += (d + 1) * 4.0 * n * n
+                if is_gram[i]:
+                    step_bytes += (2.0 * gd + 4.0) * gm * gn      # 2 d passes over FP8 M, one over FP32 M
+                else:
+                    n, d = int(ns[i]), int(ds[i])
+                    step_bytes += (d + 1) * 4.0 * n * n
                 done_steps += 1
                 last_done = time.perf_counter()
                 left[i] -= 1
                 if left[i] > 0:
-                    with torch.cuda.stream(cs):
-                        perturb(Xs[i], i, steps - left[i])
+                    if not is_gram[i]:                         # M stays fixed over a Gram session
+                        with torch.cuda.stream(cs):
+                            perturb(Xs[i][0], i, steps - left[i])
                     resubmit.append(i)
                 else:
                     pf.pf_server_close(srv, ids[i])
@@ -947,7 +980,7 @@ def serve_main(args):
             if resubmit:
                 cs.synchronize()
                 for i in resubmit:
-                    pf.pf_server_submit(srv, ids[i], Xs[i], Xs[i], tag=i)
+                    pf.pf_server_submit(srv, ids[i], Xs[i][0], Xs[i][1], tag=i)
             if done_steps and done_steps % 5000 < len(evs):
                 log(f"serving {label}: {done_steps} steps done")
         st = pf.pf_server_stats(srv)
@@ -981,6 +1014,7 @@ def serve_main(args):
         "config": {"workload": "serving", "sessions": nS, "steps_per_session": steps,
                    "n_choices": list(S["n_choices"]), "p_choices": list(S["p_choices"]),
                    "degree_choices": list(S["degree_choices"]), "arrivals": f"Poisson at {args.load} x saturated",
+                   "gram_sessions": int(is_gram.sum()), "gram_form": f"M {gm}x{gn} FP8-E4M3, p={gp}, d={gd}, fixed",
                    "hbm_budget_gb": args.hbm_budget_gb},
         "latency_ms": {"p50": round(pois["p50_ms"], 3), "p99": round(pois["p99_ms"], 3)},
         "hbm_GBps_algorithmic": round(pois["gbps"], 1),

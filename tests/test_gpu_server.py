@@ -207,3 +207,66 @@ def test_server_reports_step_errors_and_continues():
             assert ev.status == want, (ev.session, ev.status)
     finally:
         pf.pf_server_destroy(srv)
+
+
+def gram_fp8_operands(m, n, config):
+    """M = A B^T + 0.01 N(0,1) (rank 10) as FP32 on the device, its FP8-E4M3
+    codes with per-128x128 scales from pf_quantize, and ||M||_F^2."""
+    pf = pf_module()
+    M = wl.lowrank_plus_noise(m, n, 10, 0.01, config=config).astype(np.float32)
+    Mr = device_matrix(M, torch.float32)
+    codes = pf.colmajor(m, n, torch.uint8, "cuda", ld=-(-m // 16) * 16)
+    scales = torch.zeros((-(-n // 128), -(-m // 128)), dtype=torch.float32, device="cuda").t()
+    pf.pf_quantize(codes, scales, 128, pf.PF_F8E4M3, Mr)
+    torch.cuda.synchronize()
+    return (codes, scales, 128), Mr, float((Mr.double() ** 2).sum())
+
+
+def test_server_gram_fp8_session_matches_eager():
+    """A Gram-form session (FP8 M in the filter, FP32 M for Rayleigh-Ritz, M
+    fixed over the chain with PF_FLAG_OPERATOR_UNCHANGED, scaled recurrence)
+    served next to a planted session: its graph-replayed warm steps are
+    bitwise the eager session's steps."""
+    pf = pf_module()
+    m, n, p, d, steps = 640, 300, 24, 6, 5
+    Mf, Mr, fro2 = gram_fp8_operands(m, n, config=111)
+    dsc = pf.desc(n, p, d, 0.0, 4.0 * 0.01 ** 2 * m, work=pf.PF_F32, op=pf.PF_OP_GRAM, m=m,
+                  flags=pf.PF_FLAG_SCALED | pf.PF_FLAG_OPERATOR_UNCHANGED, spec_ub=fro2)
+    h = pf.pf_session_open(dsc, seed=11)
+    eager = []
+    for _ in range(steps):
+        pf.pf_session_step(h, Mf, Mr)
+        s, r = pf.pf_session_wait(h)
+        assert s == pf.PF_OK and r.status == 0, (s, r.status)
+        eager.append(read_result(pf, r, n, p))
+    torch.cuda.synchronize()
+    pf.pf_session_close(h)
+
+    other = Case(*CASES[0])
+    srv = pf.pf_server_create(64 << 30, streams=2)
+    try:
+        Xo = other.fresh_x()
+        gid = pf.pf_server_open(srv, dsc, seed=11, operator_bytes=n * m * 5)
+        oid = pf.pf_server_open(srv, other.desc(), seed=other.idx, operator_bytes=other.n * other.n * 4)
+        graphs = []
+        for k in range(steps):
+            torch.cuda.synchronize()
+            pf.pf_server_submit(srv, gid, Mf, Mr, tag=k)
+            pf.pf_server_submit(srv, oid, Xo, Xo, tag=k)
+            got = {}
+            while len(got) < 2:
+                for ev in pf.pf_server_poll(srv, timeout_s=5.0):
+                    got[ev.session] = (ev.status, ev.step, ev.graph)
+            assert got[gid][0] == pf.PF_OK and got[gid][1] == k and got[oid][0] == pf.PF_OK
+            graphs.append(got[gid][2])
+            th, V = read_result(pf, pf.pf_server_result(srv, gid), n, p)
+            np.testing.assert_array_equal(th, eager[k][0], err_msg=f"theta step {k}")
+            np.testing.assert_array_equal(V, eager[k][1], err_msg=f"V step {k}")
+            if k + 1 < steps:
+                other.perturb(Xo, k + 1)
+        torch.cuda.synchronize()
+        assert graphs == [0] + [1] * (steps - 1), graphs
+        pf.pf_server_close(srv, gid)
+        pf.pf_server_close(srv, oid)
+    finally:
+        pf.pf_server_destroy(srv)
