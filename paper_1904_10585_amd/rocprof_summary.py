@@ -3,6 +3,9 @@
     python -m paper_1904_10585_amd.rocprof_summary trace <results.db> [--steps K]
         per-kernel call count, total and average duration from a
         ``rocprofv3 --kernel-trace`` SQLite database;
+    python -m paper_1904_10585_amd.rocprof_summary counters <run.csv>... --kernel NAME
+        per-dispatch mean of every counter of one kernel over one or more
+        ``rocprofv3 --pmc`` runs (CSV output);
     python -m paper_1904_10585_amd.rocprof_summary bytes <fetch.csv> <write.csv> --kernel NAME
         HBM bytes per dispatch of one kernel from two ``rocprofv3 --pmc``
         runs (FETCH_SIZE, then WRITE_SIZE, CSV output), each scaled by what
@@ -74,6 +77,13 @@ def bytes_per_dispatch(fetch_csv, write_csv, kernel):
     print(f"- traffic_bytes_per_launch: {fetch_b + write_b:.0f}")
 
 
+def counters(paths, kernel):
+    for path in paths:
+        for (name, counter), (mean, cnt) in sorted(counter_means(path).items()):
+            if name == kernel:
+                print(f"- {counter}: {mean:.6g} per dispatch over {cnt} dispatches")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -84,9 +94,14 @@ def main():
     b.add_argument("fetch_csv")
     b.add_argument("write_csv")
     b.add_argument("--kernel", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("csv", nargs="+")
+    c.add_argument("--kernel", required=True)
     a = ap.parse_args()
     if a.cmd == "trace":
         trace(a.db, a.steps)
+    elif a.cmd == "counters":
+        counters(a.csv, a.kernel)
     else:
         bytes_per_dispatch(a.fetch_csv, a.write_csv, a.kernel)
 
