@@ -497,7 +497,8 @@ pf_status pf_nce_pfpg(const pf_nce_opts* opts, int64_t n, const double* G, int64
  *      ||dZ||, 1/2 ||G - P||_F^2, n_pos, p, a, b, max |diag(P) - 1|), or NULL.
  * Synchronous, with device scratch allocated stream-ordered and freed before
  * return (about 8 (n p_max + 3 n^2 / 256) bytes plus one extraction
- * workspace per block size).  Errors as pf_nce_pfpg. */
+ * workspace per block size).  Errors as pf_nce_pfpg; after a numerical
+ * failure Z holds the last good iterate and X is unspecified. */
 typedef struct pf_pfam_opts {
   uint32_t struct_size;     /* sizeof(pf_pfam_opts) */
   int32_t degree;           /* Chebyshev degree d >= 1 */
