@@ -178,6 +178,22 @@ pf_status pf_extract(const pf_desc* desc, const pf_mat* X_filter, const pf_mat* 
                      void* U_inout, int64_t ldu, double* theta_out, pf_info* info_out,
                      void* stream);
 
+/* Many independent extractions in one call: the blocks of a block-diagonal
+ * operator (the per-block filtering of block-diagonal SDPs in section 5),
+ * or any set of small problems.  Block i is exactly
+ *   pf_extract(&descs[i], &X_filter[i], &X_rr[i], U_inout[i], ldu[i],
+ *              theta_out[i], info_out ? info_out[i] : NULL, ...)
+ * (the same kernels and results), but the blocks run concurrently: the call
+ * forks the caller's stream onto a pool of 8 library streams (block i on
+ * stream i mod 8, created on first use and kept until the process ends)
+ * and joins them back, so later work on `stream` sees every block done.
+ * Every block is validated before any work is enqueued (PF_ERR_ARG names
+ * the block in pf_last_error); numerical outcomes land in each info_out[i].
+ * Arrays are host arrays of count entries; info_out may be NULL. */
+pf_status pf_extract_batch(int32_t count, const pf_desc* descs, const pf_mat* X_filter, const pf_mat* X_rr,
+                           void* const* U_inout, const int64_t* ldu, double* const* theta_out,
+                           pf_info* const* info_out, void* stream);
+
 /* A caller-supplied symmetric operator in place of a dense X (matrix-free
  * or sparse A; the paper's extraction only ever needs the products A Y).
  * apply(ctx, Y, ldy, AY, lday, cols, stream) enqueues AY = A Y on stream for

@@ -2,6 +2,7 @@
 // per-stream workspace cache of pf_extract, and sessions.
 #include "pf_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <functional>
@@ -116,7 +117,9 @@ Plan* cached_plan(const pf_desc& d, hipStream_t st) {
     // that do not change its layout
     return it->second;
   }
-  Plan* P = plan_create(d);
+  // cleared on the stream it serves, ordered before its first extraction: a
+  // clear on the null stream would not be ordered with a non-blocking stream
+  Plan* P = plan_create(d, st, true);
   g_plans[key] = P;
   return P;
 }
@@ -237,6 +240,91 @@ pf_status pf_extract(const pf_desc* desc, const pf_mat* X_filter, const pf_mat* 
     Plan* P = cached_plan(*desc, st);
     plan_set_desc(P, *desc);
     enqueue_extraction(P, *X_filter, *X_rr, U_inout, ldu, U_inout, ldu, theta_out, info_out, st);
+  });
+}
+
+namespace {
+// Streams pf_extract_batch forks onto: a fixed pool per device, created on
+// first use (non-blocking, default priority) and kept until the process
+// ends.  Calls that share the pool are serialised by its mutex while they
+// enqueue.
+constexpr int kBatchStreams = 8;
+std::mutex g_batch_mu;
+std::map<int, std::vector<hipStream_t>> g_batch_streams;
+
+std::vector<hipStream_t>& batch_streams(int dev) {
+  auto& v = g_batch_streams[dev];
+  while ((int)v.size() < kBatchStreams) {
+    hipStream_t st;
+    PFX_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    v.push_back(st);
+  }
+  return v;
+}
+}  // namespace
+
+pf_status pf_extract_batch(int32_t count, const pf_desc* descs, const pf_mat* X_filter, const pf_mat* X_rr,
+                           void* const* U_inout, const int64_t* ldu, double* const* theta_out,
+                           pf_info* const* info_out, void* stream) {
+  return guarded([&] {
+    if (count < 0) fail(PF_ERR_ARG, "count must be >= 0");
+    if (count == 0) return;
+    if (!descs || !X_filter || !X_rr || !U_inout || !ldu || !theta_out) fail(PF_ERR_ARG, "NULL array");
+    // every block is checked before any work is enqueued
+    for (int i = 0; i < count; ++i) {
+      try {
+        plan_validate(descs[i], &X_filter[i], &X_rr[i]);
+        if (!U_inout[i]) fail(PF_ERR_ARG, "U_inout is NULL");
+        if (ldu[i] < descs[i].n) fail(PF_ERR_ARG, "ldu is smaller than n");
+        if (!theta_out[i]) fail(PF_ERR_ARG, "theta_out is NULL");
+      } catch (const Error& e) {
+        fail(e.status, "block " + std::to_string(i) + ": " + e.msg);
+      }
+    }
+    hipStream_t caller = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    PFX_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    std::vector<hipStream_t>& pool = batch_streams(dev);
+    const int used = std::min<int>(count, kBatchStreams);
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> joins(used, nullptr);
+    auto release = [&] {
+      if (fork) (void)hipEventDestroy(fork);
+      for (hipEvent_t e : joins)
+        if (e) (void)hipEventDestroy(e);
+    };
+    try {
+      PFX_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+      PFX_HIP(hipEventRecord(fork, caller));
+      for (int w = 0; w < used; ++w) PFX_HIP(hipStreamWaitEvent(pool[w], fork, 0));
+      // block i on pool stream i mod used, in order on each stream
+      for (int i = 0; i < count; ++i) {
+        hipStream_t st = pool[i % used];
+        Plan* P = cached_plan(descs[i], st);
+        plan_set_desc(P, descs[i]);
+        enqueue_extraction(P, X_filter[i], X_rr[i], U_inout[i], ldu[i], U_inout[i], ldu[i], theta_out[i],
+                           info_out ? info_out[i] : nullptr, st);
+      }
+      for (int w = 0; w < used; ++w) {
+        PFX_HIP(hipEventCreateWithFlags(&joins[w], hipEventDisableTiming));
+        PFX_HIP(hipEventRecord(joins[w], pool[w]));
+        PFX_HIP(hipStreamWaitEvent(caller, joins[w], 0));
+      }
+    } catch (...) {
+      // the caller's stream still waits for whatever was enqueued
+      for (int w = 0; w < used; ++w) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
+          (void)hipEventRecord(e, pool[w]);
+          (void)hipStreamWaitEvent(caller, e, 0);
+          (void)hipEventDestroy(e);
+        }
+      }
+      release();
+      throw;
+    }
+    release();
   });
 }
 

@@ -139,6 +139,7 @@ def _load():
         "pf_eigh": (i32, [vp, i64, i32, vp, vp, i64, vp]),
         "pf_workspace_size": (i32, [P(PfDesc), P(ctypes.c_size_t)]),
         "pf_lanczos_bounds": (i32, [P(PfMat), i64, vp, i64, i32, vp, vp]),
+        "pf_extract_batch": (i32, [i32, vp, vp, vp, vp, vp, vp, vp, vp]),
         "pf_nce_pfpg": (i32, [P(PfNceOpts), i64, vp, i64, vp, vp, i64, vp, i64, P(PfNceResult), vp, vp]),
         "pf_nce_pfam": (i32, [P(PfPfamOpts), i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, P(PfPfamResult), vp,
                               vp]),
@@ -357,6 +358,22 @@ def pf_lanczos_bounds(X, V0, steps, stream=None, out=None):
     else:
         torch.cuda.synchronize(X.device)
     return bounds_of(dst)
+
+
+def pf_extract_batch(blocks, stream=None):
+    """Independent extractions in one call (pf_extract_batch).  blocks: a
+    list of (desc, X_filter, X_rr, U, theta, info) as for pf_extract (info
+    may be None); U and theta are updated in place, stream-ordered."""
+    n = len(blocks)
+    D = (PfDesc * n)(*[b[0] for b in blocks])
+    XF = (PfMat * n)(*[mat(b[1]) for b in blocks])
+    XR = (PfMat * n)(*[mat(b[2]) for b in blocks])
+    U = (ctypes.c_void_p * n)(*[b[3].data_ptr() for b in blocks])
+    LD = (ctypes.c_int64 * n)(*[ld_of(b[3]) for b in blocks])
+    TH = (ctypes.c_void_p * n)(*[b[4].data_ptr() for b in blocks])
+    has_info = any(b[5] is not None for b in blocks)
+    INF = (ctypes.c_void_p * n)(*[(b[5].data_ptr() if b[5] is not None else None) for b in blocks]) if has_info else None
+    _check(LIB.pf_extract_batch(n, D, XF, XR, U, LD, TH, INF, _stream(stream)))
 
 
 def pf_nce_pfpg(G, x, U0, V0, *, degree=10, guards=8, p_max=128, max_iter=500, extrapolation_len=3,

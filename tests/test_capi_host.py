@@ -344,3 +344,22 @@ def test_pfam_rejects_before_launch():
     assert call(opts(), X=P(0x80000)) == pf.PF_ERR_ARG               # X aliases Z
     assert call(opts(), Z=None) == pf.PF_ERR_ARG
     assert call(opts(p_max=16), n=70000, ld=70000) == pf.PF_ERR_ARG  # grid extent
+
+
+def test_extract_batch_rejects_before_launch():
+    """pf_extract_batch checks every block before any HIP call; an invalid
+    block is named in the message."""
+    assert pf.LIB.pf_extract_batch(-1, None, None, None, None, None, None, None, None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_extract_batch(0, None, None, None, None, None, None, None, None) == pf.PF_OK
+    assert pf.LIB.pf_extract_batch(2, None, None, None, None, None, None, None, None) == pf.PF_ERR_ARG
+    good = pf.desc(256, 16, 6, -1.0, 0.5, work=pf.PF_F32)
+    bad = pf.desc(256, 0, 6, -1.0, 0.5, work=pf.PF_F32)
+    D = (pf.PfDesc * 2)(good, bad)
+    m = fake_mat(dtype=pf.PF_F32, ld=256)
+    M = (pf.PfMat * 2)(m, m)
+    P = ctypes.c_void_p
+    U = (P * 2)(0x40000, 0x80000)
+    LD = (ctypes.c_int64 * 2)(256, 256)
+    TH = (P * 2)(0xC0000, 0x100000)
+    assert pf.LIB.pf_extract_batch(2, D, M, M, U, LD, TH, None, None) == pf.PF_ERR_ARG
+    assert "block 1" in pf.last_error()
