@@ -84,3 +84,32 @@ def test_batch_then_caller_stream_work_sees_results():
     for c, b in zip(copies, blocks):
         np.testing.assert_array_equal(c.cpu().numpy(), b[4].cpu().numpy())
         assert float(c.abs().max()) > 0.0
+
+
+def test_extract_on_a_nonblocking_stream_first_use():
+    """pf_extract on a non-blocking stream with a shape its workspace cache
+    has not seen: the new workspace is cleared on that stream before the
+    extraction (a null-stream clear is not ordered with it), so the result
+    equals the same extraction on the default stream, bitwise."""
+    pf = pf_module()
+    n, p, d = 389, 24, 8                                 # a shape no other test uses
+    X, U, a, b, r = block_case(40, n, p, d, "f64")
+    out = []
+    for use_stream in (True, False):
+        Xd = device_matrix(X, torch.float64)
+        Ud = device_matrix(U, torch.float64)
+        th = torch.zeros(p, dtype=torch.float64, device="cuda")
+        info = torch.zeros(8, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        if use_stream:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                pf.pf_extract(pf.desc(n, p, d, a, b, work=pf.PF_F64), Xd, Xd, Ud, th, info, stream=st)
+            st.synchronize()
+        else:
+            pf.pf_extract(pf.desc(n, p, d, a, b, work=pf.PF_F64), Xd, Xd, Ud, th, info)
+            torch.cuda.synchronize()
+        assert int(info[0]) == 0
+        out.append((th.cpu().numpy(), Ud.cpu().numpy()))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
