@@ -34,7 +34,7 @@ SessionCore* session_create(const pf_desc& d, const void* U0, int64_t ldu0, uint
   try {
     PFX_HIP(hipGetDevice(&s->device));
     s->desc = d;
-    s->plan = plan_create(d, st, !sync);
+    s->plan = plan_create(d, st, true);                // cleared in order with st's later work
     const Elem W = d.work == PF_F64 ? Elem::F64 : Elem::F32;
     const size_t esz = W == Elem::F64 ? 8 : 4;
     s->ldu = round_up(d.n, 64);
