@@ -113,3 +113,33 @@ def test_extract_on_a_nonblocking_stream_first_use():
         out.append((th.cpu().numpy(), Ud.cpu().numpy()))
     np.testing.assert_array_equal(out[0][0], out[1][0])
     np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
+def test_batch_of_identical_shapes():
+    """17 blocks of one shape (different data): blocks i and i + 8 share a
+    pool stream and its cached workspace, one after the other; every block
+    still equals its own sequential extraction, bitwise."""
+    pf = pf_module()
+    shape = (160, 16, 8, "f64")
+    cases = [block_case(100 + i, *shape) for i in range(17)]
+
+    def blocks():
+        out = []
+        for X, U, a, b, r in cases:
+            Xd = device_matrix(X, torch.float64)
+            out.append((pf.desc(shape[0], shape[1], shape[2], a, b, work=pf.PF_F64), Xd, Xd,
+                        device_matrix(U, torch.float64), torch.zeros(shape[1], dtype=torch.float64, device="cuda"),
+                        torch.zeros(8, dtype=torch.int32, device="cuda")))
+        return out
+
+    seq = blocks()
+    for dsc, Xf, Xr, U, th, info in seq:
+        pf.pf_extract(dsc, Xf, Xr, U, th, info)
+    bat = blocks()
+    torch.cuda.synchronize()
+    pf.pf_extract_batch(bat)
+    torch.cuda.synchronize()
+    for i, (s, t) in enumerate(zip(seq, bat)):
+        np.testing.assert_array_equal(t[5].cpu().numpy(), s[5].cpu().numpy(), err_msg=f"info block {i}")
+        np.testing.assert_array_equal(t[4].cpu().numpy(), s[4].cpu().numpy(), err_msg=f"theta block {i}")
+        np.testing.assert_array_equal(t[3].cpu().numpy(), s[3].cpu().numpy(), err_msg=f"V block {i}")
