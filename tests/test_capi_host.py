@@ -44,7 +44,9 @@ def test_struct_layout_matches_c_compiler(tmp_path):
         pytest.skip("no C compiler")
     structs = {"pf_desc": pf.PfDesc, "pf_mat": pf.PfMat, "pf_info": pf.PfInfo, "pf_result": pf.PfResult,
                "pf_server_config": pf.PfServerConfig, "pf_server_event": pf.PfServerEvent,
-               "pf_server_stats": pf.PfServerStats}
+               "pf_server_stats": pf.PfServerStats, "pf_bounds": pf.PfBounds, "pf_operator": pf.PfOperator,
+               "pf_nce_opts": pf.PfNceOpts, "pf_nce_result": pf.PfNceResult, "pf_pfam_opts": pf.PfPfamOpts,
+               "pf_pfam_result": pf.PfPfamResult}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pf.h"', "int main(void){"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
