@@ -11,6 +11,8 @@ unoptimised reference of what one extraction computes (Li, Liu, Wen, Yuan,
     (section 2.2, eq. RR), with the low-rank projection P_V(X) and the PSD
     projection P_+(P_V(X)) used by PFPG/PFAM (section 2.2-2.3),
   * the SVD route through A^T A (section 5.2.1),
+  * the same extraction in 80-bit extended precision, which bounds the
+    FP64 oracle's own rounding on ill-conditioned (cold-start) inputs,
   * the BF16 / FP8-E4M3 quantisers that define the low-precision copies
     of X the GPU filter reads.
   * the Lanczos estimate of the smallest eigenvalue and the damping
@@ -35,6 +37,7 @@ from .extract import (orthonormalize, rayleigh_ritz, extract, extract_gram,
                       psd_projection, lowrank_projection, ritz_residuals)
 from .metrics import sin_theta, projector_distance, ritz_rel_err, orth_error
 from .jacobi import jacobi_eigh
+from .extended import extract_longdouble, jacobi_eigh_ld
 from .lanczos import block_krylov_ritz, lanczos_bounds, interval_policy, block_size_policy, degree_policy
 from .nce import nce_dual, nce_primal, rna_extrapolate, nce_grad, nce_pfpg, nce_drs, nce_pfam
 from .quantize import (bf16_round, fp8_e4m3_round, fp8_tile_quantize,
@@ -46,7 +49,7 @@ __all__ = [
     "psd_projection", "lowrank_projection", "ritz_residuals",
     "sin_theta", "projector_distance", "ritz_rel_err", "orth_error",
     "block_krylov_ritz", "lanczos_bounds", "interval_policy", "block_size_policy", "degree_policy",
-    "jacobi_eigh",
+    "jacobi_eigh", "extract_longdouble", "jacobi_eigh_ld",
     "nce_dual", "nce_primal", "rna_extrapolate", "nce_grad", "nce_pfpg", "nce_drs", "nce_pfam",
     "bf16_round", "fp8_e4m3_round", "fp8_tile_quantize", "fp8_tile_dequantize",
 ]

@@ -102,21 +102,20 @@ namespace {
 
 // pf_extract workspaces: one per (device, stream, shape); calls on one
 // stream are ordered, so a workspace is never used by two extractions at once.
-using PlanKey = std::tuple<int, uintptr_t, int64_t, int64_t, int, int, int, int, int>;
+// The key holds exactly what the workspace layout depends on (n, m, p, work
+// dtype, operator kind): degree, power, interval and flags only change the
+// descriptor, which every call installs with plan_set_desc.
+using PlanKey = std::tuple<int, uintptr_t, int64_t, int64_t, int, int, int>;
 std::mutex g_plans_mu;
 std::map<PlanKey, Plan*> g_plans;
 
 Plan* cached_plan(const pf_desc& d, hipStream_t st) {
   int dev = 0;
   PFX_HIP(hipGetDevice(&dev));
-  PlanKey key{dev, (uintptr_t)st, d.n, d.op == PF_OP_GRAM ? d.m : 0, d.p, (int)d.work, (int)d.op, d.degree, d.q};
+  PlanKey key{dev, (uintptr_t)st, d.n, d.op == PF_OP_GRAM ? d.m : 0, d.p, (int)d.work, (int)d.op};
   std::lock_guard<std::mutex> lk(g_plans_mu);
   auto it = g_plans.find(key);
-  if (it != g_plans.end()) {
-    // the plan keeps the descriptor it was built for; refresh the fields
-    // that do not change its layout
-    return it->second;
-  }
+  if (it != g_plans.end()) return it->second;
   // cleared on the stream it serves, ordered before its first extraction: a
   // clear on the null stream would not be ordered with a non-blocking stream
   Plan* P = plan_create(d, st, true);

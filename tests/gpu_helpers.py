@@ -48,3 +48,33 @@ def compare(theta_g, V_g, ref, r):
     Qg, _ = np.linalg.qr(Vg)
     sin = oracle.sin_theta(Qg, ref["V"][:, :r])
     return rel, sin
+
+
+def grade_f64(theta_g, V_g, X, U, degree, a, b, r, q=1, cold=False, label=""):
+    """FP64 parity of one step, asserted at the FP64 tolerance.
+
+    Warm step: Ritz relative error and sin-angle <= 1e-10 against the oracle
+    fed the same U and X.  Cold step (a random start block): the filtered
+    block is ill-conditioned and the FP64 oracle's own top-r subspace can
+    be off by more than 1e-10, so the reference is the extended-precision
+    extraction; Ritz values <= 1e-10 and the subspace <= eps * kappa(Y_d)
+    (kappa after column equilibration), the accuracy any FP64 evaluation of
+    that block can reach.  Returns (rel, sin, bound)."""
+    if not cold:
+        ref = oracle.extract(X, X, U, degree, a, b, q=q)
+        rel, sin = compare(theta_g, V_g, ref, r)
+        print(f"{label} rel {rel:.2e} sin {sin:.2e}", flush=True)
+        assert rel <= 1e-10 and sin <= 1e-10, (label, rel, sin)
+        return rel, sin, 1e-10
+    ext = oracle.extract_longdouble(X, U, degree, a, b, q=q)
+    Y = ext["Y"].astype(np.float64)
+    sv = np.linalg.svd(Y / np.linalg.norm(Y, axis=0), compute_uv=False)
+    bound = max(1e-10, np.finfo(np.float64).eps * sv[0] / sv[-1])
+    refL = {"theta": ext["theta"].astype(np.float64), "V": ext["V"].astype(np.float64)}
+    rel, sin = compare(theta_g, V_g, refL, r)
+    ref = oracle.extract(X, X, U, degree, a, b, q=q)
+    rel_o, sin_o = compare(ref["theta"], ref["V"], refL, r)
+    print(f"{label} cold, against extended precision: rel {rel:.2e} sin {sin:.2e} (FP64 oracle: rel {rel_o:.2e}"
+          f" sin {sin_o:.2e}; subspace bound eps*kappa {bound:.2e})", flush=True)
+    assert rel <= 1e-10 and sin <= bound, (label, rel, sin, bound)
+    return rel, sin, bound

@@ -64,7 +64,7 @@ def test_batch_matches_sequential_and_oracle():
         V = t[3].cpu().double().numpy()
         rel, sin = compare(t[4].cpu().numpy(), V, ref, r)
         print(f"  block {i} n={n} p={p} {work}: rel {rel:.2e} sin {sin:.2e}")
-        tol = (1e-10, 1e-9) if work == "f64" else (1e-5, 1e-4)
+        tol = (1e-10, 1e-10) if work == "f64" else (1e-5, 1e-4)
         assert rel <= tol[0] and sin <= tol[1], (i, rel, sin)
 
 

@@ -11,7 +11,7 @@ import torch
 
 import oracle
 from paper_1904_10585_amd import workloads as wl
-from gpu_helpers import run_extract, compare, device_matrix, pf_module
+from gpu_helpers import run_extract, compare, device_matrix, pf_module, grade_f64
 
 pytestmark = pytest.mark.gpu
 
@@ -203,12 +203,15 @@ def test_session_chain_matches_oracle_chain():
             pf.pf_session_step(h, Xd, Xd)
             s, res = pf.pf_session_wait(h)
             assert s == pf.PF_OK and res.status == 0
+            # the oracle is fed the session's own U_in (its previous Ritz
+            # vectors), so each step is graded on its own arithmetic
             ref = oracle.extract(X, X, U, w.degree, w.a, w.b)
-            U = ref["V"]
             th = pf.device_to_numpy(res.theta, (w.p,), np.float64)
             V = pf.device_to_numpy(res.V, (w.p, res.ldv), np.float64).T[:w.n]
             rel, sin = compare(th, V, ref, w.n_top)
-            assert rel <= 1e-9 and sin <= 1e-9, (k, rel, sin)
+            print(f"session chain step {k}: rel {rel:.2e} sin {sin:.2e}")
+            assert rel <= 1e-10 and sin <= 1e-10, (k, rel, sin)
+            U = V
     finally:
         pf.pf_session_close(h)
 
@@ -244,13 +247,8 @@ def test_guard_columns_chain(work):
             info = pf.device_to_numpy(res.info, (8,), np.int32)
             rel, sin = compare(th, V, ref, r)
             print(f"guards {work} step {k}: rel {rel:.2e} sin {sin:.2e} dense rr/pre {info[2]}/{info[3]}")
-            if f64 and k == 0:
-                # cold start: Ritz values r and r+1 are still close, so the
-                # top-r subspace carries the orthonormalisation's rounding
-                # (CholeskyQR2 here, Householder in the oracle) amplified
-                assert rel <= 1e-10 and sin <= 1e-7, (k, rel, sin)
-            elif f64:
-                assert rel <= 1e-10 and sin <= 1e-9, (k, rel, sin)
+            if f64:
+                grade_f64(th, V, Xs, U, d, a, b, r, cold=(k == 0), label=f"guards f64 step {k}")
             elif k >= 2:
                 assert rel <= 1e-5 and sin <= 1e-4, (k, rel, sin)
             if k >= 2:

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import compare, device_matrix, pf_module
+from gpu_helpers import compare, device_matrix, pf_module, grade_f64
 from paper_1904_10585_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -71,7 +71,7 @@ def test_sparse_operator_matches_oracle(n, p, r, d, work):
     rel, sin = compare(theta.cpu().numpy(), V, ref, r)
     print(f"  rel {rel:.2e} sin {sin:.2e}")
     if f64:
-        assert rel <= 1e-10 and sin <= 1e-9, (rel, sin)
+        assert rel <= 1e-10 and sin <= 1e-10, (rel, sin)
     else:
         assert rel <= 1e-5 and sin <= 1e-4, (rel, sin)
 
@@ -108,7 +108,7 @@ def test_sparse_operator_session_chain(work):
             rel, sin = compare(th, V, ref, r)
             print(f"operator chain {work} step {k}: rel {rel:.2e} sin {sin:.2e}")
             if f64:
-                assert rel <= 1e-10 and sin <= (1e-7 if k == 0 else 1e-9), (k, rel, sin)
+                grade_f64(th, V, As, U, d, a, b, r, cold=(k == 0), label=f"operator chain f64 step {k}")
             elif k >= 2:
                 assert rel <= 1e-5 and sin <= 1e-4, (k, rel, sin)
             U = V
