@@ -55,26 +55,26 @@ def grade_f64(theta_g, V_g, X, U, degree, a, b, r, q=1, cold=False, label=""):
 
     Warm step: Ritz relative error and sin-angle <= 1e-10 against the oracle
     fed the same U and X.  Cold step (a random start block): the filtered
-    block is ill-conditioned and the FP64 oracle's own top-r subspace can
-    be off by more than 1e-10, so the reference is the extended-precision
-    extraction; Ritz values <= 1e-10 and the subspace <= eps * kappa(Y_d)
-    (kappa after column equilibration), the accuracy any FP64 evaluation of
-    that block can reach.  Returns (rel, sin, bound)."""
+    block is ill-conditioned (kappa after column equilibration up to ~1e8)
+    and the FP64 oracle's own top-r subspace can be off by more than 1e-10
+    (its Householder QR and unscaled recurrence are accurate to about
+    eps * kappa), so the reference is the extended-precision extraction,
+    against which both are asserted at 1e-10.  Returns (rel, sin)."""
     if not cold:
         ref = oracle.extract(X, X, U, degree, a, b, q=q)
         rel, sin = compare(theta_g, V_g, ref, r)
         print(f"{label} rel {rel:.2e} sin {sin:.2e}", flush=True)
         assert rel <= 1e-10 and sin <= 1e-10, (label, rel, sin)
-        return rel, sin, 1e-10
+        return rel, sin
     ext = oracle.extract_longdouble(X, U, degree, a, b, q=q)
     Y = ext["Y"].astype(np.float64)
     sv = np.linalg.svd(Y / np.linalg.norm(Y, axis=0), compute_uv=False)
-    bound = max(1e-10, np.finfo(np.float64).eps * sv[0] / sv[-1])
+    ekappa = np.finfo(np.float64).eps * sv[0] / sv[-1]
     refL = {"theta": ext["theta"].astype(np.float64), "V": ext["V"].astype(np.float64)}
     rel, sin = compare(theta_g, V_g, refL, r)
     ref = oracle.extract(X, X, U, degree, a, b, q=q)
     rel_o, sin_o = compare(ref["theta"], ref["V"], refL, r)
     print(f"{label} cold, against extended precision: rel {rel:.2e} sin {sin:.2e} (FP64 oracle: rel {rel_o:.2e}"
-          f" sin {sin_o:.2e}; subspace bound eps*kappa {bound:.2e})", flush=True)
-    assert rel <= 1e-10 and sin <= bound, (label, rel, sin, bound)
-    return rel, sin, bound
+          f" sin {sin_o:.2e}; eps*kappa(Y_d) {ekappa:.2e})", flush=True)
+    assert rel <= 1e-10 and sin <= 1e-10, (label, rel, sin)
+    return rel, sin
