@@ -178,6 +178,23 @@ pf_status pf_extract(const pf_desc* desc, const pf_mat* X_filter, const pf_mat* 
                      void* U_inout, int64_t ldu, double* theta_out, pf_info* info_out,
                      void* stream);
 
+/* pf_extract without device allocation, for callers that cannot call
+ * hipMalloc: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  Same arguments, semantics and results as
+ * pf_extract for PF_OP_SYM (bitwise: the same kernels run); the workspace is
+ * a fixed device array inside the library, 64 MiB on every device the
+ * library runs on (pf_extract_noalloc_max_bytes()), held until the process
+ * ends.  Shapes whose workspace (pf_workspace_size) exceeds it are rejected
+ * with PF_ERR_ARG; PF_OP_GRAM with PF_ERR_UNSUPPORTED.  Each call clears the
+ * part of the array it uses with a kernel (no memset, so it can be
+ * captured).  All calls on one device share that array: calls that overlap
+ * on one device (on different streams, or from several threads without
+ * stream order between them) race and give undefined results. */
+pf_status pf_extract_noalloc(const pf_desc* desc, const pf_mat* X_filter, const pf_mat* X_rr,
+                             void* U_inout, int64_t ldu, double* theta_out, pf_info* info_out,
+                             void* stream);
+size_t pf_extract_noalloc_max_bytes(void);
+
 /* Many independent extractions in one call: the blocks of a block-diagonal
  * operator (the per-block filtering of block-diagonal SDPs in section 5),
  * or any set of small problems.  Block i is exactly

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpfx.so")
 SOURCES = ["k_contract.hip", "k_filter.hip", "k_small.hip", "k_block.hip", "k_nce.hip", "pipeline.cpp", "capi.cpp",
-           "server.cpp", "lanczos.cpp", "nce.cpp"]
+           "server.cpp", "lanczos.cpp", "nce.cpp", "noalloc.cpp"]
 ARCH = "gfx950"
 
 

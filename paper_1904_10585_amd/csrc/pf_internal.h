@@ -217,6 +217,11 @@ void plan_validate(const pf_desc& d, const pf_mat* Xf, const pf_mat* Xr);
 void enqueue_extraction(Plan* plan, const pf_mat& Xf, const pf_mat& Xr, const void* U_in,
                         int64_t ldu_in, void* U_out, int64_t ldu_out, double* theta_out,
                         pf_info* info_out, hipStream_t st, const pf_operator* op = nullptr);
+// One PF_OP_SYM extraction whose workspace (plan_bytes(d) bytes, cleared by
+// the caller, 256-byte aligned) starts at base: no allocation.  U_inout is
+// both the start block and the output.
+void enqueue_extraction_in(const pf_desc& d, void* base, const pf_mat& Xf, const pf_mat& Xr, void* U_inout,
+                           int64_t ldu, double* theta_out, pf_info* info_out, hipStream_t st);
 // refresh the numeric fields (interval, flags) of a cached plan
 void plan_set_desc(Plan* P, const pf_desc& d);
 // plan-owned buffers (for sessions)

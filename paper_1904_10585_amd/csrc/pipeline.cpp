@@ -174,6 +174,9 @@ void host_coefficients(const pf_desc& d, std::vector<double>& tau) {
   }
 }
 
+// pointers of a plan's buffers from its layout and base address P->mem
+void carve(Plan* P, const Layout& L);
+
 }  // namespace
 
 void plan_validate(const pf_desc& d, const pf_mat* Xf, const pf_mat* Xr) {
@@ -236,6 +239,31 @@ Plan* plan_create(const pf_desc& d, hipStream_t zero_stream, bool async_zero) {
     delete P;
     fail(PF_ERR_DEVICE, "hipMemset of the workspace failed");
   }
+  carve(P, L);
+  return P;
+}
+
+void enqueue_extraction_in(const pf_desc& d, void* base, const pf_mat& Xf, const pf_mat& Xr, void* U_inout,
+                           int64_t ldu, double* theta_out, pf_info* info_out, hipStream_t st) {
+  if (d.op != PF_OP_SYM) fail(PF_ERR_UNSUPPORTED, "a caller-placed workspace serves PF_OP_SYM only");
+  Layout L = layout_for(d);
+  Plan P;
+  P.d = d;
+  P.work = d.work == PF_F64 ? Elem::F64 : Elem::F32;
+  P.esz = P.work == Elem::F64 ? 8 : 4;
+  P.n = d.n;
+  P.n_pad = round_up(d.n, 64);
+  P.p = d.p;
+  P.p_pad = (int)round_up(d.p, 16);
+  P.bytes = L.total;
+  P.mem = base;
+  carve(&P, L);
+  enqueue_extraction(&P, Xf, Xr, U_inout, ldu, U_inout, ldu, theta_out, info_out, st);
+}
+
+namespace {
+void carve(Plan* P, const Layout& L) {
+  const pf_desc& d = P->d;
   char* b = static_cast<char*>(P->mem);
   P->U = b + L.off_U;
   P->Z = b + L.off_Z;
@@ -266,8 +294,8 @@ Plan* plan_create(const pf_desc& d, hipStream_t zero_stream, bool async_zero) {
     P->tplane = P->m_pad * P->p_pad;
     P->B = reinterpret_cast<double*>(b + L.off_B);
   }
-  return P;
 }
+}  // namespace
 
 void plan_destroy(Plan* P) {
   if (!P) return;

@@ -130,6 +130,8 @@ def _load():
     vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     sig = {
         "pf_extract": (i32, [P(PfDesc), P(PfMat), P(PfMat), vp, i64, vp, vp, vp]),
+        "pf_extract_noalloc": (i32, [P(PfDesc), P(PfMat), P(PfMat), vp, i64, vp, vp, vp]),
+        "pf_extract_noalloc_max_bytes": (ctypes.c_size_t, []),
         "pf_session_open": (i32, [P(PfDesc), vp, i64, ctypes.c_uint64, P(vp)]),
         "pf_session_step": (i32, [vp, P(PfMat), P(PfMat), P(PfResult), vp]),
         "pf_session_wait": (i32, [vp, P(PfResult)]),
@@ -245,6 +247,18 @@ def pf_extract(d, X_filter, X_rr, U, theta, info=None, stream=None):
     _check(LIB.pf_extract(ctypes.byref(d), ctypes.byref(xf), ctypes.byref(xr), ctypes.c_void_p(U.data_ptr()),
                           ld_of(U), ctypes.c_void_p(theta.data_ptr()),
                           ctypes.c_void_p(info.data_ptr()) if info is not None else None, _stream(stream)))
+
+
+def pf_extract_noalloc(d, X_filter, X_rr, U, theta, info=None, stream=None):
+    """pf_extract with the library's fixed device workspace (no allocation)."""
+    xf, xr = mat(X_filter), mat(X_rr)
+    _check(LIB.pf_extract_noalloc(ctypes.byref(d), ctypes.byref(xf), ctypes.byref(xr), ctypes.c_void_p(U.data_ptr()),
+                                  ld_of(U), ctypes.c_void_p(theta.data_ptr()),
+                                  ctypes.c_void_p(info.data_ptr()) if info is not None else None, _stream(stream)))
+
+
+def pf_extract_noalloc_max_bytes():
+    return int(LIB.pf_extract_noalloc_max_bytes())
 
 
 def pf_session_open(d, U0=None, seed=0):
