@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--gram-share", type=float, default=0.05,
                     help="serving: share of sessions in the Gram form (FP8 M 12000x6000, p=48, d=8, M fixed)")
     ap.add_argument("--load", type=float, default=0.7, help="serving: arrival rate / saturated session rate")
+    ap.add_argument("--more-loads", default="0.5,0.9",
+                    help="serving: further Poisson loads reported beside --load (comma-separated, '' for none)")
+    ap.add_argument("--no-grouping", action="store_true",
+                    help="serving: every session runs its own steps (no batches of grouped launches)")
     ap.add_argument("--hbm-budget-gb", type=float, default=160.0, help="serving: HBM budget of the server")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (the byte-counter calibration of a profiler run)")
@@ -997,7 +1001,8 @@ def serve_main(args):
     cs = torch.cuda.Stream()
 
     def run(arrivals, label):
-        srv = pf.pf_server_create(int(args.hbm_budget_gb * (1 << 30)), max_active=256, streams=8)
+        srv = pf.pf_server_create(int(args.hbm_budget_gb * (1 << 30)), max_active=256, streams=8,
+                                  flags=pf.PF_SERVER_NO_GROUPING if args.no_grouping else 0)
         Xs, ids, left, lat, step_bytes = {}, {}, {}, [], 0.0
         pending = sorted(range(nS), key=lambda i: arrivals[i])
         t_start = time.perf_counter()
@@ -1072,16 +1077,26 @@ def serve_main(args):
         wall = last_done - first_submit
         lat = np.array(lat)
         log(f"serving {label}: {done_steps} steps in {wall:.2f}s, p50 {np.percentile(lat, 50):.3f} ms, "
-            f"p99 {np.percentile(lat, 99):.3f} ms, graphs {st.graph_launches}/{st.launched}")
+            f"p99 {np.percentile(lat, 99):.3f} ms, graphs {st.graph_launches}/{st.launched}, "
+            f"batches {st.batches} ({st.batched_steps} steps)")
         return dict(steps_per_s=done_steps / wall, sessions_per_s=nS / wall, wall_s=wall,
                     p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                     gbps=step_bytes / wall / 1e9, graph_launches=int(st.graph_launches),
-                    launched=int(st.launched), captures=int(st.captures))
+                    launched=int(st.launched), captures=int(st.captures), batches=int(st.batches),
+                    batched_steps=int(st.batched_steps))
 
     sat = run(np.zeros(nS), "saturated")
-    rate = args.load * sat["sessions_per_s"]
-    arr = np.cumsum(wl.rng(4, wl.S_ARRIVAL).exponential(1.0 / rate, nS))
-    pois = run(arr, f"poisson load {args.load}")
+
+    def poisson(load):
+        rate = load * sat["sessions_per_s"]
+        arr = np.cumsum(wl.rng(4, wl.S_ARRIVAL).exponential(1.0 / rate, nS))
+        return run(arr, f"poisson load {load}")
+
+    pois = poisson(args.load)
+    others = {}
+    for ld in [float(x) for x in args.more_loads.split(",") if x.strip()]:
+        r_ = poisson(ld)
+        others[str(ld)] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r_.items()}
     out = {
         "metric": "serving steps/s with p50/p99 step latency (mixed n, p, degree sessions)",
         "value": round(pois["steps_per_s"], 2),
@@ -1104,6 +1119,8 @@ def serve_main(args):
         "hbm_GBps_algorithmic": round(pois["gbps"], 1),
         "saturated": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sat.items()},
         "poisson": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in pois.items()},
+        "poisson_other_loads": others,
+        "grouped_launches": not args.no_grouping,
     }
     print(json.dumps(out), flush=True)
 

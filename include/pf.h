@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define PF_ABI_VERSION 1
+#define PF_ABI_VERSION 2
 
 typedef enum pf_status {
   PF_OK = 0,
@@ -200,10 +200,13 @@ size_t pf_extract_noalloc_max_bytes(void);
  * or any set of small problems.  Block i is exactly
  *   pf_extract(&descs[i], &X_filter[i], &X_rr[i], U_inout[i], ldu[i],
  *              theta_out[i], info_out ? info_out[i] : NULL, ...)
- * (the same kernels and results), but the blocks run concurrently: the call
- * forks the caller's stream onto a pool of 8 library streams (block i on
- * stream i mod 8, created on first use and kept until the process ends)
- * and joins them back, so later work on `stream` sees every block done.
+ * (the same kernels, bitwise the same results), but the blocks share their
+ * launches: every phase of the extraction (a filter product, a Gram matrix,
+ * a Cholesky factor, a p x p eigensolve, a block apply) is one grouped
+ * launch per kernel instance over all blocks, enqueued on `stream`, each
+ * block with its own workspace (cached per stream and shape, one per block
+ * of a shape in the call).  Blocks on PF_OP_GRAM run one after another
+ * before the grouped ones.
  * Every block is validated before any work is enqueued (PF_ERR_ARG names
  * the block in pf_last_error); numerical outcomes land in each info_out[i].
  * Arrays are host arrays of count entries; info_out may be NULL. */
@@ -271,12 +274,19 @@ pf_status pf_session_close(pf_session* s);
  *    budget is full wait in FIFO order and are admitted as closed sessions
  *    free memory.  footprint = the session's device bytes + operator_bytes
  *    (what the caller declares for its X, so that the budget covers it).
- *  - Continuous batching: a worker thread launches every resident session's
- *    next requested step as soon as its previous step is done; the steps of
- *    different sessions run concurrently on a pool of HIP streams.
- *  - HIP graphs: a session's first step runs eagerly (cold start); its warm
- *    step is captured once as a graph and replayed for later steps whose
- *    operator buffers are the ones captured (re-captured when they change).
+ *  - Continuous batching: a worker thread takes the next requested step of
+ *    every ready resident session (its previous step done) on PF_OP_SYM into
+ *    one batch of grouped launches: each phase of the extraction is one
+ *    launch per kernel instance for the whole batch, whatever the sessions'
+ *    n, p, degree and interval; steps requested while batches run form the
+ *    next batch on the next of the worker's streams, so batches overlap.
+ *  - HIP graphs: sessions on PF_OP_GRAM run their own steps; a session's
+ *    first step runs eagerly (cold start); its warm step is captured once
+ *    as a graph and replayed for later steps whose operator buffers are the
+ *    ones captured (re-captured when they change).
+ *  - Closed sessions leave their device memory to later sessions of the
+ *    same shape; it is freed (a device synchronisation) only when the budget
+ *    needs the room for another shape.
  *  - Every finished step produces a pf_server_event with host timestamps
  *    (steady clock, ns) of submission, launch and observed completion.
  *  - Results of a session are bitwise the same whether it runs alone or in
@@ -288,7 +298,8 @@ pf_status pf_session_close(pf_session* s);
  * is capturing a graph. */
 typedef struct pf_server pf_server;
 
-#define PF_SERVER_NO_GRAPHS 0x1u  /* launch warm steps eagerly, no capture */
+#define PF_SERVER_NO_GRAPHS 0x1u    /* launch warm steps eagerly, no capture */
+#define PF_SERVER_NO_GROUPING 0x2u  /* every session runs its own steps (no batches) */
 
 typedef struct pf_server_config {
   uint32_t struct_size;   /* sizeof(pf_server_config) */
@@ -312,6 +323,8 @@ typedef struct pf_server_stats {
   int32_t active, waiting;
   size_t used_bytes;
   int64_t launched, completed, graph_launches, captures;
+  int64_t batches;        /* batches of grouped launches */
+  int64_t batched_steps;  /* steps that ran in them */
 } pf_server_stats;
 
 pf_status pf_server_create(const pf_server_config* cfg, pf_server** out);

@@ -1,6 +1,7 @@
 // The C ABI of include/pf.h: argument validation, error reporting, the
 // per-stream workspace cache of pf_extract, and sessions.
 #include "pf_internal.h"
+#include "group.h"
 
 #include <algorithm>
 #include <cmath>
@@ -105,14 +106,19 @@ namespace {
 // The key holds exactly what the workspace layout depends on (n, m, p, work
 // dtype, operator kind): degree, power, interval and flags only change the
 // descriptor, which every call installs with plan_set_desc.
-using PlanKey = std::tuple<int, uintptr_t, int64_t, int64_t, int, int, int>;
+// pf_extract_batch keeps one workspace per block of a shape (slot).
+using PlanKey = std::tuple<int, uintptr_t, int64_t, int64_t, int, int, int, int>;
 std::mutex g_plans_mu;
 std::map<PlanKey, Plan*> g_plans;
 
-Plan* cached_plan(const pf_desc& d, hipStream_t st) {
+PlanKey plan_key(const pf_desc& d, hipStream_t st, int slot) {
   int dev = 0;
   PFX_HIP(hipGetDevice(&dev));
-  PlanKey key{dev, (uintptr_t)st, d.n, d.op == PF_OP_GRAM ? d.m : 0, d.p, (int)d.work, (int)d.op};
+  return PlanKey{dev, (uintptr_t)st, d.n, d.op == PF_OP_GRAM ? d.m : 0, d.p, (int)d.work, (int)d.op, slot};
+}
+
+Plan* cached_plan(const pf_desc& d, hipStream_t st, int slot = 0) {
+  const PlanKey key = plan_key(d, st, slot);
   std::lock_guard<std::mutex> lk(g_plans_mu);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) return it->second;
@@ -139,7 +145,13 @@ bool g_prof_on = false;
 ProfClass g_prof[kProfClasses];
 }  // namespace
 
-bool prof_enabled() { return g_prof_on; }
+// (launches being recorded for a grouped enqueue are not timed one by one)
+bool prof_enabled() { return g_prof_on && current_recorder() == nullptr; }
+
+Recorder*& current_recorder() {
+  static thread_local Recorder* r = nullptr;
+  return r;
+}
 
 void prof_begin(int cls, hipStream_t st) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -242,25 +254,6 @@ pf_status pf_extract(const pf_desc* desc, const pf_mat* X_filter, const pf_mat* 
   });
 }
 
-namespace {
-// Streams pf_extract_batch forks onto: a fixed pool per device, created on
-// first use (non-blocking, default priority) and kept until the process
-// ends.  Calls that share the pool are serialised by its mutex while they
-// enqueue.
-constexpr int kBatchStreams = 8;
-std::mutex g_batch_mu;
-std::map<int, std::vector<hipStream_t>> g_batch_streams;
-
-std::vector<hipStream_t>& batch_streams(int dev) {
-  auto& v = g_batch_streams[dev];
-  while ((int)v.size() < kBatchStreams) {
-    hipStream_t st;
-    PFX_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    v.push_back(st);
-  }
-  return v;
-}
-}  // namespace
 
 pf_status pf_extract_batch(int32_t count, const pf_desc* descs, const pf_mat* X_filter, const pf_mat* X_rr,
                            void* const* U_inout, const int64_t* ldu, double* const* theta_out,
@@ -280,50 +273,38 @@ pf_status pf_extract_batch(int32_t count, const pf_desc* descs, const pf_mat* X_
         fail(e.status, "block " + std::to_string(i) + ": " + e.msg);
       }
     }
-    hipStream_t caller = static_cast<hipStream_t>(stream);
-    int dev = 0;
-    PFX_HIP(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lk(g_batch_mu);
-    std::vector<hipStream_t>& pool = batch_streams(dev);
-    const int used = std::min<int>(count, kBatchStreams);
-    hipEvent_t fork = nullptr;
-    std::vector<hipEvent_t> joins(used, nullptr);
-    auto release = [&] {
-      if (fork) (void)hipEventDestroy(fork);
-      for (hipEvent_t e : joins)
-        if (e) (void)hipEventDestroy(e);
-    };
-    try {
-      PFX_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-      PFX_HIP(hipEventRecord(fork, caller));
-      for (int w = 0; w < used; ++w) PFX_HIP(hipStreamWaitEvent(pool[w], fork, 0));
-      // block i on pool stream i mod used, in order on each stream
-      for (int i = 0; i < count; ++i) {
-        hipStream_t st = pool[i % used];
-        Plan* P = cached_plan(descs[i], st);
-        plan_set_desc(P, descs[i]);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // a workspace per block: the k-th block of a shape takes the k-th
+    // workspace of that shape on this stream
+    std::map<PlanKey, int> seen;
+    std::vector<ExtractionJob> jobs;
+    jobs.reserve(count);
+    for (int i = 0; i < count; ++i) {
+      const pf_desc& d = descs[i];
+      const int slot = seen[plan_key(d, st, 0)]++;
+      Plan* P = cached_plan(d, st, slot);
+      if (d.op != PF_OP_SYM) {
+        // the Gram operator (transposed copies made on first use) runs on its own
+        plan_set_desc(P, d);
         enqueue_extraction(P, X_filter[i], X_rr[i], U_inout[i], ldu[i], U_inout[i], ldu[i], theta_out[i],
                            info_out ? info_out[i] : nullptr, st);
+        continue;
       }
-      for (int w = 0; w < used; ++w) {
-        PFX_HIP(hipEventCreateWithFlags(&joins[w], hipEventDisableTiming));
-        PFX_HIP(hipEventRecord(joins[w], pool[w]));
-        PFX_HIP(hipStreamWaitEvent(caller, joins[w], 0));
-      }
-    } catch (...) {
-      // the caller's stream still waits for whatever was enqueued
-      for (int w = 0; w < used; ++w) {
-        hipEvent_t e = nullptr;
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
-          (void)hipEventRecord(e, pool[w]);
-          (void)hipStreamWaitEvent(caller, e, 0);
-          (void)hipEventDestroy(e);
-        }
-      }
-      release();
-      throw;
+      ExtractionJob j;
+      j.plan = P;
+      j.desc = d;
+      j.Xf = X_filter[i];
+      j.Xr = X_rr[i];
+      j.U_in = U_inout[i];
+      j.ldu_in = ldu[i];
+      j.U_out = U_inout[i];
+      j.ldu_out = ldu[i];
+      j.theta_out = theta_out[i];
+      j.info_out = info_out ? info_out[i] : nullptr;
+      jobs.push_back(j);
     }
-    release();
+    // the blocks' phases as grouped launches on the caller's stream
+    enqueue_extractions_grouped((int)jobs.size(), jobs.data(), st);
   });
 }
 

@@ -10,6 +10,7 @@
 //    saturating at 448.
 //  * psd_dense: P_+ = V_+ diag(theta_+) V_+^T (eq. PFAM1) as a dense matrix.
 #include "pf_internal.h"
+#include "group.h"
 
 #include <cmath>
 
@@ -40,19 +41,48 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 // S may be rectangular (p x q, q output columns), and with D the result is
 // C1 = D - A1 S (D may be C1 itself: each element is read, then written, by
 // one lane) -- a Gram-Schmidt update Y -= V C in one launch.
+template <typename T>
+struct ApplyDev {
+  int64_t n; int p, q;
+  const T* A1; int64_t lda1;
+  const T* A2; int64_t lda2;
+  const double* S; int lds_;
+  T* C1; int64_t ldc1;
+  T* C2; int64_t ldc2;
+  double alpha, beta;
+  const int* deficient;
+  const pf_info* gate; pf_info* info_out;
+  const double* theta; double* theta_out;
+  const T* D; int64_t ldd;
+};
+
 template <typename T, int NB, bool TWO>
-__global__ __launch_bounds__(256) void apply_kernel(int64_t n, int p, int q, const T* __restrict__ A1, int64_t lda1,
-                                                    const T* __restrict__ A2, int64_t lda2,
-                                                    const double* __restrict__ S, int lds_, T* C1, int64_t ldc1,
-                                                    T* C2, int64_t ldc2, double alpha, double beta,
-                                                    const int* __restrict__ deficient,
-                                                    const pf_info* gate, pf_info* info_out,
-                                                    const double* __restrict__ theta, double* theta_out,
-                                                    const T* D, int64_t ldd) {
+struct ApplyK {
+  using Args = ApplyDev<T>;
+  static constexpr int kThreads = 256, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const Args& a, uint3 bid);
+};
+
+template <typename T, int NB, bool TWO>
+__device__ void ApplyK<T, NB, TWO>::body(const ApplyDev<T>& a, uint3 bid) {
+  const int64_t n = a.n, lda1 = a.lda1, lda2 = a.lda2, ldc1 = a.ldc1, ldc2 = a.ldc2, ldd = a.ldd;
+  const int p = a.p, q = a.q, lds_ = a.lds_;
+  const T* __restrict__ A1 = a.A1;
+  const T* __restrict__ A2 = a.A2;
+  const double* __restrict__ S = a.S;
+  T* C1 = a.C1;
+  T* C2 = a.C2;
+  const double alpha = a.alpha, beta = a.beta;
+  const int* __restrict__ deficient = a.deficient;
+  const pf_info* gate = a.gate;
+  pf_info* info_out = a.info_out;
+  const double* __restrict__ theta = a.theta;
+  double* theta_out = a.theta_out;
+  const T* D = a.D;
   constexpr int KS = 4 * NB;                         // K steps of 4 cover the padded width 16 NB
   const int l = threadIdx.x & 63, c = l & 15, g = l >> 4;
-  const int64_t row0 = (int64_t)blockIdx.x * 64 + 16 * (threadIdx.x >> 6);
-  const int j = 16 * (int)blockIdx.y + c;            // B column of this lane = its output column
+  const int64_t row0 = (int64_t)bid.x * 64 + 16 * (threadIdx.x >> 6);
+  const int j = 16 * (int)bid.y + c;                 // B column of this lane = its output column
   const int64_t arow = row0 + c;
   const bool rok = arow < n, jok = j < q;
   const int gst = gate ? gate->status : 0;
@@ -73,7 +103,7 @@ __global__ __launch_bounds__(256) void apply_kernel(int64_t n, int p, int q, con
     acc1[ks & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[ks], b[ks], acc1[ks & 1], 0, 0, 0);
     if constexpr (TWO) acc2[ks & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[ks], b[ks], acc2[ks & 1], 0, 0, 0);
   }
-  if (gate && blockIdx.x == 0 && blockIdx.y == 0) {
+  if (gate && bid.x == 0 && bid.y == 0) {
     if (info_out && threadIdx.x == 0) *info_out = *gate;
     if (theta_out && gst == 0)
       for (int i = threadIdx.x; i < p; i += 256) theta_out[i] = theta[i];
@@ -122,13 +152,21 @@ __global__ void combine_kernel(const T* __restrict__ A, const T* __restrict__ D1
 }
 
 template <typename T>
-__global__ void axpby_kernel(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ dst, int64_t ld,
-                             int64_t n, int p, double alpha, double beta) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int j = blockIdx.y;
-  if (i >= n || j >= p) return;
-  dst[i + j * ld] = (T)(alpha * (double)A[i + j * ld] + beta * (double)B[i + j * ld]);
-}
+struct AxpbyArgs {
+  const T* A; const T* B; T* dst; int64_t ld; int64_t n; int p; double alpha, beta;
+};
+template <typename T>
+struct AxpbyK {
+  using Args = AxpbyArgs<T>;
+  static constexpr int kThreads = 256, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const Args& a, uint3 bid) {
+    const int64_t i = (int64_t)bid.x * 256 + threadIdx.x;
+    const int j = bid.y;
+    if (i >= a.n || j >= a.p) return;
+    const int64_t o = i + j * a.ld;
+    a.dst[o] = (T)(a.alpha * (double)a.A[o] + a.beta * (double)a.B[o]);
+  }
+};
 
 __global__ void info_copy_kernel(const pf_info* src, pf_info* dst, const double* th, double* thd, int p) {
   const int t = threadIdx.x;
@@ -136,6 +174,18 @@ __global__ void info_copy_kernel(const pf_info* src, pf_info* dst, const double*
   if (thd && src->status == 0)
     for (int i = t; i < p; i += blockDim.x) thd[i] = th[i];
 }
+
+// a step's pf_info to host-visible memory
+struct InfoArgs {
+  const pf_info* src; pf_info* dst;
+};
+struct InfoK {
+  using Args = InfoArgs;
+  static constexpr int kThreads = 64, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const Args& a, uint3) {
+    if (threadIdx.x == 0) *a.dst = *a.src;
+  }
+};
 
 template <typename T>
 __global__ void normal_block_kernel(T* dst, int64_t ld, int64_t n, int p, uint64_t seed) {
@@ -278,10 +328,9 @@ void apply_t(const ApplyArgs& a, hipStream_t st) {
   const T* A2 = static_cast<const T*>(a.A2);
   T* C1 = static_cast<T*>(a.C1);
   T* C2 = static_cast<T*>(a.C2);
-#define PFX_APPLY(NB)                                                                                    \
-  apply_kernel<T, NB, TWO><<<grid, 256, 0, st>>>(a.n, a.p, q, A1, a.lda1, A2, a.lda2, a.S, a.lds_, C1, a.ldc1, \
-                                                C2, a.ldc2, a.alpha, a.beta, a.deficient, a.gate, a.info_out,        \
-                                                a.theta, a.theta_out, D, a.ldd)
+  const ApplyDev<T> dv{a.n, a.p, q, A1, a.lda1, A2, a.lda2, a.S, a.lds_, C1, a.ldc1, C2, a.ldc2, a.alpha, a.beta,
+                       a.deficient, a.gate, a.info_out, a.theta, a.theta_out, D, a.ldd};
+#define PFX_APPLY(NB) emit<ApplyK<T, NB, TWO>>(dv, grid, 0, st)
   switch (nb) {
     case 1: PFX_APPLY(1); break;
     case 2: PFX_APPLY(2); break;
@@ -293,7 +342,6 @@ void apply_t(const ApplyArgs& a, hipStream_t st) {
     default: PFX_APPLY(8); break;
   }
 #undef PFX_APPLY
-  PFX_HIP(hipGetLastError());
 }
 
 // dst = src^T for a rows x cols column-major matrix (element type T), in
@@ -383,18 +431,20 @@ void launch_copy_block(const void* src, int64_t lds_, Elem ts, void* dst, int64_
 void launch_axpby(const void* A, const void* B, void* dst, int64_t ld, Elem t, int64_t n, int p, double alpha,
                   double beta, hipStream_t st) {
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)p);
-  if (t == Elem::F64)
-    axpby_kernel<double><<<grid, 256, 0, st>>>(static_cast<const double*>(A), static_cast<const double*>(B),
-                                               static_cast<double*>(dst), ld, n, p, alpha, beta);
-  else
-    axpby_kernel<float><<<grid, 256, 0, st>>>(static_cast<const float*>(A), static_cast<const float*>(B),
-                                              static_cast<float*>(dst), ld, n, p, alpha, beta);
-  PFX_HIP(hipGetLastError());
+  if (t == Elem::F64) {
+    const AxpbyArgs<double> a{static_cast<const double*>(A), static_cast<const double*>(B), static_cast<double*>(dst),
+                              ld, n, p, alpha, beta};
+    emit<AxpbyK<double>>(a, grid, 0, st);
+  } else {
+    const AxpbyArgs<float> a{static_cast<const float*>(A), static_cast<const float*>(B), static_cast<float*>(dst), ld,
+                             n, p, alpha, beta};
+    emit<AxpbyK<float>>(a, grid, 0, st);
+  }
 }
 
 void launch_info_to_host(const pf_info* src, pf_info* host_mapped, hipStream_t st) {
-  info_copy_kernel<<<1, 64, 0, st>>>(src, host_mapped, nullptr, nullptr, 0);
-  PFX_HIP(hipGetLastError());
+  const InfoArgs a{src, host_mapped};
+  emit<InfoK>(a, dim3(1), 0, st);
 }
 
 void launch_normal_block(void* dst, int64_t ld, Elem t, int64_t n, int p, uint64_t seed, hipStream_t st) {

@@ -21,6 +21,7 @@
 // contributes K index k0 + VEC*g + j; the same permutation on both
 // operands leaves the sum unchanged.
 #include "pf_internal.h"
+#include "group.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -126,7 +127,14 @@ template <bool F64>
 __device__ inline int acc_row(int g, int r) { return F64 ? (4 * r + g) : (4 * g + r); }
 
 template <typename TA, typename TB, typename TO, bool F64, int MB, int NB>
-__global__ __launch_bounds__(kThreads) void contract_kernel(DevArgs a) {
+struct ContractK {
+  using Args = DevArgs;
+  static constexpr int kThreads = pfx::kThreads, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const DevArgs& a, uint3 bid);
+};
+
+template <typename TA, typename TB, typename TO, bool F64, int MB, int NB>
+__device__ void ContractK<TA, TB, TO, F64, MB, NB>::body(const DevArgs& a, uint3 bid) {
   using T = Tile<TA, TB, F64, MB, NB>;
   using TC = typename T::TC;
   using AccV = typename T::AccV;
@@ -138,9 +146,9 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(DevArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int c = lane & 15, g = lane >> 4;
-  const int64_t m0 = (int64_t)blockIdx.x * (16 * MB);
-  const int64_t n0 = (int64_t)blockIdx.y * (16 * NB);
-  const int s = blockIdx.z;
+  const int64_t m0 = (int64_t)bid.x * (16 * MB);
+  const int64_t n0 = (int64_t)bid.y * (16 * NB);
+  const int s = bid.z;
 
   const int64_t kbeg_wg = (int64_t)s * a.kchunk;
   const int64_t kend_wg = min(a.K, kbeg_wg + a.kchunk);
@@ -278,9 +286,16 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(DevArgs a) {
 
 // out = alpha * sum_s part[s] + beta * D1 + gamma * D2, slabs summed in order.
 template <typename TC, typename TO>
-__global__ __launch_bounds__(256) void splitk_reduce_kernel(DevArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t j = blockIdx.y;
+struct SplitkReduceK {
+  using Args = DevArgs;
+  static constexpr int kThreads = 256, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const DevArgs& a, uint3 bid);
+};
+
+template <typename TC, typename TO>
+__device__ void SplitkReduceK<TC, TO>::body(const DevArgs& a, uint3 bid) {
+  const int64_t i = (int64_t)bid.x * 256 + threadIdx.x;
+  const int64_t j = bid.y;
   if (i >= a.M) return;
   const TC* part = static_cast<const TC*>(a.part) + i + j * a.ldp;
   const int64_t slab = a.ldp * a.N;
@@ -360,18 +375,14 @@ void launch_tile(const DevArgs& d, const Split& sp, int prof_main, int prof_redu
   using TC = std::conditional_t<F64, double, float>;
   dim3 grid((unsigned)sp.mtiles, (unsigned)sp.ntiles, (unsigned)sp.S);
   const size_t lds = 2 * (size_t)MB * NB * 4 * 64 * sizeof(TC);
-  static size_t cur = 0;
-  ensure_lds((const void*)contract_kernel<TA, TB, TO, F64, MB, NB>, lds, cur);
   const bool prof = prof_enabled();
   if (prof && prof_main >= 0) prof_begin(prof_main, st);
-  contract_kernel<TA, TB, TO, F64, MB, NB><<<grid, dim3(kThreads), lds, st>>>(d);
-  PFX_HIP(hipGetLastError());
+  emit<ContractK<TA, TB, TO, F64, MB, NB>>(d, grid, lds, st);
   if (prof && prof_main >= 0) prof_end(prof_main, st);
   if (sp.S > 1) {
     dim3 g2((unsigned)((d.M + 255) / 256), (unsigned)d.N);
     if (prof && prof_reduce >= 0) prof_begin(prof_reduce, st);
-    splitk_reduce_kernel<TC, TO><<<g2, dim3(256), 0, st>>>(d);
-    PFX_HIP(hipGetLastError());
+    emit<SplitkReduceK<TC, TO>>(d, g2, 0, st);
     if (prof && prof_reduce >= 0) prof_end(prof_reduce, st);
   }
 }

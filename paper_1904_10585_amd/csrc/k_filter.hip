@@ -23,6 +23,7 @@
 // values of one X column: 32 bytes, one cache line per column and step) and
 // B[k = 8(l/16) .. +7][n = l%16] (16 bytes of one Y plane column).
 #include "pf_internal.h"
+#include "group.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -174,7 +175,14 @@ __device__ inline void wg_barrier() {
 }
 
 template <int XK, int MB, int NB>
-__global__ __launch_bounds__(kThreads, 1) void filter_bf16x6_kernel(FArgs a) {
+struct FilterK {
+  using Args = FArgs;
+  static constexpr int kThreads = pfx::kThreads, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const FArgs& a, uint3 bid);
+};
+
+template <int XK, int MB, int NB>
+__device__ void FilterK<XK, MB, NB>::body(const FArgs& a, uint3 bid) {
   using C = FCfg<XK, MB, NB>;
   static_assert(C::STAGE <= kStageChunks, "stage does not fit its LDS buffer");
   u4v* const st0 = g_st0;
@@ -187,7 +195,7 @@ __global__ __launch_bounds__(kThreads, 1) void filter_bf16x6_kernel(FArgs a) {
   // XCD-aware tile order: workgroups are dispatched round-robin over the 8
   // XCDs, so the K range (slab) is the fast index and each XCD works on few
   // K ranges, keeping their Y rows in its L2.
-  const int64_t L = blockIdx.x;
+  const int64_t L = bid.x;
   const int zslab = (int)(L % a.splitk);
   const int64_t mtile = L / a.splitk;
   const int64_t mt0 = mtile * C::ROWS;
@@ -413,9 +421,15 @@ __global__ __launch_bounds__(kThreads, 1) void filter_bf16x6_kernel(FArgs a) {
 }
 
 // Sum of the split-K slabs in slab order, then the epilogue.
-__global__ __launch_bounds__(256) void filter_reduce_kernel(FArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t j = blockIdx.y;
+struct FilterReduceK {
+  using Args = FArgs;
+  static constexpr int kThreads = 256, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const FArgs& a, uint3 bid);
+};
+
+__device__ void FilterReduceK::body(const FArgs& a, uint3 bid) {
+  const int64_t i = (int64_t)bid.x * 256 + threadIdx.x;
+  const int64_t j = bid.y;
   if (i >= a.M) return;
   const float* part = a.part + i + j * a.ldp;
   const int64_t slab = a.ldp * a.N;
@@ -434,10 +448,20 @@ __global__ __launch_bounds__(256) void filter_reduce_kernel(FArgs a) {
 
 // Three BF16 planes of an n x p FP32 block (rows up to n_pad, columns up to
 // p_pad; padding is zero).
-__global__ void split_planes_kernel(const float* __restrict__ src, int64_t lds_, int64_t n, int p,
-                                    uint16_t* __restrict__ dst, int64_t ldd, int64_t plane, int64_t n_pad) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int j = blockIdx.y;
+struct SplitPlanesArgs {
+  const float* src; int64_t lds_; int64_t n; int p;
+  uint16_t* dst; int64_t ldd; int64_t plane; int64_t n_pad;
+};
+struct SplitPlanesK {
+  using Args = SplitPlanesArgs;
+  static constexpr int kThreads = 256, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const Args& a, uint3 bid) {
+    const float* __restrict__ src = a.src;
+    uint16_t* __restrict__ dst = a.dst;
+    const int64_t lds_ = a.lds_, n = a.n, ldd = a.ldd, plane = a.plane, n_pad = a.n_pad;
+    const int p = a.p;
+  const int64_t i = (int64_t)bid.x * 256 + threadIdx.x;
+  const int j = bid.y;
   if (i >= n_pad) return;
   const float v = (i < n && j < p) ? src[i + j * lds_] : 0.0f;
   uint16_t p1, p2, p3;
@@ -446,17 +470,30 @@ __global__ void split_planes_kernel(const float* __restrict__ src, int64_t lds_,
   o[0] = p1;
   o[plane] = p2;
   o[2 * plane] = p3;
-}
+  }
+};
 
 // Start of an extraction in one launch: the n x p start block copied into
 // the padded work buffer (zero padding up to n_pad x p_pad), its three BF16
 // planes when `planes` is set, and the step's pf_info cleared.
 template <typename T>
-__global__ void begin_block_kernel(const T* __restrict__ src, int64_t lds_, T* __restrict__ dst, int64_t ldd,
-                                   int64_t n, int p, int64_t n_pad, uint16_t* __restrict__ planes, int64_t plane,
-                                   pf_info* info) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int j = blockIdx.y;
+struct BeginArgs {
+  const T* src; int64_t lds_; T* dst; int64_t ldd;
+  int64_t n; int p; int64_t n_pad; uint16_t* planes; int64_t plane; pf_info* info;
+};
+template <typename T>
+struct BeginK {
+  using Args = BeginArgs<T>;
+  static constexpr int kThreads = 256, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const Args& a, uint3 bid) {
+    const T* __restrict__ src = a.src;
+    T* __restrict__ dst = a.dst;
+    uint16_t* __restrict__ planes = a.planes;
+    const int64_t lds_ = a.lds_, ldd = a.ldd, n = a.n, n_pad = a.n_pad, plane = a.plane;
+    const int p = a.p;
+    pf_info* info = a.info;
+  const int64_t i = (int64_t)bid.x * 256 + threadIdx.x;
+  const int j = bid.y;
   if (info && i == 0 && j == 0) *info = pf_info{};
   if (i >= n_pad) return;
   const T v = (i < n && j < p) ? src[i + j * lds_] : T(0);
@@ -471,7 +508,8 @@ __global__ void begin_block_kernel(const T* __restrict__ src, int64_t lds_, T* _
       o[2 * plane] = p3;
     }
   }
-}
+  }
+};
 
 struct FSplit {
   int S;
@@ -504,14 +542,12 @@ void launch_f(FArgs& a, const FSplit& sp, int pm, int pr, hipStream_t st) {
   dim3 grid((unsigned)(sp.mtiles * sp.S), 1, 1);
   const bool prof = prof_enabled();
   if (prof && pm >= 0) prof_begin(pm, st);
-  filter_bf16x6_kernel<XK, MB, NB><<<grid, kThreads, 0, st>>>(a);
-  PFX_HIP(hipGetLastError());
+  emit<FilterK<XK, MB, NB>>(a, grid, 0, st);
   if (prof && pm >= 0) prof_end(pm, st);
   if (sp.S > 1) {
     dim3 g2((unsigned)((a.M + 255) / 256), (unsigned)a.N);
     if (prof && pr >= 0) prof_begin(pr, st);
-    filter_reduce_kernel<<<g2, 256, 0, st>>>(a);
-    PFX_HIP(hipGetLastError());
+    emit<FilterReduceK>(a, g2, 0, st);
     if (prof && pr >= 0) prof_end(pr, st);
   }
 }
@@ -602,20 +638,21 @@ void launch_begin_block(const void* src, int64_t lds, Elem t, void* dst, int64_t
   dim3 grid((unsigned)((n_pad + 255) / 256), (unsigned)p_pad);
   if (t == Elem::F64) {
     if (planes) fail(PF_ERR_ARG, "begin_block: BF16 planes need FP32 work");
-    begin_block_kernel<double><<<grid, 256, 0, st>>>(static_cast<const double*>(src), lds, static_cast<double*>(dst),
-                                                     ldd, n, p, n_pad, nullptr, 0, info);
+    const BeginArgs<double> a{static_cast<const double*>(src), lds, static_cast<double*>(dst), ldd, n, p, n_pad,
+                              nullptr, 0, info};
+    emit<BeginK<double>>(a, grid, 0, st);
   } else {
-    begin_block_kernel<float><<<grid, 256, 0, st>>>(static_cast<const float*>(src), lds, static_cast<float*>(dst), ldd,
-                                                    n, p, n_pad, planes, plane, info);
+    const BeginArgs<float> a{static_cast<const float*>(src), lds, static_cast<float*>(dst), ldd, n, p, n_pad,
+                             planes, plane, info};
+    emit<BeginK<float>>(a, grid, 0, st);
   }
-  PFX_HIP(hipGetLastError());
 }
 
 void launch_split_planes(const float* src, int64_t lds, int64_t n, int p, uint16_t* dst, int64_t ldd,
                          int64_t plane, int64_t n_pad, int p_pad, hipStream_t st) {
   dim3 grid((unsigned)((n_pad + 255) / 256), (unsigned)p_pad);
-  split_planes_kernel<<<grid, 256, 0, st>>>(src, lds, n, p, dst, ldd, plane, n_pad);
-  PFX_HIP(hipGetLastError());
+  const SplitPlanesArgs a{src, lds, n, p, dst, ldd, plane, n_pad};
+  emit<SplitPlanesK>(a, grid, 0, st);
 }
 
 }  // namespace pfx

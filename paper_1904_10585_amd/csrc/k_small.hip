@@ -11,6 +11,7 @@
 //    nearly diagonal matrices of warm steps; a direct dense solver
 //    (tridiagonal reduction, bisection, inverse iteration) takes the rest.
 #include "pf_internal.h"
+#include "group.h"
 
 #include <cmath>
 
@@ -57,7 +58,7 @@ __device__ __attribute__((always_inline)) inline void static_for(F& f) {
 //     R^{-1}[i][j] = s_i W[j][i] / sqrt(d_j),   i <= j,
 // with s = diag(G)^{-1/2} the equilibration.
 template <int PMAX, int BR, int BC, bool UNROLL>
-__global__ __launch_bounds__((PMAX / BR) * (PMAX / BC)) void chol_rinv_kernel(
+__device__ __attribute__((always_inline)) inline void chol_rinv_impl(
     const double* __restrict__ G, int ldg, int p, double* __restrict__ Rinv, int ldr,
     int* __restrict__ deficient, pf_info* info, int pass, double tol, double near_tol) {
   static_assert(BC % BR == 0 && BC % 2 == 0, "a step block spans whole row blocks");
@@ -437,10 +438,10 @@ __device__ inline double start_entry(int i, int j) {
 }
 
 template <int PMAX>
-__global__ __launch_bounds__(8 * PMAX) void syev_kernel(const double* __restrict__ H, int ldh, int p,
-                                                        double* __restrict__ theta, double* __restrict__ Z,
-                                                        int ldz, int pad, pf_info* info, int which,
-                                                        const int* skip) {
+__device__ __attribute__((always_inline)) inline void syev_impl(const double* __restrict__ H, int ldh, int p,
+                                                               double* __restrict__ theta, double* __restrict__ Z,
+                                                               int ldz, int pad, pf_info* info, int which,
+                                                               const int* skip) {
   if (skip && *skip) return;                     // the refinement solved this matrix
   constexpr int NT = 8 * PMAX;
   constexpr int NW = NT / 64;
@@ -1047,10 +1048,11 @@ __device__ inline void gemm_pp(double* __restrict__ C, const double* __restrict_
 }
 
 template <int PMAX, bool SH>
-__global__ __launch_bounds__(256) void eig_refine_kernel(const double* __restrict__ H, int ldh, int p,
-                                                         double* __restrict__ theta, double* __restrict__ Z,
-                                                         int ldz, double* __restrict__ gscratch, int* refined,
-                                                         pf_info* info, int which, int max_iter) {
+__device__ __attribute__((always_inline)) inline void eig_refine_impl(const double* __restrict__ H, int ldh, int p,
+                                                                     double* __restrict__ theta,
+                                                                     double* __restrict__ Z, int ldz,
+                                                                     double* __restrict__ gscratch, int* refined,
+                                                                     pf_info* info, int which, int max_iter) {
   constexpr int PP = PMAX, LD = PP + 1, MS = PP * LD;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* buf;
@@ -1220,6 +1222,42 @@ __global__ __launch_bounds__(256) void eig_refine_kernel(const double* __restric
   }
 }
 
+struct CholArgs {
+  const double* G; int ldg; int p; double* Rinv; int ldr; int* deficient; pf_info* info; int pass;
+  double tol, near_tol;
+};
+template <int PMAX, int BR, int BC, bool UNROLL>
+struct CholK {
+  using Args = CholArgs;
+  static constexpr int kThreads = (PMAX / BR) * (PMAX / BC), kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const Args& a, uint3) {
+    chol_rinv_impl<PMAX, BR, BC, UNROLL>(a.G, a.ldg, a.p, a.Rinv, a.ldr, a.deficient, a.info, a.pass, a.tol,
+                                         a.near_tol);
+  }
+};
+
+struct EigArgs {
+  const double* H; int ldh; int p; double* theta; double* Z; int ldz; int pad; double* gscratch; int* refined;
+  pf_info* info; int which; int max_iter; const int* skip;
+};
+template <int PMAX>
+struct SyevK {
+  using Args = EigArgs;
+  static constexpr int kThreads = 8 * PMAX, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const Args& a, uint3) {
+    syev_impl<PMAX>(a.H, a.ldh, a.p, a.theta, a.Z, a.ldz, a.pad, a.info, a.which, a.skip);
+  }
+};
+template <int PMAX, bool SH>
+struct RefineK {
+  using Args = EigArgs;
+  static constexpr int kThreads = 256, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const Args& a, uint3) {
+    eig_refine_impl<PMAX, SH>(a.H, a.ldh, a.p, a.theta, a.Z, a.ldz, a.gscratch, a.refined, a.info, a.which,
+                              a.max_iter);
+  }
+};
+
 }  // namespace
 
 void launch_chol_rinv(const double* G, int ldg, int p, double* Rinv, int ldr, int* deficient,
@@ -1229,16 +1267,15 @@ void launch_chol_rinv(const double* G, int ldg, int p, double* Rinv, int ldr, in
   // the column is treated as dependent: CholeskyQR2 reaches working
   // orthogonality only while cond(Y) stays well below 1/sqrt(eps).
   const double tol = 1e-10;
+  const CholArgs a{G, ldg, p, Rinv, ldr, deficient, info, pass, tol, near_tol};
   if (p <= 32) {
-    chol_rinv_kernel<32, 4, 4, true><<<1, 64, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol, near_tol);
+    emit<CholK<32, 4, 4, true>>(a, dim3(1), 0, st);
   } else if (p <= 64) {
-    chol_rinv_kernel<64, 4, 4, true><<<1, 256, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol, near_tol);
+    emit<CholK<64, 4, 4, true>>(a, dim3(1), 0, st);
   } else {
     // 128 registers a lane at 1024 threads: the steps stay rolled
-    chol_rinv_kernel<128, 4, 4, false><<<1, 1024, 0, st>>>(G, ldg, p, Rinv, ldr, deficient, info, pass, tol,
-                                                           near_tol);
+    emit<CholK<128, 4, 4, false>>(a, dim3(1), 0, st);
   }
-  PFX_HIP(hipGetLastError());
 }
 
 size_t eig_scratch_bytes(int p) {
@@ -1247,41 +1284,18 @@ size_t eig_scratch_bytes(int p) {
 
 void launch_eigh(const double* H, int ldh, int p, double* theta, double* Z, int ldz, int pad, pf_info* info,
                  int which, hipStream_t st, double* escratch, int* refined) {
-  static size_t ecur32 = 0, ecur64 = 0, scur64 = 0, scur128 = 0;
-  const int* skip = nullptr;
+  EigArgs a{H, ldh, p, theta, Z, ldz, pad, escratch, refined, info, which, 6, nullptr};
   if (refined) {
     // quadratically convergent refinement first; the dense solver below
     // returns at once when it succeeded
-    const int iters = 6;
-    if (p <= 32) {
-      const size_t e = (size_t)4 * 32 * 33 * 8;
-      ensure_lds((const void*)eig_refine_kernel<32, true>, e, ecur32);
-      eig_refine_kernel<32, true><<<1, 256, e, st>>>(H, ldh, p, theta, Z, ldz, escratch, refined, info, which,
-                                                     iters);
-    } else if (p <= 64) {
-      const size_t e = (size_t)4 * 64 * 65 * 8;
-      ensure_lds((const void*)eig_refine_kernel<64, true>, e, ecur64);
-      eig_refine_kernel<64, true><<<1, 256, e, st>>>(H, ldh, p, theta, Z, ldz, escratch, refined, info, which,
-                                                     iters);
-    } else {
-      eig_refine_kernel<128, false><<<1, 256, 0, st>>>(H, ldh, p, theta, Z, ldz, escratch, refined, info, which,
-                                                       iters);
-    }
-    PFX_HIP(hipGetLastError());
-    skip = refined;
+    if (p <= 32) emit<RefineK<32, true>>(a, dim3(1), (size_t)4 * 32 * 33 * 8, st);
+    else if (p <= 64) emit<RefineK<64, true>>(a, dim3(1), (size_t)4 * 64 * 65 * 8, st);
+    else emit<RefineK<128, false>>(a, dim3(1), 0, st);
+    a.skip = refined;
   }
-  if (p <= 32) {
-    syev_kernel<32><<<1, 256, (size_t)32 * 33 * 8, st>>>(H, ldh, p, theta, Z, ldz, pad, info, which, skip);
-  } else if (p <= 64) {
-    const size_t lds = (size_t)64 * 65 * 8;
-    ensure_lds((const void*)syev_kernel<64>, lds, scur64);
-    syev_kernel<64><<<1, 512, lds, st>>>(H, ldh, p, theta, Z, ldz, pad, info, which, skip);
-  } else {
-    const size_t lds = (size_t)128 * 129 * 8;
-    ensure_lds((const void*)syev_kernel<128>, lds, scur128);
-    syev_kernel<128><<<1, 1024, lds, st>>>(H, ldh, p, theta, Z, ldz, pad, info, which, skip);
-  }
-  PFX_HIP(hipGetLastError());
+  if (p <= 32) emit<SyevK<32>>(a, dim3(1), (size_t)32 * 33 * 8, st);
+  else if (p <= 64) emit<SyevK<64>>(a, dim3(1), (size_t)64 * 65 * 8, st);
+  else emit<SyevK<128>>(a, dim3(1), (size_t)128 * 129 * 8, st);
 }
 
 }  // namespace pfx

@@ -222,6 +222,22 @@ void enqueue_extraction(Plan* plan, const pf_mat& Xf, const pf_mat& Xr, const vo
 // both the start block and the output.
 void enqueue_extraction_in(const pf_desc& d, void* base, const pf_mat& Xf, const pf_mat& Xr, void* U_inout,
                            int64_t ldu, double* theta_out, pf_info* info_out, hipStream_t st);
+// Many independent PF_OP_SYM extractions with dense operators, enqueued on
+// st as grouped launches (each phase of every job in as few launches as its
+// kernel instances allow).  Jobs must use distinct plans.  Each job's
+// results are bitwise those of enqueue_extraction alone.  info_host, when
+// set, receives the job's pf_info (a mapped pinned address) at the end.
+struct ExtractionJob {
+  Plan* plan;
+  pf_desc desc;
+  pf_mat Xf, Xr;
+  const void* U_in; int64_t ldu_in;
+  void* U_out; int64_t ldu_out;
+  double* theta_out;
+  pf_info* info_out;
+  pf_info* info_host = nullptr;
+};
+void enqueue_extractions_grouped(int count, const ExtractionJob* jobs, hipStream_t st);
 // refresh the numeric fields (interval, flags) of a cached plan
 void plan_set_desc(Plan* P, const pf_desc& d);
 // plan-owned buffers (for sessions)

@@ -20,6 +20,7 @@
 // leaves span(rho(A) U) unchanged because the recurrence acts column by
 // column (section 2.1: rho(A) (U W) = (rho(A) U) W).
 #include "pf_internal.h"
+#include "group.h"
 
 #include <algorithm>
 #include <cmath>
@@ -502,6 +503,14 @@ void apply(Plan* P, const void* A1, const void* A2, const double* S, void* C1, i
   launch_apply(a, st);
 }
 
+// Phases of one extraction, in increasing order (grouped launches line up
+// the same phase of many extractions).  Filter product t of the whole
+// sequence (t = pass * degree + k) is phase kPhFilter + 10 t; the steps
+// after the first product of a pass follow it at + 5 ..; orthonormalisation
+// and Rayleigh-Ritz come after every product.
+constexpr int64_t kPhBegin = 0, kPhFilter = 100, kPhOrth = 1 << 30, kPhRR = kPhOrth + 100;
+int64_t ph_product(int64_t t) { return kPhFilter + 10 * t; }
+
 }  // namespace
 
 void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void* U_in, int64_t ldu_in,
@@ -515,9 +524,13 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
   const Elem tr = elem_of(Xr.dtype);
   const int64_t ld = P->n_pad;
 
+  if (current_recorder() && (d.op != PF_OP_SYM || op))
+    fail(PF_ERR_UNSUPPORTED, "grouped extractions take PF_OP_SYM with a dense operator only");
+  if ((int64_t)d.q * d.degree > 10000000) fail(PF_ERR_ARG, "degree * q is too large");
   const bool prof = prof_enabled();
   if (prof) prof_begin(PF_PROF_EXTRACT, st);
   const bool split = W == Elem::F32 && !(d.flags & PF_FLAG_NATIVE_F32) && !op;
+  set_phase(kPhBegin);
   // U_in into the work buffer (with the planes of Y_0 = U for the split
   // filter) and pf_info cleared, in one launch
   launch_begin_block(U_in, ldu_in, W, P->U, ld, P->n, P->p, P->n_pad, P->p_pad, split ? planes_of(P, P->U) : nullptr,
@@ -538,14 +551,19 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
     // the planes of Y_0 come with the copy of U; later passes start from
     // Y_d, whose planes the last step wrote
     // first product Z = A Y_0
+    const int64_t ph0 = ph_product((int64_t)pass * d.degree);
+    set_phase(ph0);
     filter_product(P, Xf, cur, P->Z, nullptr, nullptr, 1.0, 0.0, 0.0, false, st, op);
     const double a1 = 1.0 / (e * tau[1]), b1 = -c / (e * tau[1]);
     void* y_prev;
     void* y_cur;
+    set_phase(ph0 + 5);
     if (pass == 0 && !(d.flags & PF_FLAG_NO_PREROTATE)) {
       gram(P, cur, W, P->Z, W, P->G, st);
+      set_phase(ph0 + 6);
       launch_eigh(P->G, P->p_pad, P->p, P->theta_pre, P->Zeig, P->p_pad, P->p_pad, P->info, 0, st, P->Ework,
                   P->refined);
+      set_phase(ph0 + 7);
       apply(P, cur, P->Z, P->Zeig, P->Yb[0], ld, P->Yb[1], a1, b1, nullptr, nullptr, st);
       y_prev = P->Yb[0];
       y_cur = P->Yb[1];
@@ -555,6 +573,7 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
       y_prev = cur;
       y_cur = dst;
     }
+    set_phase(ph0 + 8);
     if (split && (d.degree > 1 || pass + 1 < d.q)) refresh_planes(P, y_cur, st);
     const bool cold = (d.flags & PF_FLAG_COLD) && pass == 0;
     if (y_prev == P->U && cold) {
@@ -571,6 +590,7 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
       const bool reorth = cold && (k + 1) % 2 == 0 && k + 1 < d.degree;
       // planes of Y_{k+1} feed the next product (or the next pass)
       const bool want = split && ((k + 1 < d.degree && !reorth) || (k + 1 == d.degree && pass + 1 < d.q));
+      set_phase(ph_product((int64_t)pass * d.degree + k));
       filter_product(P, Xf, y_cur, y_next, y_cur, y_prev, al, be, ga, want, st, op);
       y_prev = y_cur;
       y_cur = y_next;
@@ -592,17 +612,24 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
   }
 
   // CholeskyQR2 (section 2.1: orthonormalise the filtered block)
+  set_phase(kPhOrth);
   gram(P, cur, W, cur, W, P->G, st);
+  set_phase(kPhOrth + 1);
   launch_chol_rinv(P->G, P->p_pad, P->p, P->Rinv, P->p_pad, P->deficient, P->info, 1, st);
+  set_phase(kPhOrth + 2);
   apply(P, cur, nullptr, P->Rinv, P->Q1, ld, nullptr, 0.0, 0.0, P->deficient, nullptr, st);
+  set_phase(kPhOrth + 3);
   gram(P, P->Q1, W, P->Q1, W, P->G, st);
   // the second pass sees I + E, |E| ~ cond(Y) * eps of the work precision:
   // first order suffices once |E|^2 is below that precision
+  set_phase(kPhOrth + 4);
   launch_chol_rinv(P->G, P->p_pad, P->p, P->Rinv, P->p_pad, P->deficient, P->info, 2, st,
                    W == Elem::F64 ? 1e-8 : 3e-4);
+  set_phase(kPhOrth + 5);
   apply(P, P->Q1, nullptr, P->Rinv, P->Q, ld, nullptr, 0.0, 0.0, P->deficient, nullptr, st);
 
   // Rayleigh-Ritz in FP64 (eq. RR)
+  set_phase(kPhRR);
   if (d.op == PF_OP_GRAM) {
     // B = M Q (FP64), H = B^T B = Q^T (M^T M) Q: theta = sigma^2
     contract_into(P, rr_copy->data, rr_copy->ld, tr, P->Q, ld, W, P->n, P->m, P->B, P->m_pad, Elem::F64, nullptr,
@@ -616,12 +643,36 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
   } else {
     contract_into(P, Xr.data, Xr.ld, tr, P->Q, ld, W, P->n, P->n, P->W, ld, Elem::F64, nullptr, nullptr, ld, 1.0,
                   0.0, 0.0, true, st, PF_PROF_RR, -1);
+    set_phase(kPhRR + 1);
     gram(P, P->Q, W, P->W, Elem::F64, P->G, st);
   }
+  set_phase(kPhRR + 2);
   launch_eigh(P->G, P->p_pad, P->p, P->theta, P->Zeig, P->p_pad, P->p_pad, P->info, 1, st, P->Ework, P->refined);
   // Ritz vectors, with pf_info and theta copied out in the same launch
+  set_phase(kPhRR + 3);
   apply(P, P->Q, nullptr, P->Zeig, U_out, ldu_out, nullptr, 0.0, 0.0, nullptr, P->info, st, info_out, theta_out);
+  set_phase(kPhRR + 4);
   if (prof) prof_end(PF_PROF_EXTRACT, st);
+}
+
+void enqueue_extractions_grouped(int count, const ExtractionJob* jobs, hipStream_t st) {
+  for (int i = 0; i < count; ++i) {
+    if (jobs[i].desc.op != PF_OP_SYM) fail(PF_ERR_UNSUPPORTED, "grouped extractions take PF_OP_SYM only");
+    for (int j = 0; j < i; ++j)
+      if (jobs[j].plan == jobs[i].plan) fail(PF_ERR_ARG, "grouped extractions need a workspace each");
+  }
+  grouped_enqueue(
+      count,
+      [&](int i) {
+        const ExtractionJob& j = jobs[i];
+        plan_set_desc(j.plan, j.desc);
+        enqueue_extraction(j.plan, j.Xf, j.Xr, j.U_in, j.ldu_in, j.U_out, j.ldu_out, j.theta_out, j.info_out, st);
+        if (j.info_host) {
+          set_phase(kPhRR + 10);
+          launch_info_to_host(j.plan->info, j.info_host, st);
+        }
+      },
+      st);
 }
 
 }  // namespace pfx

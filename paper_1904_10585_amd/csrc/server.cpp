@@ -1,15 +1,27 @@
 // The serving loop of include/pf.h: admission by HBM footprint, continuous
-// launching of many sessions' steps over a pool of HIP streams, and HIP
-// graph replay of warm steps.
+// batching of many sessions' steps, and HIP graph replay of the sessions
+// that run on their own.
 //
 // One worker thread owns every HIP call on session state.  Caller threads
 // only queue work (open / submit / close) under the server mutex and read
 // finished-step events.  Per session at most one step is in flight: a step
-// starts from the V its predecessor wrote, so the next one is launched when
-// the previous one's event has completed; other sessions fill the GPU
-// meanwhile.  A finished step's status reaches the host through a mapped
-// pinned pf_info written by the last kernel of the step.
+// starts from the V its predecessor wrote, so a session is ready again when
+// its previous step's event has completed.  Every pass of the worker takes
+// all ready sessions on the symmetric operator and enqueues their steps as
+// one batch of grouped launches (each phase of the extraction -- a filter
+// product, a Gram matrix, a Cholesky factor, a p x p eigensolve, a block
+// apply -- one launch per kernel instance for the whole batch); steps that
+// arrive while batches run form the next batch, on the next stream.  Other
+// sessions (the Gram operator) run their own steps, warm steps as graph
+// replays.  A finished step's status reaches the host through a mapped
+// pinned pf_info written by the last launch of the step.
+//
+// Device memory of closed sessions is kept for sessions of the same shape
+// (a slot: workspace, block, theta, pf_info, event, pinned record) and only
+// freed when the budget needs the room, so opening and closing sessions
+// does not synchronise the device.
 #include "pf_internal.h"
+#include "group.h"
 
 #include <chrono>
 #include <condition_variable>
@@ -19,6 +31,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 namespace pfx {
@@ -46,6 +59,19 @@ struct InFlight {
   bool graph;
 };
 
+// Device resources of a session, recycled across sessions of one layout.
+struct Slot {
+  SessionCore* core = nullptr;
+  hipEvent_t done = nullptr;
+  pf_info* host_info = nullptr;     // mapped pinned: host address
+  pf_info* host_info_dev = nullptr; // the same memory as the device sees it
+  size_t bytes = 0;                 // device bytes held
+};
+
+// what a slot's layout depends on
+using SlotKey = std::tuple<int64_t, int64_t, int, int, int>;
+SlotKey slot_key(const pf_desc& d) { return SlotKey{d.n, d.op == PF_OP_GRAM ? d.m : 0, d.p, (int)d.work, (int)d.op}; }
+
 struct SrvSession {
   int32_t id = 0;
   pf_desc desc{};
@@ -55,11 +81,8 @@ struct SrvSession {
   const void* U0 = nullptr;
   int64_t ldu0 = 0;
   uint64_t seed = 0;
-  SessionCore* core = nullptr;
+  Slot slot;
   hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;
-  pf_info* host_info = nullptr;     // mapped pinned: host address
-  pf_info* host_info_dev = nullptr; // the same memory as the device sees it
   std::deque<Request> pending;
   bool busy = false;
   InFlight cur{};
@@ -83,6 +106,8 @@ struct pf_server {
   std::deque<pf_server_event> events;
   size_t used = 0;
   int active = 0;
+  std::multimap<SlotKey, Slot> pool;   // slots of closed sessions
+  size_t pooled = 0;
   int32_t next_id = 1;
   std::vector<hipStream_t> streams;
   int next_stream = 0;
@@ -93,26 +118,76 @@ struct pf_server {
 
 namespace {
 
+void free_slot(Slot& t) {
+  if (t.done) (void)hipEventDestroy(t.done);
+  if (t.host_info) (void)hipHostFree(t.host_info);
+  session_destroy(t.core);
+  t = Slot{};
+}
+
+// Close: the session is drained (no step queued or running), so its slot
+// goes back to the pool as it is; no HIP call.
 void free_session(pf_server* S, SrvSession* s) {
   if (s->exec) (void)hipGraphExecDestroy(s->exec);
-  if (s->done) (void)hipEventDestroy(s->done);
-  if (s->host_info) (void)hipHostFree(s->host_info);
-  session_destroy(s->core);
   if (s->resident) {
     S->used -= s->footprint;
     S->active--;
+    S->pooled += s->slot.bytes;
+    S->pool.emplace(slot_key(s->desc), s->slot);
+    s->slot = Slot{};
   }
   delete s;
 }
 
-// Admit s: allocate and initialise it on its stream (no device-wide sync).
+// Free pooled slots until `need` more bytes fit the budget (slots of other
+// shapes first; the mutex is released while the device memory is freed).
+void make_room(pf_server* S, std::unique_lock<std::mutex>& lk, size_t need) {
+  while (!S->pool.empty() && S->used + S->pooled + need > S->cfg.hbm_budget) {
+    auto it = S->pool.begin();
+    Slot t = it->second;
+    S->pool.erase(it);
+    S->pooled -= t.bytes;
+    lk.unlock();
+    free_slot(t);
+    lk.lock();
+  }
+}
+
+// Admit s on its stream: a pooled slot of its shape when there is one
+// (the start block re-initialised in place), a new one otherwise.  The
+// slot's event marks the end of the initialisation.
 void admit(pf_server* S, SrvSession* s) {
   s->stream = S->streams[S->next_stream];
   S->next_stream = (S->next_stream + 1) % (int)S->streams.size();
-  PFX_HIP(hipEventCreateWithFlags(&s->done, hipEventDisableTiming));
-  PFX_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->host_info), sizeof(pf_info), hipHostMallocMapped));
-  PFX_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&s->host_info_dev), s->host_info, 0));
-  s->core = session_create(s->desc, s->U0, s->ldu0, s->seed, s->stream, false);
+  auto it = S->pool.find(slot_key(s->desc));
+  if (it != S->pool.end()) {
+    s->slot = it->second;
+    S->pool.erase(it);
+    S->pooled -= s->slot.bytes;
+    SessionCore* c = s->slot.core;
+    c->desc = s->desc;
+    c->steps = 0;
+    plan_set_desc(c->plan, s->desc);
+    const Elem W = s->desc.work == PF_F64 ? Elem::F64 : Elem::F32;
+    // the previous user's last step has completed (its session was drained)
+    if (s->U0) launch_copy_block(s->U0, s->ldu0, W, c->U, c->ldu, W, s->desc.n, s->desc.p, s->desc.n, s->desc.p,
+                                 s->stream);
+    else launch_normal_block(c->U, c->ldu, W, s->desc.n, s->desc.p, s->seed, s->stream);
+  } else {
+    Slot t;
+    try {
+      PFX_HIP(hipEventCreateWithFlags(&t.done, hipEventDisableTiming));
+      PFX_HIP(hipHostMalloc(reinterpret_cast<void**>(&t.host_info), sizeof(pf_info), hipHostMallocMapped));
+      PFX_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&t.host_info_dev), t.host_info, 0));
+      t.core = session_create(s->desc, s->U0, s->ldu0, s->seed, s->stream, false);
+      t.bytes = session_bytes(s->desc);
+    } catch (...) {
+      free_slot(t);
+      throw;
+    }
+    s->slot = t;
+  }
+  PFX_HIP(hipEventRecord(s->slot.done, s->stream));
   s->resident = true;
   S->used += s->footprint;
   S->active++;
@@ -126,7 +201,7 @@ void launch_step(pf_server* S, SrvSession* s, const Request& r, int64_t step);
 void launch(pf_server* S, SrvSession* s) {
   Request r = s->pending.front();
   s->pending.pop_front();
-  const int64_t step = s->core->steps;
+  const int64_t step = s->slot.core->steps;
   try {
     launch_step(S, s, r, step);
   } catch (const Error& e) {
@@ -148,10 +223,10 @@ void launch_step(pf_server* S, SrvSession* s, const Request& r, int64_t step) {
     hipGraph_t g = nullptr;
     try {
       pf_desc d = s->desc;                          // warm: no cold-start flag
-      plan_set_desc(s->core->plan, d);
-      enqueue_extraction(s->core->plan, r.xf, r.xr, s->core->U, s->core->ldu, s->core->U, s->core->ldu,
-                         s->core->theta, s->core->info, s->stream);
-      launch_info_to_host(s->core->info, s->host_info_dev, s->stream);
+      SessionCore* c = s->slot.core;
+      plan_set_desc(c->plan, d);
+      enqueue_extraction(c->plan, r.xf, r.xr, c->U, c->ldu, c->U, c->ldu, c->theta, c->info, s->stream);
+      launch_info_to_host(c->info, s->slot.host_info_dev, s->stream);
     } catch (...) {
       (void)hipStreamEndCapture(s->stream, &g);
       if (g) (void)hipGraphDestroy(g);
@@ -167,13 +242,13 @@ void launch_step(pf_server* S, SrvSession* s, const Request& r, int64_t step) {
   }
   if (graph) {
     PFX_HIP(hipGraphLaunch(s->exec, s->stream));
-    s->core->steps++;
+    s->slot.core->steps++;
     S->stats.graph_launches++;
   } else {
-    session_enqueue_step(s->core, r.xf, r.xr, s->stream);
-    launch_info_to_host(s->core->info, s->host_info_dev, s->stream);
+    session_enqueue_step(s->slot.core, r.xf, r.xr, s->stream);
+    launch_info_to_host(s->slot.core->info, s->slot.host_info_dev, s->stream);
   }
-  PFX_HIP(hipEventRecord(s->done, s->stream));
+  PFX_HIP(hipEventRecord(s->slot.done, s->stream));
   s->busy = true;
   s->cur = InFlight{r, step, now_ns(), graph};
   S->stats.launched++;
@@ -196,9 +271,66 @@ void finish(pf_server* S, SrvSession* s, int32_t status, int32_t n_pos) {
 }
 
 void fail_request(pf_server* S, SrvSession* s, const Request& r, int32_t status) {
-  s->cur = InFlight{r, s->core ? s->core->steps : 0, now_ns(), false};
+  s->cur = InFlight{r, s->slot.core ? s->slot.core->steps : 0, now_ns(), false};
   finish(S, s, status, 0);
 }
+
+// One batch: the next step of every session in `members` (ready, on the
+// symmetric operator), as grouped launches on the next stream.  Each
+// member's stream order with its earlier work (initialisation, previous
+// step) comes from its slot event.
+void launch_batch(pf_server* S, const std::vector<SrvSession*>& members) {
+  hipStream_t B = S->streams[S->next_stream];
+  S->next_stream = (S->next_stream + 1) % (int)S->streams.size();
+  std::vector<ExtractionJob> jobs(members.size());
+  std::vector<Request> reqs(members.size());
+  for (size_t i = 0; i < members.size(); ++i) {
+    SrvSession* m = members[i];
+    reqs[i] = m->pending.front();
+    SessionCore* c = m->slot.core;
+    ExtractionJob& j = jobs[i];
+    j.plan = c->plan;
+    j.desc = m->desc;
+    if (c->steps == 0) j.desc.flags |= PF_FLAG_COLD;     // the first step starts from U0
+    j.Xf = reqs[i].xf;
+    j.Xr = reqs[i].xr;
+    j.U_in = c->U;
+    j.ldu_in = c->ldu;
+    j.U_out = c->U;
+    j.ldu_out = c->ldu;
+    j.theta_out = c->theta;
+    j.info_out = c->info;
+    j.info_host = m->slot.host_info_dev;
+  }
+  try {
+    for (SrvSession* m : members) PFX_HIP(hipStreamWaitEvent(B, m->slot.done, 0));
+    enqueue_extractions_grouped((int)jobs.size(), jobs.data(), B);
+  } catch (const Error& e) {
+    for (size_t i = 0; i < members.size(); ++i) {
+      members[i]->pending.pop_front();
+      fail_request(S, members[i], reqs[i], e.status);
+    }
+    return;
+  }
+  const int64_t t = now_ns();
+  for (size_t i = 0; i < members.size(); ++i) {
+    SrvSession* m = members[i];
+    m->pending.pop_front();
+    const hipError_t e = hipEventRecord(m->slot.done, B);
+    m->cur = InFlight{reqs[i], m->slot.core->steps, t, false};
+    m->slot.core->steps++;
+    if (e != hipSuccess) {
+      finish(S, m, PF_ERR_DEVICE, 0);
+      continue;
+    }
+    m->busy = true;
+    S->stats.launched++;
+  }
+  S->stats.batches++;
+  S->stats.batched_steps += (int64_t)members.size();
+}
+
+constexpr size_t kMaxBatch = 256;
 
 void worker_loop(pf_server* S) {
   (void)hipSetDevice(S->device);
@@ -209,12 +341,12 @@ void worker_loop(pf_server* S) {
     for (auto& kv : S->sessions) {
       SrvSession* s = kv.second;
       if (!s->busy) continue;
-      const hipError_t q = hipEventQuery(s->done);
+      const hipError_t q = hipEventQuery(s->slot.done);
       if (q == hipErrorNotReady) continue;
       if (q != hipSuccess) {
         finish(S, s, PF_ERR_DEVICE, 0);
       } else {
-        const volatile pf_info* hi = s->host_info;
+        const volatile pf_info* hi = s->slot.host_info;
         finish(S, s, hi->status, hi->n_pos);
       }
       progress = true;
@@ -238,6 +370,7 @@ void worker_loop(pf_server* S) {
     while (!S->waitq.empty()) {
       SrvSession* s = S->sessions[S->waitq.front()];
       if (S->used + s->footprint > S->cfg.hbm_budget || S->active >= S->cfg.max_active) break;
+      if (S->pool.find(slot_key(s->desc)) == S->pool.end()) make_room(S, lk, s->footprint);
       S->waitq.pop_front();
       try {
         admit(S, s);
@@ -251,13 +384,25 @@ void worker_loop(pf_server* S) {
       }
       progress = true;
     }
-    // launches
+    // launches: the ready sessions on the symmetric operator as one batch
+    // of grouped launches, the others one by one
+    std::vector<SrvSession*> batch;
+    const bool group = !(S->cfg.flags & PF_SERVER_NO_GROUPING);
     for (auto& kv : S->sessions) {
       SrvSession* s = kv.second;
       if (!s->resident || s->busy || s->pending.empty()) continue;
-      launch(S, s);
+      if (group && s->desc.op == PF_OP_SYM) {
+        batch.push_back(s);
+        if (batch.size() == kMaxBatch) {
+          launch_batch(S, batch);
+          batch.clear();
+        }
+      } else {
+        launch(S, s);
+      }
       progress = true;
     }
+    if (!batch.empty()) launch_batch(S, batch);
     if (!S->events.empty()) S->done_cv.notify_all();
     if (S->stop) {
       bool idle = S->waitq.empty();
@@ -274,6 +419,9 @@ void worker_loop(pf_server* S) {
   }
   for (auto& kv : S->sessions) free_session(S, kv.second);
   S->sessions.clear();
+  for (auto& kv : S->pool) free_slot(kv.second);
+  S->pool.clear();
+  S->pooled = 0;
   S->waitq.clear();
   S->done_cv.notify_all();
 }
@@ -293,7 +441,8 @@ pf_status pf_server_create(const pf_server_config* cfg, pf_server** out) {
     if (cfg->struct_size != sizeof(pf_server_config)) fail(PF_ERR_ARG, "pf_server_config.struct_size mismatch");
     if (cfg->hbm_budget == 0) fail(PF_ERR_ARG, "pf_server_config.hbm_budget must be > 0");
     if (cfg->max_active < 0 || cfg->streams < 0 || cfg->streams > 64) fail(PF_ERR_ARG, "bad server limits");
-    if (cfg->flags & ~PF_SERVER_NO_GRAPHS) fail(PF_ERR_ARG, "unknown bits in pf_server_config.flags");
+    if (cfg->flags & ~(PF_SERVER_NO_GRAPHS | PF_SERVER_NO_GROUPING))
+      fail(PF_ERR_ARG, "unknown bits in pf_server_config.flags");
     pf_server* S = new pf_server();
     S->cfg = *cfg;
     if (S->cfg.max_active == 0) S->cfg.max_active = 64;
@@ -378,12 +527,12 @@ pf_status pf_server_result(pf_server* S, int32_t session, pf_result* out) {
     if (it == S->sessions.end() || !it->second->resident) fail(PF_ERR_ARG, "session is not resident");
     SrvSession* s = it->second;
     if (s->busy || !s->pending.empty()) fail(PF_ERR_BUSY, "session has steps queued or running");
-    out->status = s->host_info->status;
-    out->n_pos = s->host_info->n_pos;
-    out->theta = s->core->theta;
-    out->V = s->core->U;
-    out->ldv = s->core->ldu;
-    out->info = s->core->info;
+    out->status = s->slot.host_info->status;
+    out->n_pos = s->slot.host_info->n_pos;
+    out->theta = s->slot.core->theta;
+    out->V = s->slot.core->U;
+    out->ldv = s->slot.core->ldu;
+    out->info = s->slot.core->info;
   });
 }
 

@@ -97,6 +97,7 @@ class PfPfamResult(ctypes.Structure):
 
 
 PF_SERVER_NO_GRAPHS = 0x1
+PF_SERVER_NO_GROUPING = 0x2
 
 
 class PfServerConfig(ctypes.Structure):
@@ -113,7 +114,7 @@ class PfServerEvent(ctypes.Structure):
 class PfServerStats(ctypes.Structure):
     _fields_ = [("active", ctypes.c_int32), ("waiting", ctypes.c_int32), ("used_bytes", ctypes.c_size_t),
                 ("launched", ctypes.c_int64), ("completed", ctypes.c_int64), ("graph_launches", ctypes.c_int64),
-                ("captures", ctypes.c_int64)]
+                ("captures", ctypes.c_int64), ("batches", ctypes.c_int64), ("batched_steps", ctypes.c_int64)]
 
 
 class PfError(RuntimeError):

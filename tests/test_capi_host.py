@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version_and_strings():
-    assert pf.LIB.pf_abi_version() == 1
+    assert pf.LIB.pf_abi_version() == 2
     for s in range(9):
         assert pf.status_string(s).startswith("PF_")
     assert pf.status_string(99) == "unknown pf_status"

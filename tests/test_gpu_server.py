@@ -110,28 +110,49 @@ def run_server(cases, steps, flags=0, streams=0):
 CASES = [(1000, 16, 6, 1), (777, 32, 8, 2), (2048, 48, 10, 3), (300, 8, 4, 4), (1536, 96, 6, 5)]
 
 
+def test_server_batches_match_eager_sessions():
+    """Sessions of different n, p and degree served together: every pass of
+    the worker runs their steps as one batch of grouped launches, and each
+    session's steps are bitwise the eager session's."""
+    cases = [Case(*c) for c in CASES]
+    steps = 4
+    eager = run_eager(cases, steps)
+    served, graphs, stats = run_server(cases, steps)
+    for c in cases:
+        assert graphs[c.idx] == [0] * steps, graphs[c.idx]
+        for k in range(steps):
+            np.testing.assert_array_equal(served[c.idx][k][0], eager[c.idx][k][0], err_msg=f"theta {c.idx} {k}")
+            np.testing.assert_array_equal(served[c.idx][k][1], eager[c.idx][k][1], err_msg=f"V {c.idx} {k}")
+    # all ready sessions of a pass form one batch (lockstep submission here)
+    assert stats.batched_steps == len(cases) * steps and stats.batches < len(cases) * steps, (stats.batches,
+                                                                                       stats.batched_steps)
+
+
 def test_server_graphs_match_eager_sessions():
-    """Warm steps replayed from captured graphs, with eager work (the X
-    perturbation, reads of every result) between replays, are bitwise the
-    eager session's steps."""
+    """Without batching, warm steps replayed from captured graphs, with
+    eager work (the X perturbation, reads of every result) between replays,
+    are bitwise the eager session's steps."""
+    pf = pf_module()
     cases = [Case(*c) for c in CASES[:3]]
     steps = 5
     eager = run_eager(cases, steps)
-    served, graphs, stats = run_server(cases, steps)
+    served, graphs, stats = run_server(cases, steps, flags=pf.PF_SERVER_NO_GROUPING)
     for c in cases:
         assert graphs[c.idx] == [0] + [1] * (steps - 1), graphs[c.idx]
         for k in range(steps):
             np.testing.assert_array_equal(served[c.idx][k][0], eager[c.idx][k][0], err_msg=f"theta {c.idx} {k}")
             np.testing.assert_array_equal(served[c.idx][k][1], eager[c.idx][k][1], err_msg=f"V {c.idx} {k}")
     assert stats.captures == len(cases) and stats.graph_launches == len(cases) * (steps - 1)
+    assert stats.batches == 0
 
 
 def test_server_alone_equals_mix():
-    """A session's results are the same alone and among four others running
-    concurrently on the server's streams."""
+    """A session's results are the same alone and batched with four others
+    of different n, p and degree."""
     steps = 4
     alone, _, _ = run_server([Case(*CASES[0])], steps)
-    mix, _, _ = run_server([Case(*c) for c in CASES], steps)
+    mix, _, st = run_server([Case(*c) for c in CASES], steps)
+    assert st.batches > 0
     idx = CASES[0][3]
     for k in range(steps):
         np.testing.assert_array_equal(alone[idx][k][0], mix[idx][k][0])
@@ -141,11 +162,53 @@ def test_server_alone_equals_mix():
 def test_server_without_graphs_matches():
     pf = pf_module()
     cases = [Case(*CASES[1])]
-    a, ga, _ = run_server(cases, 3)
-    b, gb, _ = run_server([Case(*CASES[1])], 3, flags=pf.PF_SERVER_NO_GRAPHS)
+    a, ga, _ = run_server(cases, 3, flags=pf.PF_SERVER_NO_GROUPING)
+    b, gb, _ = run_server([Case(*CASES[1])], 3, flags=pf.PF_SERVER_NO_GRAPHS | pf.PF_SERVER_NO_GROUPING)
     assert gb[CASES[1][3]] == [0, 0, 0]
     for k in range(3):
         np.testing.assert_array_equal(a[CASES[1][3]][k][1], b[CASES[1][3]][k][1])
+
+
+def test_served_batch_matches_oracle():
+    """Served, batched steps against the FP64 oracle fed the same U_in (the
+    previous served V) and the same X_k: FP32 tolerance on warm steps."""
+    import oracle
+    pf = pf_module()
+    cases = [Case(*CASES[0]), Case(*CASES[1]), Case(*CASES[3])]
+    steps = 4
+    srv = pf.pf_server_create(16 << 30)
+    try:
+        Xs = {c.idx: c.fresh_x() for c in cases}
+        ids = {c.idx: pf.pf_server_open(srv, c.desc(), seed=c.idx) for c in cases}
+        U_prev = {}
+        for k in range(steps):
+            torch.cuda.synchronize()
+            Xh = {c.idx: Xs[c.idx].cpu().double().numpy() for c in cases}
+            for c in cases:
+                pf.pf_server_submit(srv, ids[c.idx], Xs[c.idx], Xs[c.idx], tag=k)
+            got = 0
+            while got < len(cases):
+                for ev in pf.pf_server_poll(srv, timeout_s=5.0):
+                    assert ev.status == pf.PF_OK
+                    got += 1
+            for c in cases:
+                th, V = read_result(pf, pf.pf_server_result(srv, ids[c.idx]), c.n, c.p)
+                V = V.astype(np.float64)
+                if k >= 2:
+                    ref = oracle.extract(Xh[c.idx], Xh[c.idx], U_prev[c.idx], c.d, c.a, c.b)
+                    r = max(1, c.p // 2)
+                    rel = oracle.ritz_rel_err(th, ref["theta"], r)
+                    Qg, _ = np.linalg.qr(V[:, :r])
+                    sin = oracle.sin_theta(Qg, ref["V"][:, :r])
+                    print(f"served session {c.idx} step {k}: rel {rel:.2e} sin {sin:.2e}")
+                    assert rel <= 1e-5 and sin <= 1e-4, (c.idx, k, rel, sin)
+                U_prev[c.idx] = V
+            for c in cases:
+                if k + 1 < steps:
+                    c.perturb(Xs[c.idx], k + 1)
+        assert pf.pf_server_stats(srv).batches > 0
+    finally:
+        pf.pf_server_destroy(srv)
 
 
 def test_server_admission_within_budget():
