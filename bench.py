@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--load", type=float, default=0.7, help="serving: arrival rate / saturated session rate")
     ap.add_argument("--more-loads", default="0.5,0.9",
                     help="serving: further Poisson loads reported beside --load (comma-separated, '' for none)")
+    ap.add_argument("--max-batches", type=int, default=0,
+                    help="serving: batches of grouped launches in flight at most (0 = the library's default)")
     ap.add_argument("--no-grouping", action="store_true",
                     help="serving: every session runs its own steps (no batches of grouped launches)")
     ap.add_argument("--hbm-budget-gb", type=float, default=160.0, help="serving: HBM budget of the server")
@@ -1002,7 +1004,8 @@ def serve_main(args):
 
     def run(arrivals, label):
         srv = pf.pf_server_create(int(args.hbm_budget_gb * (1 << 30)), max_active=256, streams=8,
-                                  flags=pf.PF_SERVER_NO_GROUPING if args.no_grouping else 0)
+                                  flags=pf.PF_SERVER_NO_GROUPING if args.no_grouping else 0,
+                                  max_batches=args.max_batches)
         Xs, ids, left, lat, step_bytes = {}, {}, {}, [], 0.0
         pending = sorted(range(nS), key=lambda i: arrivals[i])
         t_start = time.perf_counter()

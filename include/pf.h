@@ -278,8 +278,10 @@ pf_status pf_session_close(pf_session* s);
  *    every ready resident session (its previous step done) on PF_OP_SYM into
  *    one batch of grouped launches: each phase of the extraction is one
  *    launch per kernel instance for the whole batch, whatever the sessions'
- *    n, p, degree and interval; steps requested while batches run form the
- *    next batch on the next of the worker's streams, so batches overlap.
+ *    n, p, degree and interval; steps requested while max_batches batches
+ *    run wait and form the next batch (on the next of the worker's
+ *    streams) when one finishes, so batches stay large under load and
+ *    overlap on the device.
  *  - HIP graphs: sessions on PF_OP_GRAM run their own steps; a session's
  *    first step runs eagerly (cold start); its warm step is captured once
  *    as a graph and replayed for later steps whose operator buffers are the
@@ -307,6 +309,9 @@ typedef struct pf_server_config {
   size_t hbm_budget;      /* bytes sessions may hold together (> 0) */
   int32_t max_active;     /* resident sessions at most (0 = 64) */
   int32_t streams;        /* HIP streams of the worker (0 = 8, at most 64) */
+  int32_t max_batches;    /* batches in flight at most (0 = 4): ready steps
+                             wait for the next batch while this many run */
+  int32_t reserved;       /* 0 */
 } pf_server_config;
 
 typedef struct pf_server_event {

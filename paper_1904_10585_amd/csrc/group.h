@@ -7,9 +7,10 @@
 //   static constexpr int kThreads, kMinWaves;  block size, launch bounds
 //   static __device__ void body(const Args&, uint3 bid);
 // and is only ever launched through grouped_kernel<K, N>: a single problem
-// is a group of one.  Every problem therefore runs the same machine code
-// whether it is launched alone or beside others, and its results are
-// bitwise the same either way.
+// is a group of one.  A problem runs the same kernel body whether it is
+// launched alone or beside others (the instances for one member and for
+// many differ only in the size of their argument block), and its results
+// are bitwise the same either way (checked by the batch and serving tests).
 //
 // Members' block ranges are laid end to end, each starting at a multiple of
 // 8 (the XCD count, so a member's block b lands on XCD b mod 8 as it would
@@ -88,10 +89,11 @@ inline void set_phase(int64_t phase) {
   }
 }
 
-template <typename K>
-void flush_group(LaunchRec* const* recs, int count, hipStream_t st) {
+// Launches of at most N members each (N = 1: a single problem, with a
+// kernel-argument block of one record; larger blocks cost launch time).
+template <typename K, int N>
+void flush_n(LaunchRec* const* recs, int count, hipStream_t st) {
   using A = typename K::Args;
-  constexpr int N = group_n<A>();
   static_assert(sizeof(GroupArgs<A, N>) <= kGroupArgBytes, "group record too large");
   static size_t cur_lds = 0;
   for (int c0 = 0; c0 < count; c0 += N) {
@@ -117,6 +119,12 @@ void flush_group(LaunchRec* const* recs, int count, hipStream_t st) {
     grouped_kernel<K, N><<<dim3((unsigned)total), dim3(K::kThreads), lds, st>>>(g);
     PFX_HIP(hipGetLastError());
   }
+}
+
+template <typename K>
+void flush_group(LaunchRec* const* recs, int count, hipStream_t st) {
+  if (count == 1) flush_n<K, 1>(recs, 1, st);
+  else flush_n<K, group_n<typename K::Args>()>(recs, count, st);
 }
 
 // Launch kernel K on one problem, or record the launch when a recorder is

@@ -111,6 +111,8 @@ struct pf_server {
   int32_t next_id = 1;
   std::vector<hipStream_t> streams;
   int next_stream = 0;
+  std::vector<hipEvent_t> batch_running;   // one event per batch in flight
+  std::vector<hipEvent_t> batch_free;
   bool stop = false;
   pf_server_stats stats{};
   std::thread worker;
@@ -328,6 +330,31 @@ void launch_batch(pf_server* S, const std::vector<SrvSession*>& members) {
   }
   S->stats.batches++;
   S->stats.batched_steps += (int64_t)members.size();
+  hipEvent_t be = nullptr;
+  if (!S->batch_free.empty()) {
+    be = S->batch_free.back();
+    S->batch_free.pop_back();
+  } else if (hipEventCreateWithFlags(&be, hipEventDisableTiming) != hipSuccess) {
+    be = nullptr;
+  }
+  if (be) {
+    if (hipEventRecord(be, B) == hipSuccess) S->batch_running.push_back(be);
+    else S->batch_free.push_back(be);
+  }
+}
+
+// Batches still running (finished ones leave the list).
+int batches_in_flight(pf_server* S) {
+  for (size_t i = 0; i < S->batch_running.size();) {
+    if (hipEventQuery(S->batch_running[i]) != hipErrorNotReady) {
+      S->batch_free.push_back(S->batch_running[i]);
+      S->batch_running[i] = S->batch_running.back();
+      S->batch_running.pop_back();
+    } else {
+      ++i;
+    }
+  }
+  return (int)S->batch_running.size();
 }
 
 constexpr size_t kMaxBatch = 256;
@@ -385,13 +412,16 @@ void worker_loop(pf_server* S) {
       progress = true;
     }
     // launches: the ready sessions on the symmetric operator as one batch
-    // of grouped launches, the others one by one
+    // of grouped launches while fewer than max_batches batches run (they
+    // wait for the next batch otherwise), the others one by one
     std::vector<SrvSession*> batch;
     const bool group = !(S->cfg.flags & PF_SERVER_NO_GROUPING);
+    const bool room = group && batches_in_flight(S) < S->cfg.max_batches;
     for (auto& kv : S->sessions) {
       SrvSession* s = kv.second;
       if (!s->resident || s->busy || s->pending.empty()) continue;
       if (group && s->desc.op == PF_OP_SYM) {
+        if (!room) continue;
         batch.push_back(s);
         if (batch.size() == kMaxBatch) {
           launch_batch(S, batch);
@@ -417,6 +447,10 @@ void worker_loop(pf_server* S) {
       else S->cv.wait_for(lk, std::chrono::milliseconds(5));
     }
   }
+  for (hipEvent_t e : S->batch_running) (void)hipEventDestroy(e);
+  for (hipEvent_t e : S->batch_free) (void)hipEventDestroy(e);
+  S->batch_running.clear();
+  S->batch_free.clear();
   for (auto& kv : S->sessions) free_session(S, kv.second);
   S->sessions.clear();
   for (auto& kv : S->pool) free_slot(kv.second);
@@ -440,13 +474,16 @@ pf_status pf_server_create(const pf_server_config* cfg, pf_server** out) {
     if (!cfg || !out) fail(PF_ERR_ARG, "NULL argument");
     if (cfg->struct_size != sizeof(pf_server_config)) fail(PF_ERR_ARG, "pf_server_config.struct_size mismatch");
     if (cfg->hbm_budget == 0) fail(PF_ERR_ARG, "pf_server_config.hbm_budget must be > 0");
-    if (cfg->max_active < 0 || cfg->streams < 0 || cfg->streams > 64) fail(PF_ERR_ARG, "bad server limits");
+    if (cfg->max_active < 0 || cfg->streams < 0 || cfg->streams > 64 || cfg->max_batches < 0)
+      fail(PF_ERR_ARG, "bad server limits");
+    if (cfg->reserved != 0) fail(PF_ERR_ARG, "pf_server_config.reserved must be 0");
     if (cfg->flags & ~(PF_SERVER_NO_GRAPHS | PF_SERVER_NO_GROUPING))
       fail(PF_ERR_ARG, "unknown bits in pf_server_config.flags");
     pf_server* S = new pf_server();
     S->cfg = *cfg;
     if (S->cfg.max_active == 0) S->cfg.max_active = 64;
     if (S->cfg.streams == 0) S->cfg.streams = 8;
+    if (S->cfg.max_batches == 0) S->cfg.max_batches = 4;
     try {
       PFX_HIP(hipGetDevice(&S->device));
       for (int i = 0; i < S->cfg.streams; ++i) {

@@ -102,7 +102,8 @@ PF_SERVER_NO_GROUPING = 0x2
 
 class PfServerConfig(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("hbm_budget", ctypes.c_size_t),
-                ("max_active", ctypes.c_int32), ("streams", ctypes.c_int32)]
+                ("max_active", ctypes.c_int32), ("streams", ctypes.c_int32), ("max_batches", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class PfServerEvent(ctypes.Structure):
@@ -286,10 +287,11 @@ def pf_session_close(h):
     _check(LIB.pf_session_close(h))
 
 
-def pf_server_create(hbm_budget, max_active=0, streams=0, flags=0):
+def pf_server_create(hbm_budget, max_active=0, streams=0, flags=0, max_batches=0):
     c = PfServerConfig()
     c.struct_size = ctypes.sizeof(PfServerConfig)
     c.flags, c.hbm_budget, c.max_active, c.streams = flags, int(hbm_budget), max_active, streams
+    c.max_batches, c.reserved = max_batches, 0
     h = ctypes.c_void_p()
     _check(LIB.pf_server_create(ctypes.byref(c), ctypes.byref(h)))
     return h
