@@ -93,6 +93,23 @@ typedef enum pf_op {
                                      transposed copies of M instead of
                                      rebuilding them (a fixed M over a chain
                                      of extractions) */
+#define PF_FLAG_REORTH 0x20u      /* dynamic-range control on warm steps: every
+                                     fourth product the pair (Y_k, Y_{k-1}) is
+                                     multiplied by the same R^{-1} from a
+                                     CholeskyQR2 of Y_k (as on cold steps,
+                                     where it happens every second product).
+                                     With the columns ordered by descending
+                                     Ritz value this removes from each column
+                                     the components along the faster-growing
+                                     directions before they swamp it: an FP32
+                                     filter then keeps the smallest wanted
+                                     directions when the growth ratio between
+                                     the largest and the smallest wanted
+                                     eigenvalue is far beyond single
+                                     precision (a damping interval at the
+                                     bulk's edge).  Same span; costs two Gram
+                                     products, Cholesky factors and applies
+                                     per re-orthonormalisation. */
 #define PF_FLAG_COLD 0x4u         /* the start block is not a warm start:
                                      every second step the pair (Y_k, Y_{k-1})
                                      is multiplied by the same R^{-1} from a

@@ -194,7 +194,7 @@ void plan_validate(const pf_desc& d, const pf_mat* Xf, const pf_mat* Xr) {
   if ((d.flags & PF_FLAG_SCALED) && !(std::isfinite(d.spec_ub) && d.spec_ub > d.b))
     fail(PF_ERR_ARG, "PF_FLAG_SCALED needs a finite spec_ub > b");
   if (d.flags & ~(PF_FLAG_NO_PREROTATE | PF_FLAG_SCALED | PF_FLAG_COLD | PF_FLAG_NATIVE_F32 |
-                  PF_FLAG_OPERATOR_UNCHANGED))
+                  PF_FLAG_OPERATOR_UNCHANGED | PF_FLAG_REORTH))
     fail(PF_ERR_ARG, "unknown bits in pf_desc.flags");
   if (d.reserved != 0) fail(PF_ERR_ARG, "pf_desc.reserved must be 0");
   if (Xf || Xr) {
@@ -575,7 +575,10 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
     }
     set_phase(ph0 + 8);
     if (split && (d.degree > 1 || pass + 1 < d.q)) refresh_planes(P, y_cur, st);
-    const bool cold = (d.flags & PF_FLAG_COLD) && pass == 0;
+    // re-orthonormalisation of the recurrence pair every `every` products:
+    // a cold start (every second one) or dynamic-range control on warm steps
+    const int every = ((d.flags & PF_FLAG_COLD) && pass == 0) ? 2 : (d.flags & PF_FLAG_REORTH) ? 4 : 0;
+    const bool cold = every > 0;
     if (y_prev == P->U && cold) {
       // keep U intact for re-orthonormalisation: move Y_0 into the ring
       launch_axpby(y_prev, y_prev, P->Yb[0], ld, W, P->n, P->p_pad, 1.0, 0.0, st);
@@ -587,7 +590,7 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
         if (P->Yb[i] != y_cur && P->Yb[i] != y_prev) { y_next = P->Yb[i]; break; }
       const double r = tau[k] / tau[k + 1];
       const double al = 2.0 * r / e, be = -2.0 * c * r / e, ga = -tau[k - 1] / tau[k + 1];
-      const bool reorth = cold && (k + 1) % 2 == 0 && k + 1 < d.degree;
+      const bool reorth = cold && (k + 1) % every == 0 && k + 1 < d.degree;
       // planes of Y_{k+1} feed the next product (or the next pass)
       const bool want = split && ((k + 1 < d.degree && !reorth) || (k + 1 == d.degree && pass + 1 < d.q));
       set_phase(ph_product((int64_t)pass * d.degree + k));

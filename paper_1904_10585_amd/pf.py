@@ -27,6 +27,7 @@ PF_FLAG_SCALED = 0x2
 PF_FLAG_COLD = 0x4
 PF_FLAG_NATIVE_F32 = 0x8
 PF_FLAG_OPERATOR_UNCHANGED = 0x10
+PF_FLAG_REORTH = 0x20
 PF_PROF_FILTER, PF_PROF_FILTER_REDUCE, PF_PROF_RR, PF_PROF_EXTRACT = range(4)
 
 

@@ -6,8 +6,9 @@
     python -m paper_1904_10585_amd.rocprof_summary counters <run.csv>... --kernel NAME
         per-dispatch mean of every counter of one kernel over one or more
         ``rocprofv3 --pmc`` runs (CSV output);
-    python -m paper_1904_10585_amd.rocprof_summary bytes <fetch.csv> <write.csv> --kernel NAME
-        HBM bytes per dispatch of one kernel from two ``rocprofv3 --pmc``
+    python -m paper_1904_10585_amd.rocprof_summary bytes <fetch.csv> <write.csv> --kernel NAME [--kernel NAME2]
+        HBM bytes per dispatch of one kernel (plus the kernels that complete
+        each of its launches, e.g. a split-K slab sum) from two ``rocprofv3 --pmc``
         runs (FETCH_SIZE, then WRITE_SIZE, CSV output), each scaled by what
         the same counter reads for the runtime's device-to-device copy of a
         known size (``bench.py --calib-copy``: 256 MiB read, 256 MiB written).
@@ -57,21 +58,29 @@ def counter_means(path):
     return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
 
 
-def bytes_per_dispatch(fetch_csv, write_csv, kernel):
+def bytes_per_dispatch(fetch_csv, write_csv, kernels):
+    """HBM bytes per launch of the first kernel, summed over the kernels
+    given (e.g. a product and the slab sum that completes it), each
+    weighted by its dispatches per dispatch of the first."""
     f = counter_means(fetch_csv)
     w = counter_means(write_csv)
     cf, nf = f[(CALIB_KERNEL, "FETCH_SIZE")]
     cw, nw = w[(CALIB_KERNEL, "WRITE_SIZE")]
-    kf, nkf = f[(kernel, "FETCH_SIZE")]
-    kw, nkw = w[(kernel, "WRITE_SIZE")]
     sf = cf * 1024 / CALIB_BYTES            # counter bytes per byte moved
     sw = cw * 1024 / CALIB_BYTES
-    fetch_b = kf * 1024 / sf
-    write_b = kw * 1024 / sw
     print(f"- calibration copy FETCH_SIZE per dispatch: {cf:.1f} KiB over {nf} dispatches (scale {sf:.5f})")
     print(f"- calibration copy WRITE_SIZE per dispatch: {cw:.1f} KiB over {nw} dispatches (scale {sw:.5f})")
-    print(f"- kernel FETCH_SIZE per dispatch: {kf:.1f} KiB over {nkf} dispatches")
-    print(f"- kernel WRITE_SIZE per dispatch: {kw:.1f} KiB over {nkw} dispatches")
+    fetch_b = write_b = 0.0
+    n0 = None
+    for kernel in kernels:
+        kf, nkf = f[(kernel, "FETCH_SIZE")]
+        kw, nkw = w[(kernel, "WRITE_SIZE")]
+        n0 = nkf if n0 is None else n0
+        weight = nkf / n0
+        print(f"- `{kernel}` FETCH_SIZE per dispatch: {kf:.1f} KiB over {nkf} dispatches; "
+              f"WRITE_SIZE {kw:.1f} KiB over {nkw}")
+        fetch_b += weight * kf * 1024 / sf
+        write_b += weight * kw * 1024 / sw
     print(f"- fetch_bytes_per_launch: {fetch_b:.0f}")
     print(f"- write_bytes_per_launch: {write_b:.0f}")
     print(f"- traffic_bytes_per_launch: {fetch_b + write_b:.0f}")
@@ -93,7 +102,8 @@ def main():
     b = sub.add_parser("bytes")
     b.add_argument("fetch_csv")
     b.add_argument("write_csv")
-    b.add_argument("--kernel", required=True)
+    b.add_argument("--kernel", required=True, action="append",
+                   help="kernel name (repeat to add the kernels that complete one launch of the first)")
     c = sub.add_parser("counters")
     c.add_argument("csv", nargs="+")
     c.add_argument("--kernel", required=True)

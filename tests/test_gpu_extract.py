@@ -486,3 +486,43 @@ def test_gram_operator_unchanged_reuses_copy():
     np.testing.assert_array_equal(th1, th2)
     np.testing.assert_array_equal(th1, th3)
     np.testing.assert_array_equal(V1, V3)
+
+
+def test_reorth_keeps_fp32_parity_at_the_bulk_edge():
+    """The damping interval at the edge of the unwanted spectrum ([-2, 0.8])
+    with degree 10: the top wanted eigenvalue (20) grows ~1e12 times more
+    than the smallest (1).  With PF_FLAG_REORTH (the recurrence pair
+    re-orthonormalised every fourth product) a warm-started FP32 chain
+    meets the FP32 tolerances against the FP64 oracle fed the same U and
+    X_k; the FP64 form with the flag still meets 1e-10."""
+    pf = pf_module()
+    n, p, r, d, a, b = 2000, 32, 16, 10, -2.0, 0.8
+    X, _, _ = wl.planted(n, r, (1.0, 20.0), (-2.0, 0.8), config=160)
+    U0 = wl.start_block(n, p, config=160)
+    for work in ("f32", "f64"):
+        f64 = work == "f64"
+        tdt, wk = (torch.float64, pf.PF_F64) if f64 else (torch.float32, pf.PF_F32)
+        h = pf.pf_session_open(pf.desc(n, p, d, a, b, work=wk, flags=pf.PF_FLAG_REORTH), device_matrix(U0, tdt),
+                               seed=0)
+        Xk, U = X.copy(), U0
+        try:
+            for k in range(6):
+                if k:
+                    Xk = Xk + wl.perturbation(n, 160, k)
+                Xs = Xk if f64 else Xk.astype(np.float32).astype(np.float64)
+                pf.pf_session_step(h, device_matrix(Xs, tdt), device_matrix(Xs, tdt))
+                s, res = pf.pf_session_wait(h)
+                assert s == pf.PF_OK and res.status == 0
+                th = pf.device_to_numpy(res.theta, (p,), np.float64)
+                V = pf.device_to_numpy(res.V, (p, res.ldv), np.float64 if f64 else np.float32).T[:n]
+                V = V.astype(np.float64)
+                if f64:
+                    grade_f64(th, V, Xs, U, d, a, b, r, cold=(k == 0), label=f"reorth f64 step {k}")
+                elif k >= 3:
+                    ref = oracle.extract(Xs, Xs, U, d, a, b)
+                    rel, sin = compare(th, V, ref, r)
+                    print(f"reorth f32 step {k}: rel {rel:.2e} sin {sin:.2e}")
+                    assert rel <= 1e-5 and sin <= 1e-4, (k, rel, sin)
+                U = V
+        finally:
+            pf.pf_session_close(h)
