@@ -42,7 +42,7 @@ def parse():
                     help="skip the Lanczos interval-policy leg (keeps kernel traces to the extraction)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event hooks")
     ap.add_argument("--reorth", action="store_true",
-                    help="re-orthonormalise the recurrence every fourth product (dynamic-range control)")
+                    help="re-orthonormalise the recurrence in mid-filter (dynamic-range control, PF_FLAG_REORTH)")
     ap.add_argument("--sessions", type=int, default=2000, help="serving: sessions in the Poisson stream")
     ap.add_argument("--session-steps", type=int, default=30, help="serving: steps per session")
     ap.add_argument("--gram-share", type=float, default=0.05,
@@ -260,7 +260,7 @@ def main():
         "data": "synthetic planted-spectrum (seeded), resident in HBM",
         "config": {"workload": w.name, "n": n, "p": p, "degree": d, "interval": [w.a, w.b],
                    "work": "f32", "rayleigh_ritz": "f64", "orth": "cholqr2 (f64 gram)",
-                   "reorth_every_4": bool(args.reorth),
+                   "reorth": bool(args.reorth),
                    "steps_chain": "X_k = X_{k-1} + 1e-3 sym(N(0,1))/sqrt(n)"},
         "hbm_GBps_algorithmic": round(bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
         "bytes_per_step_algorithmic": bytes_step,

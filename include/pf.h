@@ -94,7 +94,9 @@ typedef enum pf_op {
                                      rebuilding them (a fixed M over a chain
                                      of extractions) */
 #define PF_FLAG_REORTH 0x20u      /* dynamic-range control on warm steps: every
-                                     fourth product the pair (Y_k, Y_{k-1}) is
+                                     max(4, ceil(degree / 2)) products (once,
+                                     in the middle, for degree 10) the pair
+                                     (Y_k, Y_{k-1}) is
                                      multiplied by the same R^{-1} from a
                                      CholeskyQR2 of Y_k (as on cold steps,
                                      where it happens every second product).

@@ -14,7 +14,8 @@
 //
 // Members' block ranges are laid end to end, each starting at a multiple of
 // 8 (the XCD count, so a member's block b lands on XCD b mod 8 as it would
-// alone); blocks past a member's own grid return at once.
+// alone); blocks past a member's own grid return at once.  A group of one
+// is launched on the member's own grid.
 #pragma once
 
 #include "pf_internal.h"
@@ -48,14 +49,19 @@ struct GroupArgs {
 
 template <typename K, int N>
 __global__ __launch_bounds__(K::kThreads, K::kMinWaves) void grouped_kernel(GroupArgs<typename K::Args, N> g) {
-  const int b = (int)blockIdx.x;
-  int i = 0;
-  while (i + 1 < g.count && b >= g.first[i + 1]) ++i;
-  const unsigned local = (unsigned)(b - g.first[i]);
-  if (local >= g.nb[i]) return;
-  const unsigned gx = g.gx[i], gy = g.gy[i];
-  const uint3 bid = make_uint3(local % gx, (local / gx) % gy, local / (gx * gy));
-  K::body(g.a[i], bid);
+  if constexpr (N == 1) {
+    // one member: launched on its own grid, its arguments at fixed offsets
+    K::body(g.a[0], make_uint3(blockIdx.x, blockIdx.y, blockIdx.z));
+  } else {
+    const int b = (int)blockIdx.x;
+    int i = 0;
+    while (i + 1 < g.count && b >= g.first[i + 1]) ++i;
+    const unsigned local = (unsigned)(b - g.first[i]);
+    if (local >= g.nb[i]) return;
+    const unsigned gx = g.gx[i], gy = g.gy[i];
+    const uint3 bid = make_uint3(local % gx, (local / gx) % gy, local / (gx * gy));
+    K::body(g.a[i], bid);
+  }
 }
 
 // One recorded launch: its kernel instance, arguments, grid and where it
@@ -116,7 +122,8 @@ void flush_n(LaunchRec* const* recs, int count, hipStream_t st) {
     g.count = cnt;
     if (total == 0) continue;
     ensure_lds((const void*)grouped_kernel<K, N>, lds, cur_lds);
-    grouped_kernel<K, N><<<dim3((unsigned)total), dim3(K::kThreads), lds, st>>>(g);
+    const dim3 grid = N == 1 ? recs[c0]->grid : dim3((unsigned)total);
+    grouped_kernel<K, N><<<grid, dim3(K::kThreads), lds, st>>>(g);
     PFX_HIP(hipGetLastError());
   }
 }

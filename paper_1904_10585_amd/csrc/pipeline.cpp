@@ -577,7 +577,10 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
     if (split && (d.degree > 1 || pass + 1 < d.q)) refresh_planes(P, y_cur, st);
     // re-orthonormalisation of the recurrence pair every `every` products:
     // a cold start (every second one) or dynamic-range control on warm steps
-    const int every = ((d.flags & PF_FLAG_COLD) && pass == 0) ? 2 : (d.flags & PF_FLAG_REORTH) ? 4 : 0;
+    // (every max(4, ceil(d/2)): once in the middle of a degree-10 filter)
+    const int every = ((d.flags & PF_FLAG_COLD) && pass == 0) ? 2
+                      : (d.flags & PF_FLAG_REORTH)           ? std::max(4, (d.degree + 1) / 2)
+                                                              : 0;
     const bool cold = every > 0;
     if (y_prev == P->U && cold) {
       // keep U intact for re-orthonormalisation: move Y_0 into the ring

@@ -492,7 +492,7 @@ def test_reorth_keeps_fp32_parity_at_the_bulk_edge():
     """The damping interval at the edge of the unwanted spectrum ([-2, 0.8])
     with degree 10: the top wanted eigenvalue (20) grows ~1e12 times more
     than the smallest (1).  With PF_FLAG_REORTH (the recurrence pair
-    re-orthonormalised every fourth product) a warm-started FP32 chain
+    re-orthonormalised after the fifth of the ten products) a warm-started FP32 chain
     meets the FP32 tolerances against the FP64 oracle fed the same U and
     X_k; the FP64 form with the flag still meets 1e-10."""
     pf = pf_module()
