@@ -118,6 +118,17 @@ def main():
     from paper_1904_10585_amd import pf
     from paper_1904_10585_amd import workloads as wl
 
+    if args.calib_copy:
+        # a plain copy of known size, 256 MiB read + 256 MiB written per
+        # launch: the scale of a profiler run's byte counters
+        torch.cuda.set_device(0)
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     if args.workload == "serving":
         return serve_main(args)
     if args.workload == "planted_16384_bf16":
@@ -170,15 +181,6 @@ def main():
     s, _ = pf.pf_session_wait(sess)
     if s != pf.PF_OK:
         raise SystemExit(f"warm-up step failed: {pf.status_string(s)}")
-
-    if args.calib_copy:
-        # a plain copy of known size: 256 MiB read + 256 MiB written per launch
-        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     # ---- timed region (no instrumentation) ----------------------------------
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
