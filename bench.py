@@ -52,6 +52,9 @@ def parse():
                     help="serving: further Poisson loads reported beside --load (comma-separated, '' for none)")
     ap.add_argument("--max-batches", type=int, default=0,
                     help="serving: batches of grouped launches in flight at most (0 = the library's default)")
+    ap.add_argument("--form", default="split", choices=("split", "native", "bf16"),
+                    help="serving: form of the symmetric sessions (FP32 X with the exact BF16-split products, "
+                         "FP32 X on the native FP32 MFMA, or a BF16 copy of X for the filter)")
     ap.add_argument("--no-grouping", action="store_true",
                     help="serving: every session runs its own steps (no batches of grouped launches)")
     ap.add_argument("--hbm-budget-gb", type=float, default=160.0, help="serving: HBM budget of the server")
@@ -1036,9 +1039,18 @@ def serve_main(args):
                     n, p, d = int(ns[i]), int(ps[i]), int(ds[i])
                     a, b = wl.serving_interval(d)
                     with torch.cuda.stream(cs):
-                        Xs[i] = (session_x(i),) * 2
-                    dsc = pf.desc(n, p, d, a, b, work=pf.PF_F32)
-                    ids[i] = pf.pf_server_open(srv, dsc, seed=i, operator_bytes=n * n * 4)
+                        Xf = session_x(i)
+                        if args.form == "bf16":
+                            # the filter reads a BF16 copy, Rayleigh-Ritz the FP32 X
+                            Xq = pf.colmajor(n, n, torch.bfloat16, dev)
+                            pf.pf_quantize(Xq, None, 0, pf.PF_BF16, Xf, stream=cs)
+                            Xs[i] = (Xq, Xf)
+                        else:
+                            Xs[i] = (Xf, Xf)
+                    flags = pf.PF_FLAG_NATIVE_F32 if args.form == "native" else 0
+                    dsc = pf.desc(n, p, d, a, b, work=pf.PF_F32, flags=flags)
+                    ids[i] = pf.pf_server_open(srv, dsc, seed=i,
+                                               operator_bytes=n * n * (6 if args.form == "bf16" else 4))
                 left[i] = steps
                 opened.append(i)
             if opened:
@@ -1062,14 +1074,17 @@ def serve_main(args):
                     step_bytes += (2.0 * gd + 4.0) * gm * gn      # 2 d passes over FP8 M, one over FP32 M
                 else:
                     n, d = int(ns[i]), int(ds[i])
-                    step_bytes += (d + 1) * 4.0 * n * n
+                    # d passes over the filter's X (FP32 or its BF16 copy), one over the FP32 X
+                    step_bytes += (d * (2.0 if args.form == "bf16" else 4.0) + 4.0) * n * n
                 done_steps += 1
                 last_done = time.perf_counter()
                 left[i] -= 1
                 if left[i] > 0:
                     if not is_gram[i]:                         # M stays fixed over a Gram session
                         with torch.cuda.stream(cs):
-                            perturb(Xs[i][0], i, steps - left[i])
+                            perturb(Xs[i][1], i, steps - left[i])
+                            if args.form == "bf16":
+                                pf.pf_quantize(Xs[i][0], None, 0, pf.PF_BF16, Xs[i][1], stream=cs)
                     resubmit.append(i)
                 else:
                     pf.pf_server_close(srv, ids[i])
@@ -1122,6 +1137,7 @@ def serve_main(args):
                    "n_choices": list(S["n_choices"]), "p_choices": list(S["p_choices"]),
                    "degree_choices": list(S["degree_choices"]), "arrivals": f"Poisson at {args.load} x saturated",
                    "gram_sessions": int(is_gram.sum()), "gram_form": f"M {gm}x{gn} FP8-E4M3, p={gp}, d={gd}, fixed",
+                   "symmetric_form": args.form,
                    "hbm_budget_gb": args.hbm_budget_gb},
         "latency_ms": {"p50": round(pois["p50_ms"], 3), "p99": round(pois["p99_ms"], 3)},
         "hbm_GBps_algorithmic": round(pois["gbps"], 1),

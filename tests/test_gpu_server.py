@@ -333,3 +333,51 @@ def test_server_gram_fp8_session_matches_eager():
         pf.pf_server_close(srv, oid)
     finally:
         pf.pf_server_destroy(srv)
+
+
+def test_served_bf16_session_matches_oracle():
+    """A precision-form session (the filter on a BF16 copy of X, made by
+    pf_quantize each step; Rayleigh-Ritz on the FP32 X) batched with an
+    FP32 session: warm steps against the oracle fed the dequantised copy
+    for the filter and the FP32 X for Rayleigh-Ritz (same math), at the
+    FP32 tolerance."""
+    import oracle
+    pf = pf_module()
+    c, other = Case(*CASES[1]), Case(*CASES[0])
+    steps = 4
+    srv = pf.pf_server_create(16 << 30)
+    try:
+        Xf, Xo = c.fresh_x(), other.fresh_x()
+        Xq = pf.colmajor(c.n, c.n, torch.bfloat16, "cuda")
+        sid = pf.pf_server_open(srv, c.desc(), seed=c.idx)
+        oid = pf.pf_server_open(srv, other.desc(), seed=other.idx)
+        U_prev = None
+        for k in range(steps):
+            pf.pf_quantize(Xq, None, 0, pf.PF_BF16, Xf)
+            torch.cuda.synchronize()
+            Xh = Xf.cpu().double().numpy()
+            Xqh = Xq.cpu().double().numpy()
+            pf.pf_server_submit(srv, sid, Xq, Xf, tag=k)
+            pf.pf_server_submit(srv, oid, Xo, Xo, tag=k)
+            got = 0
+            while got < 2:
+                for ev in pf.pf_server_poll(srv, timeout_s=5.0):
+                    assert ev.status == pf.PF_OK
+                    got += 1
+            th, V = read_result(pf, pf.pf_server_result(srv, sid), c.n, c.p)
+            V = V.astype(np.float64)
+            if k >= 2:
+                np.testing.assert_array_equal(Xqh, oracle.bf16_round(Xh))
+                ref = oracle.extract(Xqh, Xh, U_prev, c.d, c.a, c.b)
+                r = c.p // 2
+                rel = oracle.ritz_rel_err(th, ref["theta"], r)
+                sin = oracle.sin_theta(np.linalg.qr(V[:, :r])[0], ref["V"][:, :r])
+                print(f"served bf16 session step {k}: rel {rel:.2e} sin {sin:.2e}")
+                assert rel <= 1e-5 and sin <= 1e-4, (k, rel, sin)
+            U_prev = V
+            if k + 1 < steps:
+                c.perturb(Xf, k + 1)
+                other.perturb(Xo, k + 1)
+        assert pf.pf_server_stats(srv).batches > 0
+    finally:
+        pf.pf_server_destroy(srv)
