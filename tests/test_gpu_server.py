@@ -348,7 +348,7 @@ def test_served_bf16_session_matches_oracle():
     srv = pf.pf_server_create(16 << 30)
     try:
         Xf, Xo = c.fresh_x(), other.fresh_x()
-        Xq = pf.colmajor(c.n, c.n, torch.bfloat16, "cuda")
+        Xq = pf.colmajor(c.n, c.n, torch.bfloat16, "cuda", ld=-(-c.n // 8) * 8)   # 16-byte columns
         sid = pf.pf_server_open(srv, c.desc(), seed=c.idx)
         oid = pf.pf_server_open(srv, other.desc(), seed=other.idx)
         U_prev = None
