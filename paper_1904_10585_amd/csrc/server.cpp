@@ -22,6 +22,7 @@
 // does not synchronise the device.
 #include "pf_internal.h"
 #include "group.h"
+#include "admission.h"
 
 #include <chrono>
 #include <condition_variable>
@@ -104,10 +105,7 @@ struct pf_server {
   std::map<int32_t, SrvSession*> sessions;
   std::deque<int32_t> waitq;
   std::deque<pf_server_event> events;
-  size_t used = 0;
-  int active = 0;
-  std::multimap<SlotKey, Slot> pool;   // slots of closed sessions
-  size_t pooled = 0;
+  Admission<SlotKey, Slot>* adm = nullptr;   // budget, residents, pool of closed sessions' slots
   int32_t next_id = 1;
   std::vector<hipStream_t> streams;
   int next_stream = 0;
@@ -132,27 +130,20 @@ void free_slot(Slot& t) {
 void free_session(pf_server* S, SrvSession* s) {
   if (s->exec) (void)hipGraphExecDestroy(s->exec);
   if (s->resident) {
-    S->used -= s->footprint;
-    S->active--;
-    S->pooled += s->slot.bytes;
-    S->pool.emplace(slot_key(s->desc), s->slot);
+    S->adm->release(s->footprint, slot_key(s->desc), s->slot, s->slot.bytes);
     s->slot = Slot{};
   }
   delete s;
 }
 
-// Free pooled slots until `need` more bytes fit the budget (slots of other
-// shapes first; the mutex is released while the device memory is freed).
+// Free pooled slots until `need` more bytes fit the budget (the mutex is
+// released while the device memory is freed).
 void make_room(pf_server* S, std::unique_lock<std::mutex>& lk, size_t need) {
-  while (!S->pool.empty() && S->used + S->pooled + need > S->cfg.hbm_budget) {
-    auto it = S->pool.begin();
-    Slot t = it->second;
-    S->pool.erase(it);
-    S->pooled -= t.bytes;
-    lk.unlock();
-    free_slot(t);
-    lk.lock();
-  }
+  std::vector<Slot> out = S->adm->evict_for(need);
+  if (out.empty()) return;
+  lk.unlock();
+  for (Slot& t : out) free_slot(t);
+  lk.lock();
 }
 
 // Admit s on its stream: a pooled slot of its shape when there is one
@@ -161,11 +152,7 @@ void make_room(pf_server* S, std::unique_lock<std::mutex>& lk, size_t need) {
 void admit(pf_server* S, SrvSession* s) {
   s->stream = S->streams[S->next_stream];
   S->next_stream = (S->next_stream + 1) % (int)S->streams.size();
-  auto it = S->pool.find(slot_key(s->desc));
-  if (it != S->pool.end()) {
-    s->slot = it->second;
-    S->pool.erase(it);
-    S->pooled -= s->slot.bytes;
+  if (S->adm->take(slot_key(s->desc), s->slot)) {
     SessionCore* c = s->slot.core;
     c->desc = s->desc;
     c->steps = 0;
@@ -191,8 +178,7 @@ void admit(pf_server* S, SrvSession* s) {
   }
   PFX_HIP(hipEventRecord(s->slot.done, s->stream));
   s->resident = true;
-  S->used += s->footprint;
-  S->active++;
+  S->adm->admit(s->footprint);
 }
 
 void finish(pf_server* S, SrvSession* s, int32_t status, int32_t n_pos);
@@ -396,8 +382,8 @@ void worker_loop(pf_server* S) {
     // admission in FIFO order
     while (!S->waitq.empty()) {
       SrvSession* s = S->sessions[S->waitq.front()];
-      if (S->used + s->footprint > S->cfg.hbm_budget || S->active >= S->cfg.max_active) break;
-      if (S->pool.find(slot_key(s->desc)) == S->pool.end()) make_room(S, lk, s->footprint);
+      if (!S->adm->fits(s->footprint)) break;
+      if (!S->adm->pooled(slot_key(s->desc))) make_room(S, lk, s->footprint);
       S->waitq.pop_front();
       try {
         admit(S, s);
@@ -453,9 +439,7 @@ void worker_loop(pf_server* S) {
   S->batch_free.clear();
   for (auto& kv : S->sessions) free_session(S, kv.second);
   S->sessions.clear();
-  for (auto& kv : S->pool) free_slot(kv.second);
-  S->pool.clear();
-  S->pooled = 0;
+  for (Slot& t : S->adm->drain()) free_slot(t);
   S->waitq.clear();
   S->done_cv.notify_all();
 }
@@ -484,6 +468,7 @@ pf_status pf_server_create(const pf_server_config* cfg, pf_server** out) {
     if (S->cfg.max_active == 0) S->cfg.max_active = 64;
     if (S->cfg.streams == 0) S->cfg.streams = 8;
     if (S->cfg.max_batches == 0) S->cfg.max_batches = 4;
+    S->adm = new Admission<SlotKey, Slot>(S->cfg.hbm_budget, S->cfg.max_active);
     try {
       PFX_HIP(hipGetDevice(&S->device));
       for (int i = 0; i < S->cfg.streams; ++i) {
@@ -494,6 +479,7 @@ pf_status pf_server_create(const pf_server_config* cfg, pf_server** out) {
       S->worker = std::thread(worker_loop, S);
     } catch (...) {
       for (hipStream_t st : S->streams) (void)hipStreamDestroy(st);
+      delete S->adm;
       delete S;
       throw;
     }
@@ -589,9 +575,9 @@ pf_status pf_server_stats_get(pf_server* S, pf_server_stats* out) {
     if (!S || !out) fail(PF_ERR_ARG, "NULL argument");
     std::lock_guard<std::mutex> lk(S->mu);
     *out = S->stats;
-    out->active = S->active;
+    out->active = S->adm->active();
     out->waiting = (int32_t)S->waitq.size();
-    out->used_bytes = S->used;
+    out->used_bytes = S->adm->used();
   });
 }
 
@@ -606,6 +592,7 @@ pf_status pf_server_destroy(pf_server* S) {
     }
     S->worker.join();
     for (hipStream_t st : S->streams) (void)hipStreamDestroy(st);
+    delete S->adm;
     delete S;
   });
 }
