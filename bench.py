@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--no-grouping", action="store_true",
                     help="serving: every session runs its own steps (no batches of grouped launches)")
     ap.add_argument("--hbm-budget-gb", type=float, default=160.0, help="serving: HBM budget of the server")
+    ap.add_argument("--basis", default="haar", choices=("haar", "householder"),
+                    help="precision form: Haar eigenbasis of the planted X (default) or a product of 8 "
+                         "Householder reflectors (profiler runs: no device QR)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (the byte-counter calibration of a profiler run)")
     return ap.parse_args()
@@ -415,10 +418,20 @@ def precision_main(args):
     t0 = time.time()
     gen = torch.Generator(device=dev)
     gen.manual_seed(wl.SEED_ROOT * 10 + w.config)
-    G = torch.randn((n, n), generator=gen, device=dev, dtype=torch.float64)
-    Q, R = torch.linalg.qr(G)
-    Q = Q * torch.sign(torch.diagonal(R))
-    del G, R
+    if args.basis == "haar":
+        G = torch.randn((n, n), generator=gen, device=dev, dtype=torch.float64)
+        Q, R = torch.linalg.qr(G)
+        Q = Q * torch.sign(torch.diagonal(R))
+        del G, R
+    else:
+        # a product of 8 seeded Householder reflectors: the same planted
+        # spectrum in a cheaper orthogonal basis, for profiler runs (the
+        # byte counters depend only on the shapes)
+        Q = torch.eye(n, dtype=torch.float64, device=dev)
+        for _ in range(8):
+            v = torch.randn(n, generator=gen, device=dev, dtype=torch.float64)
+            v = v / torch.linalg.vector_norm(v)
+            Q = Q - 2.0 * torch.outer(Q @ v, v)
     lam = torch.from_numpy(wl.planted_eigenvalues(n, w.n_top, w.top, w.rest, wl.rng(w.config, wl.S_LAMBDA))).to(dev)
     X = (Q * lam) @ Q.t()
     X0 = (0.5 * (X + X.t())).float()
