@@ -10,7 +10,8 @@ unoptimised reference of what one extraction computes (Li, Liu, Wen, Yuan,
   * the Rayleigh-Ritz step H = Q^T X Q, H = Z Theta Z^T, V = Q Z
     (section 2.2, eq. RR), with the low-rank projection P_V(X) and the PSD
     projection P_+(P_V(X)) used by PFPG/PFAM (section 2.2-2.3),
-  * the SVD route through A^T A (section 5.2.1),
+  * the SVD route through A^T A (section 5.2.1) and its singular-value
+    shrinkage, the residual norms of the Ritz pairs,
   * the same extraction in 80-bit extended precision, which bounds the
     FP64 oracle's own rounding on ill-conditioned (cold-start) inputs,
   * the BF16 / FP8-E4M3 quantisers that define the low-precision copies
@@ -34,7 +35,7 @@ invariants, brute force or an independent algorithm.
 
 from .chebyshev import cheb_T, interval_map, rho, chebyshev_filter
 from .extract import (orthonormalize, rayleigh_ritz, extract, extract_gram,
-                      psd_projection, lowrank_projection, ritz_residuals)
+                      psd_projection, lowrank_projection, ritz_residuals, svd_shrink, svd_shrink_factor)
 from .metrics import sin_theta, projector_distance, ritz_rel_err, orth_error
 from .jacobi import jacobi_eigh
 from .extended import extract_longdouble, jacobi_eigh_ld
@@ -46,7 +47,7 @@ from .quantize import (bf16_round, fp8_e4m3_round, fp8_tile_quantize,
 __all__ = [
     "cheb_T", "interval_map", "rho", "chebyshev_filter",
     "orthonormalize", "rayleigh_ritz", "extract", "extract_gram",
-    "psd_projection", "lowrank_projection", "ritz_residuals",
+    "psd_projection", "lowrank_projection", "ritz_residuals", "svd_shrink", "svd_shrink_factor",
     "sin_theta", "projector_distance", "ritz_rel_err", "orth_error",
     "block_krylov_ritz", "lanczos_bounds", "interval_policy", "block_size_policy", "degree_policy",
     "jacobi_eigh", "extract_longdouble", "jacobi_eigh_ld",

@@ -109,6 +109,33 @@ def extract_gram(M_filter, M_rr, U, d, a, b, q=1):
     }
 
 
+def svd_shrink(M, tau):
+    """Singular-value shrinkage shrink_tau(M) = U diag(max(s_i - tau, 0)) V^T
+    (section 5.2.1: the proximal map of tau times the nuclear norm), from
+    the full SVD of M."""
+    M = np.asarray(M, dtype=np.float64)
+    Uf, s, Vt = np.linalg.svd(M, full_matrices=False)
+    return (Uf * np.maximum(s - tau, 0.0)) @ Vt
+
+
+def svd_shrink_factor(M, V, theta, tau):
+    """Left factor L of the shrinkage of M restricted to the Ritz subspace.
+
+    With V the right Ritz vectors of Rayleigh-Ritz on M^T M (section 5.2.1)
+    and theta their Ritz values, B = M V has orthogonal columns of norms
+    sigma_i = sqrt(theta_i), so M P_V = B V^T is an SVD up to normalising
+    the columns of B, and shrink_tau(M P_V) = L V^T with
+    L = B diag(max(sigma_i - tau, 0) / sigma_i) (zero where sigma_i = 0).
+    """
+    M = np.asarray(M, dtype=np.float64)
+    B = M @ np.asarray(V, dtype=np.float64)
+    sigma = np.sqrt(np.maximum(np.asarray(theta, dtype=np.float64), 0.0))
+    f = np.zeros_like(sigma)
+    keep = sigma > tau
+    f[keep] = (sigma[keep] - tau) / sigma[keep]
+    return B * f
+
+
 def lowrank_projection(V, theta):
     """P_V(X) = V diag(theta) V^T for Ritz pairs (section 2.2, eq. RR)."""
     return (V * theta) @ V.T
