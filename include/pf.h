@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define PF_ABI_VERSION 2
+#define PF_ABI_VERSION 3
 
 typedef enum pf_status {
   PF_OK = 0,
@@ -197,6 +197,45 @@ pf_status pf_extract(const pf_desc* desc, const pf_mat* X_filter, const pf_mat* 
                      void* U_inout, int64_t ldu, double* theta_out, pf_info* info_out,
                      void* stream);
 
+/* Optional outputs of an extraction, computed from the Rayleigh-Ritz step's
+ * own buffers after the Ritz vectors are written (struct_size must be
+ * sizeof(pf_extras); unused members NULL / 0).
+ *  resid:       device, p doubles, or NULL.  Residual norms
+ *               ||A v_i - theta_i v_i||_2 of the Ritz pairs (the convergence
+ *               measure of eq. RR), in the order of theta.  Formed in FP64
+ *               as the column norms of E Z with E = A Q - Q H (Q the
+ *               orthonormal block, H = Q^T A Q, Z its eigenvectors), so they
+ *               are those of the FP64 Ritz vectors Q Z; one Gram product of
+ *               E and one block apply.  PF_OP_GRAM adds one product M^T (M Q)
+ *               over X_rr.  Not available with a caller-supplied operator.
+ *  shrink_left: PF_OP_GRAM only: device m-by-p block (work dtype, leading
+ *               dimension ld_shrink >= m), or NULL.  The singular-value
+ *               shrinkage of section 5.2.1 (the proximal map of
+ *               shrink_tau * nuclear norm) applied to M restricted to the
+ *               Ritz subspace: M P_V = B V^T with B = M V, whose columns are
+ *               orthogonal with norms sigma_i = sqrt(theta_i), so
+ *                 shrink_tau(M P_V) = L V^T,
+ *                 L = B diag(max(sigma_i - shrink_tau, 0) / sigma_i)
+ *               (columns with sigma_i = 0 are zero).  The library writes L;
+ *               the right factor is the V the call returns.
+ *  shrink_tau:  the threshold, finite and >= 0.
+ * Outputs are written even when the step reports a numerical error in
+ * pf_info (they are then meaningless). */
+typedef struct pf_extras {
+  uint32_t struct_size;
+  int32_t reserved;          /* must be 0 */
+  double* resid;
+  double shrink_tau;
+  void* shrink_left;
+  int64_t ld_shrink;
+} pf_extras;
+
+/* pf_extract with optional outputs (extras may be NULL: then exactly
+ * pf_extract). */
+pf_status pf_extract_ex(const pf_desc* desc, const pf_mat* X_filter, const pf_mat* X_rr, void* U_inout,
+                        int64_t ldu, double* theta_out, pf_info* info_out, const pf_extras* extras,
+                        void* stream);
+
 /* pf_extract without device allocation, for callers that cannot call
  * hipMalloc: code under HIP graph capture, tight serving loops, harnesses
  * that forbid allocation.  Same arguments, semantics and results as
@@ -270,6 +309,9 @@ typedef struct pf_result {
   const void* V;           /* device n-by-p Ritz vectors (work dtype) */
   int64_t ldv;
   const pf_info* info;     /* device */
+  const double* resid;     /* device residual norms of the last step
+                              (pf_session_step_ex with extras->resid), else NULL */
+  double resid_max;        /* their maximum (after wait), else NaN */
 } pf_result;
 
 pf_status pf_session_open(const pf_desc* desc, const void* U0, int64_t ldu0, uint64_t seed,
@@ -278,10 +320,37 @@ pf_status pf_session_open(const pf_desc* desc, const void* U0, int64_t ldu0, uin
  * device pointers immediately and host status fields after pf_session_wait. */
 pf_status pf_session_step(pf_session* s, const pf_mat* X_filter, const pf_mat* X_rr,
                           pf_result* out, void* stream);
+/* pf_session_step with optional outputs (pf_extras; NULL: pf_session_step).
+ * extras->resid and extras->shrink_left are caller-owned device buffers
+ * written by this step. */
+pf_status pf_session_step_ex(pf_session* s, const pf_mat* X_filter, const pf_mat* X_rr, const pf_extras* extras,
+                             pf_result* out, void* stream);
 /* Block until the session's last step is done; fills out->status/n_pos. */
 pf_status pf_session_wait(pf_session* s, pf_result* out);
 /* Free the session.  PF_ERR_BUSY if a step is still in flight. */
 pf_status pf_session_close(pf_session* s);
+
+/* Checkpoint and resume of a session.  The state of a warm chain is its
+ * subspace: the block U (the Ritz vectors of the last step), theta, the
+ * descriptor (interval, degree and power as last set) and the step count
+ * (a session's first step is a cold start, later ones are warm).
+ * pf_session_export waits for the session's last step, then copies U
+ * (n-by-p, work dtype, into the caller's device buffer U_out, ld ldu >= n)
+ * and theta (p doubles, device, may be NULL) on stream, and fills *state.
+ * pf_session_import opens a session from such a state: its next step is
+ * the step the exported session would have taken, bitwise (the same
+ * kernels on the same U).  U and theta are device pointers (theta may be
+ * NULL: then the session's theta reads zero until its first step). */
+typedef struct pf_session_state {
+  uint32_t struct_size;    /* sizeof(pf_session_state) */
+  int32_t reserved;        /* 0 */
+  pf_desc desc;
+  int64_t steps;           /* steps taken */
+} pf_session_state;
+pf_status pf_session_export(pf_session* s, void* U_out, int64_t ldu, double* theta_out, pf_session_state* state,
+                            void* stream);
+pf_status pf_session_import(const pf_session_state* state, const void* U, int64_t ldu, const double* theta,
+                            pf_session** out);
 
 /* ------------------------------------------------------------------------
  * Serving loop: many warm-started sessions of different n, p, degree and
@@ -605,11 +674,18 @@ pf_status pf_nce_pfam(const pf_pfam_opts* opts, int64_t n, const double* G, int6
  * Classes: PF_PROF_FILTER (the filter product kernel of the Chebyshev
  * recurrence, without its split-K sum), PF_PROF_FILTER_REDUCE (that sum),
  * PF_PROF_RR (the Rayleigh-Ritz product X Q), PF_PROF_EXTRACT (one whole
- * extraction, first to last launch).  pf_profile_set(1) clears the counts. */
+ * extraction, first to last launch), PF_PROF_FILTER_PRODUCT (one whole
+ * filter product: the product kernel and its split-K sum under a single
+ * event pair, with no event recorded between them).
+ * pf_profile_set(1) times FILTER, FILTER_REDUCE, RR and EXTRACT;
+ * pf_profile_set(PF_PROF_MODE_PRODUCT) times FILTER_PRODUCT, RR and EXTRACT;
+ * pf_profile_set(0) stops.  Every call clears the counts. */
 #define PF_PROF_FILTER 0
 #define PF_PROF_FILTER_REDUCE 1
 #define PF_PROF_RR 2
 #define PF_PROF_EXTRACT 3
+#define PF_PROF_FILTER_PRODUCT 4
+#define PF_PROF_MODE_PRODUCT 2
 pf_status pf_profile_set(int enable);
 pf_status pf_profile_read(int which, int64_t* launches, double* total_ms);
 

@@ -3,10 +3,15 @@
 #include "pf_internal.h"
 #include "group.h"
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
+#include <cstring>
 #include <functional>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -66,11 +71,11 @@ void session_destroy(SessionCore* s) {
 }
 
 void session_enqueue_step(SessionCore* s, const pf_mat& Xf, const pf_mat& Xr, hipStream_t st,
-                          const pf_operator* op) {
+                          const pf_operator* op, const pf_extras* ex) {
   pf_desc d = s->desc;
   if (s->steps == 0) d.flags |= PF_FLAG_COLD;        // first step starts from U0
   plan_set_desc(s->plan, d);
-  enqueue_extraction(s->plan, Xf, Xr, s->U, s->ldu, s->U, s->ldu, s->theta, s->info, st, op);
+  enqueue_extraction(s->plan, Xf, Xr, s->U, s->ldu, s->U, s->ldu, s->theta, s->info, st, op, ex);
   s->steps++;
 }
 
@@ -142,11 +147,52 @@ struct ProfClass {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+int g_prof_mode = 0;
 ProfClass g_prof[kProfClasses];
+
+// classes timed in the current mode: per kernel (1), or the filter product
+// as one pair (PF_PROF_MODE_PRODUCT)
+bool prof_class_on(int cls) {
+  if (cls == PF_PROF_RR || cls == PF_PROF_EXTRACT) return true;
+  return g_prof_mode == PF_PROF_MODE_PRODUCT ? cls == PF_PROF_FILTER_PRODUCT : cls != PF_PROF_FILTER_PRODUCT;
+}
 }  // namespace
 
 // (launches being recorded for a grouped enqueue are not timed one by one)
 bool prof_enabled() { return g_prof_on && current_recorder() == nullptr; }
+
+// roctx ranges (host-side, per thread) around the phases of an extraction,
+// for rocprofv3 --marker-trace.  On when PF_ROCTX=1 is in the environment at
+// the first range; the functions are resolved from ROCm's roctx library
+// (missing library: no ranges).
+namespace {
+struct Roctx {
+  int (*push)(const char*) = nullptr;
+  int (*pop)() = nullptr;
+};
+const Roctx& roctx() {
+  static const Roctx r = [] {
+    Roctx x;
+    const char* e = std::getenv("PF_ROCTX");
+    if (!e || std::strcmp(e, "1") != 0) return x;
+    void* h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (!h) h = dlopen("libroctx64.so.4", RTLD_NOW | RTLD_LOCAL);
+    if (!h) return x;
+    x.push = reinterpret_cast<int (*)(const char*)>(dlsym(h, "roctxRangePushA"));
+    x.pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+    if (!x.push || !x.pop) x = Roctx{};
+    return x;
+  }();
+  return r;
+}
+}  // namespace
+
+void trace_push(const char* name) {
+  if (auto f = roctx().push) f(name);
+}
+void trace_pop() {
+  if (auto f = roctx().pop) f();
+}
 
 Recorder*& current_recorder() {
   static thread_local Recorder* r = nullptr;
@@ -155,6 +201,7 @@ Recorder*& current_recorder() {
 
 void prof_begin(int cls, hipStream_t st) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!prof_class_on(cls)) return;
   ProfClass& c = g_prof[cls];
   if (c.used == c.pool.size()) {
     hipEvent_t a, b;
@@ -168,6 +215,7 @@ void prof_begin(int cls, hipStream_t st) {
 
 void prof_end(int cls, hipStream_t st) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!prof_class_on(cls)) return;
   ProfClass& c = g_prof[cls];
   if (!c.open) return;
   PFX_HIP(hipEventRecord(c.pool[c.used].second, st));
@@ -181,8 +229,37 @@ struct pf_session {
   pfx::SessionCore* core = nullptr;
   hipEvent_t done = nullptr;
   bool stepped = false;
+  const double* resid = nullptr;   // the caller's residual buffer of the last step
 };
 using namespace pfx;
+
+namespace {
+
+// The optional outputs of an extraction, checked before anything is enqueued.
+void check_extras(const pf_desc& d, const pf_extras* ex, bool op) {
+  if (!ex) return;
+  if (ex->struct_size != sizeof(pf_extras)) fail(PF_ERR_ARG, "pf_extras.struct_size must be sizeof(pf_extras)");
+  if (ex->reserved != 0) fail(PF_ERR_ARG, "pf_extras.reserved must be 0");
+  if (ex->resid && op) fail(PF_ERR_UNSUPPORTED, "residual norms need a dense operator");
+  if (ex->shrink_left) {
+    if (d.op != PF_OP_GRAM) fail(PF_ERR_ARG, "shrink_left needs PF_OP_GRAM");
+    if (!std::isfinite(ex->shrink_tau) || ex->shrink_tau < 0.0) fail(PF_ERR_ARG, "shrink_tau must be finite and >= 0");
+    if (ex->ld_shrink < d.m) fail(PF_ERR_ARG, "ld_shrink is smaller than m");
+  }
+}
+
+void fill_result(const pf_session* s, pf_result* out) {
+  out->status = 0;
+  out->n_pos = 0;
+  out->theta = s->core->theta;
+  out->V = s->core->U;
+  out->ldv = s->core->ldu;
+  out->info = s->core->info;
+  out->resid = s->resid;
+  out->resid_max = std::numeric_limits<double>::quiet_NaN();
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -207,8 +284,10 @@ int pf_abi_version(void) { return PF_ABI_VERSION; }
 
 pf_status pf_profile_set(int enable) {
   return guarded([&] {
+    if (enable != 0 && enable != 1 && enable != PF_PROF_MODE_PRODUCT) fail(PF_ERR_ARG, "unknown profiling mode");
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = enable != 0;
+    g_prof_mode = enable;
     for (auto& c : g_prof) { c.used = 0; c.open = false; }
   });
 }
@@ -241,16 +320,23 @@ pf_status pf_workspace_size(const pf_desc* desc, size_t* bytes) {
 
 pf_status pf_extract(const pf_desc* desc, const pf_mat* X_filter, const pf_mat* X_rr, void* U_inout, int64_t ldu,
                      double* theta_out, pf_info* info_out, void* stream) {
+  return pf_extract_ex(desc, X_filter, X_rr, U_inout, ldu, theta_out, info_out, nullptr, stream);
+}
+
+pf_status pf_extract_ex(const pf_desc* desc, const pf_mat* X_filter, const pf_mat* X_rr, void* U_inout,
+                        int64_t ldu, double* theta_out, pf_info* info_out, const pf_extras* extras,
+                        void* stream) {
   return guarded([&] {
     if (!desc) fail(PF_ERR_ARG, "desc is NULL");
     plan_validate(*desc, X_filter, X_rr);
     if (!U_inout) fail(PF_ERR_ARG, "U_inout is NULL");
     if (ldu < desc->n) fail(PF_ERR_ARG, "ldu is smaller than n");
     if (!theta_out) fail(PF_ERR_ARG, "theta_out is NULL");
+    check_extras(*desc, extras, false);
     hipStream_t st = static_cast<hipStream_t>(stream);
     Plan* P = cached_plan(*desc, st);
     plan_set_desc(P, *desc);
-    enqueue_extraction(P, *X_filter, *X_rr, U_inout, ldu, U_inout, ldu, theta_out, info_out, st);
+    enqueue_extraction(P, *X_filter, *X_rr, U_inout, ldu, U_inout, ldu, theta_out, info_out, st, nullptr, extras);
   });
 }
 
@@ -353,21 +439,21 @@ pf_status pf_session_open(const pf_desc* desc, const void* U0, int64_t ldu0, uin
 
 pf_status pf_session_step(pf_session* s, const pf_mat* X_filter, const pf_mat* X_rr, pf_result* out,
                           void* stream) {
+  return pf_session_step_ex(s, X_filter, X_rr, nullptr, out, stream);
+}
+
+pf_status pf_session_step_ex(pf_session* s, const pf_mat* X_filter, const pf_mat* X_rr, const pf_extras* extras,
+                             pf_result* out, void* stream) {
   return guarded([&] {
     if (!s) fail(PF_ERR_ARG, "session is NULL");
     plan_validate(s->core->desc, X_filter, X_rr);
+    check_extras(s->core->desc, extras, false);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    session_enqueue_step(s->core, *X_filter, *X_rr, st);
+    session_enqueue_step(s->core, *X_filter, *X_rr, st, nullptr, extras);
     PFX_HIP(hipEventRecord(s->done, st));
     s->stepped = true;
-    if (out) {
-      out->status = 0;
-      out->n_pos = 0;
-      out->theta = s->core->theta;
-      out->V = s->core->U;
-      out->ldv = s->core->ldu;
-      out->info = s->core->info;
-    }
+    s->resid = extras ? extras->resid : nullptr;
+    if (out) fill_result(s, out);
   });
 }
 
@@ -380,14 +466,8 @@ pf_status pf_session_step_op(pf_session* s, const pf_operator* op, pf_result* ou
     session_enqueue_step(s->core, none, none, st, op);
     PFX_HIP(hipEventRecord(s->done, st));
     s->stepped = true;
-    if (out) {
-      out->status = 0;
-      out->n_pos = 0;
-      out->theta = s->core->theta;
-      out->V = s->core->U;
-      out->ldv = s->core->ldu;
-      out->info = s->core->info;
-    }
+    s->resid = nullptr;
+    if (out) fill_result(s, out);
   });
 }
 
@@ -398,12 +478,16 @@ pf_status pf_session_wait(pf_session* s, pf_result* out) {
     if (s->stepped) PFX_HIP(hipEventSynchronize(s->done));
     PFX_HIP(hipMemcpy(&host, s->core->info, sizeof(pf_info), hipMemcpyDeviceToHost));
     if (out) {
+      fill_result(s, out);
       out->status = host.status;
       out->n_pos = host.n_pos;
-      out->theta = s->core->theta;
-      out->V = s->core->U;
-      out->ldv = s->core->ldu;
-      out->info = s->core->info;
+      if (s->resid) {
+        std::vector<double> r(s->core->desc.p);
+        PFX_HIP(hipMemcpy(r.data(), s->resid, sizeof(double) * r.size(), hipMemcpyDeviceToHost));
+        double mx = 0.0;
+        for (double v : r) mx = std::isnan(v) || v > mx ? v : mx;
+        out->resid_max = mx;
+      }
     }
   });
   if (st != PF_OK) return st;
@@ -412,6 +496,55 @@ pf_status pf_session_wait(pf_session* s, pf_result* out) {
     return (pf_status)host.status;
   }
   return PF_OK;
+}
+
+pf_status pf_session_export(pf_session* s, void* U_out, int64_t ldu, double* theta_out, pf_session_state* state,
+                            void* stream) {
+  return guarded([&] {
+    if (!s || !U_out || !state) fail(PF_ERR_ARG, "NULL argument");
+    const pf_desc& d = s->core->desc;
+    if (ldu < d.n) fail(PF_ERR_ARG, "ldu is smaller than n");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // the last step's U, in order after it
+    if (s->stepped) PFX_HIP(hipStreamWaitEvent(st, s->done, 0));
+    const Elem W = d.work == PF_F64 ? Elem::F64 : Elem::F32;
+    launch_copy_block(s->core->U, s->core->ldu, W, U_out, ldu, W, d.n, d.p, d.n, d.p, st);
+    if (theta_out)
+      PFX_HIP(hipMemcpyAsync(theta_out, s->core->theta, sizeof(double) * d.p, hipMemcpyDeviceToDevice, st));
+    pf_session_state out{};
+    out.struct_size = sizeof(pf_session_state);
+    out.desc = d;
+    out.steps = s->core->steps;
+    *state = out;
+  });
+}
+
+pf_status pf_session_import(const pf_session_state* state, const void* U, int64_t ldu, const double* theta,
+                            pf_session** out) {
+  return guarded([&] {
+    if (!state || !U || !out) fail(PF_ERR_ARG, "NULL argument");
+    if (state->struct_size != sizeof(pf_session_state))
+      fail(PF_ERR_ARG, "pf_session_state.struct_size must be sizeof(pf_session_state)");
+    if (state->reserved != 0) fail(PF_ERR_ARG, "pf_session_state.reserved must be 0");
+    if (state->steps < 0) fail(PF_ERR_ARG, "pf_session_state.steps must be >= 0");
+    const pf_desc& d = state->desc;
+    plan_validate(d, nullptr, nullptr);
+    if (ldu < d.n) fail(PF_ERR_ARG, "ldu is smaller than n");
+    pf_session* s = new pf_session();
+    try {
+      s->core = session_create(d, U, ldu, 0, nullptr, false);
+      if (theta)
+        PFX_HIP(hipMemcpyAsync(s->core->theta, theta, sizeof(double) * d.p, hipMemcpyDeviceToDevice, nullptr));
+      PFX_HIP(hipStreamSynchronize(nullptr));
+      s->core->steps = state->steps;
+      PFX_HIP(hipEventCreateWithFlags(&s->done, hipEventDisableTiming));
+    } catch (...) {
+      session_destroy(s->core);
+      delete s;
+      throw;
+    }
+    *out = s;
+  });
 }
 
 pf_status pf_session_close(pf_session* s) {

@@ -187,6 +187,69 @@ struct InfoK {
   }
 };
 
+// Optional outputs of an extraction (residual norms, singular-value
+// shrinkage).  Off the hot path: plain one-thread-per-element kernels.
+//
+// C = D - A S or C = A S for an n x q block C, A n x p (element TA), S p x q
+// (FP64), D n x q (FP64, may be C itself: each thread reads and writes only
+// its own element of D / C), accumulated in FP64.
+template <typename TA, typename TC>
+struct RectArgs {
+  int64_t n; int p, q;
+  const TA* A; int64_t lda;
+  const double* S; int64_t lds_;
+  const double* D; int64_t ldd;
+  TC* C; int64_t ldc;
+};
+template <typename TA, typename TC>
+struct RectK {
+  using Args = RectArgs<TA, TC>;
+  static constexpr int kThreads = 256, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const Args& a, uint3 bid) {
+    const int64_t i = (int64_t)bid.x * 256 + threadIdx.x;
+    const int j = bid.y;
+    if (i >= a.n || j >= a.q) return;
+    double acc = 0.0;
+    for (int k = 0; k < a.p; ++k) acc = fma((double)a.A[i + k * a.lda], a.S[k + j * a.lds_], acc);
+    const double r = a.D ? a.D[i + j * a.ldd] - acc : acc;
+    a.C[i + j * a.ldc] = (TC)r;
+  }
+};
+
+// Per Ritz pair j < p: resid[j] = sqrt(z_j^T G z_j) (G = E^T E, so this is
+// ||E z_j||), and the shrinkage weights of the Gram form:
+// Zs[:, j] = Z[:, j] * max(sigma_j - tau, 0) / sigma_j, sigma_j =
+// sqrt(max(theta_j, 0)) (zero when sigma_j = 0).  One workgroup.
+struct ExtrasArgs {
+  int p; int ld;                 // p x p matrices, leading dimension ld
+  const double* Z; const double* G; const double* theta;
+  double* resid;                 // may be null
+  double tau; double* Zs;        // Zs may be null
+};
+struct ExtrasK {
+  using Args = ExtrasArgs;
+  static constexpr int kThreads = 128, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const Args& a, uint3) {
+    for (int j = threadIdx.x; j < a.p; j += 128) {
+      const double* z = a.Z + (int64_t)j * a.ld;
+      if (a.resid) {
+        double s = 0.0;
+        for (int c = 0; c < a.p; ++c) {
+          double t = 0.0;
+          for (int r = 0; r < a.p; ++r) t = fma(a.G[r + (int64_t)c * a.ld], z[r], t);
+          s = fma(z[c], t, s);
+        }
+        a.resid[j] = sqrt(fmax(s, 0.0));
+      }
+      if (a.Zs) {
+        const double sigma = sqrt(fmax(a.theta[j], 0.0));
+        const double f = sigma > a.tau ? (sigma - a.tau) / sigma : 0.0;
+        for (int r = 0; r < a.p; ++r) a.Zs[r + (int64_t)j * a.ld] = z[r] * f;
+      }
+    }
+  }
+};
+
 template <typename T>
 __global__ void normal_block_kernel(T* dst, int64_t ld, int64_t n, int p, uint64_t seed) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -440,6 +503,33 @@ void launch_axpby(const void* A, const void* B, void* dst, int64_t ld, Elem t, i
                              n, p, alpha, beta};
     emit<AxpbyK<float>>(a, grid, 0, st);
   }
+}
+
+void launch_rect(int64_t n, int p, int q, const void* A, int64_t lda, Elem ta, const double* S, int64_t lds_,
+                 const double* D, int64_t ldd, void* C, int64_t ldc, Elem tc, hipStream_t st) {
+  if (n <= 0 || p <= 0 || q <= 0) return;
+  const dim3 grid((unsigned)((n + 255) / 256), (unsigned)q);
+  if (ta == Elem::F64 && tc == Elem::F64) {
+    const RectArgs<double, double> a{n, p, q, static_cast<const double*>(A), lda, S, lds_, D, ldd,
+                                     static_cast<double*>(C), ldc};
+    emit<RectK<double, double>>(a, grid, 0, st);
+  } else if (ta == Elem::F32 && tc == Elem::F64) {
+    const RectArgs<float, double> a{n, p, q, static_cast<const float*>(A), lda, S, lds_, D, ldd,
+                                    static_cast<double*>(C), ldc};
+    emit<RectK<float, double>>(a, grid, 0, st);
+  } else if (ta == Elem::F64 && tc == Elem::F32) {
+    const RectArgs<double, float> a{n, p, q, static_cast<const double*>(A), lda, S, lds_, D, ldd,
+                                    static_cast<float*>(C), ldc};
+    emit<RectK<double, float>>(a, grid, 0, st);
+  } else {
+    fail(PF_ERR_UNSUPPORTED, "rect: element types");
+  }
+}
+
+void launch_extras(int p, int ld, const double* Z, const double* G, const double* theta, double* resid, double tau,
+                   double* Zs, hipStream_t st) {
+  const ExtrasArgs a{p, ld, Z, G, theta, resid, tau, Zs};
+  emit<ExtrasK>(a, dim3(1), 0, st);
 }
 
 void launch_info_to_host(const pf_info* src, pf_info* host_mapped, hipStream_t st) {

@@ -541,6 +541,9 @@ template <int XK, int MB, int NB>
 void launch_f(FArgs& a, const FSplit& sp, int pm, int pr, hipStream_t st) {
   dim3 grid((unsigned)(sp.mtiles * sp.S), 1, 1);
   const bool prof = prof_enabled();
+  // the whole product (kernel and slab sum) is its own timing class
+  const int pp = pm == PF_PROF_FILTER ? PF_PROF_FILTER_PRODUCT : -1;
+  if (prof && pp >= 0) prof_begin(pp, st);
   if (prof && pm >= 0) prof_begin(pm, st);
   emit<FilterK<XK, MB, NB>>(a, grid, 0, st);
   if (prof && pm >= 0) prof_end(pm, st);
@@ -550,6 +553,7 @@ void launch_f(FArgs& a, const FSplit& sp, int pm, int pr, hipStream_t st) {
     emit<FilterReduceK>(a, g2, 0, st);
     if (prof && pr >= 0) prof_end(pr, st);
   }
+  if (prof && pp >= 0) prof_end(pp, st);
 }
 
 // Rows per workgroup (16-row blocks per wave): every workgroup reloads the

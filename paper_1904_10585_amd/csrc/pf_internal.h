@@ -171,10 +171,26 @@ void launch_psd_dense(const void* V, int64_t ldv, Elem t, const double* theta, i
 
 // ---------------------------------------------------------------------------
 // Kernel timing hooks (pf_profile_*): event pairs around launches of a class.
-constexpr int kProfClasses = 4;
+constexpr int kProfClasses = 5;
 bool prof_enabled();
 void prof_begin(int cls, hipStream_t st);
 void prof_end(int cls, hipStream_t st);
+
+// Named host-side ranges for a tracing profiler (roctx; no-ops unless
+// PF_ROCTX=1).  TraceRange: one range for a scope; next() closes the
+// current range and opens another.
+void trace_push(const char* name);
+void trace_pop();
+struct TraceRange {
+  explicit TraceRange(const char* name) { trace_push(name); }
+  void next(const char* name) {
+    trace_pop();
+    trace_push(name);
+  }
+  ~TraceRange() { trace_pop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // ---------------------------------------------------------------------------
 // Nearest-correlation PFPG loop (k_nce.hip, nce.cpp).
@@ -214,9 +230,11 @@ void plan_validate(const pf_desc& d, const pf_mat* Xf, const pf_mat* Xr);
 // Enqueue one extraction.  U_in (ld ldu_in) may alias U_out.
 // With op, the caller's operator takes the place of Xf and Xr (PF_OP_SYM;
 // no BF16 split).
+// ex: optional outputs (residual norms, the Gram form's shrinkage), or null.
 void enqueue_extraction(Plan* plan, const pf_mat& Xf, const pf_mat& Xr, const void* U_in,
                         int64_t ldu_in, void* U_out, int64_t ldu_out, double* theta_out,
-                        pf_info* info_out, hipStream_t st, const pf_operator* op = nullptr);
+                        pf_info* info_out, hipStream_t st, const pf_operator* op = nullptr,
+                        const pf_extras* ex = nullptr);
 // One PF_OP_SYM extraction whose workspace (plan_bytes(d) bytes, cleared by
 // the caller, 256-byte aligned) starts at base: no allocation.  U_inout is
 // both the start block and the output.
@@ -267,9 +285,18 @@ SessionCore* session_create(const pf_desc& d, const void* U0, int64_t ldu0, uint
 void session_destroy(SessionCore* s);
 // Enqueue one step on st (the first step of a session runs as a cold start).
 void session_enqueue_step(SessionCore* s, const pf_mat& Xf, const pf_mat& Xr, hipStream_t st,
-                          const pf_operator* op = nullptr);
+                          const pf_operator* op = nullptr, const pf_extras* ex = nullptr);
 // Copy the info record of the last step to host-visible memory (a mapped
 // pinned buffer), stream-ordered: the host reads it once the step is done.
 void launch_info_to_host(const pf_info* src, pf_info* host_mapped, hipStream_t st);
+// C (n x q, ld ldc) = D - A S (D FP64 n x q, may be C) or A S (D null);
+// A n x p, S p x q FP64; element types (ta, tc): (F64, F64), (F32, F64),
+// (F64, F32).  FP64 accumulation.
+void launch_rect(int64_t n, int p, int q, const void* A, int64_t lda, Elem ta, const double* S, int64_t lds_,
+                 const double* D, int64_t ldd, void* C, int64_t ldc, Elem tc, hipStream_t st);
+// resid[j] = sqrt(z_j^T G z_j) (resid may be null); Zs[:, j] = z_j *
+// max(sqrt(theta_j) - tau, 0) / sqrt(theta_j) (Zs may be null); j < p.
+void launch_extras(int p, int ld, const double* Z, const double* G, const double* theta, double* resid, double tau,
+                   double* Zs, hipStream_t st);
 
 }  // namespace pfx

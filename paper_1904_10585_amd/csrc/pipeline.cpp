@@ -57,6 +57,7 @@ struct Plan {
   pf_info* info;
   void* part;
   size_t part_bytes;
+  double* Xtra = nullptr;        // 2 p_pad x p_pad: E^T E and the scaled Z of the optional outputs
   // PF_OP_GRAM: M is m x n
   int64_t m = 0, m_pad = 0;
   void* T = nullptr;            // M Y (m x p, work dtype)
@@ -78,6 +79,7 @@ struct Layout {
   size_t off_Up, off_Ypl[3], off_T = 0, off_Tpl = 0, off_B = 0;
   size_t off_U, off_Z, off_Y[3], off_Q1, off_Q, off_W, off_G, off_Rinv, off_Zeig, off_theta,
       off_theta_pre, off_def, off_info, off_part, total, part_bytes, off_E, off_refined;
+  size_t off_xtra = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -107,6 +109,7 @@ Layout layout_for(const pf_desc& d) {
   L.off_theta_pre = o; o += align256((size_t)p_pad * 8);
   L.off_def = o; o += align256((size_t)p_pad * 4);
   L.off_info = o; o += align256(sizeof(pf_info));
+  L.off_xtra = o; o += 2 * sq;
   const size_t planes = align256((size_t)3 * n_pad * p_pad * 2);
   L.off_Up = o; o += (work == Elem::F32) ? planes : 0;
   for (int i = 0; i < 3; ++i) { L.off_Ypl[i] = o; o += (work == Elem::F32) ? planes : 0; }
@@ -281,6 +284,7 @@ void carve(Plan* P, const Layout& L) {
   P->theta_pre = reinterpret_cast<double*>(b + L.off_theta_pre);
   P->deficient = reinterpret_cast<int*>(b + L.off_def);
   P->info = reinterpret_cast<pf_info*>(b + L.off_info);
+  P->Xtra = reinterpret_cast<double*>(b + L.off_xtra);
   P->part = b + L.off_part;
   P->plane = P->n_pad * P->p_pad;
   P->Up = P->work == Elem::F32 ? reinterpret_cast<uint16_t*>(b + L.off_Up) : nullptr;
@@ -471,7 +475,7 @@ void filter_product(Plan* P, const pf_mat& Xf, const void* y, void* out, const v
     f.alpha = alpha; f.beta = beta; f.gamma = gamma;
     f.outp = want_planes ? planes_of(P, out) : nullptr; f.ldop = ld; f.oplane = P->plane;
     f.part = P->part; f.part_bytes = P->part_bytes;
-      f.prof_main = PF_PROF_FILTER; f.prof_reduce = PF_PROF_FILTER_REDUCE;
+    f.prof_main = PF_PROF_FILTER; f.prof_reduce = PF_PROF_FILTER_REDUCE;
     filter_bf16x6(f, st);
   } else {
     contract_into(P, Xf.data, Xf.ld, elem_of(Xf.dtype), y, ld, P->work, P->n, P->n, out, ld, P->work, D1, D2, ld,
@@ -515,7 +519,7 @@ int64_t ph_product(int64_t t) { return kPhFilter + 10 * t; }
 
 void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void* U_in, int64_t ldu_in,
                         void* U_out, int64_t ldu_out, double* theta_out, pf_info* info_out, hipStream_t st,
-                        const pf_operator* op) {
+                        const pf_operator* op, const pf_extras* ex) {
   const pf_desc& d = P->d;
   const double c = 0.5 * (d.a + d.b), e = 0.5 * (d.b - d.a);
   std::vector<double> tau;
@@ -530,6 +534,8 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
   const bool prof = prof_enabled();
   if (prof) prof_begin(PF_PROF_EXTRACT, st);
   const bool split = W == Elem::F32 && !(d.flags & PF_FLAG_NATIVE_F32) && !op;
+  TraceRange trace_all("pf.extract");
+  TraceRange trace("pf.begin");
   set_phase(kPhBegin);
   // U_in into the work buffer (with the planes of Y_0 = U for the split
   // filter) and pf_info cleared, in one launch
@@ -546,6 +552,7 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
     }
   }
 
+  trace.next("pf.filter");
   void* cur = P->U;
   for (int pass = 0; pass < d.q; ++pass) {
     // the planes of Y_0 come with the copy of U; later passes start from
@@ -618,6 +625,7 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
   }
 
   // CholeskyQR2 (section 2.1: orthonormalise the filtered block)
+  trace.next("pf.orth");
   set_phase(kPhOrth);
   gram(P, cur, W, cur, W, P->G, st);
   set_phase(kPhOrth + 1);
@@ -635,6 +643,7 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
   apply(P, P->Q1, nullptr, P->Rinv, P->Q, ld, nullptr, 0.0, 0.0, P->deficient, nullptr, st);
 
   // Rayleigh-Ritz in FP64 (eq. RR)
+  trace.next("pf.rayleigh_ritz");
   set_phase(kPhRR);
   if (d.op == PF_OP_GRAM) {
     // B = M Q (FP64), H = B^T B = Q^T (M^T M) Q: theta = sigma^2
@@ -658,6 +667,29 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
   set_phase(kPhRR + 3);
   apply(P, P->Q, nullptr, P->Zeig, U_out, ldu_out, nullptr, 0.0, 0.0, nullptr, P->info, st, info_out, theta_out);
   set_phase(kPhRR + 4);
+  if (ex && (ex->resid || ex->shrink_left)) {
+    if (current_recorder()) fail(PF_ERR_UNSUPPORTED, "grouped extractions have no optional outputs");
+    trace.next("pf.outputs");
+    double* Gres = P->Xtra;
+    double* Zs = P->Xtra + (size_t)P->p_pad * P->p_pad;
+    if (ex->resid) {
+      if (op) fail(PF_ERR_UNSUPPORTED, "residual norms need a dense operator");
+      // W = A Q (the Gram form: M^T B, B = M Q), then E = W - Q H in place;
+      // the residual of Ritz pair j is ||E z_j|| (H z_j = theta_j z_j), from
+      // the Gram matrix E^T E
+      if (d.op == PF_OP_GRAM)
+        contract_into(P, Xr.data, Xr.ld, tr, P->B, P->m_pad, Elem::F64, P->m, P->n, P->W, ld, Elem::F64, nullptr,
+                      nullptr, ld, 1.0, 0.0, 0.0, true, st, -1, -1);
+      launch_rect(P->n, P->p, P->p, P->Q, ld, W, P->G, P->p_pad, P->W, ld, P->W, ld, Elem::F64, st);
+      gram(P, P->W, Elem::F64, P->W, Elem::F64, Gres, st);
+    }
+    launch_extras(P->p, P->p_pad, P->Zeig, Gres, P->theta, ex->resid, ex->shrink_tau,
+                  ex->shrink_left ? Zs : nullptr, st);
+    // shrink_tau(M P_V) = (B Zs) V^T
+    if (ex->shrink_left)
+      launch_rect(P->m, P->p, P->p, P->B, P->m_pad, Elem::F64, Zs, P->p_pad, nullptr, 0, ex->shrink_left,
+                  ex->ld_shrink, W, st);
+  }
   if (prof) prof_end(PF_PROF_EXTRACT, st);
 }
 

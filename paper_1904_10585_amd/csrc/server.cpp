@@ -28,6 +28,7 @@
 #include <condition_variable>
 #include <deque>
 #include <functional>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <string>
@@ -268,6 +269,7 @@ void fail_request(pf_server* S, SrvSession* s, const Request& r, int32_t status)
 // member's stream order with its earlier work (initialisation, previous
 // step) comes from its slot event.
 void launch_batch(pf_server* S, const std::vector<SrvSession*>& members) {
+  TraceRange trace("pf.server.batch");
   hipStream_t B = S->streams[S->next_stream];
   S->next_stream = (S->next_stream + 1) % (int)S->streams.size();
   std::vector<ExtractionJob> jobs(members.size());
@@ -556,6 +558,8 @@ pf_status pf_server_result(pf_server* S, int32_t session, pf_result* out) {
     out->V = s->slot.core->U;
     out->ldv = s->slot.core->ldu;
     out->info = s->slot.core->info;
+    out->resid = nullptr;
+    out->resid_max = std::numeric_limits<double>::quiet_NaN();
   });
 }
 

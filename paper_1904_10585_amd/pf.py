@@ -28,7 +28,8 @@ PF_FLAG_COLD = 0x4
 PF_FLAG_NATIVE_F32 = 0x8
 PF_FLAG_OPERATOR_UNCHANGED = 0x10
 PF_FLAG_REORTH = 0x20
-PF_PROF_FILTER, PF_PROF_FILTER_REDUCE, PF_PROF_RR, PF_PROF_EXTRACT = range(4)
+PF_PROF_FILTER, PF_PROF_FILTER_REDUCE, PF_PROF_RR, PF_PROF_EXTRACT, PF_PROF_FILTER_PRODUCT = range(5)
+PF_PROF_MODE_PRODUCT = 2
 
 
 class PfMat(ctypes.Structure):
@@ -52,7 +53,18 @@ class PfInfo(ctypes.Structure):
 
 class PfResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("n_pos", ctypes.c_int32), ("theta", ctypes.c_void_p),
-                ("V", ctypes.c_void_p), ("ldv", ctypes.c_int64), ("info", ctypes.c_void_p)]
+                ("V", ctypes.c_void_p), ("ldv", ctypes.c_int64), ("info", ctypes.c_void_p),
+                ("resid", ctypes.c_void_p), ("resid_max", ctypes.c_double)]
+
+
+class PfExtras(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("reserved", ctypes.c_int32), ("resid", ctypes.c_void_p),
+                ("shrink_tau", ctypes.c_double), ("shrink_left", ctypes.c_void_p), ("ld_shrink", ctypes.c_int64)]
+
+
+class PfSessionState(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("reserved", ctypes.c_int32), ("desc", PfDesc),
+                ("steps", ctypes.c_int64)]
 
 
 APPLY_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
@@ -133,6 +145,10 @@ def _load():
     vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     sig = {
         "pf_extract": (i32, [P(PfDesc), P(PfMat), P(PfMat), vp, i64, vp, vp, vp]),
+        "pf_extract_ex": (i32, [P(PfDesc), P(PfMat), P(PfMat), vp, i64, vp, vp, P(PfExtras), vp]),
+        "pf_session_step_ex": (i32, [vp, P(PfMat), P(PfMat), P(PfExtras), P(PfResult), vp]),
+        "pf_session_export": (i32, [vp, vp, i64, vp, P(PfSessionState), vp]),
+        "pf_session_import": (i32, [P(PfSessionState), vp, i64, vp, P(vp)]),
         "pf_extract_noalloc": (i32, [P(PfDesc), P(PfMat), P(PfMat), vp, i64, vp, vp, vp]),
         "pf_extract_noalloc_max_bytes": (ctypes.c_size_t, []),
         "pf_session_open": (i32, [P(PfDesc), vp, i64, ctypes.c_uint64, P(vp)]),
@@ -252,6 +268,28 @@ def pf_extract(d, X_filter, X_rr, U, theta, info=None, stream=None):
                           ctypes.c_void_p(info.data_ptr()) if info is not None else None, _stream(stream)))
 
 
+def extras(resid=None, shrink_left=None, shrink_tau=0.0):
+    """A pf_extras record: resid (device, p doubles) and/or the left factor
+    of the Gram form's singular-value shrinkage (device m x p, column-major)."""
+    e = PfExtras()
+    e.struct_size = ctypes.sizeof(PfExtras)
+    e.reserved = 0
+    e.resid = resid.data_ptr() if resid is not None else None
+    e.shrink_tau = float(shrink_tau)
+    e.shrink_left = shrink_left.data_ptr() if shrink_left is not None else None
+    e.ld_shrink = ld_of(shrink_left) if shrink_left is not None else 0
+    return e
+
+
+def pf_extract_ex(d, X_filter, X_rr, U, theta, ex, info=None, stream=None):
+    """pf_extract with the optional outputs of ``ex`` (see ``extras``)."""
+    xf, xr = mat(X_filter), mat(X_rr)
+    _check(LIB.pf_extract_ex(ctypes.byref(d), ctypes.byref(xf), ctypes.byref(xr), ctypes.c_void_p(U.data_ptr()),
+                             ld_of(U), ctypes.c_void_p(theta.data_ptr()),
+                             ctypes.c_void_p(info.data_ptr()) if info is not None else None,
+                             ctypes.byref(ex) if ex is not None else None, _stream(stream)))
+
+
 def pf_extract_noalloc(d, X_filter, X_rr, U, theta, info=None, stream=None):
     """pf_extract with the library's fixed device workspace (no allocation)."""
     xf, xr = mat(X_filter), mat(X_rr)
@@ -276,6 +314,30 @@ def pf_session_step(h, X_filter, X_rr, stream=None):
     xf, xr = mat(X_filter), mat(X_rr)
     _check(LIB.pf_session_step(h, ctypes.byref(xf), ctypes.byref(xr), ctypes.byref(r), _stream(stream)))
     return r
+
+
+def pf_session_step_ex(h, X_filter, X_rr, ex, stream=None):
+    r = PfResult()
+    xf, xr = mat(X_filter), mat(X_rr)
+    _check(LIB.pf_session_step_ex(h, ctypes.byref(xf), ctypes.byref(xr), ctypes.byref(ex) if ex is not None else None,
+                                  ctypes.byref(r), _stream(stream)))
+    return r
+
+
+def pf_session_export(h, U_out, theta_out=None, stream=None):
+    """Copy the session's block (and theta) into caller buffers; returns its state."""
+    st = PfSessionState()
+    _check(LIB.pf_session_export(h, ctypes.c_void_p(U_out.data_ptr()), ld_of(U_out),
+                                 ctypes.c_void_p(theta_out.data_ptr()) if theta_out is not None else None,
+                                 ctypes.byref(st), _stream(stream)))
+    return st
+
+
+def pf_session_import(state, U, theta=None):
+    h = ctypes.c_void_p()
+    _check(LIB.pf_session_import(ctypes.byref(state), ctypes.c_void_p(U.data_ptr()), ld_of(U),
+                                 ctypes.c_void_p(theta.data_ptr()) if theta is not None else None, ctypes.byref(h)))
+    return h
 
 
 def pf_session_wait(h):
@@ -542,8 +604,10 @@ def pf_workspace_size(d):
     return n.value
 
 
-def pf_profile_set(enable):
-    _check(LIB.pf_profile_set(1 if enable else 0))
+def pf_profile_set(mode):
+    """0: off; 1 (or True): per-kernel classes; PF_PROF_MODE_PRODUCT: the
+    filter product (kernel and split-K sum) under one event pair."""
+    _check(LIB.pf_profile_set(int(mode)))
 
 
 def pf_profile_read(which):

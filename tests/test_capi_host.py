@@ -29,10 +29,29 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version_and_strings():
-    assert pf.LIB.pf_abi_version() == 2
+    assert pf.LIB.pf_abi_version() == 3
     for s in range(9):
         assert pf.status_string(s).startswith("PF_")
     assert pf.status_string(99) == "unknown pf_status"
+
+
+def test_binding_constants_match_header():
+    """Every #define of pf.h that the binding mirrors has the header's value."""
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"^#define (PF_[A-Z0-9_]+) (0x[0-9a-fA-F]+|[0-9]+)u?\b", text, re.M))
+    assert len(defs) >= 14
+    mirrored = 0
+    for name, val in defs.items():
+        if hasattr(pf, name):
+            assert getattr(pf, name) == int(val, 0), name
+            mirrored += 1
+    assert mirrored >= 12
+
+
+def test_profile_mode_rejects_unknown():
+    assert pf.LIB.pf_profile_set(7) == pf.PF_ERR_ARG
+    assert "profiling mode" in pf.LIB.pf_last_error().decode()
+    assert pf.LIB.pf_profile_set(0) == 0
 
 
 def test_struct_layout_matches_c_compiler(tmp_path):
@@ -46,7 +65,7 @@ def test_struct_layout_matches_c_compiler(tmp_path):
                "pf_server_config": pf.PfServerConfig, "pf_server_event": pf.PfServerEvent,
                "pf_server_stats": pf.PfServerStats, "pf_bounds": pf.PfBounds, "pf_operator": pf.PfOperator,
                "pf_nce_opts": pf.PfNceOpts, "pf_nce_result": pf.PfNceResult, "pf_pfam_opts": pf.PfPfamOpts,
-               "pf_pfam_result": pf.PfPfamResult}
+               "pf_pfam_result": pf.PfPfamResult, "pf_extras": pf.PfExtras, "pf_session_state": pf.PfSessionState}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pf.h"', "int main(void){"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -156,6 +175,60 @@ def test_extract_rejects_before_launch(case):
         d.flags = pf.PF_FLAG_NATIVE_F32
     assert _extract_raw(d, xf, xr, U, ldu, theta) == want
     assert pf.last_error()
+
+
+def _extras(**kw):
+    e = pf.PfExtras()
+    e.struct_size = ctypes.sizeof(pf.PfExtras)
+    for k, v in kw.items():
+        setattr(e, k, v)
+    return e
+
+
+@pytest.mark.parametrize("case,want", [
+    ("size", pf.PF_ERR_ARG), ("reserved", pf.PF_ERR_ARG), ("shrink_sym", pf.PF_ERR_ARG),
+    ("tau_neg", pf.PF_ERR_ARG), ("tau_nan", pf.PF_ERR_ARG), ("ld_shrink", pf.PF_ERR_ARG),
+])
+def test_extract_ex_rejects_before_launch(case, want):
+    """Bad optional-output records are refused before anything is enqueued."""
+    gram = case in ("tau_neg", "tau_nan", "ld_shrink")
+    d = good_desc(op=pf.PF_OP_GRAM, m=300) if gram else good_desc()
+    xf = fake_mat(ld=300 if gram else 256)
+    e = _extras(shrink_left=0x20000, shrink_tau=0.5, ld_shrink=300)
+    if case == "size":
+        e.struct_size = 8
+    elif case == "reserved":
+        e.reserved = 1
+    elif case == "tau_neg":
+        e.shrink_tau = -1.0
+    elif case == "tau_nan":
+        e.shrink_tau = float("nan")
+    elif case == "ld_shrink":
+        e.ld_shrink = 299
+    r = pf.LIB.pf_extract_ex(ctypes.byref(d), ctypes.byref(xf), ctypes.byref(xf), ctypes.c_void_p(0x30000), 256,
+                             ctypes.c_void_p(0x40000), None, ctypes.byref(e), None)
+    assert r == want, pf.last_error()
+    assert pf.last_error()
+
+
+def test_session_import_rejects_bad_state():
+    st = pf.PfSessionState()
+    st.struct_size = ctypes.sizeof(pf.PfSessionState)
+    st.desc = good_desc()
+    h = ctypes.c_void_p()
+    U = ctypes.c_void_p(0x10000)
+    bad = [("struct_size", 4), ("reserved", 1), ("steps", -1)]
+    for field, value in bad:
+        s2 = pf.PfSessionState.from_buffer_copy(st)
+        setattr(s2, field, value)
+        assert pf.LIB.pf_session_import(ctypes.byref(s2), U, 256, None, ctypes.byref(h)) == pf.PF_ERR_ARG, field
+    s2 = pf.PfSessionState.from_buffer_copy(st)
+    s2.desc.p = 0
+    assert pf.LIB.pf_session_import(ctypes.byref(s2), U, 256, None, ctypes.byref(h)) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_session_import(ctypes.byref(st), U, 100, None, ctypes.byref(h)) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_session_import(None, U, 256, None, ctypes.byref(h)) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_session_export(None, U, 256, None, ctypes.byref(st), None) == pf.PF_ERR_ARG
+    assert pf.LIB.pf_session_step_ex(None, None, None, None, None, None) == pf.PF_ERR_ARG
 
 
 def test_session_and_helpers_reject_nulls():
