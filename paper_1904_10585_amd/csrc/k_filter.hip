@@ -17,9 +17,9 @@
 // Layout: X is K x M column-major and used as X^T (X symmetric).  A
 // workgroup of four waves owns 4 * 16 * MB output rows (16 * MB per wave)
 // and all 16 * NB columns over a K range; grid.z splits K (summed in slab
-// order by a second kernel).  The three Y planes of each K step of 32 are
-// staged once per workgroup in double-buffered LDS and shared by the four
-// waves.  Lane l holds A[m = l%16][k = 8(l/16) .. +7] (eight consecutive K
+// order by a second kernel).  The Y planes of each K step of 32 are staged
+// once per workgroup in an LDS ring of four or five stages and shared by the
+// four waves.  Lane l holds A[m = l%16][k = 8(l/16) .. +7] (eight consecutive K
 // values of one X column: 32 bytes, one cache line per column and step) and
 // B[k = 8(l/16) .. +7][n = l%16] (16 bytes of one Y plane column).
 #include "pf_internal.h"
@@ -116,15 +116,17 @@ __device__ inline void store_out(const FArgs& a, int64_t row, int64_t col, float
 // stage keeps the compiler's LDS-DMA dependency tracking exact.
 //
 // X element kinds.  F32: split exactly into three BF16 pieces in registers
-// (six MFMA cross terms).  BF16: used as stored (three MFMAs, one per Y
-// plane).  FP8 (OCP E4M3FN): decoded exactly to BF16 in registers, three
-// MFMAs per tile, then scaled by the FP32 scale of its tile x tile block.
+// (six MFMA cross terms).  BF16: used as stored, against the leading two Y
+// planes (two MFMAs): Y is then carried to 16 significand bits (relative
+// error below 2^-15), far finer than the 8 bits of X itself.  FP8 (OCP
+// E4M3FN): decoded exactly to BF16 in registers, two MFMAs per tile as for
+// BF16, then scaled by the FP32 scale of its tile x tile block.
 constexpr int XK_F32 = 0, XK_BF16 = 1, XK_FP8 = 2;
 
 // X stage: ROWS columns of X x 32 K values in 16-byte chunks, XCPC chunks
 // per column; chunk (col, kc) at col * XCPC + (kc ^ swizzle(col)), the
 // swizzle spreading the lanes of one LDS read over the banks.  Y stage:
-// 3 planes x N columns x 32 K values, chunk (q, j, kc) at
+// YPL planes x N columns x 32 K values, chunk (q, j, kc) at
 // ((q * N + j) * 4) + (kc ^ ((j >> 1) & 3)).
 template <int XK, int MB, int NB>
 struct FCfg {
@@ -133,8 +135,16 @@ struct FCfg {
   static constexpr int EPC = 16 / ES;             // X elements per chunk
   static constexpr int ROWS = kWaves * 16 * MB;   // output rows (X columns) per workgroup
   static constexpr int N16 = 16 * NB;
+  // Y planes read per stage: all three for an FP32 X (the exact product);
+  // the leading two for a BF16 or FP8 X, whose own rounding (2^-9 and
+  // below) is far above the 2^-15 that dropping Y's third plane adds
+  static constexpr int YPL = XK == XK_F32 ? 3 : 2;
+  // LDS ring depth: four 40 KiB stages for an FP32 X, five 32 KiB stages
+  // for the smaller two-plane stages of a BF16 or FP8 X (more bytes in
+  // flight per CU against the load latency)
+  static constexpr int NS = XK == XK_F32 ? 4 : 5;
   static constexpr int XCH = ROWS * XCPC;         // 16-byte X chunks per stage
-  static constexpr int YCH = 3 * N16 * 4;         // 16-byte Y chunks per stage
+  static constexpr int YCH = YPL * N16 * 4;       // 16-byte Y chunks per stage
   static constexpr int XOPS = XCH / kThreads;     // X wave-loads per wave per stage
   static_assert(XOPS * kThreads == XCH, "X stage must be a whole number of wave-loads");
   static constexpr int YINSTR = YCH / 64;         // Y wave-loads per workgroup per stage
@@ -151,8 +161,19 @@ struct FCfg {
 // The four stage buffers are file-scope LDS objects (sized for the largest
 // tile): the compiler gives each its own alias scope, so the LDS reads of one
 // stage wait only for the direct loads into that stage.
-constexpr int kStageChunks = 2560;                 // 40 KiB per stage, 160 KiB for the ring
+constexpr int kStageChunks = 2560;                 // 40 KiB per stage, 160 KiB for a 4-stage ring
 __shared__ u4v g_st0[kStageChunks], g_st1[kStageChunks], g_st2[kStageChunks], g_st3[kStageChunks];
+constexpr int kStage5Chunks = 2048;                // 32 KiB per stage, 160 KiB for a 5-stage ring
+__shared__ u4v g_sf0[kStage5Chunks], g_sf1[kStage5Chunks], g_sf2[kStage5Chunks], g_sf3[kStage5Chunks],
+    g_sf4[kStage5Chunks];
+
+template <int B, int E, typename F>
+__device__ __attribute__((always_inline)) inline void unroll_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    unroll_for<B + 1, E>(f);
+  }
+}
 
 // One 16-byte direct global->LDS load per lane (global_load_lds_dwordx4).
 // Kept out of the kernel templates: the builtin exists only for the device.
@@ -184,11 +205,16 @@ struct FilterK {
 template <int XK, int MB, int NB>
 __device__ void FilterK<XK, MB, NB>::body(const FArgs& a, uint3 bid) {
   using C = FCfg<XK, MB, NB>;
-  static_assert(C::STAGE <= kStageChunks, "stage does not fit its LDS buffer");
-  u4v* const st0 = g_st0;
-  u4v* const st1 = g_st1;
-  u4v* const st2 = g_st2;
-  u4v* const st3 = g_st3;
+  constexpr int NS = C::NS;
+  static_assert(C::STAGE <= (NS == 4 ? kStageChunks : kStage5Chunks), "stage does not fit its LDS buffer");
+  u4v* slot[NS];
+  if constexpr (NS == 4) {
+    slot[0] = g_st0; slot[1] = g_st1; slot[2] = g_st2; slot[3] = g_st3;
+  } else {
+    static_assert(NS == 5, "ring depth");
+    slot[0] = g_sf0; slot[1] = g_sf1; slot[2] = g_sf2; slot[3] = g_sf3; slot[4] = g_sf4;
+  }
+  u4v* const st0 = slot[0];
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int c = lane & 15, g = lane >> 4;
@@ -297,16 +323,13 @@ __device__ void FilterK<XK, MB, NB>::body(const FArgs& a, uint3 bid) {
           const int sw = g ^ ((j >> 1) & 3);
           const bf8v b1 = as_bf8(ys[(0 * C::N16 + j) * 4 + sw]);
           const bf8v b2 = as_bf8(ys[(1 * C::N16 + j) * 4 + sw]);
-          const bf8v b3 = as_bf8(ys[(2 * C::N16 + j) * 4 + sw]);
           if constexpr (XK == XK_BF16) {
             f4v cc = acc[mb][nb];
-            cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, b3, cc, 0, 0, 0);
             cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, b2, cc, 0, 0, 0);
             cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, b1, cc, 0, 0, 0);
             acc[mb][nb] = cc;
           } else {
             f4v cc = f4v{0, 0, 0, 0};
-            cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, b3, cc, 0, 0, 0);
             cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, b2, cc, 0, 0, 0);
             cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, b1, cc, 0, 0, 0);
 #pragma unroll
@@ -317,38 +340,32 @@ __device__ void FilterK<XK, MB, NB>::body(const FArgs& a, uint3 bid) {
     }
   };
 
-  u4v* const slot[4] = {st0, st1, st2, st3};
   const int64_t nfull = (kend - kbeg) / KSTEP;
-  // Every stage issues the loads of the stage three ahead; past the last
+  // Every stage issues the loads of the stage NS - 1 ahead; past the last
   // full stage they repeat the last one (an L2 hit, never consumed), so the
   // issue code and the wait counts are the same on every stage.
   const int64_t klast = kbeg + (nfull - 1) * KSTEP;
-  // sl is a literal at every call, so each stage's LDS object is known
-  auto body = [&](int sl, int64_t st) {
-    // this wave's loads of stage st are done once only the loads of the two
-    // stages issued after it are outstanding, and its LDS reads of stage
-    // st - 1 once lgkmcnt is 0; the barrier then makes every wave's loads
-    // of stage st visible and frees the slot of stage st - 1
-    wait_vmcnt<2 * C::OPS, 0>();
+  // the slot index is a compile-time constant at every call, so each
+  // stage's LDS object is known
+  auto body = [&](auto SL, int64_t st) {
+    constexpr int sl = decltype(SL)::value;
+    // this wave's loads of stage st are done once only the loads of the
+    // NS - 2 stages issued after it are outstanding, and its LDS reads of
+    // stage st - 1 once lgkmcnt is 0; the barrier then makes every wave's
+    // loads of stage st visible and frees the slot of stage st - 1
+    wait_vmcnt<(NS - 2) * C::OPS, 0>();
     wg_barrier();
     const float sc = xscale(kbeg + st * KSTEP);
-    issue(slot[(sl + 3) & 3], min(kbeg + (st + 3) * KSTEP, klast));
+    issue(slot[(sl + NS - 1) % NS], min(kbeg + (st + NS - 1) * KSTEP, klast));
     compute(slot[sl], slot[sl] + C::XCH, sc);
   };
   if (nfull > 0) {
-    issue(st0, kbeg);
-    issue(st1, min(kbeg + KSTEP, klast));
-    issue(st2, min(kbeg + 2 * KSTEP, klast));
+    unroll_for<0, NS - 1>([&](auto I) { issue(slot[decltype(I)::value], min(kbeg + decltype(I)::value * KSTEP, klast)); });
     int64_t st = 0;
-    for (; st + 4 <= nfull; st += 4) {
-      body(0, st);
-      body(1, st + 1);
-      body(2, st + 2);
-      body(3, st + 3);
-    }
-    if (st < nfull) body(0, st);
-    if (st + 1 < nfull) body(1, st + 1);
-    if (st + 2 < nfull) body(2, st + 2);
+    for (; st + NS <= nfull; st += NS) unroll_for<0, NS>([&](auto I) { body(I, st + decltype(I)::value); });
+    unroll_for<0, NS - 1>([&](auto I) {
+      if (st + decltype(I)::value < nfull) body(I, st + decltype(I)::value);
+    });
     wait_vmcnt<0>();                       // the repeated loads land before LDS is reused
   }
   const int64_t ktail = kbeg + nfull * KSTEP;

@@ -1,8 +1,9 @@
 """Summaries of rocprofv3 output for the extraction kernels.
 
-    python -m paper_1904_10585_amd.rocprof_summary trace <results.db> [--steps K]
+    python -m paper_1904_10585_amd.rocprof_summary trace <results.db> [--steps K] [--match TEXT]
         per-kernel call count, total and average duration from a
-        ``rocprofv3 --kernel-trace`` SQLite database;
+        ``rocprofv3 --kernel-trace`` SQLite database (optionally only the
+        kernels whose name contains TEXT);
     python -m paper_1904_10585_amd.rocprof_summary counters <run.csv>... --kernel NAME
         per-dispatch mean of every counter of one kernel over one or more
         ``rocprofv3 --pmc`` runs (CSV output);
@@ -37,10 +38,12 @@ def short_name(name):
     return re.sub(r"\(.*", "", s)
 
 
-def trace(db, steps):
+def trace(db, steps, match=None):
     con = sqlite3.connect(db)
     rows = con.execute("select name, count(*), sum(duration), avg(duration), min(duration), max(duration) "
                        "from kernels group by name order by sum(duration) desc").fetchall()
+    if match:
+        rows = [r for r in rows if any(m in short_name(r[0]) for m in match)]
     print(f"| kernel | calls | total ms | avg us | min us | max us |" + (" ms/step |" if steps else ""))
     print("|---|---:|---:|---:|---:|---:|" + ("---:|" if steps else ""))
     for name, n, tot, avg, mn, mx in rows:
@@ -170,6 +173,8 @@ def main():
     t = sub.add_parser("trace")
     t.add_argument("db")
     t.add_argument("--steps", type=float, default=0)
+    t.add_argument("--match", action="append",
+                   help="keep only kernels whose short name contains this text (repeatable)")
     b = sub.add_parser("bytes")
     b.add_argument("fetch_csv")
     b.add_argument("write_csv")
@@ -184,7 +189,7 @@ def main():
     c.add_argument("--kernel", required=True)
     a = ap.parse_args()
     if a.cmd == "trace":
-        trace(a.db, a.steps)
+        trace(a.db, a.steps, a.match)
     elif a.cmd == "counters":
         counters(a.csv, a.kernel)
     elif a.cmd == "product":
