@@ -691,6 +691,16 @@ pf_status pf_profile_read(int which, int64_t* launches, double* total_ms);
 
 /* Device workspace bytes pf_extract uses for desc (allocated on first use). */
 pf_status pf_workspace_size(const pf_desc* desc, size_t* bytes);
+/* The workspace cache of pf_extract / pf_extract_batch: one workspace per
+ * device, stream and shape (n, m, p, work dtype, operator; degree, power,
+ * interval and flags do not make a new one).  pf_workspace_cached reports
+ * the device bytes and the number of cached workspaces (all devices and
+ * streams, operator copies of the Gram form included).  pf_workspace_release
+ * waits for the stream (on the current device), then frees the workspaces
+ * cached for it; later calls on that stream allocate again.  Sessions and
+ * servers own their workspaces and are not affected. */
+pf_status pf_workspace_cached(size_t* bytes, int32_t* count);
+pf_status pf_workspace_release(void* stream);
 
 const char* pf_status_string(pf_status s);
 const char* pf_last_error(void);

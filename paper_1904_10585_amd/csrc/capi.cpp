@@ -310,6 +310,40 @@ pf_status pf_profile_read(int which, int64_t* launches, double* total_ms) {
   });
 }
 
+pf_status pf_workspace_cached(size_t* bytes, int32_t* count) {
+  return guarded([&] {
+    if (!bytes || !count) fail(PF_ERR_ARG, "NULL output");
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    size_t b = 0;
+    for (const auto& kv : g_plans) b += plan_device_bytes(kv.second);
+    *bytes = b;
+    *count = (int32_t)g_plans.size();
+  });
+}
+
+pf_status pf_workspace_release(void* stream) {
+  return guarded([&] {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    PFX_HIP(hipGetDevice(&dev));
+    std::vector<Plan*> gone;
+    {
+      std::lock_guard<std::mutex> lk(g_plans_mu);
+      for (auto it = g_plans.begin(); it != g_plans.end();) {
+        if (std::get<0>(it->first) == dev && std::get<1>(it->first) == reinterpret_cast<uintptr_t>(st)) {
+          gone.push_back(it->second);
+          it = g_plans.erase(it);
+        } else {
+          ++it;
+        }
+      }
+    }
+    if (gone.empty()) return;
+    PFX_HIP(hipStreamSynchronize(st));        // the stream's extractions are done with them
+    for (Plan* P : gone) plan_destroy(P);
+  });
+}
+
 pf_status pf_workspace_size(const pf_desc* desc, size_t* bytes) {
   return guarded([&] {
     if (!desc || !bytes) fail(PF_ERR_ARG, "NULL argument");

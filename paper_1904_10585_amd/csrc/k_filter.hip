@@ -269,26 +269,50 @@ __device__ void FilterK<XK, MB, NB>::body(const FArgs& a, uint3 bid) {
     if constexpr (XK == XK_FP8) return a.xscale[k0 / a.tile + (mt0 / a.tile) * a.ldsc];
     else return 1.0f;
   };
-  auto compute = [&](const u4v* xs, const u4v* ys, float sc) {
+  // One stage's operands in registers: per 16-row block of the wave its X
+  // chunk(s) (FP32: the two 16-byte halves of eight values; BF16: one chunk;
+  // FP8: eight codes), per 16-column block its Y planes.  They are read from
+  // LDS one stage ahead of the MFMAs that use them.
+  struct Frags {
+    u4v xa[MB], xb[MB];
+    uint2v xq[MB];
+    u4v y[NB][C::YPL];
+  };
+  auto load = [&](Frags& f, const u4v* xs, const u4v* ys) {
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
       const int col = wave * (16 * MB) + 16 * mb + c;
       if constexpr (XK == XK_F32) {
-        const u4v lo = xs[col * 8 + ((2 * g) ^ C::xswz(col))];
-        const u4v hi = xs[col * 8 + ((2 * g + 1) ^ C::xswz(col))];
+        f.xa[mb] = xs[col * 8 + ((2 * g) ^ C::xswz(col))];
+        f.xb[mb] = xs[col * 8 + ((2 * g + 1) ^ C::xswz(col))];
+      } else if constexpr (XK == XK_BF16) {
+        f.xa[mb] = xs[col * 4 + (g ^ C::xswz(col))];
+      } else {
+        const uint2v* xh = reinterpret_cast<const uint2v*>(xs);
+        f.xq[mb] = xh[(col * 2 + ((g >> 1) ^ C::xswz(col))) * 2 + (g & 1)];
+      }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int j = 16 * nb + c;
+      const int sw = g ^ ((j >> 1) & 3);
+#pragma unroll
+      for (int q = 0; q < C::YPL; ++q) f.y[nb][q] = ys[(q * C::N16 + j) * 4 + sw];
+    }
+  };
+  auto mma = [&](const Frags& f, float sc) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      if constexpr (XK == XK_F32) {
         float xv[8];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) { xv[i] = __uint_as_float(lo[i]); xv[4 + i] = __uint_as_float(hi[i]); }
+        for (int i = 0; i < 4; ++i) { xv[i] = __uint_as_float(f.xa[mb][i]); xv[4 + i] = __uint_as_float(f.xb[mb][i]); }
         u4v x1, x2, x3;
         split8(xv, x1, x2, x3);
         const bf8v a1 = as_bf8(x1), a2 = as_bf8(x2), a3 = as_bf8(x3);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-          const int j = 16 * nb + c;
-          const int sw = g ^ ((j >> 1) & 3);
-          const bf8v b1 = as_bf8(ys[(0 * C::N16 + j) * 4 + sw]);
-          const bf8v b2 = as_bf8(ys[(1 * C::N16 + j) * 4 + sw]);
-          const bf8v b3 = as_bf8(ys[(2 * C::N16 + j) * 4 + sw]);
+          const bf8v b1 = as_bf8(f.y[nb][0]), b2 = as_bf8(f.y[nb][1]), b3 = as_bf8(f.y[nb][2]);
           f4v cc = acc[mb][nb];
           cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, b1, cc, 0, 0, 0);   // smallest terms first
           cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b2, cc, 0, 0, 0);
@@ -301,11 +325,10 @@ __device__ void FilterK<XK, MB, NB>::body(const FArgs& a, uint3 bid) {
       } else {
         bf8v ax;
         if constexpr (XK == XK_BF16) {
-          ax = as_bf8(xs[col * 4 + (g ^ C::xswz(col))]);
+          ax = as_bf8(f.xa[mb]);
         } else {
-          // eight E4M3 codes (half a chunk) -> exact BF16 via FP32
-          const uint2v* xh = reinterpret_cast<const uint2v*>(xs);
-          const uint2v q = xh[(col * 2 + ((g >> 1) ^ C::xswz(col))) * 2 + (g & 1)];
+          // eight E4M3 codes -> exact BF16 via FP32
+          const uint2v q = f.xq[mb];
           const f2v f0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)q[0], false);
           const f2v f1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)q[0], true);
           const f2v f2 = __builtin_amdgcn_cvt_pk_f32_fp8((int)q[1], false);
@@ -319,10 +342,7 @@ __device__ void FilterK<XK, MB, NB>::body(const FArgs& a, uint3 bid) {
         }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-          const int j = 16 * nb + c;
-          const int sw = g ^ ((j >> 1) & 3);
-          const bf8v b1 = as_bf8(ys[(0 * C::N16 + j) * 4 + sw]);
-          const bf8v b2 = as_bf8(ys[(1 * C::N16 + j) * 4 + sw]);
+          const bf8v b1 = as_bf8(f.y[nb][0]), b2 = as_bf8(f.y[nb][1]);
           if constexpr (XK == XK_BF16) {
             f4v cc = acc[mb][nb];
             cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, b2, cc, 0, 0, 0);
@@ -341,32 +361,70 @@ __device__ void FilterK<XK, MB, NB>::body(const FArgs& a, uint3 bid) {
   };
 
   const int64_t nfull = (kend - kbeg) / KSTEP;
-  // Every stage issues the loads of the stage NS - 1 ahead; past the last
-  // full stage they repeat the last one (an L2 hit, never consumed), so the
-  // issue code and the wait counts are the same on every stage.
+  // Past the last full stage the loads repeat the last one (an L2 hit, never
+  // consumed), so the issue code and the wait counts are the same on every
+  // stage.
   const int64_t klast = kbeg + (nfull - 1) * KSTEP;
-  // the slot index is a compile-time constant at every call, so each
-  // stage's LDS object is known
-  auto body = [&](auto SL, int64_t st) {
-    constexpr int sl = decltype(SL)::value;
-    // this wave's loads of stage st are done once only the loads of the
-    // NS - 2 stages issued after it are outstanding, and its LDS reads of
-    // stage st - 1 once lgkmcnt is 0; the barrier then makes every wave's
-    // loads of stage st visible and frees the slot of stage st - 1
-    wait_vmcnt<(NS - 2) * C::OPS, 0>();
-    wg_barrier();
-    const float sc = xscale(kbeg + st * KSTEP);
-    issue(slot[(sl + NS - 1) % NS], min(kbeg + (st + NS - 1) * KSTEP, klast));
-    compute(slot[sl], slot[sl] + C::XCH, sc);
-  };
-  if (nfull > 0) {
-    unroll_for<0, NS - 1>([&](auto I) { issue(slot[decltype(I)::value], min(kbeg + decltype(I)::value * KSTEP, klast)); });
+  // Operands read from LDS one stage ahead of their MFMAs where that pays:
+  // the tall BF16 tiles (p > 64) and the FP8 tiles up to p = 96 (wider ones
+  // have no room for the second set of registers).  Measured one product at
+  // a time: BF16 n = 16384, p = 128 261 -> 234 us; FP8 Gram products,
+  // p = 48, 54.9 / 43.3 -> 50.7 / 41.0 us; the FP32 product (p = 64) and
+  // the BF16 product at p = 64 gain nothing (72.7 -> 74.4, 36.2 -> 36.6 us).
+  constexpr bool kAhead = (XK == XK_BF16 && MB == 4) || (XK == XK_FP8 && NB <= 6);
+  if (nfull > 0 && kAhead) {
+    // The ring holds NS stages; the loads of stage st + NS go into the slot
+    // of stage st once stage st's operands are in registers.
+    unroll_for<0, NS>([&](auto I) { issue(slot[decltype(I)::value], min(kbeg + decltype(I)::value * KSTEP, klast)); });
+    wait_vmcnt<(NS - 1) * C::OPS, 0>();    // this wave's loads of stage 0 are done
+    wg_barrier();                          // and every wave's
+    Frags cur;
+    load(cur, slot[0], slot[0] + C::XCH);
+    // the slot index is a compile-time constant at every call, so each
+    // stage's LDS object is known
+    auto body = [&](auto SL, int64_t st) {
+      constexpr int sl = decltype(SL)::value, nx = (sl + 1) % NS;
+      // stage st + 1 has landed once only the loads of the NS - 2 stages
+      // issued after it are outstanding; lgkmcnt 0: this wave's LDS reads
+      // of stage st (into registers) are done.  After the barrier no wave
+      // reads slot sl any more.
+      wait_vmcnt<(NS - 2) * C::OPS, 0>();
+      wg_barrier();
+      issue(slot[sl], min(kbeg + (st + NS) * KSTEP, klast));
+      Frags nxt;
+      if (st + 1 < nfull) load(nxt, slot[nx], slot[nx] + C::XCH);
+      mma(cur, xscale(kbeg + st * KSTEP));
+      cur = nxt;
+    };
     int64_t st = 0;
     for (; st + NS <= nfull; st += NS) unroll_for<0, NS>([&](auto I) { body(I, st + decltype(I)::value); });
     unroll_for<0, NS - 1>([&](auto I) {
       if (st + decltype(I)::value < nfull) body(I, st + decltype(I)::value);
     });
     wait_vmcnt<0>();                       // the repeated loads land before LDS is reused
+  } else if (nfull > 0) {
+    // Each stage issues the loads of the stage NS - 1 ahead into the slot
+    // the previous stage used, then reads its own operands and multiplies.
+    auto body = [&](auto SL, int64_t st) {
+      constexpr int sl = decltype(SL)::value;
+      // this wave's loads of stage st are done once only the loads of the
+      // NS - 2 stages issued after it are outstanding, and its LDS reads of
+      // stage st - 1 once lgkmcnt is 0; the barrier then makes every wave's
+      // loads of stage st visible and frees the slot of stage st - 1
+      wait_vmcnt<(NS - 2) * C::OPS, 0>();
+      wg_barrier();
+      issue(slot[(sl + NS - 1) % NS], min(kbeg + (st + NS - 1) * KSTEP, klast));
+      Frags f;
+      load(f, slot[sl], slot[sl] + C::XCH);
+      mma(f, xscale(kbeg + st * KSTEP));
+    };
+    unroll_for<0, NS - 1>([&](auto I) { issue(slot[decltype(I)::value], min(kbeg + decltype(I)::value * KSTEP, klast)); });
+    int64_t st = 0;
+    for (; st + NS <= nfull; st += NS) unroll_for<0, NS>([&](auto I) { body(I, st + decltype(I)::value); });
+    unroll_for<0, NS - 1>([&](auto I) {
+      if (st + decltype(I)::value < nfull) body(I, st + decltype(I)::value);
+    });
+    wait_vmcnt<0>();
   }
   const int64_t ktail = kbeg + nfull * KSTEP;
   if (ktail < kend) {
@@ -410,7 +468,9 @@ __device__ void FilterK<XK, MB, NB>::body(const FArgs& a, uint3 bid) {
       st0[C::XCH + pos] = u4v{w[0], w[1], w[2], w[3]};
     }
     __syncthreads();
-    compute(st0, st0 + C::XCH, xscale(ktail));
+    Frags f;
+    load(f, st0, st0 + C::XCH);
+    mma(f, xscale(ktail));
   }
   const int64_t m0 = mt0 + (int64_t)wave * (16 * MB);
 
@@ -576,10 +636,11 @@ void launch_f(FArgs& a, const FSplit& sp, int pm, int pr, hipStream_t st) {
 // Rows per workgroup (16-row blocks per wave): every workgroup reloads the
 // Y planes of its K slab, so wide blocks want tall tiles.  Four blocks per
 // wave for a BF16 X with more than 64 columns (the stage then holds 16 KiB
-// of X and 24 KiB of Y); two where the stage fits otherwise (an FP32 X stage
-// is twice a BF16 one; an FP8 workgroup must stay in one 128-row scale tile).
+// of X and 16 KiB of Y); two otherwise.  An FP32 X stage at p = 128 holds
+// 16 KiB of X and 24 KiB of Y, the whole 40 KiB slot (one block per wave
+// there, 8 KiB of X per 24 KiB of Y, was 10-20 % slower from n = 4096 up);
+// an FP8 workgroup must stay in one 128-row scale tile.
 int mb_for(int xk, int NB) {
-  if (xk == XK_F32) return NB > 4 ? 1 : 2;
   if (xk == XK_BF16) return NB > 4 ? 4 : 2;
   return 2;
 }
@@ -602,10 +663,10 @@ void launch_xk(FArgs& a, const FSplit& sp, int NB, int pm, int pr, hipStream_t s
       case 2: launch_f<XK, 2, 2>(a, sp, pm, pr, st); break;
       case 3: launch_f<XK, 2, 3>(a, sp, pm, pr, st); break;
       case 4: launch_f<XK, 2, 4>(a, sp, pm, pr, st); break;
-      case 5: launch_f<XK, 1, 5>(a, sp, pm, pr, st); break;
-      case 6: launch_f<XK, 1, 6>(a, sp, pm, pr, st); break;
-      case 7: launch_f<XK, 1, 7>(a, sp, pm, pr, st); break;
-      default: launch_f<XK, 1, 8>(a, sp, pm, pr, st); break;
+      case 5: launch_f<XK, 2, 5>(a, sp, pm, pr, st); break;
+      case 6: launch_f<XK, 2, 6>(a, sp, pm, pr, st); break;
+      case 7: launch_f<XK, 2, 7>(a, sp, pm, pr, st); break;
+      default: launch_f<XK, 2, 8>(a, sp, pm, pr, st); break;
     }
   } else {
     switch (NB) {

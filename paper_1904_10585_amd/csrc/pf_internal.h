@@ -258,6 +258,8 @@ struct ExtractionJob {
 void enqueue_extractions_grouped(int count, const ExtractionJob* jobs, hipStream_t st);
 // refresh the numeric fields (interval, flags) of a cached plan
 void plan_set_desc(Plan* P, const pf_desc& d);
+// device bytes a plan holds (workspace and operator copies)
+size_t plan_device_bytes(const Plan* P);
 // plan-owned buffers (for sessions)
 double* plan_theta(Plan* p);
 pf_info* plan_info(Plan* p);

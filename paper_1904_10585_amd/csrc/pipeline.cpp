@@ -314,6 +314,12 @@ void plan_destroy(Plan* P) {
 
 void plan_set_desc(Plan* P, const pf_desc& d) { P->d = d; }
 
+size_t plan_device_bytes(const Plan* P) {
+  size_t b = P->bytes;
+  for (const Plan::Copy* c : {&P->mft, &P->mrt}) b += c->bytes + c->scale_bytes;
+  return b;
+}
+
 double* plan_theta(Plan* p) { return p->theta; }
 pf_info* plan_info(Plan* p) { return p->info; }
 

@@ -146,6 +146,8 @@ def _load():
     sig = {
         "pf_extract": (i32, [P(PfDesc), P(PfMat), P(PfMat), vp, i64, vp, vp, vp]),
         "pf_extract_ex": (i32, [P(PfDesc), P(PfMat), P(PfMat), vp, i64, vp, vp, P(PfExtras), vp]),
+        "pf_workspace_cached": (i32, [P(ctypes.c_size_t), P(i32)]),
+        "pf_workspace_release": (i32, [vp]),
         "pf_session_step_ex": (i32, [vp, P(PfMat), P(PfMat), P(PfExtras), P(PfResult), vp]),
         "pf_session_export": (i32, [vp, vp, i64, vp, P(PfSessionState), vp]),
         "pf_session_import": (i32, [P(PfSessionState), vp, i64, vp, P(vp)]),
@@ -602,6 +604,19 @@ def pf_workspace_size(d):
     n = ctypes.c_size_t()
     _check(LIB.pf_workspace_size(ctypes.byref(d), ctypes.byref(n)))
     return n.value
+
+
+def pf_workspace_cached():
+    """(device bytes, count) of the workspaces cached by pf_extract."""
+    b = ctypes.c_size_t()
+    n = ctypes.c_int32()
+    _check(LIB.pf_workspace_cached(ctypes.byref(b), ctypes.byref(n)))
+    return b.value, n.value
+
+
+def pf_workspace_release(stream=None):
+    """Free the workspaces pf_extract cached for a stream (after waiting for it)."""
+    _check(LIB.pf_workspace_release(_stream(stream)))
 
 
 def pf_profile_set(mode):

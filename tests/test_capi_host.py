@@ -48,6 +48,12 @@ def test_binding_constants_match_header():
     assert mirrored >= 12
 
 
+def test_workspace_cache_query_needs_no_device():
+    b, c = pf.pf_workspace_cached()
+    assert b >= 0 and c >= 0 and (c > 0 or b == 0)
+    assert pf.LIB.pf_workspace_cached(None, None) == pf.PF_ERR_ARG
+
+
 def test_profile_mode_rejects_unknown():
     assert pf.LIB.pf_profile_set(7) == pf.PF_ERR_ARG
     assert "profiling mode" in pf.LIB.pf_last_error().decode()

@@ -207,3 +207,33 @@ def test_roctx_ranges_leave_results_unchanged(tmp_path):
     env = dict(os.environ, PF_ROCTX="1")
     subprocess.run([sys.executable, "-c", ROCTX_SCRIPT, root, str(out)], env=env, check=True, timeout=300)
     assert np.array_equal(np.load(out), th)
+
+
+def test_workspace_cache_is_keyed_by_shape_and_released():
+    """pf_extract caches one workspace per stream and shape: other degrees,
+    powers and intervals reuse it; pf_workspace_release frees a stream's."""
+    pf = pf_module()
+    n, p = 300, 16
+    X, U, _ = sym_case(n, p, config=124)
+    Xd = device_matrix(X, torch.float32)
+    stream = torch.cuda.Stream()
+    b0, c0 = pf.pf_workspace_cached()
+    theta = torch.zeros(p, dtype=torch.float64, device="cuda")
+    for d, q, a in ((3, 1, -1.0), (5, 2, -1.0), (8, 1, -1.5)):
+        Ud = device_matrix(U, torch.float32)
+        pf.pf_extract(pf.desc(n, p, d, a, 0.5, q=q, work=pf.PF_F32), Xd, Xd, Ud, theta, stream=stream)
+    b1, c1 = pf.pf_workspace_cached()
+    assert c1 == c0 + 1, (c0, c1)
+    Ud = device_matrix(U[:, :8], torch.float32)
+    pf.pf_extract(pf.desc(n, 8, 3, -1.0, 0.5, work=pf.PF_F32), Xd, Xd, Ud, theta, stream=stream)
+    b2, c2 = pf.pf_workspace_cached()
+    assert c2 == c0 + 2 and b2 > b1 > b0
+    pf.pf_workspace_release(stream)
+    b3, c3 = pf.pf_workspace_cached()
+    assert (b3, c3) == (b0, c0)
+    # the stream works again afterwards (a new workspace)
+    Ud = device_matrix(U, torch.float32)
+    pf.pf_extract(pf.desc(n, p, 3, -1.0, 0.5, work=pf.PF_F32), Xd, Xd, Ud, theta, stream=stream)
+    stream.synchronize()
+    assert pf.pf_workspace_cached()[1] == c0 + 1
+    pf.pf_workspace_release(stream)
