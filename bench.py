@@ -278,7 +278,7 @@ def main():
         "hbm_GBps_algorithmic": round(bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
         "bytes_per_step_algorithmic": bytes_step,
         "last_step_info": {"n_pos": int(info[1]), "dense_rr": int(info[2]), "dense_pre": int(info[3]),
-                           "deficient": int(info[4])},
+                           "deficient": int(info[4]), "dense_rows": int(info[7])},
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
                        "p99": round(float(np.percentile(step_ms, 99)), 4),
                        "max": round(float(step_ms.max()), 4)},

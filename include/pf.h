@@ -167,13 +167,18 @@ typedef struct pf_info {
   int32_t status;       /* pf_status of the numerical phase */
   int32_t n_pos;        /* #{theta_i > 0} */
   int32_t dense_rr;     /* 1: the Rayleigh-Ritz eigensolve needed the dense
-                           solver (the refinement could not converge) */
+                           solver, on the whole matrix (the refinement could
+                           not converge) or on its clusters of coupled Ritz
+                           values (dense_rows) */
   int32_t dense_pre;    /* 1: the pre-rotation needed the dense solver */
   int32_t deficient;    /* columns replaced because the block lost rank */
   int32_t refine_rr;    /* refinement iterations of the Rayleigh-Ritz
                            eigensolve (meaningless when dense_rr = 1) */
   int32_t refine_pre;   /* refinement iterations of the pre-rotation */
-  int32_t reserved;
+  int32_t dense_rows;   /* when dense_rr = 1 after a refinement that left
+                           clusters of coupled Ritz values (refine_rr > 0):
+                           the rows of the block the dense solver took (the
+                           clusters only); otherwise 0 */
 } pf_info;
 
 /* One extraction (section 2.1 then eq. RR).
@@ -340,7 +345,10 @@ pf_status pf_session_close(pf_session* s);
  * pf_session_import opens a session from such a state: its next step is
  * the step the exported session would have taken, bitwise (the same
  * kernels on the same U).  U and theta are device pointers (theta may be
- * NULL: then the session's theta reads zero until its first step). */
+ * NULL: then the session's theta reads zero until its first step); the
+ * import reads them on the null stream and returns once they are copied,
+ * so work that writes them must be complete (or ordered before the null
+ * stream) when it is called. */
 typedef struct pf_session_state {
   uint32_t struct_size;    /* sizeof(pf_session_state) */
   int32_t reserved;        /* 0 */

@@ -48,7 +48,7 @@ class PfDesc(ctypes.Structure):
 class PfInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("n_pos", ctypes.c_int32), ("dense_rr", ctypes.c_int32),
                 ("dense_pre", ctypes.c_int32), ("deficient", ctypes.c_int32),
-                ("refine_rr", ctypes.c_int32), ("refine_pre", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("refine_rr", ctypes.c_int32), ("refine_pre", ctypes.c_int32), ("dense_rows", ctypes.c_int32)]
 
 
 class PfResult(ctypes.Structure):

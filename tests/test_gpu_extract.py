@@ -220,10 +220,11 @@ def test_session_chain_matches_oracle_chain():
 def test_guard_columns_chain(work):
     """p = 2r: half of the block are guard columns in the dense unwanted part
     of the spectrum.  Their Ritz values crowd together, so on warm steps the
-    Rayleigh-Ritz eigenproblem goes to the dense solver (dense_rr = 1) while
-    the pre-rotation keeps its first-order path (near-degenerate pairs stay
-    coupled: dense_pre = 0).  Each step matches the oracle fed the same U and
-    X_k on the top r pairs."""
+    refinement of the Rayleigh-Ritz eigenproblem leaves them coupled as a
+    cluster and the dense solver takes that cluster's block only
+    (dense_rr = 1, 0 < dense_rows < p), while the pre-rotation keeps its
+    first-order path (near-degenerate pairs stay coupled: dense_pre = 0).
+    Each step matches the oracle fed the same U and X_k on the top r pairs."""
     pf = pf_module()
     n, p, r, d, a, b = 2000, 48, 24, 8, -5.0, 0.8
     X, _, _ = wl.planted(n, r, (1.0, 20.0), (-2.0, 0.8), config=120)
@@ -232,6 +233,7 @@ def test_guard_columns_chain(work):
     tdt, wk = (torch.float64, pf.PF_F64) if f64 else (torch.float32, pf.PF_F32)
     dsc = pf.desc(n, p, d, a, b, work=wk)
     h = pf.pf_session_open(dsc, device_matrix(U, tdt), seed=0)
+    clustered = []
     try:
         for k in range(6):
             if k:
@@ -246,14 +248,17 @@ def test_guard_columns_chain(work):
             V = pf.device_to_numpy(res.V, (p, res.ldv), np.float64 if f64 else np.float32).T[:n].astype(np.float64)
             info = pf.device_to_numpy(res.info, (8,), np.int32)
             rel, sin = compare(th, V, ref, r)
-            print(f"guards {work} step {k}: rel {rel:.2e} sin {sin:.2e} dense rr/pre {info[2]}/{info[3]}")
+            print(f"guards {work} step {k}: rel {rel:.2e} sin {sin:.2e} dense rr/pre {info[2]}/{info[3]} "
+                  f"rows {info[7]} refine {info[5]}")
             if f64:
                 grade_f64(th, V, Xs, U, d, a, b, r, cold=(k == 0), label=f"guards f64 step {k}")
             elif k >= 2:
                 assert rel <= 1e-5 and sin <= 1e-4, (k, rel, sin)
             if k >= 2:
                 assert info[2] == 1 and info[3] == 0, info
+                clustered.append(0 < info[7] < p)
             U = V
+        assert any(clustered), "no warm step solved only the guard cluster densely"
     finally:
         pf.pf_session_close(h)
 
