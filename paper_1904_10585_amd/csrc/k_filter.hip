@@ -263,10 +263,11 @@ __device__ void FilterK<XK, MB, NB>::body(const FArgs& a, uint3 bid) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4v{0, 0, 0, 0};
 
-  // per-stage scale of an FP8 tile: the workgroup's rows lie in one tile
-  // column (tile is a multiple of ROWS) and a stage in one tile row
+  // per-stage scale of an FP8 tile: a wave's rows lie in one tile column
+  // (tile is a multiple of 128 and a wave owns at most 64 aligned rows;
+  // rows past M take the last column's) and a stage in one tile row
   auto xscale = [&](int64_t k0) -> float {
-    if constexpr (XK == XK_FP8) return a.xscale[k0 / a.tile + (mt0 / a.tile) * a.ldsc];
+    if constexpr (XK == XK_FP8) return a.xscale[k0 / a.tile + (min(mt0 + (int64_t)wave * (16 * MB), a.M - 1) / a.tile) * a.ldsc];
     else return 1.0f;
   };
   // One stage's operands in registers: per 16-row block of the wave its X
@@ -639,9 +640,13 @@ void launch_f(FArgs& a, const FSplit& sp, int pm, int pr, hipStream_t st) {
 // of X and 16 KiB of Y); two otherwise.  An FP32 X stage at p = 128 holds
 // 16 KiB of X and 24 KiB of Y, the whole 40 KiB slot (one block per wave
 // there, 8 KiB of X per 24 KiB of Y, was 10-20 % slower from n = 4096 up);
-// an FP8 workgroup must stay in one 128-row scale tile.
-int mb_for(int xk, int NB) {
+// An FP8 X with up to 64 columns and many rows takes four blocks per wave as
+// well (each wave's 64 rows stay in one 128-row scale tile): measured on the
+// Gram form's products, 50.7 -> 42.0 us with 12000 output rows, but 40.9 ->
+// 41.6 us with 6000.
+int mb_for(int xk, int NB, int64_t M) {
   if (xk == XK_BF16) return NB > 4 ? 4 : 2;
+  if (xk == XK_FP8) return NB <= 4 && M >= 8192 ? 4 : 2;
   return 2;
 }
 
@@ -656,7 +661,7 @@ int xk_of(pf_dtype t) {
 }
 
 template <int XK>
-void launch_xk(FArgs& a, const FSplit& sp, int NB, int pm, int pr, hipStream_t st) {
+void launch_xk(FArgs& a, const FSplit& sp, int MB, int NB, int pm, int pr, hipStream_t st) {
   if constexpr (XK == XK_F32) {
     switch (NB) {
       case 1: launch_f<XK, 2, 1>(a, sp, pm, pr, st); break;
@@ -670,10 +675,22 @@ void launch_xk(FArgs& a, const FSplit& sp, int NB, int pm, int pr, hipStream_t s
     }
   } else {
     switch (NB) {
-      case 1: launch_f<XK, 2, 1>(a, sp, pm, pr, st); break;
-      case 2: launch_f<XK, 2, 2>(a, sp, pm, pr, st); break;
-      case 3: launch_f<XK, 2, 3>(a, sp, pm, pr, st); break;
-      case 4: launch_f<XK, 2, 4>(a, sp, pm, pr, st); break;
+      case 1:
+        if (XK == XK_FP8 && MB == 4) launch_f<XK, XK == XK_FP8 ? 4 : 2, 1>(a, sp, pm, pr, st);
+        else launch_f<XK, 2, 1>(a, sp, pm, pr, st);
+        break;
+      case 2:
+        if (XK == XK_FP8 && MB == 4) launch_f<XK, XK == XK_FP8 ? 4 : 2, 2>(a, sp, pm, pr, st);
+        else launch_f<XK, 2, 2>(a, sp, pm, pr, st);
+        break;
+      case 3:
+        if (XK == XK_FP8 && MB == 4) launch_f<XK, XK == XK_FP8 ? 4 : 2, 3>(a, sp, pm, pr, st);
+        else launch_f<XK, 2, 3>(a, sp, pm, pr, st);
+        break;
+      case 4:
+        if (XK == XK_FP8 && MB == 4) launch_f<XK, XK == XK_FP8 ? 4 : 2, 4>(a, sp, pm, pr, st);
+        else launch_f<XK, 2, 4>(a, sp, pm, pr, st);
+        break;
       case 5: launch_f<XK, XK == XK_BF16 ? 4 : 2, 5>(a, sp, pm, pr, st); break;
       case 6: launch_f<XK, XK == XK_BF16 ? 4 : 2, 6>(a, sp, pm, pr, st); break;
       case 7: launch_f<XK, XK == XK_BF16 ? 4 : 2, 7>(a, sp, pm, pr, st); break;
@@ -686,7 +703,7 @@ void launch_xk(FArgs& a, const FSplit& sp, int NB, int pm, int pr, hipStream_t s
 
 size_t filter_bf16x6_part_bytes(pf_dtype xdt, int64_t K, int64_t M, int64_t N) {
   const int NB = (int)(N / 16);
-  const FSplit sp = fplan(mb_for(xk_of(xdt), NB), K, M, 0);
+  const FSplit sp = fplan(mb_for(xk_of(xdt), NB, M), K, M, 0);
   return sp.S > 1 ? (size_t)sp.S * sp.ldp * N * sizeof(float) : 0;
 }
 
@@ -696,7 +713,7 @@ void filter_bf16x6(const FilterArgs& x, hipStream_t st) {
   if (xk == XK_FP8 && (x.xscale == nullptr || x.tile <= 0 || x.tile % 128 != 0))
     fail(PF_ERR_ARG, "filter: FP8 X needs tile scales with a tile that is a multiple of 128");
   const int NB = (int)(x.N / 16);
-  const int MB = mb_for(xk, NB);
+  const int MB = mb_for(xk, NB, x.M);
   FSplit sp = fplan(MB, x.K, x.M, x.splitk);
   while (sp.S > 1 && (size_t)sp.S * sp.ldp * x.N * sizeof(float) > x.part_bytes) sp = fplan(MB, x.K, x.M, sp.S - 1);
   FArgs a;
@@ -709,9 +726,9 @@ void filter_bf16x6(const FilterArgs& x, hipStream_t st) {
   a.outp = x.outp; a.ldop = x.ldop; a.oplane = x.oplane;
   a.part = static_cast<float*>(x.part); a.ldp = sp.ldp; a.splitk = sp.S;
   switch (xk) {
-    case XK_F32: launch_xk<XK_F32>(a, sp, NB, x.prof_main, x.prof_reduce, st); break;
-    case XK_BF16: launch_xk<XK_BF16>(a, sp, NB, x.prof_main, x.prof_reduce, st); break;
-    default: launch_xk<XK_FP8>(a, sp, NB, x.prof_main, x.prof_reduce, st); break;
+    case XK_F32: launch_xk<XK_F32>(a, sp, MB, NB, x.prof_main, x.prof_reduce, st); break;
+    case XK_BF16: launch_xk<XK_BF16>(a, sp, MB, NB, x.prof_main, x.prof_reduce, st); break;
+    default: launch_xk<XK_FP8>(a, sp, MB, NB, x.prof_main, x.prof_reduce, st); break;
   }
 }
 
