@@ -636,7 +636,24 @@ pf_status pf_eigh(const double* H, int64_t ldh, int32_t p, double* theta, double
     const char* z0 = reinterpret_cast<const char*>(Z);
     const char* z1 = z0 + ((size_t)(p - 1) * ldz + p) * sizeof(double);
     if (h0 < z1 && z0 < h1) fail(PF_ERR_ARG, "H and Z overlap");
-    launch_eigh(H, (int)ldh, p, theta, Z, (int)ldz, p, nullptr, 1, static_cast<hipStream_t>(stream));
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p <= 64) {
+      launch_eigh(H, (int)ldh, p, theta, Z, (int)ldz, p, nullptr, 1, st);
+      return;
+    }
+    // the kernel chain of the dense solver keeps its state in device scratch
+    void* mem = nullptr;
+    if (hipMallocAsync(&mem, eig_scratch_bytes(p), st) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(PF_ERR_NOMEM, "eigensolver scratch allocation failed");
+    }
+    try {
+      launch_eigh(H, (int)ldh, p, theta, Z, (int)ldz, p, nullptr, 1, st, static_cast<double*>(mem));
+    } catch (...) {
+      (void)hipFreeAsync(mem, st);
+      throw;
+    }
+    PFX_HIP(hipFreeAsync(mem, st));
   });
 }
 

@@ -14,6 +14,7 @@
 #include "group.h"
 
 #include <cmath>
+#include <stdexcept>
 
 namespace pfx {
 namespace {
@@ -437,11 +438,316 @@ __device__ inline double start_entry(int i, int j) {
   return (double)h * (2.0 / 4294967296.0) - 1.0;
 }
 
+// Cluster of eigenvalue jj of the ascending list lam[0..p): [cs, ce) chained
+// by gaps <= 1e-3 ||T||; kind 0 = alone, 1 = loose (every gap >= 1e-11
+// ||T||), 2 = tight, 3 = an eigenspace to working accuracy (spread <= 1e-13
+// ||T||).
+__device__ inline int cluster_kind(const double* lam, int p, double tnorm, int jj, int& cs, int& ce) {
+  const double ortol = 1e-3 * tnorm;
+  cs = jj;
+  while (cs > 0 && !(lam[cs] - lam[cs - 1] > ortol)) --cs;
+  ce = jj + 1;
+  while (ce < p && !(lam[ce] - lam[ce - 1] > ortol)) ++ce;
+  if (ce - cs == 1) return 0;
+  if (lam[ce - 1] - lam[cs] <= 1e-13 * tnorm) return 3;
+  for (int q = cs + 1; q < ce; ++q)
+    if (lam[q] - lam[q - 1] < 1e-11 * tnorm) return 2;
+  return 1;
+}
+
+// Eigenvector j of the tridiagonal T (diagonal d, off-diagonal e, ascending
+// eigenvalues lam) by inverse iteration, for one 16-lane team (PMAX/16 rows
+// per lane): two solves with the row-pivoted LU of T - lam_j I from a fixed
+// pseudo-random start when lam_j is alone or in a loose cluster (the loose
+// flag is raised for the latter); a tight cluster is taken in order by the
+// team of its first member, each iterate orthogonalised against the
+// cluster's earlier vectors.  The vector goes to column j of Zt (ld ldt).
 template <int PMAX>
+__device__ __attribute__((always_inline)) inline void invit_team(int j, int p, const double* __restrict__ d,
+                                                                const double* __restrict__ e,
+                                                                const double* __restrict__ lam, double tnorm,
+                                                                double* __restrict__ Zt, int ldt, int* loose) {
+  constexpr int R16 = PMAX / 16;
+  constexpr double EPS = 2.220446049250313e-16;
+  const int part16 = threadIdx.x & 15, r0 = part16 * R16;
+  const double tiny = EPS * tnorm;
+  double ur[R16], lm[R16], zr[R16];
+  unsigned pv = 0;
+  double sig = 0.0;
+  // row-pivoted LU of T - sig I, rows r0..r0+R16-1 on this lane:
+  // ur = 1/u_ii, lm = multiplier, pv = rows i, i+1 swapped.  The rest of U
+  // follows from these: u_{i,i+1} = d_{i+1} - sig after a swap, else the
+  // running super-diagonal (e_i, or -l_{i-1} e_i after a swap at i-1);
+  // u_{i,i+2} = e_{i+1} after a swap, else 0.
+  auto factor = [&]() {
+    pv = 0;
+    double ca = 0.0, cb = 0.0;
+#pragma unroll 1
+    for (int s = 0; s < 16; ++s) {
+      if (part16 == s) {
+        double a = s == 0 ? d[0] - sig : ca;
+        double b = s == 0 ? (p > 1 ? e[0] : 0.0) : cb;
+#pragma unroll
+        for (int u = 0; u < R16; ++u) {
+          const int i = r0 + u;
+          ur[u] = 0.0;
+          lm[u] = 0.0;
+          if (i < p - 1) {
+            const double c = e[i], an = d[i + 1] - sig;
+            const double bn = i + 1 < p - 1 ? e[i + 1] : 0.0;
+            if (fabs(a) >= fabs(c)) {
+              if (fabs(a) <= tiny) a = a >= 0.0 ? tiny : -tiny;
+              const double r = rcp_nr(a);
+              const double l = c * r;
+              ur[u] = r;
+              lm[u] = l;
+              a = an - l * b;
+              b = bn;
+            } else {
+              const double r = rcp_nr(c);
+              const double l = a * r;
+              ur[u] = r;
+              lm[u] = l;
+              pv |= 1u << u;
+              a = b - l * an;
+              b = -l * bn;
+            }
+          } else if (i == p - 1) {
+            if (fabs(a) <= tiny) a = a >= 0.0 ? tiny : -tiny;
+            ur[u] = rcp_nr(a);
+          }
+        }
+        ca = a;
+        cb = b;
+      }
+      ca = dpp_mov<0x111>(ca);                 // lane s+1 receives lane s's state
+      cb = dpp_mov<0x111>(cb);
+    }
+  };
+  // zr <- (T - sig I)^{-1} zr with the factors above
+  auto solve = [&]() {
+    // forward: y = L^{-1} P z (carry w = the running value of z_i)
+    const double znext = dpp_mov<0x101>(zr[0]);  // first row of the next lane
+    double w = 0.0;
+#pragma unroll 1
+    for (int s = 0; s < 16; ++s) {
+      if (part16 == s) {
+        double wi = s == 0 ? zr[0] : w;
+#pragma unroll
+        for (int u = 0; u < R16; ++u) {
+          const int i = r0 + u;
+          if (i < p - 1) {
+            double zn = u + 1 < R16 ? zr[u + 1] : znext;
+            double zi = wi;
+            if (pv & (1u << u)) {
+              const double tmp = zi;
+              zi = zn;
+              zn = tmp;
+            }
+            zr[u] = zi;
+            wi = zn - lm[u] * zi;
+          } else if (i == p - 1) {
+            zr[u] = wi;
+          }
+        }
+        w = wi;
+      }
+      w = dpp_mov<0x111>(w);
+    }
+    // back: x_i = (y_i - u2_i x_{i+1} - u3_i x_{i+2}) / u_ii
+    const double lprev = dpp_mov<0x111>(lm[R16 - 1]);   // last row of the previous lane
+    const unsigned pprev = ((unsigned)dpp_mov_i<0x111>((int)pv) >> (R16 - 1)) & 1u;
+    double x1 = 0.0, x2 = 0.0;
+#pragma unroll 1
+    for (int s = 15; s >= 0; --s) {
+      if (part16 == s) {
+        double a1 = x1, a2 = x2;
+#pragma unroll
+        for (int u = R16 - 1; u >= 0; --u) {
+          const int i = r0 + u;
+          if (i < p) {
+            const bool sw = (pv >> u) & 1u;
+            const bool swp = u > 0 ? ((pv >> (u - 1)) & 1u) : (i > 0 && pprev);
+            const double lp = u > 0 ? lm[u > 0 ? u - 1 : 0] : lprev;
+            double u2 = 0.0, u3 = 0.0;
+            if (i < p - 1) {
+              u2 = sw ? d[i + 1] - sig : (swp ? -lp * e[i] : e[i]);
+              if (sw && i + 1 < p - 1) u3 = e[i + 1];
+            }
+            const double xi = (zr[u] - u2 * a1 - u3 * a2) * ur[u];
+            zr[u] = xi;
+            a2 = a1;
+            a1 = xi;
+          }
+        }
+        x1 = a1;
+        x2 = a2;
+      }
+      x1 = dpp_mov<0x101>(x1);                 // lane s-1 receives lane s's rows
+      x2 = dpp_mov<0x101>(x2);
+    }
+  };
+  auto start = [&](int mm, int salt) {
+#pragma unroll
+    for (int u = 0; u < R16; ++u) zr[u] = r0 + u < p ? start_entry(r0 + u, mm + salt) : 0.0;
+  };
+  // orthogonalise zr against columns j..mm-1 (modified Gram-Schmidt,
+  // `passes` times), then normalise
+  auto orthonormalise = [&](int j, int mm, int passes, int it) {
+    for (int ps = 0; ps < passes; ++ps) {
+      for (int q = j; q < mm; ++q) {
+        const double* col = Zt + (int64_t)q * ldt;
+        double dot = 0.0;
+#pragma unroll
+        for (int u = 0; u < R16; ++u)
+          if (r0 + u < p) dot += col[r0 + u] * zr[u];
+        dot = sum16(dot);
+#pragma unroll
+        for (int u = 0; u < R16; ++u)
+          if (r0 + u < p) zr[u] -= dot * col[r0 + u];
+      }
+    }
+    double ss = 0.0;
+#pragma unroll
+    for (int u = 0; u < R16; ++u) ss += zr[u] * zr[u];
+    ss = sum16(ss);
+    if (ss > 0.0 && ss < INFINITY) {
+      const double inv = 1.0 / sqrt(ss);
+#pragma unroll
+      for (int u = 0; u < R16; ++u) zr[u] *= inv;
+    } else {
+      start(mm, 7919 * (it + 1));
+    }
+  };
+  int cs, ce;
+  const int kind = cluster_kind(lam, p, tnorm, j, cs, ce);
+  if (kind <= 1) {
+    // alone or in a loose cluster: two solves from the exact shift (the
+    // loose clusters are orthonormalised together after step 4)
+    if (kind == 1) *loose = 1;
+    sig = lam[j];
+    factor();
+    start(j, 0);
+    for (int it = 0; it < 2; ++it) {
+      solve();
+      orthonormalise(j, j, 0, it);
+    }
+#pragma unroll
+    for (int u = 0; u < R16; ++u)
+      if (r0 + u < p) Zt[r0 + u + (int64_t)j * ldt] = zr[u];
+    return;
+  }
+  if (j != cs) return;                       // the cluster's first team takes it in order
+  // An eigenspace to working accuracy shares one shift just above it:
+  // it amplifies the whole eigenspace alike (so successive iterates do
+  // not collapse onto one direction) and damps the rest by >= 1e-9 per
+  // solve.  A tight cluster uses separated shifts and Gram-Schmidt.
+  const bool degen = kind == 3;
+  const double spread = lam[ce - 1] - lam[cs];
+  double sprev = 0.0;
+  for (int mm = cs; mm < ce; ++mm) {
+    if (!degen || mm == cs) {
+      sig = lam[mm];
+      if (degen) sig = lam[ce - 1] + 1e3 * fmax(spread, EPS * tnorm);
+      else if (mm > cs && sig - sprev < 10.0 * EPS * fabs(sig)) sig = sprev + 10.0 * EPS * fabs(sig);
+      sprev = sig;
+      factor();
+    }
+    start(mm, 0);
+    const int nit = degen ? 2 : 3;
+    for (int it = 0; it < nit; ++it) {
+      solve();
+      orthonormalise(cs, mm, degen ? 2 : 1, it);
+    }
+#pragma unroll
+    for (int u = 0; u < R16; ++u)
+      if (r0 + u < p) Zt[r0 + u + (int64_t)mm * ldt] = zr[u];
+  }
+}
+
+// Z <- Q Z for two vectors held by a 16-lane team (rows part16 + 16 u),
+// Q = P_0 ... P_{p-3} from the Householder vectors (entry (r, k) of v_k at
+// V[r * rs + k * ks], rows k+1..p-1) and their beta.
+template <int PMAX>
+__device__ __attribute__((always_inline)) inline void reflect_back(double (&z0)[PMAX / 16], double (&z1)[PMAX / 16],
+                                                                  int p, const double* __restrict__ V, int rs,
+                                                                  int ks, const double* __restrict__ beta) {
+  constexpr int R16 = PMAX / 16;
+  const int part16 = threadIdx.x & 15;
+  // the loads of step k-1 are issued before the arithmetic of step k, and
+  // each dot product runs as two interleaved chains
+  auto load = [&](int k, double (&av)[R16]) {
+#pragma unroll
+    for (int u = 0; u < R16; ++u) {
+      const int r = part16 + 16 * u;
+      av[u] = k >= 0 && r > k && r < p ? V[r * rs + k * ks] : 0.0;
+    }
+  };
+  double av[R16];
+  load(p - 3, av);
+  for (int k = p - 3; k >= 0; --k) {
+    double an[R16];
+    load(k - 1, an);
+    const double b = beta[k];
+    if (b != 0.0) {
+      double d0a = 0.0, d0b = 0.0, d1a = 0.0, d1b = 0.0;
+#pragma unroll
+      for (int u = 0; u < R16; u += 2) {
+        d0a = fma(av[u], z0[u], d0a);
+        d1a = fma(av[u], z1[u], d1a);
+        if (u + 1 < R16) {
+          d0b = fma(av[u + 1], z0[u + 1], d0b);
+          d1b = fma(av[u + 1], z1[u + 1], d1b);
+        }
+      }
+      const double d0 = b * sum16(d0a + d0b);
+      const double d1 = b * sum16(d1a + d1b);
+#pragma unroll
+      for (int u = 0; u < R16; ++u) {
+        z0[u] -= d0 * av[u];
+        z1[u] -= d1 * av[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < R16; ++u) av[u] = an[u];
+  }
+}
+
+// Global state of the dense solver when its phases run as separate kernels
+// (PMAX = 128): the tridiagonal T, the Householder vectors (column k of V
+// holds v_k, ld PMAX), the eigenvalues, T's eigenvectors and a copy for the
+// Newton-Schulz steps.
+template <int PMAX>
+struct SyevScratch {
+  double *d, *e, *e2, *beta, *lam, *par, *V, *Zt, *Zp;
+  int *done, *loose;
+  __device__ explicit SyevScratch(double* g) {
+    d = g;
+    e = d + PMAX;
+    e2 = e + PMAX;
+    beta = e2 + PMAX;
+    lam = beta + PMAX;
+    par = lam + PMAX;                            // Gershgorin lo, hi, pivmin, ||T||, scale
+    V = par + 8;
+    Zt = V + PMAX * PMAX;
+    Zp = Zt + PMAX * PMAX;
+    done = reinterpret_cast<int*>(Zp + PMAX * PMAX);
+    loose = done + 1;
+  }
+};
+template <int PMAX>
+constexpr size_t syev_scratch_bytes() {
+  return (size_t)(5 * PMAX + 8 + 3 * PMAX * PMAX) * sizeof(double) + 2 * sizeof(int);
+}
+
+// SPLIT: run the load and step 1 only and leave T, the Householder vectors
+// and the Gershgorin bracket in the global state at gsc (SyevScratch); the
+// other steps then run as separate kernels over many workgroups.
+template <int PMAX, bool SPLIT = false>
 __device__ __attribute__((always_inline)) inline void syev_impl(const double* __restrict__ H, int ldh, int p,
                                                                double* __restrict__ theta, double* __restrict__ Z,
                                                                int ldz, int pad, pf_info* info, int which,
-                                                               const int* skip) {
+                                                               const int* skip, double* gsc = nullptr) {
   if (skip && *skip) return;                     // the refinement solved this matrix
   constexpr int NT = 8 * PMAX;
   constexpr int NW = NT / 64;
@@ -452,6 +758,11 @@ __device__ __attribute__((always_inline)) inline void syev_impl(const double* __
   constexpr double SAFMIN = 2.2250738585072014e-308;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* A = reinterpret_cast<double*>(smem_raw);   // Householder vectors: v_k in column k
+  // entry `row` of v_k: LDS column k, or column k of the global V
+  auto vstore = [&](int row, int k, double v) {
+    if constexpr (SPLIT) SyevScratch<PMAX>(gsc).V[k * PMAX + row] = v;
+    else A[row * LDA + k] = v;
+  };
   __shared__ double s_d[PMAX], s_e[PMAX], s_e2[PMAX], s_beta[PMAX], s_v[PMAX], s_y[PMAX], s_lam[PMAX], s_x[PMAX];
   __shared__ int s_cnt[NT];
   __shared__ double s_red[NW];
@@ -498,6 +809,9 @@ __device__ __attribute__((always_inline)) inline void syev_impl(const double* __
         info->dense_pre = 1;
       }
     }
+    if constexpr (SPLIT) {
+      if (t == 0) *SyevScratch<PMAX>(gsc).done = 1;   // the later kernels return at once
+    }
     return;
   }
   int ex;
@@ -520,7 +834,7 @@ __device__ __attribute__((always_inline)) inline void syev_impl(const double* __
   // ---- 1. Householder tridiagonalisation ----------------------------------
   // The trailing matrix stays in registers; a step publishes v (s_v), y
   // (s_y) and the next column (s_x) through LDS.  v also goes to column k of
-  // the LDS array A, kept for the back-transform.
+  // the reflector store (vstore), kept for the back-transform.
   for (int k = 0; k + 2 < p; ++k) {
     const int m = p - k - 1;                     // trailing size
     if (wave == 0) {
@@ -538,11 +852,11 @@ __device__ __attribute__((always_inline)) inline void syev_impl(const double* __
       if (lane < m) {
         const double vv = lane == 0 ? v0 : xa;
         s_v[k + 1 + lane] = vv;
-        A[(k + 1 + lane) * LDA + k] = vv;
+        vstore(k + 1 + lane, k, vv);
       }
       if (lane + 64 < m) {
         s_v[k + 65 + lane] = xb;
-        A[(k + 65 + lane) * LDA + k] = xb;
+        vstore(k + 65 + lane, k, xb);
       }
       if (lane == 0) {
         s_d[k] = s_x[k];
@@ -624,6 +938,22 @@ __device__ __attribute__((always_inline)) inline void syev_impl(const double* __
     }
   }
   __syncthreads();
+  if constexpr (SPLIT) {
+    const SyevScratch<PMAX> sc(gsc);
+    for (int i = t; i < p; i += NT) {
+      sc.d[i] = s_d[i];
+      sc.e[i] = s_e[i];
+      sc.e2[i] = s_e2[i];
+      sc.beta[i] = s_beta[i];
+    }
+    if (t < 4) sc.par[t] = s_par[t];
+    if (t == 0) {
+      sc.par[4] = scale;
+      *sc.done = 0;
+      *sc.loose = 0;
+    }
+    return;
+  }
   const double pivmin = s_par[2], tnorm = s_par[3];
   // coarse pass: every thread counts at one of NT points splitting the
   // Gershgorin interval into NT + 1 parts
@@ -658,226 +988,14 @@ __device__ __attribute__((always_inline)) inline void syev_impl(const double* __
   }
   __syncthreads();
 
-  const double ortol = 1e-3 * tnorm;
-  // cluster of eigenvalue jj: [cs, ce) chained by gaps <= ortol; kind 0 =
-  // alone, 1 = loose (every gap >= 1e-11 ||T||), 2 = tight, 3 = an
-  // eigenspace to working accuracy (spread <= 1e-13 ||T||)
-  auto cluster_of = [&](int jj, int& cs, int& ce) {
-    cs = jj;
-    while (cs > 0 && !(s_lam[cs] - s_lam[cs - 1] > ortol)) --cs;
-    ce = jj + 1;
-    while (ce < p && !(s_lam[ce] - s_lam[ce - 1] > ortol)) ++ce;
-    if (ce - cs == 1) return 0;
-    if (s_lam[ce - 1] - s_lam[cs] <= 1e-13 * tnorm) return 3;
-    for (int q = cs + 1; q < ce; ++q)
-      if (s_lam[q] - s_lam[q - 1] < 1e-11 * tnorm) return 2;
-    return 1;
-  };
   __shared__ int s_loose;
   if (t == 0) s_loose = 0;
   __syncthreads();
 
-  // ---- 3. inverse iteration: 16-lane teams, R16 rows per lane ------------
-  {
-    const int part16 = t & 15, r0 = part16 * R16;
-    const double tiny = EPS * tnorm;
-    const int ldt = ldz;                         // T's eigenvectors go to Z first
-    double ur[R16], lm[R16], zr[R16];
-    unsigned pv = 0;
-    double sig = 0.0;
-    // row-pivoted LU of T - sig I, rows r0..r0+R16-1 on this lane:
-    // ur = 1/u_ii, lm = multiplier, pv = rows i, i+1 swapped.  The rest of U
-    // follows from these: u_{i,i+1} = d_{i+1} - sig after a swap, else the
-    // running super-diagonal (e_i, or -l_{i-1} e_i after a swap at i-1);
-    // u_{i,i+2} = e_{i+1} after a swap, else 0.
-    auto factor = [&]() {
-      pv = 0;
-      double ca = 0.0, cb = 0.0;
-#pragma unroll 1
-      for (int s = 0; s < 16; ++s) {
-        if (part16 == s) {
-          double a = s == 0 ? s_d[0] - sig : ca;
-          double b = s == 0 ? (p > 1 ? s_e[0] : 0.0) : cb;
-#pragma unroll
-          for (int u = 0; u < R16; ++u) {
-            const int i = r0 + u;
-            ur[u] = 0.0;
-            lm[u] = 0.0;
-            if (i < p - 1) {
-              const double c = s_e[i], an = s_d[i + 1] - sig;
-              const double bn = i + 1 < p - 1 ? s_e[i + 1] : 0.0;
-              if (fabs(a) >= fabs(c)) {
-                if (fabs(a) <= tiny) a = a >= 0.0 ? tiny : -tiny;
-                const double r = rcp_nr(a);
-                const double l = c * r;
-                ur[u] = r;
-                lm[u] = l;
-                a = an - l * b;
-                b = bn;
-              } else {
-                const double r = rcp_nr(c);
-                const double l = a * r;
-                ur[u] = r;
-                lm[u] = l;
-                pv |= 1u << u;
-                a = b - l * an;
-                b = -l * bn;
-              }
-            } else if (i == p - 1) {
-              if (fabs(a) <= tiny) a = a >= 0.0 ? tiny : -tiny;
-              ur[u] = rcp_nr(a);
-            }
-          }
-          ca = a;
-          cb = b;
-        }
-        ca = dpp_mov<0x111>(ca);                 // lane s+1 receives lane s's state
-        cb = dpp_mov<0x111>(cb);
-      }
-    };
-    // zr <- (T - sig I)^{-1} zr with the factors above
-    auto solve = [&]() {
-      // forward: y = L^{-1} P z (carry w = the running value of z_i)
-      const double znext = dpp_mov<0x101>(zr[0]);  // first row of the next lane
-      double w = 0.0;
-#pragma unroll 1
-      for (int s = 0; s < 16; ++s) {
-        if (part16 == s) {
-          double wi = s == 0 ? zr[0] : w;
-#pragma unroll
-          for (int u = 0; u < R16; ++u) {
-            const int i = r0 + u;
-            if (i < p - 1) {
-              double zn = u + 1 < R16 ? zr[u + 1] : znext;
-              double zi = wi;
-              if (pv & (1u << u)) {
-                const double tmp = zi;
-                zi = zn;
-                zn = tmp;
-              }
-              zr[u] = zi;
-              wi = zn - lm[u] * zi;
-            } else if (i == p - 1) {
-              zr[u] = wi;
-            }
-          }
-          w = wi;
-        }
-        w = dpp_mov<0x111>(w);
-      }
-      // back: x_i = (y_i - u2_i x_{i+1} - u3_i x_{i+2}) / u_ii
-      const double lprev = dpp_mov<0x111>(lm[R16 - 1]);   // last row of the previous lane
-      const unsigned pprev = ((unsigned)dpp_mov_i<0x111>((int)pv) >> (R16 - 1)) & 1u;
-      double x1 = 0.0, x2 = 0.0;
-#pragma unroll 1
-      for (int s = 15; s >= 0; --s) {
-        if (part16 == s) {
-          double a1 = x1, a2 = x2;
-#pragma unroll
-          for (int u = R16 - 1; u >= 0; --u) {
-            const int i = r0 + u;
-            if (i < p) {
-              const bool sw = (pv >> u) & 1u;
-              const bool swp = u > 0 ? ((pv >> (u - 1)) & 1u) : (i > 0 && pprev);
-              const double lp = u > 0 ? lm[u > 0 ? u - 1 : 0] : lprev;
-              double u2 = 0.0, u3 = 0.0;
-              if (i < p - 1) {
-                u2 = sw ? s_d[i + 1] - sig : (swp ? -lp * s_e[i] : s_e[i]);
-                if (sw && i + 1 < p - 1) u3 = s_e[i + 1];
-              }
-              const double xi = (zr[u] - u2 * a1 - u3 * a2) * ur[u];
-              zr[u] = xi;
-              a2 = a1;
-              a1 = xi;
-            }
-          }
-          x1 = a1;
-          x2 = a2;
-        }
-        x1 = dpp_mov<0x101>(x1);                 // lane s-1 receives lane s's rows
-        x2 = dpp_mov<0x101>(x2);
-      }
-    };
-    auto start = [&](int mm, int salt) {
-#pragma unroll
-      for (int u = 0; u < R16; ++u) zr[u] = r0 + u < p ? start_entry(r0 + u, mm + salt) : 0.0;
-    };
-    // orthogonalise zr against columns j..mm-1 (modified Gram-Schmidt,
-    // `passes` times), then normalise
-    auto orthonormalise = [&](int j, int mm, int passes, int it) {
-      for (int ps = 0; ps < passes; ++ps) {
-        for (int q = j; q < mm; ++q) {
-          const double* col = Z + (int64_t)q * ldt;
-          double dot = 0.0;
-#pragma unroll
-          for (int u = 0; u < R16; ++u)
-            if (r0 + u < p) dot += col[r0 + u] * zr[u];
-          dot = sum16(dot);
-#pragma unroll
-          for (int u = 0; u < R16; ++u)
-            if (r0 + u < p) zr[u] -= dot * col[r0 + u];
-        }
-      }
-      double ss = 0.0;
-#pragma unroll
-      for (int u = 0; u < R16; ++u) ss += zr[u] * zr[u];
-      ss = sum16(ss);
-      if (ss > 0.0 && ss < INFINITY) {
-        const double inv = 1.0 / sqrt(ss);
-#pragma unroll
-        for (int u = 0; u < R16; ++u) zr[u] *= inv;
-      } else {
-        start(mm, 7919 * (it + 1));
-      }
-    };
-    for (int pass = 0; pass < 2; ++pass) {
-      const int j = (t >> 4) + pass * (PMAX / 2);
-      if (j >= p) continue;
-      int cs, ce;
-      const int kind = cluster_of(j, cs, ce);
-      if (kind <= 1) {
-        // alone or in a loose cluster: two solves from the exact shift (the
-        // loose clusters are orthonormalised together after step 4)
-        if (kind == 1) s_loose = 1;
-        sig = s_lam[j];
-        factor();
-        start(j, 0);
-        for (int it = 0; it < 2; ++it) {
-          solve();
-          orthonormalise(j, j, 0, it);
-        }
-#pragma unroll
-        for (int u = 0; u < R16; ++u)
-          if (r0 + u < p) Z[r0 + u + (int64_t)j * ldt] = zr[u];
-        continue;
-      }
-      if (j != cs) continue;                     // the cluster's first team takes it in order
-      // An eigenspace to working accuracy shares one shift just above it:
-      // it amplifies the whole eigenspace alike (so successive iterates do
-      // not collapse onto one direction) and damps the rest by >= 1e-9 per
-      // solve.  A tight cluster uses separated shifts and Gram-Schmidt.
-      const bool degen = kind == 3;
-      const double spread = s_lam[ce - 1] - s_lam[cs];
-      double sprev = 0.0;
-      for (int mm = cs; mm < ce; ++mm) {
-        if (!degen || mm == cs) {
-          sig = s_lam[mm];
-          if (degen) sig = s_lam[ce - 1] + 1e3 * fmax(spread, EPS * tnorm);
-          else if (mm > cs && sig - sprev < 10.0 * EPS * fabs(sig)) sig = sprev + 10.0 * EPS * fabs(sig);
-          sprev = sig;
-          factor();
-        }
-        start(mm, 0);
-        const int nit = degen ? 2 : 3;
-        for (int it = 0; it < nit; ++it) {
-          solve();
-          orthonormalise(cs, mm, degen ? 2 : 1, it);
-        }
-#pragma unroll
-        for (int u = 0; u < R16; ++u)
-          if (r0 + u < p) Z[r0 + u + (int64_t)mm * ldt] = zr[u];
-      }
-    }
+  // ---- 3. inverse iteration: 16-lane teams, two eigenvalues each --------
+  for (int pass = 0; pass < 2; ++pass) {
+    const int j = (t >> 4) + pass * (PMAX / 2);
+    if (j < p) invit_team<PMAX>(j, p, s_d, s_e, s_lam, tnorm, Z, ldz, &s_loose);   // T's eigenvectors go to Z first
   }
   __syncthreads();
 
@@ -895,26 +1013,7 @@ __device__ __attribute__((always_inline)) inline void syev_impl(const double* __
     }
     __syncthreads();                             // every column read before any is rewritten
     if (j0 < p) {
-      for (int k = p - 3; k >= 0; --k) {
-        const double b = s_beta[k];
-        if (b == 0.0) continue;
-        double a[R16];
-        double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-        for (int u = 0; u < R16; ++u) {
-          const int r = part16 + 16 * u;
-          a[u] = r > k && r < p ? A[r * LDA + k] : 0.0;
-          d0 += a[u] * z0[u];
-          d1 += a[u] * z1[u];
-        }
-        d0 = b * sum16(d0);
-        d1 = b * sum16(d1);
-#pragma unroll
-        for (int u = 0; u < R16; ++u) {
-          z0[u] -= d0 * a[u];
-          z1[u] -= d1 * a[u];
-        }
-      }
+      reflect_back<PMAX>(z0, z1, p, A, LDA, 1, s_beta);
 #pragma unroll
       for (int u = 0; u < R16; ++u) {
         const int r = part16 + 16 * u;
@@ -948,7 +1047,7 @@ __device__ __attribute__((always_inline)) inline void syev_impl(const double* __
       for (int h = 0; h < 2; ++h) {
         const int j = (t >> 4) + h * (PMAX / 2);
         int cs = 0, ce = 0;
-        if (j >= p || cluster_of(j, cs, ce) != 1) continue;
+        if (j >= p || cluster_kind(s_lam, p, tnorm, j, cs, ce) != 1) continue;
         const int cj = p - 1 - j;                // final column of eigenvalue j
         double zj[R16], acc[R16];
 #pragma unroll
@@ -1466,6 +1565,224 @@ struct SyevK {
     }
   }
 };
+
+// The dense solver at PMAX = 128 as a chain of kernels.  The reduction to
+// tridiagonal form is sequential and stays in one workgroup (SyevTriK);
+// everything after it is independent per eigenvalue or per column and runs
+// over many workgroups, at the latency of one eigenvalue rather than of all
+// of them: the eigenvalues by 65-way multisection (one workgroup each,
+// SyevBisK), T's eigenvectors (four 16-lane teams per workgroup, SyevInvK),
+// the back-transform (32 columns per workgroup, SyevBackK) and the two
+// Newton-Schulz steps of loose clusters (one column per workgroup, from Z
+// to a copy and back, SyevNsK), whose second launch also pads Z and fills
+// pf_info.  The global state sits after the refinement's scratch.
+template <int PMAX>
+__device__ inline double* syev_gsc(const EigArgs& a) {
+  return a.gscratch + (cluster_scratch_bytes<PMAX>() + 255) / 256 * 256 / sizeof(double);
+}
+__device__ inline bool syev_skip(const EigArgs& a) { return a.skip && *a.skip; }
+
+template <int PMAX>
+struct SyevTriK {
+  using Args = EigArgs;
+  static constexpr int kThreads = 8 * PMAX, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const Args& a, uint3) {
+    if (syev_skip(a)) return;
+    syev_impl<PMAX, true>(a.H, a.ldh, a.p, a.theta, a.Z, a.ldz, a.pad, a.info, a.which, nullptr,
+                          syev_gsc<PMAX>(a));
+  }
+};
+template <int PMAX>
+struct SyevBisK {
+  using Args = EigArgs;
+  static constexpr int kThreads = 64, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const Args& a, uint3 bid) {
+    constexpr double EPS = 2.220446049250313e-16;
+    if (syev_skip(a)) return;
+    const SyevScratch<PMAX> sc(syev_gsc<PMAX>(a));
+    const int p = a.p, b = (int)bid.x, t = threadIdx.x;
+    if (*sc.done || b >= p) return;
+    __shared__ double s_d[PMAX], s_e2[PMAX];
+    for (int i = t; i < p; i += 64) {
+      s_d[i] = sc.d[i];
+      s_e2[i] = sc.e2[i];
+    }
+    __syncthreads();
+    // eigenvalue b (ascending): the 64 lanes count at the 64 interior points
+    // of the bracket, which shrinks 65-fold a round from the Gershgorin
+    // interval
+    double lo = sc.par[0], hi = sc.par[1];
+    const double pivmin = sc.par[2], tnorm = sc.par[3];
+    for (int it = 0; it < 32; ++it) {
+      if (hi - lo <= fmax(2.0 * EPS * fmax(fabs(lo), fabs(hi)), EPS * tnorm)) break;
+      const double wq = (hi - lo) * (1.0 / 65.0);
+      const int cnt = sturm_count(s_d, s_e2, p, lo + wq * (double)(t + 1), pivmin);
+      const unsigned long long bits = __ballot(cnt > b);
+      const int first = bits ? __builtin_ctzll(bits) : 64;   // point `first` is the first above
+      const double nlo = first == 0 ? lo : lo + wq * (double)first;
+      const double nhi = first == 64 ? hi : lo + wq * (double)(first + 1);
+      lo = nlo;
+      hi = nhi;
+    }
+    if (t == 0) sc.lam[b] = 0.5 * (lo + hi);
+  }
+};
+template <int PMAX>
+struct SyevInvK {
+  using Args = EigArgs;
+  static constexpr int kThreads = 64, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const Args& a, uint3 bid) {
+    if (syev_skip(a)) return;
+    const SyevScratch<PMAX> sc(syev_gsc<PMAX>(a));
+    const int p = a.p, t = threadIdx.x;
+    if (*sc.done) return;
+    __shared__ double s_d[PMAX], s_e[PMAX], s_lam[PMAX];
+    for (int i = t; i < p; i += 64) {
+      s_d[i] = sc.d[i];
+      s_e[i] = sc.e[i];
+      s_lam[i] = sc.lam[i];
+    }
+    __syncthreads();
+    const int j = (int)bid.x * 4 + (t >> 4);
+    if (j < p) invit_team<PMAX>(j, p, s_d, s_e, s_lam, sc.par[3], sc.Zt, PMAX, sc.loose);
+  }
+};
+template <int PMAX>
+struct SyevBackK {
+  using Args = EigArgs;
+  static constexpr int kThreads = 256, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const Args& a, uint3 bid) {
+    constexpr int R16 = PMAX / 16;
+    if (syev_skip(a)) return;
+    const SyevScratch<PMAX> sc(syev_gsc<PMAX>(a));
+    const int p = a.p, t = threadIdx.x;
+    if (*sc.done) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* V = reinterpret_cast<double*>(smem_raw);   // v_k in column k, ld PMAX
+    __shared__ double s_beta[PMAX];
+    {
+      // columns 0..p-3 of V, 16 bytes a lane, eight loads in flight
+      const int n2 = (p - 2) * PMAX / 2;
+      const double2* src = reinterpret_cast<const double2*>(sc.V);
+      double2* dst = reinterpret_cast<double2*>(V);
+      for (int i0 = t; i0 < n2; i0 += 8 * kThreads) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u * kThreads;
+          if (i < n2) v[u] = src[i];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u * kThreads;
+          if (i < n2) dst[i] = v[u];
+        }
+      }
+    }
+    for (int i = t; i < p; i += kThreads) s_beta[i] = sc.beta[i];
+    __syncthreads();
+    const int part16 = t & 15;
+    const int j0 = (int)bid.x * 32 + (t >> 4), j1 = j0 + 16;
+    if (j0 >= p) return;
+    double z0[R16], z1[R16];
+#pragma unroll
+    for (int u = 0; u < R16; ++u) {
+      const int r = part16 + 16 * u;
+      z0[u] = r < p ? sc.Zt[r + j0 * PMAX] : 0.0;
+      z1[u] = j1 < p && r < p ? sc.Zt[r + j1 * PMAX] : 0.0;
+    }
+    reflect_back<PMAX>(z0, z1, p, V, 1, PMAX, s_beta);
+    // columns in descending order of the eigenvalues
+#pragma unroll
+    for (int u = 0; u < R16; ++u) {
+      const int r = part16 + 16 * u;
+      if (r < p) {
+        a.Z[r + (int64_t)(p - 1 - j0) * a.ldz] = z0[u];
+        if (j1 < p) a.Z[r + (int64_t)(p - 1 - j1) * a.ldz] = z1[u];
+      }
+    }
+    if (part16 == 0) {
+      const double scale = sc.par[4];
+      a.theta[p - 1 - j0] = sc.lam[j0] * scale;
+      if (j1 < p) a.theta[p - 1 - j1] = sc.lam[j1] * scale;
+    }
+  }
+};
+// One Newton-Schulz step z_j <- (3 z_j - sum_q (z_q . z_j) z_q) / 2 over the
+// final columns q of a loose cluster (STEP 0: Z to the copy, 1: back).
+template <int PMAX, int STEP>
+struct SyevNsK {
+  using Args = EigArgs;
+  static constexpr int kThreads = 64, kMinWaves = 1;
+  static __device__ __attribute__((always_inline)) void body(const Args& a, uint3 bid) {
+    constexpr int XR = (PMAX + 63) / 64;
+    if (syev_skip(a)) return;
+    const SyevScratch<PMAX> sc(syev_gsc<PMAX>(a));
+    const int p = a.p, t = threadIdx.x, j = (int)bid.x;
+    if (*sc.done) return;
+    __shared__ double s_lam[PMAX];
+    if (*sc.loose && j < p) {
+      for (int i = t; i < p; i += 64) s_lam[i] = sc.lam[i];
+      __syncthreads();
+      int cs, ce;
+      if (cluster_kind(s_lam, p, sc.par[3], j, cs, ce) == 1) {
+        const double* src = STEP == 0 ? a.Z : sc.Zp;
+        double* dst = STEP == 0 ? sc.Zp : a.Z;
+        const int ls = STEP == 0 ? a.ldz : PMAX, ld = STEP == 0 ? PMAX : a.ldz;
+        const int cj = p - 1 - j;
+        double zj[XR], acc[XR];
+#pragma unroll
+        for (int x = 0; x < XR; ++x) {
+          const int r = t + 64 * x;
+          zj[x] = r < p ? src[r + (int64_t)cj * ls] : 0.0;
+          acc[x] = 0.0;
+        }
+        // four cluster columns a round: their loads and sums overlap
+        for (int q0 = p - ce; q0 < p - cs; q0 += 4) {
+          double zq[4][XR], dot[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int q = q0 + c;
+            dot[c] = 0.0;
+#pragma unroll
+            for (int x = 0; x < XR; ++x) {
+              const int r = t + 64 * x;
+              zq[c][x] = q < p - cs && r < p ? src[r + (int64_t)q * ls] : 0.0;
+              dot[c] += zq[c][x] * zj[x];
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < 4; ++c) dot[c] = sum64(dot[c]);
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int x = 0; x < XR; ++x) acc[x] += dot[c] * zq[c][x];
+        }
+#pragma unroll
+        for (int x = 0; x < XR; ++x) {
+          const int r = t + 64 * x;
+          if (r < p) dst[r + (int64_t)cj * ld] = 1.5 * zj[x] - 0.5 * acc[x];
+        }
+      }
+    }
+    if (STEP == 1 && bid.x == 0) {
+      for (int idx = t; idx < a.pad * a.pad; idx += 64) {
+        const int row = idx % a.pad, col = idx / a.pad;
+        if (row >= p || col >= p) a.Z[row + (int64_t)col * a.ldz] = row == col ? 1.0 : 0.0;
+      }
+      if (t == 0 && a.info) {
+        if (a.which == 1) {
+          int npos = 0;
+          for (int i = 0; i < p; ++i) npos += sc.lam[i] > 0.0;
+          a.info->n_pos = npos;
+          a.info->dense_rr = 1;
+        } else {
+          a.info->dense_pre = 1;
+        }
+      }
+    }
+  }
+};
 template <int PMAX, bool SH>
 struct RefineK {
   using Args = EigArgs;
@@ -1497,9 +1814,10 @@ void launch_chol_rinv(const double* G, int ldg, int p, double* Rinv, int ldr, in
 }
 
 size_t eig_scratch_bytes(int p) {
-  // the refinement's working matrices (p > 64) and the cluster scratch
-  return (p <= 32 ? cluster_scratch_bytes<32>() : p <= 64 ? cluster_scratch_bytes<64>() : cluster_scratch_bytes<128>()) +
-         256;
+  // the refinement's working matrices (p > 64) and the cluster scratch; for
+  // p > 64 also the state of the dense solver's kernel chain
+  if (p <= 64) return (p <= 32 ? cluster_scratch_bytes<32>() : cluster_scratch_bytes<64>()) + 256;
+  return (cluster_scratch_bytes<128>() + 255) / 256 * 256 + syev_scratch_bytes<128>() + 256;
 }
 
 void launch_eigh(const double* H, int ldh, int p, double* theta, double* Z, int ldz, int pad, pf_info* info,
@@ -1513,9 +1831,19 @@ void launch_eigh(const double* H, int ldh, int p, double* theta, double* Z, int 
     else emit<RefineK<128, false>>(a, dim3(1), 0, st);
     a.skip = refined;
   }
-  if (p <= 32) emit<SyevK<32>>(a, dim3(1), (size_t)32 * 33 * 8, st);
-  else if (p <= 64) emit<SyevK<64>>(a, dim3(1), (size_t)64 * 65 * 8, st);
-  else emit<SyevK<128>>(a, dim3(1), (size_t)128 * 129 * 8, st);
+  if (p <= 32) {
+    emit<SyevK<32>>(a, dim3(1), (size_t)32 * 33 * 8, st);
+  } else if (p <= 64) {
+    emit<SyevK<64>>(a, dim3(1), (size_t)64 * 65 * 8, st);
+  } else {
+    if (!escratch) throw std::logic_error("launch_eigh: p > 64 needs the eigensolver scratch");
+    emit<SyevTriK<128>>(a, dim3(1), 0, st);
+    emit<SyevBisK<128>>(a, dim3(p), 0, st);
+    emit<SyevInvK<128>>(a, dim3((p + 3) / 4), 0, st);
+    emit<SyevBackK<128>>(a, dim3((p + 31) / 32), (size_t)128 * 128 * 8, st);
+    emit<SyevNsK<128, 0>>(a, dim3(p), 0, st);
+    emit<SyevNsK<128, 1>>(a, dim3(p), 0, st);
+  }
 }
 
 }  // namespace pfx

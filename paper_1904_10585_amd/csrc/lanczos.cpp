@@ -39,7 +39,7 @@ struct Arena {
 // The block steps on carved scratch (see enqueue_lanczos).
 void lanczos_steps(const pf_mat& X, int64_t n, const double* V0, int64_t ldv0, int steps, pf_bounds* out,
                    hipStream_t st, double* V, double* W, double* W1, double* H, double* S, double* G, double* R,
-                   double* Gl, double* Z, double* th, int* def, pf_info* info, void* pb, size_t part) {
+                   double* Gl, double* Z, double* th, int* def, pf_info* info, void* pb, size_t part, double* E) {
   const Elem tx = X.dtype == PF_F64 ? Elem::F64 : Elem::F32;
   const int m = kS * steps;
   const int64_t ld = round_up(n, 16);
@@ -114,7 +114,7 @@ void lanczos_steps(const pf_mat& X, int64_t n, const double* V0, int64_t ldv0, i
     }
   }
   launch_sym_from_block_upper(H, m, m, kS, st);
-  launch_eigh(H, m, m, th, Z, m, m, nullptr, 1, st);
+  launch_eigh(H, m, m, th, Z, m, m, nullptr, 1, st, E);
   launch_lanczos_out(th, Z, m, m, kS, Gl, info, out, st);
 }
 
@@ -131,7 +131,8 @@ void enqueue_lanczos(const pf_mat& X, int64_t n, const double* V0, int64_t ldv0,
                                 contract_part_bytes(n, kS, kS, Elem::F64, Elem::F64, true, 0)});
   // sizes first (a null arena counts), then one stream-ordered allocation
   auto carve = [&](Arena& a, double*& V, double*& W, double*& W1, double*& H, double*& S, double*& G,
-                   double*& R, double*& Gl, double*& Z, double*& th, int*& def, pf_info*& info, void*& pb) {
+                   double*& R, double*& Gl, double*& Z, double*& th, int*& def, pf_info*& info, void*& pb,
+                   double*& E) {
     V = a.take<double>((size_t)ld * m);
     W = a.take<double>((size_t)ld * kS);
     W1 = a.take<double>((size_t)ld * kS);
@@ -145,13 +146,14 @@ void enqueue_lanczos(const pf_mat& X, int64_t n, const double* V0, int64_t ldv0,
     def = a.take<int>(kS);
     info = a.take<pf_info>(1);
     pb = a.take<char>(std::max<size_t>(part, 256));
+    E = a.take<double>(eig_scratch_bytes(m) / sizeof(double) + 1);
   };
-  double *V, *W, *W1, *H, *S, *G, *R, *Gl, *Z, *th;
+  double *V, *W, *W1, *H, *S, *G, *R, *Gl, *Z, *th, *E;
   int* def;
   pf_info* info;
   void* pb;
   Arena a;
-  carve(a, V, W, W1, H, S, G, R, Gl, Z, th, def, info, pb);
+  carve(a, V, W, W1, H, S, G, R, Gl, Z, th, def, info, pb, E);
   void* mem = nullptr;
   if (hipMallocAsync(&mem, a.used, st) != hipSuccess) {
     (void)hipGetLastError();
@@ -159,9 +161,9 @@ void enqueue_lanczos(const pf_mat& X, int64_t n, const double* V0, int64_t ldv0,
   }
   a.base = static_cast<char*>(mem);
   a.used = 0;
-  carve(a, V, W, W1, H, S, G, R, Gl, Z, th, def, info, pb);
+  carve(a, V, W, W1, H, S, G, R, Gl, Z, th, def, info, pb, E);
   try {
-    lanczos_steps(X, n, V0, ldv0, steps, out, st, V, W, W1, H, S, G, R, Gl, Z, th, def, info, pb, part);
+    lanczos_steps(X, n, V0, ldv0, steps, out, st, V, W, W1, H, S, G, R, Gl, Z, th, def, info, pb, part, E);
   } catch (...) {
     (void)hipFreeAsync(mem, st);                       // the scratch goes back with the error
     throw;
