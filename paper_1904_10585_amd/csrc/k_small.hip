@@ -1176,6 +1176,18 @@ constexpr size_t cluster_scratch_bytes() {
          (size_t)(2 * PP + 2) * sizeof(int);
 }
 
+// The refinement's block size, and its loops over all PP x PP entries with
+// the trip count known at compile time, unrolled so that the loads of several
+// entries are in flight together (at PP = 128 the matrices live in global
+// scratch, where a rolled loop waits for each load in turn).
+constexpr int kRefineThreads = 256;
+template <int N, int NT, typename F>
+__device__ __attribute__((always_inline)) inline void pp_loop(int t, F&& f) {
+  static_assert(N % NT == 0, "whole rounds");
+#pragma unroll 8
+  for (int r = 0; r < N / NT; ++r) f(t + NT * r);
+}
+
 template <int PMAX, bool SH>
 __device__ __attribute__((always_inline)) inline void eig_refine_impl(const double* __restrict__ H, int ldh, int p,
                                                                      double* __restrict__ theta,
@@ -1194,18 +1206,18 @@ __device__ __attribute__((always_inline)) inline void eig_refine_impl(const doub
   __shared__ double wsum[4];
   __shared__ int s_rank[PMAX];
   __shared__ double s_th[PMAX];
-  const int t = threadIdx.x, nt = blockDim.x;
+  const int t = threadIdx.x, nt = kRefineThreads;
   const int lane = t & 63, wave = t >> 6;
 
   double local = 0.0;
-  for (int idx = t; idx < PP * PP; idx += nt) {
+  pp_loop<PP * PP, kRefineThreads>(t, [&](int idx) {
     const int i = idx % PP, j = idx / PP;
     double v = 0.0;
     if (i < p && j < p) v = 0.5 * (H[i + (int64_t)j * ldh] + H[j + (int64_t)i * ldh]);   // symmetrise
     Hs[i + j * LD] = v;
     Zc[i + j * LD] = i == j ? 1.0 : 0.0;
     local += v * v;
-  }
+  });
   local = wave_sum(local);
   if (lane == 0) wsum[wave] = local;
   __syncthreads();
@@ -1228,10 +1240,10 @@ __device__ __attribute__((always_inline)) inline void eig_refine_impl(const doub
   for (;; ++it) {
     if (it == 0) {
       // Z = I: A = H
-      for (int idx = t; idx < PP * PP; idx += nt) {
+      pp_loop<PP * PP, kRefineThreads>(t, [&](int idx) {
         const int i = idx % PP, j = idx / PP;
         T2[i + j * LD] = Hs[i + j * LD];
-      }
+      });
     } else {
       gemm_pp<PP, LD, false>(T1, Hs, Zc, wave, lane);     // T1 = H Z
       __syncthreads();
@@ -1289,7 +1301,7 @@ __device__ __attribute__((always_inline)) inline void eig_refine_impl(const doub
           if (!__syncthreads_or(changed)) break;
         }
       }
-      for (int idx = t; idx < PP * PP; idx += nt) {
+      pp_loop<PP * PP, kRefineThreads>(t, [&](int idx) {
         const int i = idx % PP, j = idx / PP;
         double k = 0.0;
         if (i != j && i < p && j < p && s_lab[i] != s_lab[j]) {
@@ -1301,9 +1313,9 @@ __device__ __attribute__((always_inline)) inline void eig_refine_impl(const doub
         }
         kmax = fmax(kmax, fabs(k));
         T1[i + j * LD] = k;                                // K (antisymmetric)
-      }
+      });
     } else {
-      for (int idx = t; idx < PP * PP; idx += nt) {
+      pp_loop<PP * PP, kRefineThreads>(t, [&](int idx) {
         const int i = idx % PP, j = idx / PP;
         double k = 0.0;
         if (i != j && i < p && j < p) {
@@ -1317,7 +1329,7 @@ __device__ __attribute__((always_inline)) inline void eig_refine_impl(const doub
         }
         kmax = fmax(kmax, fabs(k));
         T1[i + j * LD] = k;                                // K (antisymmetric)
-      }
+      });
     }
     kmax = wave_max(kmax);
     if (lane == 0) s_kmax[wave] = kmax;
@@ -1335,10 +1347,10 @@ __device__ __attribute__((always_inline)) inline void eig_refine_impl(const doub
       // pre-rotation: the first-order eigenvectors Z = I + K (invertible, so
       // the span is kept; each column on one eigen-direction to O(K^2)) and
       // second-order eigenvalues theta_i = a_ii + sum_j a_ij K_ji
-      for (int idx = t; idx < PP * PP; idx += nt) {
+      pp_loop<PP * PP, kRefineThreads>(t, [&](int idx) {
         const int i = idx % PP, j = idx / PP;
         Zc[i + j * LD] = (i == j ? 1.0 : 0.0) + T1[i + j * LD];
-      }
+      });
       for (int i = t; i < p; i += nt) {
         double th = T2[i + i * LD];
         for (int j = 0; j < p; ++j) th += T2[j + i * LD] * T1[j + i * LD];
@@ -1351,36 +1363,36 @@ __device__ __attribute__((always_inline)) inline void eig_refine_impl(const doub
     const bool small_k = kmax < 1e-4;
     gemm_pp<PP, LD, false>(T2, T1, T1, wave, lane);       // T2 = K^2
     __syncthreads();
-    for (int idx = t; idx < PP * PP; idx += nt) {
+    pp_loop<PP * PP, kRefineThreads>(t, [&](int idx) {
       const int i = idx % PP, j = idx / PP;
       T1[i + j * LD] = (i == j ? 1.0 : 0.0) + T1[i + j * LD] + 0.5 * T2[i + j * LD];   // M = I + K + K^2/2
-    }
+    });
     __syncthreads();
     if (it == 0) {
       // Z = I: Z M = M
-      for (int idx = t; idx < PP * PP; idx += nt) {
+      pp_loop<PP * PP, kRefineThreads>(t, [&](int idx) {
         const int i = idx % PP, j = idx / PP;
         T2[i + j * LD] = T1[i + j * LD];
-      }
+      });
     } else {
       gemm_pp<PP, LD, false>(T2, Zc, T1, wave, lane);     // T2 = Z M
     }
     __syncthreads();
     if (small_k) {
       // M is orthogonal to O(|K|^4) (M^T M = I + K^4 / 4): no re-orthonormalisation
-      for (int idx = t; idx < PP * PP; idx += nt) {
+      pp_loop<PP * PP, kRefineThreads>(t, [&](int idx) {
         const int i = idx % PP, j = idx / PP;
         Zc[i + j * LD] = T2[i + j * LD];
-      }
+      });
       __syncthreads();
       continue;
     }
     gemm_pp<PP, LD, true>(T1, T2, T2, wave, lane);        // T1 = (Z M)^T (Z M)
     __syncthreads();
-    for (int idx = t; idx < PP * PP; idx += nt) {
+    pp_loop<PP * PP, kRefineThreads>(t, [&](int idx) {
       const int i = idx % PP, j = idx / PP;
       T1[i + j * LD] = 0.5 * ((i == j ? 3.0 : 0.0) - T1[i + j * LD]);   // (3 I - Z^T Z) / 2
-    }
+    });
     __syncthreads();
     gemm_pp<PP, LD, false>(Zc, T2, T1, wave, lane);       // Z <- Z M (3 I - ...) / 2
     __syncthreads();
@@ -1786,7 +1798,7 @@ struct SyevNsK {
 template <int PMAX, bool SH>
 struct RefineK {
   using Args = EigArgs;
-  static constexpr int kThreads = 256, kMinWaves = 1;
+  static constexpr int kThreads = kRefineThreads, kMinWaves = 1;
   static __device__ __attribute__((always_inline)) void body(const Args& a, uint3) {
     eig_refine_impl<PMAX, SH>(a.H, a.ldh, a.p, a.theta, a.Z, a.ldz, a.gscratch, a.refined, a.info, a.which,
                               a.max_iter);
