@@ -48,6 +48,7 @@ struct DevArgs {
   double alpha, beta, gamma;
   void* part; int64_t ldp;  // split-K slabs, ldp rows each
   int splitk;
+  int lower;                // A symmetric, read as L + D/2 (see ContractArgs)
 };
 
 template <typename T, int VEC> struct VecLoad;
@@ -146,15 +147,30 @@ __device__ void ContractK<TA, TB, TO, F64, MB, NB>::body(const DevArgs& a, uint3
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int c = lane & 15, g = lane >> 4;
-  const int64_t m0 = (int64_t)bid.x * (16 * MB);
+  // a `lower` product's work grows with the row: its heaviest (bottom) row
+  // tiles are dispatched first, the light ones fill the end
+  const int64_t mtiles = (a.M + 16 * MB - 1) / (16 * MB);
+  const int64_t m0 = (a.lower ? mtiles - 1 - (int64_t)bid.x : (int64_t)bid.x) * (16 * MB);
   const int64_t n0 = (int64_t)bid.y * (16 * NB);
   const int s = bid.z;
 
-  const int64_t kbeg_wg = (int64_t)s * a.kchunk;
-  const int64_t kend_wg = min(a.K, kbeg_wg + a.kchunk);
-  const int64_t kw = a.kchunk / kWaves;
+  // K range of this workgroup.  With `lower` the rows of this tile need K
+  // up to the end of its diagonal block only, split evenly over the slabs
+  // (the work per tile grows with its row; many tiles per CU even it out).
+  int64_t kchunk = a.kchunk, kend_all = a.K;
+  if (a.lower) {
+    constexpr int64_t unit = (int64_t)kWaves * KSTEP;
+    kend_all = min(a.M, m0 + 16 * MB);
+    kchunk = ((kend_all + a.splitk - 1) / a.splitk + unit - 1) / unit * unit;
+  }
+  const int64_t kbeg_wg = (int64_t)s * kchunk;
+  const int64_t kend_wg = min(kend_all, kbeg_wg + kchunk);
+  const int64_t kw = kchunk / kWaves;
   const int64_t kb = kbeg_wg + (int64_t)wave * kw;
-  const int64_t ke = min(kend_wg, kb + kw);
+  const int64_t ke_all = min(kend_wg, kb + kw);
+  // the diagonal block [m0, m0 + 16 MB) of a `lower` product is weighted
+  // entry by entry after the plain steps
+  const int64_t ke = a.lower ? min(ke_all, m0) : ke_all;
 
   const TA* A = static_cast<const TA*>(a.A);
   const TB* B = static_cast<const TB*>(a.B);
@@ -202,6 +218,24 @@ __device__ void ContractK<TA, TB, TO, F64, MB, NB>::body(const DevArgs& a, uint3
       T t;
       // mask rows past this wave's range as well as past K
       t.template load<true>(acol, aok, bcol, k + goff, ke);
+      t.mma(acc);
+    }
+  }
+  if (a.lower) {
+    // entry (k, col) of the diagonal block: weight 1 below the diagonal,
+    // 1/2 on it, 0 above (exact scalings)
+    for (int64_t k = max(kb, m0); k < ke_all; k += KSTEP) {
+      T t;
+      t.template load<true>(acol, aok, bcol, k + goff, ke_all);
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int64_t col = m0 + 16 * mb + c;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const int64_t kk = k + goff + v;
+          t.ra[mb][v] = kk < col ? t.ra[mb][v] : (kk == col ? t.ra[mb][v] * (TA)0.5 : (TA)0);
+        }
+      }
       t.mma(acc);
     }
   }
@@ -442,6 +476,8 @@ int contract(const ContractArgs& x, hipStream_t st) {
   d.out = x.out; d.ldo = x.ldo; d.D1 = x.D1; d.ld1 = x.ld1; d.D2 = x.D2; d.ld2 = x.ld2;
   d.alpha = x.alpha; d.beta = x.beta; d.gamma = x.gamma;
   d.part = x.part; d.ldp = sp.ldp; d.splitk = sp.S;
+  d.lower = x.lower ? 1 : 0;
+  if (x.lower && x.K != x.M) fail(PF_ERR_ARG, "contract: a lower-triangle product needs a square A");
   const bool of64 = x.to == Elem::F64;
   const int NB = ch.NB;
   if (!ch.f64) {

@@ -200,53 +200,55 @@ __device__ __attribute__((always_inline)) inline void chol_rinv_impl(
       static_for<0, BC>(step);
     }
   } else {
-    // One step per iteration (at 1024 threads a lane has 128 registers: the
-    // unrolled form spills inside the loop).  kr is uniform: a scalar branch
-    // picks the published registers.
-    static_assert(BR == 4 && BC == 4, "rolled steps take 4 x 4 blocks");
+    // One step per iteration (the unrolled form spills inside the loop at
+    // the larger sizes).  k's position in its blocks is uniform: scalar
+    // branches pick the published registers.
     for (int k = 0; k < p; ++k) {
-      const int buf = k & 1, kb = k >> 2, kr = k & 3;
-      if (bj == kb) {
-        switch (kr) {
-          case 0: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][0]; break;
-          case 1: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][1]; break;
-          case 2: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][2]; break;
-          default: for (int r = 0; r < 4; ++r) s_col[buf][i0 + r] = g[r][3]; break;
-        }
+      const int buf = k & 1, kbc = k / BC, kc = k % BC, kbr = k / BR, kr = k % BR;
+      if (bj == kbc) {
+#pragma unroll
+        for (int c = 0; c < BC; ++c)
+          if (c == kc) {
+#pragma unroll
+            for (int r = 0; r < BR; ++r) s_col[buf][i0 + r] = g[r][c];
+          }
       }
-      if (bi == kb) {
-        switch (kr) {
-          case 0: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[0][c]; break;
-          case 1: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[1][c]; break;
-          case 2: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[2][c]; break;
-          default: for (int c = 0; c < 4; ++c) s_row[buf][j0 + c] = w[3][c]; break;
-        }
+      if (bi == kbr) {
+#pragma unroll
+        for (int r = 0; r < BR; ++r)
+          if (r == kr) {
+#pragma unroll
+            for (int c = 0; c < BC; ++c) s_row[buf][j0 + c] = w[r][c];
+          }
       }
       __syncthreads();
       const double pk = s_col[buf][k];
-      double ci[4], cj[4], wk[4];
+      double ci[BR], cj[BC], wk[BC];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        ci[u] = s_col[buf][i0 + u];
+      for (int u = 0; u < BR; ++u) ci[u] = s_col[buf][i0 + u];
+#pragma unroll
+      for (int u = 0; u < BC; ++u) {
         cj[u] = s_col[buf][j0 + u];
         wk[u] = s_row[buf][j0 + u];
       }
       const bool ok = pk > tol;
       if (t == 0) { s_piv[k] = ok ? pk : 1.0; s_def[k] = ok ? 0 : 1; }
       const double inv = ok ? 1.0 / pk : 0.0;
-      double li[4], gj[4];
+      double li[BR], gj[BC];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        li[u] = (i0 + u > k) ? ci[u] * inv : 0.0;
-        gj[u] = (j0 + u > k) ? cj[u] : 0.0;
+      for (int u = 0; u < BR; ++u) li[u] = (i0 + u > k) ? ci[u] * inv : 0.0;
+#pragma unroll
+      for (int u = 0; u < BC; ++u) gj[u] = (j0 + u > k) ? cj[u] : 0.0;
+      // rows of this block all at or above k: nothing left to eliminate
+      if (i0 + BR - 1 > k) {
+#pragma unroll
+        for (int r = 0; r < BR; ++r)
+#pragma unroll
+          for (int c = 0; c < BC; ++c) {
+            g[r][c] -= li[r] * gj[c];
+            w[r][c] -= li[r] * wk[c];
+          }
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          g[r][c] -= li[r] * gj[c];
-          w[r][c] -= li[r] * wk[c];
-        }
     }
   }
   __syncthreads();
@@ -1820,7 +1822,8 @@ void launch_chol_rinv(const double* G, int ldg, int p, double* Rinv, int ldr, in
   } else if (p <= 64) {
     emit<CholK<64, 4, 4, true>>(a, dim3(1), 0, st);
   } else {
-    // 128 registers a lane at 1024 threads: the steps stay rolled
+    // 128 registers a lane at 1024 threads: the steps stay rolled (4 x 8
+    // blocks on 512 threads were slower, 125 against 113 us, at p = 128)
     emit<CholK<128, 4, 4, false>>(a, dim3(1), 0, st);
   }
 }

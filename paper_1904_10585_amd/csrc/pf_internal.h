@@ -57,6 +57,10 @@ struct ContractArgs {
   bool f64_mfma;            // contract in FP64 (products and sums) even for F32 operands
   int prof_main = -1;       // profiling class of the product kernel (-1: none)
   int prof_reduce = -1;     // profiling class of the split-K sum
+  // A symmetric (K == M) and read below its diagonal only: the product is
+  // (L + D/2) B with L the strict lower triangle and D the diagonal of A, so
+  // that Q^T (L + D/2) Q + its transpose is Q^T A Q at half the work
+  bool lower = false;
 };
 // Enqueue; returns the split-K factor used.
 int contract(const ContractArgs& a, hipStream_t st);

@@ -329,13 +329,14 @@ Elem elem_of(pf_dtype t) { return t == PF_F64 ? Elem::F64 : Elem::F32; }
 void contract_into(Plan* P, const void* A, int64_t lda, Elem ta, const void* B, int64_t ldb, Elem tb,
                    int64_t K, int64_t M, void* out, int64_t ldo, Elem to, const void* D1,
                    const void* D2, int64_t ldd, double alpha, double beta, double gamma, bool f64,
-                   hipStream_t st, int prof_main, int prof_reduce);
+                   hipStream_t st, int prof_main, int prof_reduce, bool lower = false);
 
 void contract_into(Plan* P, const void* A, int64_t lda, Elem ta, const void* B, int64_t ldb, Elem tb,
                    int64_t K, int64_t M, void* out, int64_t ldo, Elem to, const void* D1,
                    const void* D2, int64_t ldd, double alpha, double beta, double gamma, bool f64,
-                   hipStream_t st, int prof_main, int prof_reduce) {
+                   hipStream_t st, int prof_main, int prof_reduce, bool lower) {
   ContractArgs c;
+  c.lower = lower;
   c.A = A; c.lda = lda; c.ta = ta;
   c.B = B; c.ldb = ldb; c.tb = tb;
   c.K = K; c.M = M; c.N = P->p_pad;
@@ -662,8 +663,12 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
     operator_product(P, op, P->Q, P->W, st);
     gram(P, P->Q, W, P->W, W, P->G, st);
   } else {
-    contract_into(P, Xr.data, Xr.ld, tr, P->Q, ld, W, P->n, P->n, P->W, ld, Elem::F64, nullptr, nullptr, ld, 1.0,
-                  0.0, 0.0, true, st, PF_PROF_RR, -1);
+    // X is symmetric: W = 2 (L + D/2) Q from its lower triangle, half the
+    // products of X Q, and G = Q^T W has the symmetric part Q^T X Q, the
+    // part the eigensolver reads.  The residual norms need W = X Q itself.
+    const bool half = !(ex && ex->resid);
+    contract_into(P, Xr.data, Xr.ld, tr, P->Q, ld, W, P->n, P->n, P->W, ld, Elem::F64, nullptr, nullptr, ld,
+                  half ? 2.0 : 1.0, 0.0, 0.0, true, st, PF_PROF_RR, -1, half);
     set_phase(kPhRR + 1);
     gram(P, P->Q, W, P->W, Elem::F64, P->G, st);
   }
