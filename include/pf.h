@@ -186,10 +186,12 @@ typedef struct pf_info {
  *            PF_OP_GRAM); F64 (work F64), F32/BF16/F8E4M3 (work F32).
  *  X_rr:     the operator Rayleigh-Ritz projects; same shape; F64 or F32
  *            (may equal X_filter).  BF16/FP8 filters need an F32 X_rr.
- *            PF_OP_SYM: X is symmetric, and Rayleigh-Ritz reads X_rr on
- *            and below its diagonal only (Q^T X Q as the symmetric part of
- *            2 Q^T (L + D/2) Q) unless residual norms are asked for
- *            (pf_extras.resid), which use the whole X_rr.
+ *            PF_OP_SYM: X is symmetric, and Rayleigh-Ritz reads the
+ *            entries X_rr[i][j] with i <= j only (on and above the
+ *            diagonal; Q^T X Q as the symmetric part of 2 Q^T (L + D/2) Q,
+ *            L the strict lower triangle, whose values these hold) unless
+ *            residual norms are asked for (pf_extras.resid), which use the
+ *            whole X_rr.
  *  U_inout:  n-by-p block in the work dtype, leading dimension ldu >= n.
  *            In: start block (any full-rank block; Ritz vectors of the
  *            previous call for a warm start).  Out: the Ritz vectors V,

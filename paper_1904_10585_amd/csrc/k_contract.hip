@@ -48,7 +48,7 @@ struct DevArgs {
   double alpha, beta, gamma;
   void* part; int64_t ldp;  // split-K slabs, ldp rows each
   int splitk;
-  int lower;                // A symmetric, read as L + D/2 (see ContractArgs)
+  int lower;                // A symmetric, read as L + D/2 from its entries (k, m), k <= m
 };
 
 template <typename T, int VEC> struct VecLoad;
@@ -222,8 +222,8 @@ __device__ void ContractK<TA, TB, TO, F64, MB, NB>::body(const DevArgs& a, uint3
     }
   }
   if (a.lower) {
-    // entry (k, col) of the diagonal block: weight 1 below the diagonal,
-    // 1/2 on it, 0 above (exact scalings)
+    // entry (k, col) of the diagonal block: weight 1 for k < col, 1/2 on
+    // the diagonal, 0 for k > col (exact scalings)
     for (int64_t k = max(kb, m0); k < ke_all; k += KSTEP) {
       T t;
       t.template load<true>(acol, aok, bcol, k + goff, ke_all);

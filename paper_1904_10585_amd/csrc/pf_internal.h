@@ -57,9 +57,11 @@ struct ContractArgs {
   bool f64_mfma;            // contract in FP64 (products and sums) even for F32 operands
   int prof_main = -1;       // profiling class of the product kernel (-1: none)
   int prof_reduce = -1;     // profiling class of the split-K sum
-  // A symmetric (K == M) and read below its diagonal only: the product is
-  // (L + D/2) B with L the strict lower triangle and D the diagonal of A, so
-  // that Q^T (L + D/2) Q + its transpose is Q^T A Q at half the work
+  // A symmetric (K == M) and read on and above its diagonal only (entries
+  // (k, m) with k <= m of the column-major A, which by symmetry hold the
+  // lower triangle's values): the product is (L + D/2) B with L the strict
+  // lower triangle and D the diagonal of A, so that Q^T (L + D/2) Q plus
+  // its transpose is Q^T A Q at half the work
   bool lower = false;
 };
 // Enqueue; returns the split-K factor used.

@@ -663,9 +663,10 @@ void enqueue_extraction(Plan* P, const pf_mat& Xf, const pf_mat& Xr, const void*
     operator_product(P, op, P->Q, P->W, st);
     gram(P, P->Q, W, P->W, W, P->G, st);
   } else {
-    // X is symmetric: W = 2 (L + D/2) Q from its lower triangle, half the
-    // products of X Q, and G = Q^T W has the symmetric part Q^T X Q, the
-    // part the eigensolver reads.  The residual norms need W = X Q itself.
+    // X is symmetric: W = 2 (L + D/2) Q from one triangle (the entries on
+    // and above the diagonal), half the products of X Q, and G = Q^T W has
+    // the symmetric part Q^T X Q, the part the eigensolver reads.  The
+    // residual norms need W = X Q itself.
     const bool half = !(ex && ex->resid);
     contract_into(P, Xr.data, Xr.ld, tr, P->Q, ld, W, P->n, P->n, P->W, ld, Elem::F64, nullptr, nullptr, ld,
                   half ? 2.0 : 1.0, 0.0, 0.0, true, st, PF_PROF_RR, -1, half);

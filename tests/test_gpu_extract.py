@@ -531,3 +531,33 @@ def test_reorth_keeps_fp32_parity_at_the_bulk_edge():
                 U = V
         finally:
             pf.pf_session_close(h)
+
+
+@pytest.mark.parametrize("work", ["f64", "f32"])
+@pytest.mark.parametrize("n,p", [(300, 16), (1030, 96)])
+def test_rayleigh_ritz_reads_the_lower_triangle(work, n, p):
+    """Rayleigh-Ritz of a symmetric X forms Q^T X Q from the entries of X on
+    and above its diagonal (the symmetric part of 2 Q^T (L + D/2) Q; eq. RR):
+    NaN written over the strict lower triangle of X_rr changes nothing, bit
+    for bit, and the result stays within the tolerance of the oracle on the
+    whole X."""
+    r = max(1, p // 2)
+    X, _, _ = wl.planted(n, r, (4.0, 10.0), (-1.0, 0.5), config=91, index=n + p)
+    U = wl.start_block(n, p, config=91, index=n * 7 + p)
+    a, b = -1.0, 0.5
+    for _ in range(3):
+        U = oracle.extract(X, X, U, 6, a, b)["V"]
+    if work == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+        U = U.astype(np.float32).astype(np.float64)
+    garbled = X.copy()
+    garbled[np.tril_indices(n, -1)] = np.nan
+    th, V, info = run_extract(X, U, 3, a, b, work=work)
+    th_g, V_g, info_g = run_extract(X, U, 3, a, b, work=work, Xrr=garbled)
+    assert info["status"] == 0 and info_g["status"] == 0, (info, info_g)
+    assert np.array_equal(th, th_g) and np.array_equal(V, V_g)
+    ref = oracle.extract(X, X, U, 3, a, b)
+    rel, sin = compare(th_g, V_g, ref, r)
+    tol = (1e-10, 1e-10) if work == "f64" else (1e-5, 1e-4)
+    print(f"lower-triangle RR {work} n={n} p={p}: rel {rel:.2e} sin {sin:.2e}")
+    assert rel <= tol[0] and sin <= tol[1], (rel, sin)
