@@ -288,16 +288,17 @@ __device__ __attribute__((always_inline)) inline void chol_rinv_impl(
 
 // ---------------------------------------------------------------------------
 // Dense symmetric eigensolver H = Z diag(theta) Z^T for the p x p matrices of
-// an extraction (p <= PMAX <= 128), one workgroup of 8 * PMAX threads with
-// H in LDS.  It runs where the refinement below cannot (cold steps, guard
-// columns whose Ritz values crowd together), so its cost does not depend on
-// how far H is from diagonal:
+// an extraction (p <= PMAX <= 128), steps 1-4 below in one workgroup of
+// 8 * PMAX threads (p <= 64; at p > 64 step 1 alone, the rest run as the
+// kernel chain after RefineK).  It runs where the refinement below cannot
+// (cold steps, guard columns whose Ritz values crowd together), so its cost
+// does not depend on how far H is from diagonal:
 //  1. Householder reduction to tridiagonal T = Q^T H Q (H scaled by a power
 //     of two so that max |h_ij| is in [0.5, 1)).  Step k reflects column k
 //     with P = I - beta v v^T; the trailing block is updated as
 //     A <- A - v w^T - w v^T, y = beta A v, w = y - (beta/2)(v^T y) v.
 //     The matrix lives in registers (R8 entries of one row per lane); the
-//     reflectors are kept in LDS.
+//     reflectors are kept in LDS (in global scratch when SPLIT).
 //  2. Eigenvalues of T by bisection on Sturm counts (the number of negative
 //     pivots of the LDL^T factorisation of T - x I, pivots kept away from
 //     zero by pivmin): one count per thread at 8 PMAX points of the
