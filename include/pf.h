@@ -473,8 +473,11 @@ pf_status pf_quantize(void* dst, int64_t ld_dst, float* tile_scale, int32_t tile
  *  theta: device, p values, written in descending order.
  *  Z:     device, column-major, ldz >= p; columns 0..p-1 (rows 0..p-1)
  *         written with the orthonormal eigenvectors in theta's order.
- * H and Z must not overlap.  Asynchronous on stream.  A non-finite entry
- * in H gives NaN theta and Z = I; H = 0 gives theta = 0 and Z = I.
+ * H and Z must not overlap.  Asynchronous on stream.  For p > 64 the
+ * solver runs as a chain of kernels whose state (about 1.3 MB) is taken
+ * with a stream-ordered allocation and freed on the stream after it; a
+ * failed allocation returns PF_ERR_NOMEM.  A non-finite entry in H gives
+ * NaN theta and Z = I; H = 0 gives theta = 0 and Z = I.
  * Accuracy: |theta_i - lambda_i| and ||H z_i - theta_i z_i|| of a few
  * eps ||H||, Z orthonormal to ~1e-13. */
 pf_status pf_eigh(const double* H, int64_t ldh, int32_t p, double* theta, double* Z, int64_t ldz,
