@@ -774,14 +774,16 @@ __device__ __attribute__((always_inline)) inline void syev_impl(const double* __
   const int team = t >> 3, part = t & 7, base8 = lane & ~7;
 
   // ---- load sym(H) into registers: lane (row team, part) holds row `team`,
-  // columns R8*part .. R8*part+R8-1; find max |h_ij| and non-finite entries
-  const int c0 = R8 * part;
+  // columns part, part+8, part+16, ... (interleaved, so that the eight
+  // lanes of a team read eight adjacent doubles of v and y, free of LDS
+  // bank conflicts); find max |h_ij| and non-finite entries
+  auto colj = [&](int u) { return part + 8 * u; };
   double a[R8];
   double amax = 0.0;
   int bad = 0;
 #pragma unroll
   for (int u = 0; u < R8; ++u) {
-    const int j = c0 + u;
+    const int j = colj(u);
     double v = 0.0;
     if (team < p && j < p) {
       v = 0.5 * (H[team + (int64_t)j * ldh] + H[j + (int64_t)team * ldh]);
@@ -828,7 +830,7 @@ __device__ __attribute__((always_inline)) inline void syev_impl(const double* __
     double v = 0.0;
 #pragma unroll
     for (int u = 0; u < R8; ++u)
-      if (c0 + u == col) v = a[u];
+      if (colj(u) == col) v = a[u];
     return v;
   };
   if (part == 0 && team < p) s_x[team] = a[0];  // column 0
@@ -874,7 +876,7 @@ __device__ __attribute__((always_inline)) inline void syev_impl(const double* __
       double vj[R8];
 #pragma unroll
       for (int u = 0; u < R8; ++u) {
-        const int j = c0 + u;
+        const int j = colj(u);
         vj[u] = j > k && j < p ? s_v[j] : 0.0;
       }
       if (row_on) {
@@ -893,16 +895,16 @@ __device__ __attribute__((always_inline)) inline void syev_impl(const double* __
         const double vi = s_v[team], ci = s_y[team] - 2.0 * kv * vi;
 #pragma unroll
         for (int u = 0; u < R8; ++u) {
-          const int j = c0 + u;
+          const int j = colj(u);
           if (j > k && j < p) a[u] -= vi * s_y[j] + ci * vj[u];
         }
       }
     }
     // publish column k+1 (rows k+1.., the diagonal included)
-    if (team > k && team < p && c0 <= k + 1 && k + 1 < c0 + R8) s_x[team] = entry(k + 1);
+    if (team > k && team < p && ((k + 1) & 7) == part) s_x[team] = entry(k + 1);
     __syncthreads();
   }
-  if (team == p - 1 && c0 <= p - 1 && p - 1 < c0 + R8) s_d[p - 1] = entry(p - 1);
+  if (team == p - 1 && ((p - 1) & 7) == part) s_d[p - 1] = entry(p - 1);
   if (t == 0) {
     if (p >= 2) {
       s_d[p - 2] = s_x[p - 2];
